@@ -1,0 +1,201 @@
+"""CPU oracle of the k-mer counting path.
+
+TEST INFRASTRUCTURE ONLY: the test suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` are the only callers.  The product library
+never imports, links or runs anything in this directory.
+
+``kc_oracle.c`` (plain C, built with gcc) holds the reference computation;
+``brute.py`` is a second, pure-Python reading of the same definitions used to
+pin the C code on tiny inputs.  Each function names the passage of the paper it
+follows in the C source header.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "kc_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+U64P = ctypes.POINTER(ctypes.c_uint64)
+U32P = ctypes.POINTER(ctypes.c_uint32)
+U8P = ctypes.POINTER(ctypes.c_uint8)
+
+
+class OrParams(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("n_counters", ctypes.c_uint32),
+                ("min_count", ctypes.c_uint32), ("m_log2", ctypes.c_uint32),
+                ("h", ctypes.c_uint32), ("block_log2", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64)]
+
+
+class OrStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "n_valid", "n_distinct", "n_pass", "entries", "sum_counts", "fp_singletons",
+        "b1_pop", "b2_pop")]
+
+
+class OrResult(ctypes.Structure):
+    _fields_ = [("st", OrStats), ("n_entries", ctypes.c_uint64), ("keys", U64P),
+                ("counts", U32P), ("m_words", ctypes.c_uint64), ("b1", U64P), ("b2", U64P)]
+
+
+def build(force: bool = True) -> str:
+    """Compile kc_oracle.c into liboracle.so with gcc."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC,
+                               "-lpthread"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER(OrParams)
+        lib.or_mix64.argtypes = [ctypes.c_uint64]
+        lib.or_mix64.restype = ctypes.c_uint64
+        lib.or_count.argtypes = [P, U8P, U64P, ctypes.c_uint64, U8P, ctypes.c_int]
+        lib.or_count.restype = ctypes.POINTER(OrResult)
+        lib.or_free.argtypes = [ctypes.POINTER(OrResult)]
+        lib.or_enumerate.argtypes = [P, U8P, U64P, ctypes.c_uint64, U8P, U64P, ctypes.c_uint64]
+        lib.or_enumerate.restype = ctypes.c_uint64
+        lib.or_bloom_bits.argtypes = [P, ctypes.c_uint64, U64P]
+        lib.or_bloom_bits.restype = ctypes.c_uint32
+        lib.or_sample_counts.argtypes = [P, U8P, U64P, ctypes.c_uint64, U8P, U64P,
+                                         ctypes.c_uint64, U32P, U64P, ctypes.c_int]
+        lib.or_sample_counts.restype = ctypes.c_int
+        lib.or_sample_hits.argtypes = [P, U8P, U64P, ctypes.c_uint64, U64P, ctypes.c_uint64,
+                                       U32P, ctypes.c_int]
+        lib.or_sample_hits.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+@dataclass
+class Params:
+    k: int = 31
+    n_counters: int = 1
+    min_count: int = 2
+    m_log2: int = 24
+    h: int = 3
+    block_log2: int = 19
+    seed: int = 0
+
+    def c(self) -> OrParams:
+        return OrParams(self.k, self.n_counters, self.min_count, self.m_log2, self.h,
+                        min(self.block_log2, self.m_log2), self.seed & ((1 << 64) - 1))
+
+
+@dataclass
+class Result:
+    keys: np.ndarray       # uint64 [E], ascending
+    counts: np.ndarray     # uint32 [E, n_counters]
+    b1: np.ndarray | None  # uint64 [m/64]
+    b2: np.ndarray | None
+    stats: dict
+
+
+def _arrays(bases, offsets, tags):
+    bases = np.ascontiguousarray(bases, dtype=np.uint8)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    if tags is not None:
+        tags = np.ascontiguousarray(tags, dtype=np.uint8)
+    return bases, offsets, tags
+
+
+def _ptr(a, t):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def mix64(z: int) -> int:
+    return int(_load().or_mix64(z & ((1 << 64) - 1)))
+
+
+def count(params: Params, bases, offsets, tags=None, want_bloom: bool = True) -> Result:
+    """Full count: final table, Bloom levels and statistics."""
+    bases, offsets, tags = _arrays(bases, offsets, tags)
+    n_reads = offsets.size - 1
+    p = params.c()
+    r = _load().or_count(ctypes.byref(p), _ptr(bases, U8P), _ptr(offsets, U64P), n_reads,
+                         _ptr(tags, U8P), 1 if want_bloom else 0)
+    if not r:
+        raise ValueError("oracle rejected the parameters or input")
+    try:
+        res = r.contents
+        ne = res.n_entries
+        nc = params.n_counters
+        keys = np.ctypeslib.as_array(res.keys, shape=(max(ne, 1),))[:ne].copy()
+        counts = np.ctypeslib.as_array(res.counts, shape=(max(ne * nc, 1),))[:ne * nc].copy()
+        b1 = b2 = None
+        if want_bloom:
+            b1 = np.ctypeslib.as_array(res.b1, shape=(res.m_words,)).copy()
+            b2 = np.ctypeslib.as_array(res.b2, shape=(res.m_words,)).copy()
+        st = {name: int(getattr(res.st, name)) for name, _ in OrStats._fields_}
+    finally:
+        _load().or_free(r)
+    return Result(keys, counts.reshape(ne, nc), b1, b2, st)
+
+
+def enumerate_keys(params: Params, bases, offsets, tags=None) -> np.ndarray:
+    """Canonical keys of every valid window, in read order, tagged (x << 1 | tag)."""
+    bases, offsets, tags = _arrays(bases, offsets, tags)
+    p = params.c()
+    lib = _load()
+    n = lib.or_enumerate(ctypes.byref(p), _ptr(bases, U8P), _ptr(offsets, U64P),
+                         offsets.size - 1, _ptr(tags, U8P), None, 0)
+    out = np.empty(max(int(n), 1), dtype=np.uint64)
+    lib.or_enumerate(ctypes.byref(p), _ptr(bases, U8P), _ptr(offsets, U64P), offsets.size - 1,
+                     _ptr(tags, U8P), _ptr(out, U64P), n)
+    return out[:n]
+
+
+def bloom_bits(params: Params, x: int) -> list[int]:
+    p = params.c()
+    out = np.zeros(8, dtype=np.uint64)
+    n = _load().or_bloom_bits(ctypes.byref(p), x, _ptr(out, U64P))
+    return [int(v) for v in out[:n]]
+
+
+def sample_counts(params: Params, bases, offsets, sample_keys, tags=None, threads: int = 0):
+    """Exact per-counter counts of distinct canonical keys (any order); also N_valid."""
+    bases, offsets, tags = _arrays(bases, offsets, tags)
+    keys = np.unique(np.asarray(sample_keys, dtype=np.uint64))
+    out = np.zeros(max(keys.size * params.n_counters, 1), dtype=np.uint32)
+    nv = ctypes.c_uint64(0)
+    p = params.c()
+    rc = _load().or_sample_counts(ctypes.byref(p), _ptr(bases, U8P), _ptr(offsets, U64P),
+                                  offsets.size - 1, _ptr(tags, U8P), _ptr(keys, U64P), keys.size,
+                                  _ptr(out, U32P), ctypes.byref(nv), threads or _threads())
+    if rc:
+        raise ValueError("or_sample_counts failed (%d)" % rc)
+    return keys, out[:keys.size * params.n_counters].reshape(keys.size, params.n_counters), \
+        int(nv.value)
+
+
+def sample_hits(params: Params, bases, offsets, sample_bits, threads: int = 0):
+    """min(2, hits(b)) for distinct bit positions (any order)."""
+    bases, offsets, _ = _arrays(bases, offsets, None)
+    bits = np.unique(np.asarray(sample_bits, dtype=np.uint64))
+    out = np.zeros(max(bits.size, 1), dtype=np.uint32)
+    p = params.c()
+    rc = _load().or_sample_hits(ctypes.byref(p), _ptr(bases, U8P), _ptr(offsets, U64P),
+                                offsets.size - 1, _ptr(bits, U64P), bits.size, _ptr(out, U32P),
+                                threads or _threads())
+    if rc:
+        raise ValueError("or_sample_hits failed (%d)" % rc)
+    return bits, out[:bits.size]
+
+
+def _threads():
+    return max(1, min(16, os.cpu_count() or 1))

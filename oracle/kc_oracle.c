@@ -1,0 +1,391 @@
+/*
+ * kc_oracle.c - plain CPU reference of the k-mer counting path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU baseline may load this library.  It shares no code, header,
+ * table or constant generator with the GPU library, and neither one includes
+ * or links the other.
+ *
+ * What it computes (paper: Cadenelli, Polo, Carrera, "Accelerating K-mer
+ * Frequency Counting with GPU and Non-Volatile Memory"):
+ *   - the k-mers of a read are its length-k substrings, M-k+1 of them for a
+ *     read of M bases (Sec. II-A), none spanning two reads;
+ *   - a k-mer is a 64-bit code of 2 bits per base (Sec. II-A, amplification
+ *     paragraph); code A=0 C=1 G=2 T=3, first base most significant;
+ *     only the bytes A, C, G, T are valid bases; a window holding any other
+ *     byte is skipped;
+ *   - the counted key is the canonical form x = min(enc(w), enc(rc(w)));
+ *   - the count table keeps k-mers seen at least min_count (>= 2) times
+ *     (Sec. II-B, Count unit: unique k-mers are discarded);
+ *   - Prune's two-level Bloom filter (Sec. III, Prune unit) read as
+ *     saturating per-bit hit counts: B1[b] = [hits(b) >= 1],
+ *     B2[b] = [hits(b) >= 2], where every occurrence of x hits each distinct
+ *     bit of S(x) once; a key passes the screen iff S(x) is inside B2
+ *     (Sec. III, Count unit uses the second filter); keys seen once that pass
+ *     are the false-positive singletons F that Unify removes (Sec. III,
+ *     Unify unit);
+ *   - bit positions: s_i = mix64(seed + (i+1)*0x9E3779B97F4A7C15), i=0..h;
+ *     g = mix64(x ^ s_0); block = top (m_log2 - block_log2) bits of g;
+ *     bit_i = block * 2^block_log2 + top block_log2 bits of mix64(x ^ s_i),
+ *     i = 1..h, where mix64 is the SplitMix64 output function.
+ *
+ * Algorithm: enumerate every valid window, push its canonical key, sort
+ * (libc qsort), run-length encode into (x, counts), then derive B1/B2 from
+ * the run-length list with the saturating update, then the screen, F and the
+ * table.  All integer arithmetic, no floating point.
+ */
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_GAMMA 0x9E3779B97F4A7C15ULL
+
+typedef struct {
+  uint32_t k;          /* 1..31 */
+  uint32_t n_counters; /* 1 or 2 */
+  uint32_t min_count;  /* >= 2 */
+  uint32_t m_log2;     /* Bloom bits per level = 2^m_log2 */
+  uint32_t h;          /* hash functions, 1..8 */
+  uint32_t block_log2; /* 1..m_log2 */
+  uint64_t seed;
+} or_params;
+
+typedef struct {
+  uint64_t n_valid, n_distinct, n_pass, entries, sum_counts, fp_singletons, b1_pop, b2_pop;
+} or_stats;
+
+typedef struct {
+  or_stats st;
+  uint64_t n_entries;
+  uint64_t* keys;   /* [n_entries], ascending */
+  uint32_t* counts; /* [n_entries * n_counters] */
+  uint64_t m_words;
+  uint64_t* b1;     /* [m_words] little-endian bit order: bit b in word b>>6, bit b&63 */
+  uint64_t* b2;
+} or_result;
+
+/* SplitMix64 output function (Steele, Lea, Flood, OOPSLA 2014). */
+uint64_t or_mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+static int or_code(uint8_t b) {
+  switch (b) {
+    case 'A': return 0;
+    case 'C': return 1;
+    case 'G': return 2;
+    case 'T': return 3;
+    default: return -1;
+  }
+}
+
+static int or_params_ok(const or_params* p) {
+  if (p->k < 1 || p->k > 31) return 0;
+  if (p->n_counters < 1 || p->n_counters > 2) return 0;
+  if (p->min_count < 2) return 0;
+  if (p->h < 1 || p->h > 8) return 0;
+  if (p->block_log2 < 1 || p->block_log2 > p->m_log2 || p->m_log2 > 40) return 0;
+  return 1;
+}
+
+/* Window w = s[0..k-1].  enc(w) = sum_j code(w_j) * 4^(k-1-j), evaluated in
+ * Horner form.  rc(w)_j = complement of w_{k-1-j}, complement(c) = 3 - c.
+ * Returns 0 when the window holds a byte other than A, C, G, T. */
+static int or_window(const uint8_t* s, uint32_t k, uint64_t* fwd, uint64_t* rev) {
+  uint64_t f = 0, r = 0;
+  for (uint32_t j = 0; j < k; ++j) {
+    int c = or_code(s[j]);
+    if (c < 0) return 0;
+    f = f * 4 + (uint64_t)c;
+  }
+  for (uint32_t j = 0; j < k; ++j) r = r * 4 + (uint64_t)(3 - or_code(s[k - 1 - j]));
+  *fwd = f;
+  *rev = r;
+  return 1;
+}
+
+/* Canonical key of the window starting at s (assumed valid). */
+static uint64_t or_canonical(const uint8_t* s, uint32_t k, int* ok) {
+  uint64_t f, r;
+  *ok = or_window(s, k, &f, &r);
+  return f < r ? f : r;
+}
+
+/* Distinct Bloom bit positions of key x; returns how many (<= h). */
+static uint32_t or_bloom_positions(const or_params* p, const uint64_t* salt, uint64_t x,
+                                   uint64_t* pos) {
+  uint32_t sb = p->m_log2 - p->block_log2;
+  uint64_t g = or_mix64(x ^ salt[0]);
+  uint64_t block = sb ? (g >> (64 - sb)) : 0;
+  uint32_t n = 0;
+  for (uint32_t i = 1; i <= p->h; ++i) {
+    uint64_t b = (block << p->block_log2) | (or_mix64(x ^ salt[i]) >> (64 - p->block_log2));
+    int dup = 0;
+    for (uint32_t j = 0; j < n; ++j) dup |= (pos[j] == b);
+    if (!dup) pos[n++] = b;
+  }
+  return n;
+}
+
+static void or_salts(const or_params* p, uint64_t* salt) {
+  for (uint32_t i = 0; i <= p->h; ++i) salt[i] = or_mix64(p->seed + (uint64_t)(i + 1) * OR_GAMMA);
+}
+
+static int or_cmp_u64(const void* a, const void* b) {
+  uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+  return (x > y) - (x < y);
+}
+
+static inline int or_bit(const uint64_t* v, uint64_t b) { return (int)((v[b >> 6] >> (b & 63)) & 1); }
+static inline void or_set(uint64_t* v, uint64_t b) { v[b >> 6] |= 1ULL << (b & 63); }
+
+/* Every valid window's canonical key in read order, tagged (key << 1 | tag)
+ * where tag is the read's counter (0 when tags is NULL).  Returns the count,
+ * or UINT64_MAX when out is too small. */
+uint64_t or_enumerate(const or_params* p, const uint8_t* bases, const uint64_t* offsets,
+                      uint64_t n_reads, const uint8_t* tags, uint64_t* out, uint64_t cap) {
+  uint64_t n = 0;
+  for (uint64_t r = 0; r < n_reads; ++r) {
+    uint64_t lo = offsets[r], hi = offsets[r + 1];
+    if (hi - lo < p->k) continue;
+    for (uint64_t s = lo; s + p->k <= hi; ++s) {
+      int ok;
+      uint64_t x = or_canonical(bases + s, p->k, &ok);
+      if (!ok) continue;
+      if (out) {
+        if (n >= cap) return UINT64_MAX;
+        out[n] = (x << 1) | (uint64_t)(tags ? tags[r] : 0);
+      }
+      ++n;
+    }
+  }
+  return n;
+}
+
+void or_free(or_result* r) {
+  if (!r) return;
+  free(r->keys);
+  free(r->counts);
+  free(r->b1);
+  free(r->b2);
+  free(r);
+}
+
+/* Full count.  want_bloom = 0 skips returning B1/B2 (they are still used). */
+or_result* or_count(const or_params* p, const uint8_t* bases, const uint64_t* offsets,
+                    uint64_t n_reads, const uint8_t* tags, int want_bloom) {
+  if (!or_params_ok(p)) return NULL;
+  if (offsets[0] != 0) return NULL;
+  for (uint64_t r = 0; r < n_reads; ++r)
+    if (offsets[r + 1] < offsets[r]) return NULL;
+  if (tags)
+    for (uint64_t r = 0; r < n_reads; ++r)
+      if (tags[r] >= p->n_counters) return NULL;
+
+  or_result* res = (or_result*)calloc(1, sizeof(or_result));
+  if (!res) return NULL;
+  uint32_t nc = p->n_counters;
+
+  /* 1. enumerate W and push tagged canonical keys */
+  uint64_t n = or_enumerate(p, bases, offsets, n_reads, tags, NULL, 0);
+  uint64_t* occ = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
+  if (!occ) { or_free(res); return NULL; }
+  or_enumerate(p, bases, offsets, n_reads, tags, occ, n);
+  res->st.n_valid = n;
+
+  /* 2. sort and run-length encode into (x, c_0 .. c_{nc-1}) */
+  qsort(occ, n, sizeof(uint64_t), or_cmp_u64);
+  uint64_t nd = 0;
+  for (uint64_t i = 0; i < n; ++i)
+    if (i == 0 || (occ[i] >> 1) != (occ[i - 1] >> 1)) ++nd;
+  uint64_t* rk = (uint64_t*)malloc((nd ? nd : 1) * sizeof(uint64_t));
+  uint32_t* rc = (uint32_t*)calloc((nd ? nd : 1) * nc, sizeof(uint32_t));
+  if (!rk || !rc) { free(occ); free(rk); free(rc); or_free(res); return NULL; }
+  uint64_t d = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    if (i == 0 || (occ[i] >> 1) != (occ[i - 1] >> 1)) rk[d++] = occ[i] >> 1;
+    rc[(d - 1) * nc + (occ[i] & 1)] += 1;
+  }
+  free(occ);
+  res->st.n_distinct = nd;
+
+  /* 3. Bloom levels from the run-length list: hits2[b] = min(2, hits2[b] + c)
+   *    kept as two bit arrays, B1 = (hits >= 1), B2 = (hits >= 2). */
+  uint64_t m_words = p->m_log2 >= 6 ? (1ULL << (p->m_log2 - 6)) : 1;
+  uint64_t* b1 = (uint64_t*)calloc(m_words, sizeof(uint64_t));
+  uint64_t* b2 = (uint64_t*)calloc(m_words, sizeof(uint64_t));
+  if (!b1 || !b2) { free(rk); free(rc); free(b1); free(b2); or_free(res); return NULL; }
+  uint64_t salt[9], pos[8];
+  or_salts(p, salt);
+  for (uint64_t i = 0; i < nd; ++i) {
+    uint64_t c = 0;
+    for (uint32_t t = 0; t < nc; ++t) c += rc[i * nc + t];
+    uint32_t np = or_bloom_positions(p, salt, rk[i], pos);
+    for (uint32_t j = 0; j < np; ++j) {
+      if (c >= 2 || or_bit(b1, pos[j])) or_set(b2, pos[j]);
+      or_set(b1, pos[j]);
+    }
+  }
+  for (uint64_t w = 0; w < m_words; ++w) {
+    res->st.b1_pop += (uint64_t)__builtin_popcountll(b1[w]);
+    res->st.b2_pop += (uint64_t)__builtin_popcountll(b2[w]);
+  }
+
+  /* 4. screen every distinct key against B2; F, N_pass; the final table */
+  uint64_t ne = 0;
+  for (uint64_t i = 0; i < nd; ++i) {
+    uint64_t c = 0;
+    for (uint32_t t = 0; t < nc; ++t) c += rc[i * nc + t];
+    uint32_t np = or_bloom_positions(p, salt, rk[i], pos);
+    int pass = 1;
+    for (uint32_t j = 0; j < np; ++j) pass &= or_bit(b2, pos[j]);
+    if (pass) {
+      res->st.n_pass += c;
+      if (c == 1) res->st.fp_singletons += 1;
+    }
+    if (c >= p->min_count) ++ne;
+  }
+  res->keys = (uint64_t*)malloc((ne ? ne : 1) * sizeof(uint64_t));
+  res->counts = (uint32_t*)malloc((ne ? ne : 1) * nc * sizeof(uint32_t));
+  if (!res->keys || !res->counts) { free(rk); free(rc); free(b1); free(b2); or_free(res); return NULL; }
+  uint64_t e = 0;
+  for (uint64_t i = 0; i < nd; ++i) {
+    uint64_t c = 0;
+    for (uint32_t t = 0; t < nc; ++t) c += rc[i * nc + t];
+    if (c < p->min_count) continue;
+    res->keys[e] = rk[i];
+    for (uint32_t t = 0; t < nc; ++t) res->counts[e * nc + t] = rc[i * nc + t];
+    res->st.sum_counts += c;
+    ++e;
+  }
+  res->n_entries = ne;
+  res->st.entries = ne;
+  free(rk);
+  free(rc);
+  res->m_words = m_words;
+  if (want_bloom) {
+    res->b1 = b1;
+    res->b2 = b2;
+  } else {
+    free(b1);
+    free(b2);
+  }
+  return res;
+}
+
+/* Bloom bit positions of one key (distinct, in hash order); returns count. */
+uint32_t or_bloom_bits(const or_params* p, uint64_t x, uint64_t* out) {
+  uint64_t salt[9];
+  or_salts(p, salt);
+  return or_bloom_positions(p, salt, x, out);
+}
+
+/* ------------------------------------------------------ sampled checking */
+/* For workloads too large to sort on the host: exact counts of a sorted list
+ * of sample keys, and exact saturating hits of a sorted list of bit
+ * positions, each found by scanning every window (threads split the reads). */
+
+typedef struct {
+  const or_params* p;
+  const uint8_t* bases;
+  const uint64_t* offsets;
+  const uint8_t* tags;
+  const uint64_t* sample;
+  uint64_t n_sample;
+  uint32_t* counts; /* per thread [n_sample * n_counters] */
+  uint64_t n_valid;
+  uint64_t lo, hi;
+  const uint64_t* salt;
+  int mode; /* 0 = key counts, 1 = bit hits */
+} or_scan_job;
+
+static int64_t or_find(const uint64_t* a, uint64_t n, uint64_t v) {
+  uint64_t lo = 0, hi = n;
+  while (lo < hi) {
+    uint64_t mid = lo + (hi - lo) / 2;
+    if (a[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return (lo < n && a[lo] == v) ? (int64_t)lo : -1;
+}
+
+static void* or_scan_main(void* arg) {
+  or_scan_job* j = (or_scan_job*)arg;
+  const or_params* p = j->p;
+  uint64_t pos[8];
+  for (uint64_t r = j->lo; r < j->hi; ++r) {
+    uint64_t lo = j->offsets[r], hi = j->offsets[r + 1];
+    if (hi - lo < p->k) continue;
+    for (uint64_t s = lo; s + p->k <= hi; ++s) {
+      int ok;
+      uint64_t x = or_canonical(j->bases + s, p->k, &ok);
+      if (!ok) continue;
+      j->n_valid++;
+      if (j->mode == 0) {
+        int64_t at = or_find(j->sample, j->n_sample, x);
+        if (at >= 0) j->counts[at * p->n_counters + (j->tags ? j->tags[r] : 0)] += 1;
+      } else {
+        uint32_t np = or_bloom_positions(p, j->salt, x, pos);
+        for (uint32_t q = 0; q < np; ++q) {
+          int64_t at = or_find(j->sample, j->n_sample, pos[q]);
+          if (at >= 0 && j->counts[at] < 2) j->counts[at] += 1;
+        }
+      }
+    }
+  }
+  return NULL;
+}
+
+static int or_scan(const or_params* p, const uint8_t* bases, const uint64_t* offsets,
+                   uint64_t n_reads, const uint8_t* tags, const uint64_t* sample,
+                   uint64_t n_sample, uint32_t* out, uint64_t* n_valid, int threads, int mode) {
+  if (!or_params_ok(p)) return -1;
+  for (uint64_t i = 1; i < n_sample; ++i)
+    if (sample[i] <= sample[i - 1]) return -2;
+  if (threads < 1) threads = 1;
+  if (threads > 128) threads = 128;
+  uint64_t salt[9];
+  or_salts(p, salt);
+  uint64_t width = mode == 0 ? p->n_counters : 1;
+  or_scan_job jobs[128];
+  pthread_t tid[128];
+  for (int t = 0; t < threads; ++t) {
+    or_scan_job* j = &jobs[t];
+    memset(j, 0, sizeof(*j));
+    j->p = p; j->bases = bases; j->offsets = offsets; j->tags = tags;
+    j->sample = sample; j->n_sample = n_sample; j->salt = salt; j->mode = mode;
+    j->counts = (uint32_t*)calloc((n_sample ? n_sample : 1) * width, sizeof(uint32_t));
+    j->lo = n_reads * (uint64_t)t / (uint64_t)threads;
+    j->hi = n_reads * (uint64_t)(t + 1) / (uint64_t)threads;
+    pthread_create(&tid[t], NULL, or_scan_main, j);
+  }
+  uint64_t nv = 0;
+  memset(out, 0, n_sample * width * sizeof(uint32_t));
+  for (int t = 0; t < threads; ++t) {
+    pthread_join(tid[t], NULL);
+    nv += jobs[t].n_valid;
+    for (uint64_t i = 0; i < n_sample * width; ++i) {
+      out[i] += jobs[t].counts[i];
+      if (mode == 1 && out[i] > 2) out[i] = 2;
+    }
+    free(jobs[t].counts);
+  }
+  if (n_valid) *n_valid = nv;
+  return 0;
+}
+
+/* Exact counts of the sorted, distinct canonical keys in sample. */
+int or_sample_counts(const or_params* p, const uint8_t* bases, const uint64_t* offsets,
+                     uint64_t n_reads, const uint8_t* tags, const uint64_t* sample,
+                     uint64_t n_sample, uint32_t* out, uint64_t* n_valid, int threads) {
+  return or_scan(p, bases, offsets, n_reads, tags, sample, n_sample, out, n_valid, threads, 0);
+}
+
+/* min(2, hits(b)) for the sorted, distinct bit positions in sample. */
+int or_sample_hits(const or_params* p, const uint8_t* bases, const uint64_t* offsets,
+                   uint64_t n_reads, const uint64_t* sample, uint64_t n_sample, uint32_t* out,
+                   int threads) {
+  return or_scan(p, bases, offsets, n_reads, NULL, sample, n_sample, out, NULL, threads, 1);
+}

@@ -1,0 +1,173 @@
+"""Seeded synthetic genomes and reads (input generation only).
+
+The C source ``synth.c`` holds the generator; this module builds it with gcc
+(``build()``), loads it with ctypes and returns numpy arrays.  Nothing here
+encodes, hashes or counts k-mers: the counting method lives elsewhere, and both
+the CPU oracle and the GPU library read what these functions return.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "synth.c")
+_LIB = os.path.join(_HERE, "libsynth.so")
+_lib = None
+
+U64P = ctypes.POINTER(ctypes.c_uint64)
+U8P = ctypes.POINTER(ctypes.c_uint8)
+
+
+def build(force: bool = True) -> str:
+    """Compile synth.c into libsynth.so (gcc, -O2, pthreads)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC,
+                               "-lpthread", "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        lib.synth_genome.argtypes = [ctypes.c_uint64, ctypes.c_uint64, U8P, ctypes.c_int]
+        lib.synth_tumour.argtypes = [ctypes.c_uint64, U8P, ctypes.c_uint64, U8P, ctypes.c_uint64,
+                                     ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
+        lib.synth_read_offsets.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                           ctypes.c_uint32, ctypes.c_uint32, U64P]
+        lib.synth_reads.argtypes = [ctypes.c_uint64, U8P, ctypes.c_uint64, ctypes.c_uint64,
+                                    ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                    ctypes.c_double, ctypes.c_double, U64P, U8P, ctypes.c_int]
+        lib.synth_chunk_sizes.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double,
+                                          ctypes.c_double, U64P]
+        lib.synth_draws.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, U64P]
+        for f in (lib.synth_genome, lib.synth_tumour, lib.synth_read_offsets, lib.synth_reads,
+                  lib.synth_chunk_sizes, lib.synth_draws):
+            f.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _threads(threads):
+    if threads:
+        return int(threads)
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _p8(a):
+    return a.ctypes.data_as(U8P)
+
+
+def _p64(a):
+    return a.ctypes.data_as(U64P)
+
+
+def genome(seed: int, length: int, threads: int = 0) -> np.ndarray:
+    """Uniform i.i.d. ACGT genome of ``length`` bases (uint8 ASCII)."""
+    out = np.empty(int(length), dtype=np.uint8)
+    rc = _load().synth_genome(seed, length, _p8(out), _threads(threads))
+    if rc:
+        raise ValueError("synth_genome failed (%d)" % rc)
+    return out
+
+
+def tumour(seed: int, normal: np.ndarray, n_snv: int, n_inv: int, inv_min: int,
+           inv_max: int) -> np.ndarray:
+    """Normal genome plus distinct point substitutions, then in-place inversions."""
+    normal = np.ascontiguousarray(normal, dtype=np.uint8)
+    out = np.empty_like(normal)
+    rc = _load().synth_tumour(seed, _p8(normal), normal.size, _p8(out), n_snv, n_inv, inv_min,
+                              inv_max)
+    if rc:
+        raise ValueError("synth_tumour failed (%d)" % rc)
+    return out
+
+
+def read_offsets(seed: int, first: int, n: int, lmin: int, lmax: int) -> np.ndarray:
+    off = np.empty(int(n) + 1, dtype=np.uint64)
+    rc = _load().synth_read_offsets(seed, first, n, lmin, lmax, _p64(off))
+    if rc:
+        raise ValueError("synth_read_offsets failed (%d)" % rc)
+    return off
+
+
+def reads(seed: int, genome_seq: np.ndarray, first: int, n: int, lmin: int, lmax: int,
+          err: float, nrate: float = 0.0, threads: int = 0):
+    """Reads ``first .. first+n-1``: returns (bases uint8[total], offsets uint64[n+1])."""
+    genome_seq = np.ascontiguousarray(genome_seq, dtype=np.uint8)
+    off = read_offsets(seed, first, n, lmin, lmax)
+    bases = np.empty(int(off[-1]), dtype=np.uint8)
+    rc = _load().synth_reads(seed, _p8(genome_seq), genome_seq.size, first, n, lmin, lmax,
+                             float(err), float(nrate), _p64(off), _p8(bases), _threads(threads))
+    if rc:
+        raise ValueError("synth_reads failed (%d)" % rc)
+    return bases, off
+
+
+def chunk_sizes(seed: int, n_chunks: int, lo: float, hi: float) -> np.ndarray:
+    out = np.empty(int(n_chunks), dtype=np.uint64)
+    rc = _load().synth_chunk_sizes(seed, n_chunks, float(lo), float(hi), _p64(out))
+    if rc:
+        raise ValueError("synth_chunk_sizes failed (%d)" % rc)
+    return out
+
+
+def draws(seed: int, stream_id: int, n: int) -> np.ndarray:
+    out = np.empty(int(n), dtype=np.uint64)
+    _load().synth_draws(seed, stream_id, n, _p64(out))
+    return out
+
+
+@dataclass(frozen=True)
+class Workload:
+    """A synthetic workload and the counting parameters it is run with."""
+    name: str
+    seed: int
+    genome_len: int
+    n_reads: int
+    lmin: int
+    lmax: int
+    err: float
+    nrate: float
+    k: int
+    bloom_bits_log2: int
+    bloom_hashes: int
+    bloom_block_log2: int
+    partitions_log2: int
+    n_counters: int = 1
+    min_count: int = 2
+    table_budget: int = 0
+
+    def make_genome(self, threads: int = 0) -> np.ndarray:
+        return genome(self.seed, self.genome_len, threads)
+
+    def make_reads(self, genome_seq, first: int = 0, n: int | None = None, threads: int = 0):
+        n = self.n_reads - first if n is None else n
+        return reads(self.seed, genome_seq, first, n, self.lmin, self.lmax, self.err, self.nrate,
+                     threads)
+
+
+# The five workloads.  Partition counts are result-neutral; the value here is
+# the one the GPU path runs with (each partition's table lives in LDS, so the
+# count is set from the expected distinct k-mers per Bloom block).
+WORKLOADS = {
+    "plain_1mbp": Workload("plain_1mbp", 1, 1_000_000, 20_000, 100, 100, 0.01, 0.0,
+                           31, 24, 3, 19, 7),
+    "plain_100mbp": Workload("plain_100mbp", 2, 100_000_000, 10_000_000, 100, 100, 0.005, 0.001,
+                             31, 32, 4, 19, 15),
+    "batched_200mbp": Workload("batched_200mbp", 3, 200_000_000, 0, 100, 250, 0.005, 0.0,
+                               31, 35, 4, 19, 18),
+    "served_300mbp": Workload("served_300mbp", 4, 300_000_000, 30_000_000, 100, 100, 0.005, 0.0,
+                              31, 32, 4, 19, 16, n_counters=2),
+    "spill_3gbp": Workload("spill_3gbp", 5, 3_000_000_000, 200_000_000, 100, 100, 0.01, 0.0,
+                           31, 36, 4, 19, 19, table_budget=64 << 30),
+}

@@ -1,0 +1,335 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+These run without a GPU.  Each test targets a plausible mistake in the oracle:
+bit order or missing complement (worked example), windows spanning reads or an
+off-by-one in the window count (closed forms), wrong Bloom saturation or
+missing de-duplication of bit positions (brute force with tiny blocks), order
+dependence (shuffles), reverse-complement handling (strand flips).
+"""
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+
+M64 = (1 << 64) - 1
+
+
+def pack_reads(reads):
+    offs = np.zeros(len(reads) + 1, dtype=np.uint64)
+    for i, r in enumerate(reads):
+        offs[i + 1] = offs[i] + len(r)
+    data = "".join(reads).encode()
+    return np.frombuffer(data, dtype=np.uint8).copy() if data else np.zeros(0, np.uint8), offs
+
+
+def rand_reads(rng, n, lmin, lmax, nfrac=0.0, alphabet="ACGT"):
+    out = []
+    for _ in range(n):
+        L = rng.randint(lmin, lmax)
+        s = []
+        for _ in range(L):
+            if nfrac and rng.random() < nfrac:
+                s.append(rng.choice("NnRX"))
+            else:
+                s.append(rng.choice(alphabet))
+        out.append("".join(s))
+    return out
+
+
+def table_of(res):
+    return {int(k): tuple(int(c) for c in cs) for k, cs in zip(res.keys, res.counts)}
+
+
+def bits_of(words):
+    out = set()
+    for w, v in enumerate(words):
+        v = int(v)
+        while v:
+            b = v & -v
+            out.add(w * 64 + b.bit_length() - 1)
+            v ^= b
+    return out
+
+
+# ---------------------------------------------------------------- the hash
+
+def test_mix64_published_vectors(golden):
+    rows = golden("splitmix64_seed0.txt")
+    for i, (hexv,) in enumerate(rows):
+        want = int(hexv, 16)
+        z = ((i + 1) * brute.GAMMA) & M64
+        assert brute.mix64(z) == want
+        assert oracle.mix64(z) == want
+
+
+def test_mix64_c_matches_python():
+    rng = random.Random(5)
+    for _ in range(20000):
+        z = rng.getrandbits(64)
+        assert oracle.mix64(z) == brute.mix64(z)
+
+
+def test_mix64_no_collisions_small_range():
+    vals = {brute.mix64(i) for i in range(200000)}
+    assert len(vals) == 200000
+
+
+# -------------------------------------------------------- worked examples
+
+def test_worked_example(golden):
+    rows = golden("worked_example.txt")
+    read = rows[0][1]
+    k = int(rows[1][1])
+    want = [(r[1], r[3], int(r[5], 16)) for r in rows[2:]]
+    assert len(want) == len(read) - k + 1
+    p = oracle.Params(k=k, m_log2=10, h=2, block_log2=4, seed=1)
+    b, o = pack_reads([read])
+    keys = oracle.enumerate_keys(p, b, o)
+    assert [int(v) >> 1 for v in keys] == [c for _, _, c in want]
+    for i, (win, canon, code) in enumerate(want):
+        assert read[i:i + k] == win
+        assert brute.canonical(win) == canon
+        assert brute.encode(canon) == code
+
+
+def test_amplification(golden):
+    rows = dict((r[0], int(r[1])) for r in golden("amplification.txt"))
+    rng = random.Random(3)
+    read = "".join(rng.choice("ACGT") for _ in range(rows["read_len"]))
+    p = oracle.Params(k=rows["k"], m_log2=12, h=2, block_log2=6)
+    b, o = pack_reads([read])
+    res = oracle.count(p, b, o)
+    assert res.stats["n_valid"] == rows["kmers"]
+    assert res.stats["n_valid"] * 8 == rows["bytes"]
+
+
+# ----------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("k", [1, 2, 7, 13, 31])
+def test_window_count_closed_form(k):
+    rng = random.Random(k)
+    reads = rand_reads(rng, 300, 0, 60)
+    p = oracle.Params(k=k, m_log2=14, h=3, block_log2=8, seed=9)
+    b, o = pack_reads(reads)
+    res = oracle.count(p, b, o)
+    assert res.stats["n_valid"] == sum(max(0, len(r) - k + 1) for r in reads)
+
+
+def test_windows_never_span_reads():
+    # Each read alone has no valid window; concatenated they would.
+    reads = ["ACGT", "ACGT", "ACG"]
+    p = oracle.Params(k=5, m_log2=10, h=2, block_log2=5)
+    b, o = pack_reads(reads)
+    assert oracle.count(p, b, o).stats["n_valid"] == 0
+
+
+@pytest.mark.parametrize("base,code", [("A", 0), ("T", 0), ("C", None), ("G", None)])
+def test_homopolymer(base, code):
+    k, L = 21, 80
+    p = oracle.Params(k=k, m_log2=12, h=3, block_log2=6)
+    b, o = pack_reads([base * L])
+    res = oracle.count(p, b, o)
+    # A..A and T..T are each other's reverse complement -> key 0.
+    # C..C (code sum 4^j) is smaller than its reverse complement G..G.
+    want = code if code is not None else sum(4 ** j for j in range(k))
+    assert table_of(res) == {want: (L - k + 1,)}
+    assert res.stats["sum_counts"] == L - k + 1
+
+
+def test_invalid_bytes_break_windows():
+    # lowercase, N and IUPAC codes all invalidate the windows covering them
+    reads = ["ACGTAcGTACGT", "ACGTANGTACGT", "ACGTARGTACGT"]
+    p = oracle.Params(k=4, m_log2=10, h=2, block_log2=5)
+    b, o = pack_reads(reads)
+    res = oracle.count(p, b, o)
+    # each read has 9 windows, 4 of which cover position 5
+    assert res.stats["n_valid"] == 3 * (9 - 4)
+
+
+# ------------------------------------------------------------ brute force
+
+PARAM_SETS = [
+    # k, m_log2, h, block_log2, seed, min_count, n_counters
+    (5, 10, 3, 4, 11, 2, 1),
+    (7, 12, 4, 12, 12, 2, 1),
+    (9, 9, 2, 1, 13, 2, 1),      # 2-bit blocks: duplicated positions in S(x)
+    (3, 8, 8, 2, 14, 2, 1),      # h > block size: heavy duplication
+    (11, 16, 3, 6, 15, 3, 1),
+    (8, 11, 4, 5, 16, 2, 2),     # joint normal/tumour counters
+    (31, 20, 4, 19, 17, 2, 1),
+    (1, 6, 2, 3, 18, 2, 1),
+    (2, 6, 3, 6, 19, 2, 2),
+]
+
+
+@pytest.mark.parametrize("k,m_log2,h,bl,seed,minc,nc", PARAM_SETS)
+def test_oracle_matches_brute_force(k, m_log2, h, bl, seed, minc, nc):
+    rng = random.Random(seed * 1000 + k)
+    # a small alphabet of reads sampled from a short genome gives repeats
+    genome = "".join(rng.choice("ACGT") for _ in range(400))
+    reads = []
+    for _ in range(120):
+        L = rng.randint(0, 40)
+        st = rng.randint(0, len(genome) - L)
+        s = list(genome[st:st + L])
+        for j in range(L):
+            if rng.random() < 0.02:
+                s[j] = rng.choice("ACGTN")
+        r = "".join(s)
+        if rng.random() < 0.5:
+            r = brute.revcomp(r.replace("N", "A")) if "N" not in r else r[::-1]
+        reads.append(r)
+    tags = [rng.randint(0, nc - 1) for _ in reads]
+    p = oracle.Params(k=k, m_log2=m_log2, h=h, block_log2=bl, seed=seed, min_count=minc,
+                      n_counters=nc)
+    b, o = pack_reads(reads)
+    res = oracle.count(p, b, o, tags=np.array(tags, np.uint8) if nc > 1 else None)
+    t, b1, b2, st = brute.count(reads, k, m_log2, h, bl, seed, minc,
+                                tags=tags if nc > 1 else None, n_counters=nc)
+    assert table_of(res) == t
+    assert bits_of(res.b1) == b1
+    assert bits_of(res.b2) == b2
+    assert res.stats == st
+
+
+def test_bloom_bits_match_brute():
+    rng = random.Random(21)
+    for (k, m_log2, h, bl, seed, _, _) in PARAM_SETS:
+        p = oracle.Params(k=k, m_log2=m_log2, h=h, block_log2=bl, seed=seed)
+        for _ in range(200):
+            x = rng.getrandbits(2 * k)
+            assert set(oracle.bloom_bits(p, x)) == brute.bloom_set(x, m_log2, h, bl, seed)
+
+
+# ---------------------------------------------------------------- invariants
+
+def _sim_reads(seed, n, L, err=0.01):
+    rng = random.Random(seed)
+    genome = "".join(rng.choice("ACGT") for _ in range(3000))
+    out = []
+    for _ in range(n):
+        st = rng.randint(0, len(genome) - L)
+        s = list(genome[st:st + L])
+        for j in range(L):
+            if rng.random() < err:
+                s[j] = rng.choice("ACGT")
+        r = "".join(s)
+        out.append(brute.revcomp(r) if rng.random() < 0.5 else r)
+    return out
+
+
+def test_reverse_complement_invariance():
+    reads = _sim_reads(2, 400, 60)
+    p = oracle.Params(k=15, m_log2=14, h=3, block_log2=7, seed=3)
+    r1 = oracle.count(p, *pack_reads(reads))
+    r2 = oracle.count(p, *pack_reads([brute.revcomp(r) for r in reads]))
+    assert table_of(r1) == table_of(r2)
+    assert np.array_equal(r1.b1, r2.b1) and np.array_equal(r1.b2, r2.b2)
+    assert r1.stats == r2.stats
+
+
+def test_order_invariance():
+    reads = _sim_reads(4, 400, 60)
+    p = oracle.Params(k=13, m_log2=13, h=4, block_log2=6, seed=5)
+    r1 = oracle.count(p, *pack_reads(reads))
+    rng = random.Random(8)
+    sh = reads[:]
+    rng.shuffle(sh)
+    r2 = oracle.count(p, *pack_reads(sh))
+    assert table_of(r1) == table_of(r2)
+    assert np.array_equal(r1.b1, r2.b1) and np.array_equal(r1.b2, r2.b2)
+    assert r1.stats == r2.stats
+
+
+def test_sum_invariant_and_no_false_negatives():
+    reads = _sim_reads(6, 500, 80)
+    p = oracle.Params(k=21, m_log2=12, h=3, block_log2=5, seed=7)
+    b, o = pack_reads(reads)
+    res = oracle.count(p, b, o)
+    keys = oracle.enumerate_keys(p, b, o) >> np.uint64(1)
+    uniq, cnt = np.unique(keys, return_counts=True)
+    assert int(cnt.sum()) == res.stats["n_valid"]
+    assert res.stats["n_distinct"] == uniq.size
+    b2 = bits_of(res.b2)
+    for x in res.keys[:500]:
+        assert set(oracle.bloom_bits(p, int(x))) <= b2
+    # every key of the table passes, so N_pass = sum over table + F
+    assert res.stats["n_pass"] == res.stats["sum_counts"] + res.stats["fp_singletons"]
+    assert bits_of(res.b2) <= bits_of(res.b1)
+
+
+def test_saturated_bloom_passes_every_singleton():
+    reads = _sim_reads(7, 200, 50, err=0.05)
+    p = oracle.Params(k=17, m_log2=2, h=3, block_log2=2, seed=1)
+    res = oracle.count(p, *pack_reads(reads))
+    assert res.stats["b2_pop"] == 4
+    singletons = res.stats["n_distinct"] - res.stats["entries"]
+    assert res.stats["fp_singletons"] == singletons
+    assert res.stats["n_pass"] == res.stats["n_valid"]
+
+
+def test_sparse_bloom_has_no_false_positives():
+    reads = _sim_reads(9, 100, 50, err=0.05)
+    p = oracle.Params(k=17, m_log2=36, h=4, block_log2=19, seed=2)
+    res = oracle.count(p, *pack_reads(reads), want_bloom=False)
+    assert res.stats["fp_singletons"] == 0
+    assert res.stats["n_pass"] == res.stats["sum_counts"]
+
+
+def test_min_count_threshold():
+    reads = _sim_reads(10, 300, 40)
+    p2 = oracle.Params(k=11, m_log2=12, h=3, block_log2=6, seed=4, min_count=2)
+    p4 = oracle.Params(k=11, m_log2=12, h=3, block_log2=6, seed=4, min_count=4)
+    r2 = oracle.count(p2, *pack_reads(reads))
+    r4 = oracle.count(p4, *pack_reads(reads))
+    t2 = table_of(r2)
+    assert table_of(r4) == {x: c for x, c in t2.items() if c[0] >= 4}
+    assert r2.stats["fp_singletons"] == r4.stats["fp_singletons"]
+
+
+def test_joint_counts_sum_to_single():
+    reads = _sim_reads(11, 300, 50)
+    rng = random.Random(1)
+    tags = np.array([rng.randint(0, 1) for _ in reads], np.uint8)
+    p1 = oracle.Params(k=15, m_log2=13, h=3, block_log2=7, seed=6)
+    p2 = oracle.Params(k=15, m_log2=13, h=3, block_log2=7, seed=6, n_counters=2)
+    b, o = pack_reads(reads)
+    r1 = oracle.count(p1, b, o)
+    r2 = oracle.count(p2, b, o, tags=tags)
+    assert {x: (sum(c),) for x, c in table_of(r2).items()} == table_of(r1)
+    assert np.array_equal(r1.b1, r2.b1) and np.array_equal(r1.b2, r2.b2)
+    # counter split equals counting each sample alone
+    for t in (0, 1):
+        sub = [r for r, g in zip(reads, tags) if g == t]
+        alone = oracle.count(oracle.Params(k=15, m_log2=13, h=3, block_log2=7, seed=6,
+                                           min_count=2), *pack_reads(sub))
+        for x, c in table_of(r2).items():
+            if c[t] >= 2:
+                assert table_of(alone)[x] == (c[t],)
+
+
+def test_sampled_counts_and_hits_match_full():
+    reads = _sim_reads(12, 500, 70)
+    p = oracle.Params(k=19, m_log2=12, h=3, block_log2=6, seed=8)
+    b, o = pack_reads(reads)
+    res = oracle.count(p, b, o)
+    full = dict(zip(oracle.enumerate_keys(p, b, o) >> np.uint64(1), [None] * 1))
+    keys = np.concatenate([res.keys[::7], np.array([0, 12345], np.uint64)])
+    ks, cs, nv = oracle.sample_counts(p, b, o, keys, threads=3)
+    assert nv == res.stats["n_valid"]
+    t = table_of(res)
+    enum = oracle.enumerate_keys(p, b, o) >> np.uint64(1)
+    for x, c in zip(ks, cs):
+        assert int(c[0]) == int(np.count_nonzero(enum == x))
+        if int(x) in t:
+            assert t[int(x)] == (int(c[0]),)
+    bits = np.arange(0, 1 << 12, 5, dtype=np.uint64)
+    bs, hs = oracle.sample_hits(p, b, o, bits, threads=2)
+    b1, b2 = bits_of(res.b1), bits_of(res.b2)
+    for bit, hcount in zip(bs, hs):
+        assert (int(hcount) >= 1) == (int(bit) in b1)
+        assert (int(hcount) >= 2) == (int(bit) in b2)
+    del full
