@@ -1,0 +1,220 @@
+/*
+ * kc.h - C ABI of the MI355X k-mer frequency counter.
+ *
+ * The library counts canonical k-mers of DNA reads on one GPU, screens out
+ * k-mers seen once with a two-level Bloom filter and keeps exact counts of the
+ * k-mers seen at least min_count times in per-partition hash tables.  It
+ * follows the counting unit of Cadenelli, Polo, Carrera, "Accelerating K-mer
+ * Frequency Counting with GPU and Non-Volatile Memory": Sec. II-A (k-mers,
+ * 2-bit 64-bit codes), Sec. II-B (Count unit: unique k-mers are discarded),
+ * Sec. III (Prune: chained Bloom filters; Count: exact table; Unify: merge of
+ * swapped tables and removal of Bloom false positives), Sec. III-B (GPU
+ * shuffle of k-mers by consumer: histogram, exclusive prefix sum, broker
+ * scatter), Sec. III-D (swap of full tables to a slower memory tier with a hot
+ * spare and per-table metadata).
+ *
+ * Conventions that hold for every entry point:
+ *  - Pointers named *_dev are device pointers on the context's device; the
+ *    caller owns them and keeps them valid until the call has returned (for
+ *    kc_insert_reads: until the stream has passed the call).  Pointers named
+ *    *_host are ordinary host memory owned by the caller.
+ *  - hip_stream is a hipStream_t (NULL = the legacy default stream).  Work is
+ *    ordered on that stream.  Calls marked "synchronises" return only after
+ *    their device work has finished.
+ *  - Every entry point returns a kc_status.  On failure the context's error
+ *    text (kc_last_error) says what went wrong; the context stays usable
+ *    unless the status is KC_ERR_DEVICE.  No exception crosses the ABI.
+ *  - One host thread at a time per context; distinct contexts are
+ *    independent and may be used from different threads.
+ *  - Life cycle: CREATED -> (kc_insert_reads)* -> kc_finalize -> FINALIZED
+ *    (kc_query, kc_export, kc_export_bloom, kc_spill).  kc_reset returns to
+ *    CREATED.  Calls out of this order return KC_ERR_BAD_STATE.
+ */
+#ifndef KC_H
+#define KC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KC_ABI_VERSION 1u
+
+typedef struct kc_ctx kc_ctx;
+
+typedef enum kc_status {
+  KC_OK = 0,
+  KC_ERR_INVALID_ARG = -1,   /* a parameter, pointer or input value is out of range */
+  KC_ERR_OUT_OF_MEMORY = -2, /* a device or pinned host allocation failed */
+  KC_ERR_BAD_STATE = -3,     /* call not allowed in the context's current state */
+  KC_ERR_DEVICE = -4,        /* a HIP runtime call failed; the context must be destroyed */
+  KC_ERR_OVER_BUDGET = -5    /* the table budget cannot hold what the call needs */
+} kc_status;
+
+/*
+ * Counting parameters.  The result-defining fields fix every output bit
+ * (table, Bloom levels, statistics); the result-neutral fields change only
+ * speed and memory, never a result.
+ *
+ * Definitions (the paper's k-mer is a 2-bit-per-base 64-bit code, Sec. II-A;
+ * the screen is Prune's two Bloom levels, Sec. III):
+ *   code A=0 C=1 G=2 T=3; enc(w) = sum_j code(w_j) 4^(k-1-j); only the bytes
+ *   A, C, G, T are bases, any other byte breaks the windows covering it;
+ *   x = min(enc(w), enc(revcomp(w))); mix64 = SplitMix64 output function;
+ *   s_i = mix64(seed + (i+1) * 0x9E3779B97F4A7C15) for i = 0..h;
+ *   g = mix64(x ^ s_0); block(x) = top (bloom_bits_log2 - bloom_block_log2)
+ *   bits of g; S(x) = { block * 2^bloom_block_log2 + top bloom_block_log2
+ *   bits of mix64(x ^ s_i) : i = 1..h };  hits(b) = number of occurrences of
+ *   keys with b in S(x);  B1[b] = hits(b) >= 1, B2[b] = hits(b) >= 2;
+ *   a key passes the screen iff S(x) is a subset of B2.
+ */
+typedef struct kc_config {
+  /* result-defining */
+  uint32_t k;                /* k-mer length, 1..31 */
+  uint32_t n_counters;       /* 1 = one count per k-mer; 2 = normal/tumour counts */
+  uint32_t min_count;        /* keep k-mers whose total count is >= this; >= 2 */
+  uint32_t bloom_bits_log2;  /* each Bloom level holds 2^this bits; bloom_block_log2..40 */
+  uint32_t bloom_hashes;     /* h, 1..8 */
+  uint32_t bloom_block_log2; /* Bloom block size in bits (log2), 1..19 */
+  uint64_t seed;             /* derives s_0 .. s_h */
+  /* result-neutral */
+  uint32_t partitions_log2;  /* hash partitions = top bits of g; raised to
+                                bloom_bits_log2 - bloom_block_log2 when lower; <= 24 */
+  uint32_t table_log2;       /* slots per partition table; 0 = largest that fits LDS */
+  uint32_t scatter_bits;     /* first-level shuffle fan-out bits; 0 = automatic */
+  uint32_t flags;            /* must be 0 */
+  uint64_t hbm_table_budget_bytes; /* device bytes the partition tables may use; 0 = unlimited */
+} kc_config;
+
+/* Per-stage timers (kernel_ms indexes): sums of HIP-event durations. */
+enum {
+  KC_T_PACK = 0,     /* ASCII -> 2-bit stream, invalid and read-start bits */
+  KC_T_HIST = 1,     /* window extraction + first-level histogram */
+  KC_T_SCAN = 2,     /* exclusive prefix sum of the histogram */
+  KC_T_SCATTER1 = 3, /* first-level partition scatter */
+  KC_T_SCATTER2 = 4, /* second-level (in place) partition scatter */
+  KC_T_COUNT = 5,    /* per Bloom block: B1/B2 build, screen, exact count */
+  KC_T_UNIFY = 6,    /* overflow table pass, statistics reduction */
+  KC_T_QUERY = 7,
+  KC_T_SPILL = 8,    /* device -> pinned host copies of spilled partitions */
+  KC_T_COUNT_OF = 16
+};
+
+typedef struct kc_stats {
+  uint64_t n_valid;            /* valid windows (k-mer occurrences) inserted */
+  uint64_t n_pass;             /* occurrences whose key passes the Bloom screen */
+  uint64_t entries;            /* k-mers with total count >= min_count */
+  uint64_t sum_counts;         /* sum of their total counts */
+  uint64_t fp_singletons;      /* k-mers seen once that passed the screen (removed) */
+  uint64_t b1_popcount;        /* set bits of Bloom level 1 */
+  uint64_t b2_popcount;        /* set bits of Bloom level 2 */
+  uint64_t spilled_partitions; /* partitions whose table lives in pinned host memory */
+  uint64_t spilled_bytes;      /* bytes of those tables (keys + counts, no padding) */
+  uint64_t overflow_keys;      /* distinct keys counted in the device overflow table */
+  uint64_t passed_distinct;    /* distinct keys that passed the screen */
+  uint32_t partitions_log2;    /* effective partition count (log2) */
+  uint32_t table_log2;         /* effective slots per partition table (log2) */
+  uint32_t n_segments;         /* kc_insert_reads calls since the last reset */
+  uint32_t retries;            /* finalize re-runs after an overflow-table fill */
+  double kernel_ms[KC_T_COUNT_OF]; /* per-stage device time, milliseconds */
+  uint64_t kernel_launches[KC_T_COUNT_OF];
+} kc_stats;
+
+/* ABI version of the loaded library (KC_ABI_VERSION). */
+uint32_t kc_abi_version(void);
+
+/* Human-readable name of a status code (static string). */
+const char* kc_status_str(kc_status s);
+
+/* Creates a context on HIP device `device` and allocates its Bloom levels
+ * (2 * 2^bloom_bits_log2 bits).  Validates cfg.  *out receives the context,
+ * or NULL on failure (then kc_last_error(NULL) holds the reason). */
+kc_status kc_create(const kc_config* cfg, int device, kc_ctx** out);
+
+/*
+ * Adds reads (pass 1: k-mer extraction, canonical form and the hash-partition
+ * shuffle of Sec. III-B).  Reads are bases_dev[offsets_dev[i] ..
+ * offsets_dev[i+1]) for i < n_reads, ASCII, back to back; offsets_dev has
+ * n_reads + 1 entries with offsets_dev[0] = 0 and offsets_dev[n_reads] =
+ * total_bases, non-decreasing (empty reads allowed).  counter (0 or 1, <
+ * n_counters) is the sample the reads belong to (0 normal, 1 tumour).
+ * Windows never span two reads.  Synchronises once on hip_stream (to size the
+ * key buffer); the shuffle itself stays queued on the stream.  Offsets that
+ * break the rules above are detected on the device: the call then returns
+ * KC_ERR_INVALID_ARG and inserts nothing.
+ */
+kc_status kc_insert_reads(kc_ctx* ctx, const uint8_t* bases_dev, const uint64_t* offsets_dev,
+                          uint64_t n_reads, uint64_t total_bases, uint32_t counter,
+                          void* hip_stream);
+
+/*
+ * Pass 2 and Unify (Sec. III): builds the Bloom levels, screens every
+ * occurrence against level 2, counts the passing keys exactly per partition,
+ * drops keys below min_count (false-positive singletons are counted in
+ * fp_singletons) and leaves one open-addressing table per partition in HBM
+ * (or in pinned host memory for partitions spilled under the table budget).
+ * Synchronises.  out_host (may be NULL) receives the statistics.
+ */
+kc_status kc_finalize(kc_ctx* ctx, void* hip_stream, kc_stats* out_host);
+
+/*
+ * Looks up n k-mers (2-bit codes < 4^k, either orientation): counts_dev[i *
+ * n_counters + c] receives counter c of canonical(kmers_dev[i]) when its total
+ * count is >= min_count, else 0.  Synchronises.  A code >= 4^k makes the call
+ * return KC_ERR_INVALID_ARG (its output row is 0).
+ */
+kc_status kc_query(kc_ctx* ctx, const uint64_t* kmers_dev, uint64_t n, uint32_t* counts_dev,
+                   void* hip_stream);
+
+/*
+ * Moves a partition's finished table from HBM to pinned host memory (the
+ * stand-in for the paper's swap of full tables to NVM, Sec. III-D) and records
+ * it in the spill directory (partition, entries, host offset, stale flag).
+ * partition = -1 spills resident partitions, highest index first, until the
+ * resident tables fit hbm_table_budget_bytes.  *bytes_out (may be NULL)
+ * receives the bytes moved.  Queries keep working on spilled partitions.
+ */
+kc_status kc_spill(kc_ctx* ctx, int64_t partition, uint64_t* bytes_out);
+
+/*
+ * Copies the final table to host memory: keys_host[cap], counts_host[cap *
+ * n_counters].  With keys_host == NULL only *n_out (number of entries) is
+ * set.  Entries come partition by partition (unsorted within a partition).
+ * Returns KC_ERR_INVALID_ARG when cap is smaller than the number of entries.
+ */
+kc_status kc_export(kc_ctx* ctx, uint64_t* keys_host, uint32_t* counts_host, uint64_t cap,
+                    uint64_t* n_out);
+
+/* Copies the two Bloom levels (words = 2^bloom_bits_log2 / 64, at least 1,
+ * little-endian: bit b in word b >> 6 at position b & 63).  Either pointer
+ * may be NULL. */
+kc_status kc_export_bloom(kc_ctx* ctx, uint64_t* b1_host, uint64_t* b2_host, uint64_t words);
+
+/*
+ * Debug view of pass 1: every stored key occurrence (x | counter << 62) and the
+ * partition it was shuffled to, segment by segment in storage order.  With
+ * keys_host == NULL only *n_out is set.  Valid in any state after inserts.
+ */
+kc_status kc_debug_keys(kc_ctx* ctx, uint64_t* keys_host, uint32_t* partition_host,
+                        uint64_t cap, uint64_t* n_out);
+
+/* Statistics of the last finalize (plus inserts and timers since reset). */
+kc_status kc_get_stats(const kc_ctx* ctx, kc_stats* out_host);
+
+/* Drops inserted reads, tables and spilled partitions; keeps allocations for
+ * reuse.  Back to CREATED.  Synchronises the device. */
+kc_status kc_reset(kc_ctx* ctx);
+
+/* Frees everything the context owns.  NULL is ignored. */
+void kc_destroy(kc_ctx* ctx);
+
+/* Error text of the context's last failing call ("" if none); with NULL, the
+ * last kc_create failure of this thread. */
+const char* kc_last_error(const kc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KC_H */

@@ -1,0 +1,290 @@
+"""Python binding of libkc.so, the MI355X k-mer counter (C ABI in include/kc.h).
+
+Argument marshalling only: every step of the counting path runs in the HIP
+kernels of the library.  PyTorch supplies device memory and streams.  Importing
+this module does not need a GPU; creating a counter does, and a missing or
+unloadable library raises instead of falling back to anything.
+
+The functions mirror the C entry points one to one (``kc_create``,
+``kc_insert_reads``, ``kc_finalize``, ``kc_query``, ``kc_spill``,
+``kc_export``, ...).  ``KmerCounter`` wraps them for torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkc.so")
+_lib = None
+
+KC_OK = 0
+KC_ERR_INVALID_ARG = -1
+KC_ERR_OUT_OF_MEMORY = -2
+KC_ERR_BAD_STATE = -3
+KC_ERR_DEVICE = -4
+KC_ERR_OVER_BUDGET = -5
+
+STAGES = ["pack", "hist", "scan", "scatter1", "scatter2", "count", "unify", "query", "spill"]
+
+EXPORTED = ["kc_abi_version", "kc_status_str", "kc_create", "kc_insert_reads", "kc_finalize",
+            "kc_query", "kc_spill", "kc_export", "kc_export_bloom", "kc_debug_keys",
+            "kc_get_stats", "kc_reset", "kc_destroy", "kc_last_error"]
+
+
+class KcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_status_name(status), msg))
+        self.status = status
+
+
+class KcConfig(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("n_counters", ctypes.c_uint32),
+                ("min_count", ctypes.c_uint32), ("bloom_bits_log2", ctypes.c_uint32),
+                ("bloom_hashes", ctypes.c_uint32), ("bloom_block_log2", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64), ("partitions_log2", ctypes.c_uint32),
+                ("table_log2", ctypes.c_uint32), ("scatter_bits", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("hbm_table_budget_bytes", ctypes.c_uint64)]
+
+
+class KcStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "n_valid", "n_pass", "entries", "sum_counts", "fp_singletons", "b1_popcount",
+        "b2_popcount", "spilled_partitions", "spilled_bytes", "overflow_keys",
+        "passed_distinct")] + [
+        ("partitions_log2", ctypes.c_uint32), ("table_log2", ctypes.c_uint32),
+        ("n_segments", ctypes.c_uint32), ("retries", ctypes.c_uint32),
+        ("kernel_ms", ctypes.c_double * 16), ("kernel_launches", ctypes.c_uint64 * 16)]
+
+    def as_dict(self) -> dict:
+        d = {n: getattr(self, n) for n, _ in self._fields_[:15]}
+        d["kernel_ms"] = {STAGES[i]: self.kernel_ms[i] for i in range(len(STAGES))}
+        d["kernel_launches"] = {STAGES[i]: int(self.kernel_launches[i]) for i in range(len(STAGES))}
+        return d
+
+
+def _status_name(s: int) -> str:
+    return {0: "KC_OK", -1: "KC_ERR_INVALID_ARG", -2: "KC_ERR_OUT_OF_MEMORY",
+            -3: "KC_ERR_BAD_STATE", -4: "KC_ERR_DEVICE", -5: "KC_ERR_OVER_BUDGET"}.get(s, str(s))
+
+
+def load():
+    """Loads libkc.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libkc.so is not built (run __graft_entry__.build() or "
+                          "python paper_1712_03254_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    V, P, U32, U64, I64 = ctypes.c_void_p, ctypes.POINTER, ctypes.c_uint32, ctypes.c_uint64, \
+        ctypes.c_int64
+    st = ctypes.c_int
+    sig = {
+        "kc_abi_version": ([], U32),
+        "kc_status_str": ([st], ctypes.c_char_p),
+        "kc_create": ([P(KcConfig), ctypes.c_int, P(V)], st),
+        "kc_insert_reads": ([V, V, V, U64, U64, U32, V], st),
+        "kc_finalize": ([V, V, P(KcStats)], st),
+        "kc_query": ([V, V, U64, V, V], st),
+        "kc_spill": ([V, I64, P(U64)], st),
+        "kc_export": ([V, V, V, U64, P(U64)], st),
+        "kc_export_bloom": ([V, V, V, U64], st),
+        "kc_debug_keys": ([V, V, V, U64, P(U64)], st),
+        "kc_get_stats": ([V, P(KcStats)], st),
+        "kc_reset": ([V], st),
+        "kc_destroy": ([V], None),
+        "kc_last_error": ([V], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(ctx, status: int):
+    if status != KC_OK:
+        msg = load().kc_last_error(ctx)
+        raise KcError(status, msg.decode() if msg else "")
+
+
+# ---- one-to-one wrappers of the C entry points ------------------------------
+
+def kc_abi_version() -> int:
+    return int(load().kc_abi_version())
+
+
+def kc_create(cfg: KcConfig, device: int = 0):
+    h = ctypes.c_void_p()
+    _check(None, load().kc_create(ctypes.byref(cfg), device, ctypes.byref(h)))
+    return h
+
+
+def kc_insert_reads(ctx, bases_ptr: int, offsets_ptr: int, n_reads: int, total_bases: int,
+                    counter: int, stream_ptr: int):
+    _check(ctx, load().kc_insert_reads(ctx, bases_ptr, offsets_ptr, n_reads, total_bases,
+                                       counter, stream_ptr))
+
+
+def kc_finalize(ctx, stream_ptr: int) -> KcStats:
+    s = KcStats()
+    _check(ctx, load().kc_finalize(ctx, stream_ptr, ctypes.byref(s)))
+    return s
+
+
+def kc_query(ctx, kmers_ptr: int, n: int, counts_ptr: int, stream_ptr: int):
+    _check(ctx, load().kc_query(ctx, kmers_ptr, n, counts_ptr, stream_ptr))
+
+
+def kc_spill(ctx, partition: int = -1) -> int:
+    b = ctypes.c_uint64(0)
+    _check(ctx, load().kc_spill(ctx, partition, ctypes.byref(b)))
+    return int(b.value)
+
+
+def kc_export(ctx, n_counters: int):
+    n = ctypes.c_uint64(0)
+    lib = load()
+    _check(ctx, lib.kc_export(ctx, None, None, 0, ctypes.byref(n)))
+    e = int(n.value)
+    keys = np.empty(max(e, 1), dtype=np.uint64)
+    counts = np.empty(max(e * n_counters, 1), dtype=np.uint32)
+    _check(ctx, lib.kc_export(ctx, keys.ctypes.data, counts.ctypes.data, e, ctypes.byref(n)))
+    return keys[:e], counts[:e * n_counters].reshape(e, n_counters)
+
+
+def kc_export_bloom(ctx, words: int):
+    b1 = np.empty(words, dtype=np.uint64)
+    b2 = np.empty(words, dtype=np.uint64)
+    _check(ctx, load().kc_export_bloom(ctx, b1.ctypes.data, b2.ctypes.data, words))
+    return b1, b2
+
+
+def kc_debug_keys(ctx):
+    n = ctypes.c_uint64(0)
+    lib = load()
+    _check(ctx, lib.kc_debug_keys(ctx, None, None, 0, ctypes.byref(n)))
+    e = int(n.value)
+    keys = np.empty(max(e, 1), dtype=np.uint64)
+    part = np.empty(max(e, 1), dtype=np.uint32)
+    _check(ctx, lib.kc_debug_keys(ctx, keys.ctypes.data, part.ctypes.data, e, ctypes.byref(n)))
+    return keys[:e], part[:e]
+
+
+def kc_get_stats(ctx) -> KcStats:
+    s = KcStats()
+    _check(ctx, load().kc_get_stats(ctx, ctypes.byref(s)))
+    return s
+
+
+def kc_reset(ctx):
+    _check(ctx, load().kc_reset(ctx))
+
+
+def kc_destroy(ctx):
+    if ctx:
+        load().kc_destroy(ctx)
+
+
+def kc_last_error(ctx=None) -> str:
+    m = load().kc_last_error(ctx)
+    return m.decode() if m else ""
+
+
+# ---- convenience wrapper ------------------------------------------------------
+
+@dataclass
+class Config:
+    k: int = 31
+    n_counters: int = 1
+    min_count: int = 2
+    bloom_bits_log2: int = 24
+    bloom_hashes: int = 3
+    bloom_block_log2: int = 19
+    seed: int = 0
+    partitions_log2: int = 0
+    table_log2: int = 0
+    scatter_bits: int = 0
+    hbm_table_budget_bytes: int = 0
+
+    def c(self) -> KcConfig:
+        return KcConfig(self.k, self.n_counters, self.min_count, self.bloom_bits_log2,
+                        self.bloom_hashes, min(self.bloom_block_log2, self.bloom_bits_log2),
+                        self.seed & ((1 << 64) - 1), self.partitions_log2, self.table_log2,
+                        self.scatter_bits, 0, self.hbm_table_budget_bytes)
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class KmerCounter:
+    """One counting context on one GPU; inputs and outputs are torch tensors."""
+
+    def __init__(self, cfg: Config, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("KmerCounter needs a HIP device")
+        self.cfg = cfg
+        self.device = device
+        self.ctx = kc_create(cfg.c(), device)
+
+    def close(self):
+        if self.ctx:
+            kc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def insert_reads(self, bases, offsets, counter: int = 0, stream=None):
+        """bases: uint8 device tensor; offsets: int64/uint64 device tensor of n_reads+1."""
+        n_reads = offsets.numel() - 1
+        kc_insert_reads(self.ctx, bases.data_ptr() if bases.numel() else 0, offsets.data_ptr(),
+                        n_reads, bases.numel(), counter, _stream_ptr(stream))
+
+    def finalize(self, stream=None) -> dict:
+        return kc_finalize(self.ctx, _stream_ptr(stream)).as_dict()
+
+    def query(self, kmers, stream=None):
+        import torch
+        out = torch.empty((kmers.numel(), self.cfg.n_counters), dtype=torch.int32,
+                          device=kmers.device)
+        kc_query(self.ctx, kmers.data_ptr(), kmers.numel(), out.data_ptr(), _stream_ptr(stream))
+        return out
+
+    def spill(self, partition: int = -1) -> int:
+        return kc_spill(self.ctx, partition)
+
+    def export(self):
+        return kc_export(self.ctx, self.cfg.n_counters)
+
+    def export_bloom(self):
+        words = max(1, (1 << self.cfg.bloom_bits_log2) // 64)
+        return kc_export_bloom(self.ctx, words)
+
+    def debug_keys(self):
+        return kc_debug_keys(self.ctx)
+
+    def stats(self) -> dict:
+        return kc_get_stats(self.ctx).as_dict()
+
+    def reset(self):
+        kc_reset(self.ctx)

@@ -1,0 +1,115 @@
+// kc_internal.h - shared declarations between the kernels and the host runtime
+// of the k-mer counter (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kc {
+
+constexpr uint64_t kEmpty = ~0ull;              // empty table slot (no key reaches it: x < 2^62)
+constexpr uint64_t kKeyMask = (1ull << 62) - 1; // key bits; bit 62 carries the counter tag
+constexpr uint64_t kTableMul = 0xD6E8FEB86659FD93ull; // odd multiplier of the table slot hash
+constexpr int kThreads = 1024;                  // block size of the tile kernels
+constexpr int kWaves = kThreads / 64;
+constexpr int kTileWords = 512;                 // first-level tile: 512 packed words
+constexpr int kTilePos = kTileWords * 32;       // = 16384 window positions
+constexpr int kT2 = 16384;                      // second-level tile: keys per workgroup
+constexpr int kMaxA1 = 10;                      // first-level fan-out limit (bits)
+constexpr int kMaxA2 = 11;                      // second-level fan-out limit (bits)
+constexpr int kLdsMax = 163840;                 // gfx950 LDS per workgroup
+constexpr int kNst = 8;                         // statistics slots
+
+enum Stat { ST_NPASS = 0, ST_ENTRIES, ST_SUM, ST_FP, ST_B1POP, ST_B2POP, ST_PASSED, ST_OVF };
+enum Err : uint32_t { ERR_OFFSETS = 1, ERR_OVF_FULL = 2, ERR_OVF_LOAD = 4, ERR_QUERY_RANGE = 8 };
+
+// One kc_insert_reads call: its keys grouped by partition.  Partition
+// u = c * 2^a2 + sub: first-level bucket c holds keys[bucket_off[c] ..
+// bucket_off[c+1]); with a2 > 0 that range is cut into tiles of kT2 keys
+// (tile_first[c] .. tile_first[c+1]), and inside tile t the keys of sub-bucket
+// sub sit at [meta2[t*(2^a2+1)+sub], meta2[t*(2^a2+1)+sub+1]) of the tile.
+struct SegDesc {
+  const uint64_t* keys;
+  const uint64_t* bucket_off;
+  const uint32_t* tile_first;
+  const uint32_t* meta2;
+  uint32_t a1, a2;
+};
+
+struct HashCfg {
+  uint64_t salt[9];   // s_0 .. s_h
+  uint32_t k, h, bl, s_log2, p_log2, nc, min_count, cap_log2;
+};
+
+struct CountArgs {
+  HashCfg hc;
+  const SegDesc* segs;
+  uint32_t nsegs;
+  uint32_t upb_log2;     // partitions per Bloom block (log2)
+  uint32_t nbw;          // u32 words per Bloom block and level
+  uint32_t l2w;          // LDS words reserved for level 2 (even)
+  uint32_t probe_limit;
+  uint32_t ovf_log2;
+  uint32_t ovf_limit;
+  uint32_t* b1;
+  uint32_t* b2;
+  uint64_t* tkeys;
+  uint32_t* tcounts;
+  uint64_t* okeys;
+  uint32_t* ocounts;
+  uint32_t* ovf_used;
+  uint32_t* err;
+  uint64_t* pstats;      // [blocks * kNst]
+};
+
+struct QueryArgs {
+  HashCfg hc;
+  const uint64_t* tkeys;
+  const uint32_t* tcounts;
+  const uint32_t* resident; // partition -> 1 if its table is in HBM
+  const uint64_t* okeys;
+  const uint32_t* ocounts;
+  const uint32_t* ovf_used;
+  uint32_t ovf_log2;
+  uint32_t* err;
+  uint32_t* host_rows;     // indices of queries on spilled partitions
+  uint32_t* host_count;
+};
+
+// ---- launchers (kc_kernels.hip) ----
+hipError_t launch_pack(const uint8_t* bases, uint64_t total, uint64_t nwords, uint64_t* packed,
+                       uint64_t* flags, hipStream_t s);
+hipError_t launch_rstart(const uint64_t* offsets, uint64_t n_reads, uint64_t total,
+                         uint64_t* flags, uint32_t* err, hipStream_t s);
+hipError_t launch_hist1(const uint64_t* packed, const uint64_t* flags, uint64_t nwords,
+                        uint32_t k, uint64_t s0, uint32_t a1, uint32_t* hist, uint64_t ntiles,
+                        hipStream_t s);
+hipError_t launch_scan(const uint32_t* in, uint64_t n, uint64_t* out, uint64_t* parts,
+                       hipStream_t s);
+size_t scan_parts(uint64_t n);
+hipError_t launch_bucket_off(const uint64_t* off1, uint64_t ntiles, uint32_t nb1,
+                             uint64_t* bucket_off, hipStream_t s);
+hipError_t launch_scatter1(const uint64_t* packed, const uint64_t* flags, uint64_t nwords,
+                           uint32_t k, uint64_t s0, uint32_t a1, const uint64_t* off1,
+                           uint64_t ntiles, uint64_t tag, uint64_t* out, hipStream_t s);
+hipError_t launch_tiles2(const uint64_t* bucket_off, uint32_t nb1, uint32_t* tile_first,
+                         hipStream_t s);
+hipError_t launch_scatter2(uint64_t* keys, const uint64_t* bucket_off, const uint32_t* tile_first,
+                           uint32_t a1, uint32_t a2, uint64_t s0, uint32_t* meta2,
+                           uint64_t grid, hipStream_t s);
+hipError_t launch_count(const CountArgs& a, uint32_t blocks, size_t lds, hipStream_t s);
+hipError_t launch_ovf_emit(const CountArgs& a, uint64_t* pstats_ovf, uint32_t blocks,
+                           hipStream_t s);
+hipError_t launch_reduce(const uint64_t* rows, uint64_t nrows, uint64_t* out, hipStream_t s);
+hipError_t launch_query(const QueryArgs& a, const uint64_t* kmers, uint64_t n, uint32_t* out,
+                        hipStream_t s);
+hipError_t launch_export(const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,
+                         const uint32_t* resident, uint32_t cap_log2, uint32_t nc,
+                         uint64_t* out_keys, uint32_t* out_counts, uint64_t out_cap,
+                         uint64_t* cursor, hipStream_t s);
+hipError_t launch_debug_part(const SegDesc& sd, uint64_t n, uint32_t* part, hipStream_t s);
+hipError_t launch_gather_part(const uint64_t* tkeys, const uint32_t* tcounts, uint64_t base,
+                              uint64_t cap, uint32_t nc, uint64_t* out_keys, uint32_t* out_counts,
+                              uint64_t* cursor, hipStream_t s);
+
+}  // namespace kc

@@ -1,0 +1,939 @@
+// kc_runtime.hip - host runtime of the k-mer counter: the C ABI of kc.h.
+//
+// One context = one counting job on one GPU.  The runtime owns the Bloom
+// levels, the per-call key segments (pass-1 output), the per-partition tables
+// and the spill directory, and enqueues the kernels of kc_kernels.hip on the
+// caller's stream.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/kc.h"
+#include "kc_internal.h"
+
+using namespace kc;
+
+namespace {
+
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+uint64_t host_mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint32_t ceil_log2(uint64_t v) {
+  uint32_t r = 0;
+  while ((1ull << r) < v) ++r;
+  return r;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t ensure(size_t want) {
+    if (want == 0) want = 8;
+    if (bytes >= want) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      return e;
+    }
+    bytes = want;
+    return hipSuccess;
+  }
+};
+
+struct Segment {
+  DevBuf keys, bucket_off, tile_first, meta2;
+  uint64_t n = 0;
+  uint32_t counter = 0;
+  void release() {
+    keys.release();
+    bucket_off.release();
+    tile_first.release();
+    meta2.release();
+  }
+};
+
+// One spilled partition: its entries (keys ascending by slot, counts) in
+// pinned host memory.  Mirrors the paper's swap metadata record (partition,
+// stale flag, byte offset, item count; Sec. III-D).
+struct SpillRec {
+  uint32_t partition = 0;
+  bool stale = false;
+  uint64_t host_offset = 0;  // entry index into the spill pool
+  uint64_t entries = 0;
+};
+
+enum State { CREATED = 0, INSERTING = 1, FINALIZED = 2 };
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct kc_ctx {
+  kc_config cfg{};
+  int device = 0;
+  State state = CREATED;
+  std::string err;
+
+  // derived layout
+  HashCfg hc{};
+  uint32_t s_log2 = 0, p_log2 = 0, cap_log2 = 0, a1 = 0, a2 = 0, upb_log2 = 0;
+  uint32_t nbw = 1, l2w = 2, slot_bytes = 12;
+  size_t count_lds = 0;
+  uint64_t bloom_words64 = 1;
+
+  DevBuf b1, b2;
+  DevBuf dstat;   // kNst u64 stats, then ovf stats scratch
+  DevBuf derr;    // u32 error flags
+  DevBuf packed, flags, hist1, off1, parts;
+  DevBuf segdesc;
+  DevBuf tkeys, tcounts, resident, pstats, pstats_ovf;
+  DevBuf okeys, ocounts, ovf_used;
+  DevBuf qrows, qcount;
+  uint32_t ovf_log2 = 12;
+  std::vector<Segment> segs, spare_segs;
+  hipEvent_t insert_done = nullptr;
+  bool insert_done_valid = false;
+
+  uint64_t* pinned = nullptr;  // small pinned staging area (4 KiB)
+
+  // spill directory + pool (pinned host)
+  std::vector<SpillRec> spill_dir;
+  std::vector<int32_t> spill_of;  // partition -> index into spill_dir or -1
+  uint64_t* spill_keys = nullptr;
+  uint32_t* spill_counts = nullptr;
+  uint64_t spill_cap = 0, spill_used = 0;
+
+  kc_stats st{};
+
+  // timers: pending (start, stop, stage) triples
+  struct Timer {
+    hipEvent_t a, b;
+    int id;
+  };
+  std::vector<Timer> pending;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+kc_status fail(kc_ctx* c, kc_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+kc_status hip_fail(kc_ctx* c, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();
+    return fail(c, KC_ERR_OUT_OF_MEMORY, m);
+  }
+  return fail(c, KC_ERR_DEVICE, m);
+}
+
+#define KC_HIP(ctx, expr, what)                       \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+  } while (0)
+
+hipEvent_t take_event(kc_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct StageTimer {
+  kc_ctx* c;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  int id;
+  StageTimer(kc_ctx* c_, hipStream_t s_, int id_) : c(c_), s(s_), id(id_) {
+    a = take_event(c);
+    if (a) (void)hipEventRecord(a, s);
+  }
+  void stop() {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    c->pending.push_back({a, b, id});
+    a = nullptr;
+  }
+};
+
+// Folds finished timer pairs into st.kernel_ms (call after a synchronisation).
+void resolve_timers(kc_ctx* c) {
+  std::vector<kc_ctx::Timer> keep;
+  for (auto& t : c->pending) {
+    if (hipEventQuery(t.b) != hipSuccess) {
+      (void)hipGetLastError();
+      keep.push_back(t);
+      continue;
+    }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      c->st.kernel_ms[t.id] += ms;
+      c->st.kernel_launches[t.id] += 1;
+    } else {
+      (void)hipGetLastError();
+    }
+    c->event_pool.push_back(t.a);
+    c->event_pool.push_back(t.b);
+  }
+  c->pending.swap(keep);
+}
+
+kc_status validate(const kc_config* cfg, std::string* why) {
+  char buf[256];
+  auto bad = [&](const char* m) {
+    *why = m;
+    return KC_ERR_INVALID_ARG;
+  };
+  if (!cfg) return bad("config is NULL");
+  if (cfg->k < 1 || cfg->k > 31) return bad("k must be in 1..31");
+  if (cfg->n_counters < 1 || cfg->n_counters > 2) return bad("n_counters must be 1 or 2");
+  if (cfg->min_count < 2) return bad("min_count must be >= 2");
+  if (cfg->bloom_hashes < 1 || cfg->bloom_hashes > 8) return bad("bloom_hashes must be in 1..8");
+  if (cfg->bloom_block_log2 < 1 || cfg->bloom_block_log2 > 19)
+    return bad("bloom_block_log2 must be in 1..19");
+  if (cfg->bloom_bits_log2 < cfg->bloom_block_log2 || cfg->bloom_bits_log2 > 40)
+    return bad("bloom_bits_log2 must be in bloom_block_log2..40");
+  if (cfg->bloom_bits_log2 - cfg->bloom_block_log2 > 24)
+    return bad("more than 2^24 Bloom blocks (raise bloom_block_log2)");
+  if (cfg->partitions_log2 > 24) return bad("partitions_log2 must be <= 24");
+  if (cfg->flags != 0) return bad("flags must be 0");
+  if (cfg->scatter_bits > kMaxA1) {
+    snprintf(buf, sizeof buf, "scatter_bits must be <= %d", kMaxA1);
+    *why = buf;
+    return KC_ERR_INVALID_ARG;
+  }
+  return KC_OK;
+}
+
+kc_status derive(kc_ctx* c) {
+  const kc_config& f = c->cfg;
+  HashCfg& hc = c->hc;
+  for (uint32_t i = 0; i <= f.bloom_hashes; ++i) hc.salt[i] = host_mix64(f.seed + (uint64_t)(i + 1) * kGamma);
+  hc.k = f.k;
+  hc.h = f.bloom_hashes;
+  hc.bl = f.bloom_block_log2;
+  hc.nc = f.n_counters;
+  hc.min_count = f.min_count;
+  c->s_log2 = f.bloom_bits_log2 - f.bloom_block_log2;
+  c->p_log2 = std::max<uint32_t>(std::max<uint32_t>(f.partitions_log2, c->s_log2), 1);
+  if (c->p_log2 > 24) return fail(c, KC_ERR_INVALID_ARG, "more than 2^24 partitions");
+  c->upb_log2 = c->p_log2 - c->s_log2;
+  hc.s_log2 = c->s_log2;
+  hc.p_log2 = c->p_log2;
+  c->nbw = f.bloom_block_log2 >= 5 ? (1u << (f.bloom_block_log2 - 5)) : 1u;
+  c->l2w = (c->nbw + 1) & ~1u;
+  c->slot_bytes = 8 + 4 * f.n_counters;
+  const size_t table_room = (size_t)kLdsMax - 4 * (size_t)c->l2w;
+  uint32_t cap_max = 0;
+  while ((((size_t)1) << (cap_max + 1)) * c->slot_bytes <= table_room) ++cap_max;
+  if (cap_max < 4) return fail(c, KC_ERR_INVALID_ARG, "Bloom block leaves no LDS for a table");
+  if (f.table_log2) {
+    if (f.table_log2 > cap_max || f.table_log2 < 4)
+      return fail(c, KC_ERR_INVALID_ARG,
+                  "table_log2 must be in 4.." + std::to_string(cap_max) + " for this Bloom block");
+    c->cap_log2 = f.table_log2;
+  } else {
+    c->cap_log2 = cap_max;
+  }
+  hc.cap_log2 = c->cap_log2;
+  const size_t table_bytes = ((size_t)1 << c->cap_log2) * c->slot_bytes;
+  c->count_lds = 4 * (size_t)c->l2w +
+                 std::max(std::max((size_t)4 * c->nbw, table_bytes), (size_t)kWaves * kNst * 8);
+  if (c->count_lds > (size_t)kLdsMax) return fail(c, KC_ERR_INVALID_ARG, "LDS layout too large");
+  if (f.scatter_bits) {
+    c->a1 = std::min<uint32_t>(f.scatter_bits, c->p_log2);
+  } else {
+    c->a1 = c->p_log2 <= 8 ? c->p_log2 : c->p_log2 / 2;
+  }
+  c->a2 = c->p_log2 - c->a1;
+  if (c->a1 > (uint32_t)kMaxA1 || c->a2 > (uint32_t)kMaxA2)
+    return fail(c, KC_ERR_INVALID_ARG, "partition count needs a wider shuffle (set scatter_bits)");
+  c->bloom_words64 = f.bloom_bits_log2 >= 6 ? (1ull << (f.bloom_bits_log2 - 6)) : 1ull;
+  return KC_OK;
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+void free_spill(kc_ctx* c) {
+  if (c->spill_keys) (void)hipHostFree(c->spill_keys);
+  if (c->spill_counts) (void)hipHostFree(c->spill_counts);
+  c->spill_keys = nullptr;
+  c->spill_counts = nullptr;
+  c->spill_cap = c->spill_used = 0;
+  c->spill_dir.clear();
+  c->spill_of.assign(1ull << c->p_log2, -1);
+}
+
+kc_status ensure_spill_pool(kc_ctx* c, uint64_t need) {
+  if (c->spill_used + need <= c->spill_cap) return KC_OK;
+  uint64_t cap = std::max<uint64_t>(c->spill_cap * 2, c->spill_used + need);
+  cap = std::max<uint64_t>(cap, 1 << 16);
+  uint64_t* nk = nullptr;
+  uint32_t* ncs = nullptr;
+  if (hipHostMalloc(reinterpret_cast<void**>(&nk), cap * 8, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&ncs), cap * 4 * c->cfg.n_counters,
+                    hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    if (nk) (void)hipHostFree(nk);
+    return fail(c, KC_ERR_OUT_OF_MEMORY, "pinned spill pool allocation failed");
+  }
+  if (c->spill_used) {
+    memcpy(nk, c->spill_keys, c->spill_used * 8);
+    memcpy(ncs, c->spill_counts, c->spill_used * 4 * c->cfg.n_counters);
+  }
+  if (c->spill_keys) (void)hipHostFree(c->spill_keys);
+  if (c->spill_counts) (void)hipHostFree(c->spill_counts);
+  c->spill_keys = nk;
+  c->spill_counts = ncs;
+  c->spill_cap = cap;
+  return KC_OK;
+}
+
+kc_status sync_read(kc_ctx* c, hipStream_t s, const void* dev, size_t bytes, void* host) {
+  KC_HIP(c, hipMemcpyAsync(c->pinned, dev, bytes, hipMemcpyDeviceToHost, s), "readback");
+  KC_HIP(c, hipStreamSynchronize(s), "stream synchronise");
+  memcpy(host, c->pinned, bytes);
+  return KC_OK;
+}
+
+// Moves partition p's table (entries with a nonzero count, slot order) to the
+// pinned spill pool and marks it non-resident.
+kc_status spill_partition(kc_ctx* c, uint32_t p, hipStream_t s, uint64_t* bytes) {
+  if (c->spill_of[p] >= 0) return KC_OK;
+  const uint64_t cap = 1ull << c->cap_log2;
+  const uint32_t nc = c->cfg.n_counters;
+  DevBuf tmpk, tmpc, cur;
+  KC_HIP(c, tmpk.ensure(cap * 8), "spill staging");
+  KC_HIP(c, tmpc.ensure(cap * 4 * nc), "spill staging");
+  KC_HIP(c, cur.ensure(8), "spill cursor");
+  KC_HIP(c, hipMemsetAsync(cur.p, 0, 8, s), "memset");
+  StageTimer tm(c, s, KC_T_SPILL);
+  KC_HIP(c, launch_gather_part(c->tkeys.as<uint64_t>(), c->tcounts.as<uint32_t>(),
+                               (uint64_t)p << c->cap_log2, cap, nc, tmpk.as<uint64_t>(),
+                               tmpc.as<uint32_t>(), cur.as<uint64_t>(), s),
+         "gather");
+  uint64_t n = 0;
+  kc_status r = sync_read(c, s, cur.p, 8, &n);
+  if (r != KC_OK) return r;
+  r = ensure_spill_pool(c, n);
+  if (r != KC_OK) return r;
+  if (n) {
+    KC_HIP(c, hipMemcpyAsync(c->spill_keys + c->spill_used, tmpk.p, n * 8, hipMemcpyDeviceToHost, s),
+           "spill copy");
+    KC_HIP(c, hipMemcpyAsync(c->spill_counts + c->spill_used * nc, tmpc.p, n * 4 * nc,
+                             hipMemcpyDeviceToHost, s),
+           "spill copy");
+  }
+  const uint32_t zero = 0;
+  KC_HIP(c, hipMemcpyAsync(c->resident.as<uint32_t>() + p, &zero, 4, hipMemcpyHostToDevice, s),
+         "resident flag");
+  tm.stop();
+  KC_HIP(c, hipStreamSynchronize(s), "spill synchronise");
+  tmpk.release();
+  tmpc.release();
+  cur.release();
+  SpillRec rec;
+  rec.partition = p;
+  rec.stale = false;
+  rec.host_offset = c->spill_used;
+  rec.entries = n;
+  c->spill_of[p] = (int32_t)c->spill_dir.size();
+  c->spill_dir.push_back(rec);
+  c->spill_used += n;
+  c->st.spilled_partitions += 1;
+  c->st.spilled_bytes += n * (8 + 4ull * nc);
+  if (bytes) *bytes += n * (8 + 4ull * nc);
+  return KC_OK;
+}
+
+uint64_t table_bytes_total(const kc_ctx* c) {
+  return (1ull << (c->p_log2 + c->cap_log2)) * c->slot_bytes;
+}
+
+uint64_t resident_bytes(const kc_ctx* c) {
+  uint64_t n = 0;
+  for (size_t p = 0; p < c->spill_of.size(); ++p)
+    if (c->spill_of[p] < 0) ++n;
+  return n * (1ull << c->cap_log2) * c->slot_bytes;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t kc_abi_version(void) { return KC_ABI_VERSION; }
+
+const char* kc_status_str(kc_status s) {
+  switch (s) {
+    case KC_OK: return "KC_OK";
+    case KC_ERR_INVALID_ARG: return "KC_ERR_INVALID_ARG";
+    case KC_ERR_OUT_OF_MEMORY: return "KC_ERR_OUT_OF_MEMORY";
+    case KC_ERR_BAD_STATE: return "KC_ERR_BAD_STATE";
+    case KC_ERR_DEVICE: return "KC_ERR_DEVICE";
+    case KC_ERR_OVER_BUDGET: return "KC_ERR_OVER_BUDGET";
+  }
+  return "KC_UNKNOWN";
+}
+
+const char* kc_last_error(const kc_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+kc_status kc_create(const kc_config* cfg, int device, kc_ctx** out) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return KC_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  std::string why;
+  if (validate(cfg, &why) != KC_OK) {
+    g_create_error = why;
+    return KC_ERR_INVALID_ARG;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    g_create_error = "no such HIP device";
+    return KC_ERR_INVALID_ARG;
+  }
+  kc_ctx* c = new (std::nothrow) kc_ctx();
+  if (!c) {
+    g_create_error = "host allocation failed";
+    return KC_ERR_OUT_OF_MEMORY;
+  }
+  c->cfg = *cfg;
+  c->device = device;
+  kc_status r = derive(c);
+  if (r != KC_OK) {
+    g_create_error = c->err;
+    delete c;
+    return r;
+  }
+  auto bail = [&](kc_status s, const std::string& m) {
+    g_create_error = m;
+    kc_destroy(c);
+    return s;
+  };
+  if (hipSetDevice(device) != hipSuccess) return bail(KC_ERR_DEVICE, "hipSetDevice failed");
+  const size_t bloom_bytes = c->bloom_words64 * 8;
+  if (c->b1.ensure(bloom_bytes) != hipSuccess || c->b2.ensure(bloom_bytes) != hipSuccess)
+    return bail(KC_ERR_OUT_OF_MEMORY, "Bloom level allocation failed");
+  if (c->dstat.ensure(kNst * 8 * 2) != hipSuccess || c->derr.ensure(8) != hipSuccess ||
+      c->ovf_used.ensure(8) != hipSuccess || c->qcount.ensure(8) != hipSuccess)
+    return bail(KC_ERR_OUT_OF_MEMORY, "device allocation failed");
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->pinned), 4096, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    c->pinned = nullptr;
+    return bail(KC_ERR_OUT_OF_MEMORY, "pinned allocation failed");
+  }
+  if (hipEventCreateWithFlags(&c->insert_done, hipEventDisableTiming) != hipSuccess)
+    return bail(KC_ERR_DEVICE, "event creation failed");
+  c->spill_of.assign(1ull << c->p_log2, -1);
+  c->st.partitions_log2 = c->p_log2;
+  c->st.table_log2 = c->cap_log2;
+  *out = c;
+  return KC_OK;
+}
+
+kc_status kc_insert_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offsets,
+                          uint64_t n_reads, uint64_t total_bases, uint32_t counter,
+                          void* hip_stream) {
+  if (!c) return KC_ERR_INVALID_ARG;
+  if (c->state == FINALIZED) return fail(c, KC_ERR_BAD_STATE, "insert after finalize (reset first)");
+  if (counter >= c->cfg.n_counters) return fail(c, KC_ERR_INVALID_ARG, "counter >= n_counters");
+  if (!offsets) return fail(c, KC_ERR_INVALID_ARG, "offsets is NULL");
+  if (total_bases && !bases) return fail(c, KC_ERR_INVALID_ARG, "bases is NULL");
+  if (total_bases >= (1ull << 40)) return fail(c, KC_ERR_INVALID_ARG, "more than 2^40 bases in one call");
+  hipStream_t s = as_stream(hip_stream);
+  KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
+  if (c->insert_done_valid) KC_HIP(c, hipStreamWaitEvent(s, c->insert_done, 0), "stream wait");
+  c->state = INSERTING;
+
+  const uint64_t nwords = (total_bases + 31) / 32;
+  const uint64_t ntiles = (nwords + kTileWords - 1) / kTileWords;
+  const uint32_t nb1 = 1u << c->a1;
+  const uint64_t nhist = (uint64_t)nb1 * ntiles;
+  KC_HIP(c, c->packed.ensure(nwords * 8), "packed buffer");
+  KC_HIP(c, c->flags.ensure(nwords * 8), "flag buffer");
+  KC_HIP(c, c->hist1.ensure(nhist * 4), "histogram buffer");
+  KC_HIP(c, c->off1.ensure((nhist + 1) * 8), "offset buffer");
+  KC_HIP(c, c->parts.ensure(scan_parts(nhist) * 8), "scan buffer");
+  KC_HIP(c, hipMemsetAsync(c->derr.p, 0, 4, s), "memset");
+
+  const uint64_t s0 = c->hc.salt[0];
+  {
+    StageTimer t(c, s, KC_T_PACK);
+    KC_HIP(c, launch_pack(bases, total_bases, nwords, c->packed.as<uint64_t>(),
+                          c->flags.as<uint64_t>(), s),
+           "pack");
+    KC_HIP(c, launch_rstart(offsets, n_reads, total_bases, c->flags.as<uint64_t>(),
+                            c->derr.as<uint32_t>(), s),
+           "read starts");
+    t.stop();
+  }
+  if (ntiles) {
+    StageTimer t(c, s, KC_T_HIST);
+    KC_HIP(c, launch_hist1(c->packed.as<uint64_t>(), c->flags.as<uint64_t>(), nwords, c->cfg.k,
+                           s0, c->a1, c->hist1.as<uint32_t>(), ntiles, s),
+           "histogram");
+    t.stop();
+  }
+  {
+    StageTimer t(c, s, KC_T_SCAN);
+    KC_HIP(c, launch_scan(c->hist1.as<uint32_t>(), nhist, c->off1.as<uint64_t>(),
+                          c->parts.as<uint64_t>(), s),
+           "scan");
+    t.stop();
+  }
+  KC_HIP(c, hipMemcpyAsync(c->pinned, c->off1.as<uint64_t>() + nhist, 8, hipMemcpyDeviceToHost, s),
+         "readback");
+  KC_HIP(c, hipMemcpyAsync(c->pinned + 1, c->derr.p, 4, hipMemcpyDeviceToHost, s), "readback");
+  KC_HIP(c, hipStreamSynchronize(s), "stream synchronise");
+  const uint64_t n = c->pinned[0];
+  const uint32_t errf = (uint32_t)c->pinned[1];
+  if (errf & ERR_OFFSETS)
+    return fail(c, KC_ERR_INVALID_ARG,
+                "offsets must start at 0, be non-decreasing and end at total_bases");
+  if (n == 0) return KC_OK;
+
+  Segment seg;
+  // reuse a kept segment allocation when it is large enough
+  for (size_t i = 0; i < c->spare_segs.size(); ++i) {
+    if (c->spare_segs[i].keys.bytes >= n * 8) {
+      seg = c->spare_segs[i];
+      c->spare_segs.erase(c->spare_segs.begin() + i);
+      break;
+    }
+  }
+  seg.n = n;
+  seg.counter = counter;
+  const uint32_t nb2 = 1u << c->a2;
+  const uint64_t tiles2 = c->a2 ? (n + kT2 - 1) / kT2 + nb1 : 0;
+  hipError_t e;
+  if ((e = seg.keys.ensure(n * 8)) != hipSuccess || (e = seg.bucket_off.ensure((nb1 + 1) * 8)) != hipSuccess ||
+      (e = seg.tile_first.ensure((nb1 + 1) * 4)) != hipSuccess ||
+      (e = seg.meta2.ensure(tiles2 * (nb2 + 1) * 4)) != hipSuccess) {
+    seg.release();
+    return hip_fail(c, e, "segment allocation");
+  }
+  KC_HIP(c, launch_bucket_off(c->off1.as<uint64_t>(), ntiles, nb1, seg.bucket_off.as<uint64_t>(), s),
+         "bucket offsets");
+  {
+    StageTimer t(c, s, KC_T_SCATTER1);
+    KC_HIP(c, launch_scatter1(c->packed.as<uint64_t>(), c->flags.as<uint64_t>(), nwords, c->cfg.k,
+                              s0, c->a1, c->off1.as<uint64_t>(), ntiles, (uint64_t)counter << 62,
+                              seg.keys.as<uint64_t>(), s),
+           "scatter");
+    t.stop();
+  }
+  if (c->a2) {
+    StageTimer t(c, s, KC_T_SCATTER2);
+    KC_HIP(c, launch_tiles2(seg.bucket_off.as<uint64_t>(), nb1, seg.tile_first.as<uint32_t>(), s),
+           "tiles");
+    KC_HIP(c, launch_scatter2(seg.keys.as<uint64_t>(), seg.bucket_off.as<uint64_t>(),
+                              seg.tile_first.as<uint32_t>(), c->a1, c->a2, s0,
+                              seg.meta2.as<uint32_t>(), tiles2, s),
+           "scatter level 2");
+    t.stop();
+  }
+  KC_HIP(c, hipEventRecord(c->insert_done, s), "event record");
+  c->insert_done_valid = true;
+  c->segs.push_back(seg);
+  c->st.n_valid += n;
+  c->st.n_segments += 1;
+  return KC_OK;
+}
+
+kc_status kc_finalize(kc_ctx* c, void* hip_stream, kc_stats* out) {
+  if (!c) return KC_ERR_INVALID_ARG;
+  if (c->state == FINALIZED) return fail(c, KC_ERR_BAD_STATE, "already finalized");
+  hipStream_t s = as_stream(hip_stream);
+  KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
+  if (c->insert_done_valid) KC_HIP(c, hipStreamWaitEvent(s, c->insert_done, 0), "stream wait");
+  const uint32_t nc = c->cfg.n_counters;
+  const uint64_t nparts = 1ull << c->p_log2;
+  const uint64_t cap = 1ull << c->cap_log2;
+  const uint64_t all_tables = table_bytes_total(c);
+  const uint64_t budget = c->cfg.hbm_table_budget_bytes;
+  const uint64_t per_table = cap * c->slot_bytes;
+  if (budget && budget < per_table)
+    return fail(c, KC_ERR_OVER_BUDGET, "table budget smaller than one partition table");
+  // Every partition table is computed in HBM; partitions beyond the budget are
+  // moved to pinned host memory right after (highest index first).
+  KC_HIP(c, c->tkeys.ensure(nparts * cap * 8), "table allocation");
+  KC_HIP(c, c->tcounts.ensure(nparts * cap * 4 * nc), "table allocation");
+  KC_HIP(c, c->resident.ensure(nparts * 4), "residency map");
+  KC_HIP(c, c->pstats.ensure((1ull << c->s_log2) * kNst * 8), "stats rows");
+
+  std::vector<SegDesc> hd(c->segs.size());
+  for (size_t i = 0; i < c->segs.size(); ++i) {
+    const Segment& g = c->segs[i];
+    hd[i].keys = g.keys.as<uint64_t>();
+    hd[i].bucket_off = g.bucket_off.as<uint64_t>();
+    hd[i].tile_first = g.tile_first.as<uint32_t>();
+    hd[i].meta2 = g.meta2.as<uint32_t>();
+    hd[i].a1 = c->a1;
+    hd[i].a2 = c->a2;
+  }
+  KC_HIP(c, c->segdesc.ensure(std::max<size_t>(1, hd.size()) * sizeof(SegDesc)), "segment table");
+  if (!hd.empty())
+    KC_HIP(c, hipMemcpyAsync(c->segdesc.p, hd.data(), hd.size() * sizeof(SegDesc),
+                             hipMemcpyHostToDevice, s),
+           "segment table copy");
+
+  // overflow table: sized from the occurrence count, grown on a fill
+  c->ovf_log2 = std::max<uint32_t>(12, std::min<uint32_t>(30, ceil_log2(c->st.n_valid / 256 + 1)));
+  c->st.retries = 0;
+  uint64_t sv[kNst];
+  uint32_t errf = 0;
+  for (;;) {
+    const uint64_t on = 1ull << c->ovf_log2;
+    KC_HIP(c, c->okeys.ensure(on * 8), "overflow table");
+    KC_HIP(c, c->ocounts.ensure(on * 4 * nc), "overflow table");
+    const uint32_t oblocks = (uint32_t)std::min<uint64_t>(1024, (on + 255) / 256);
+    KC_HIP(c, c->pstats_ovf.ensure((uint64_t)oblocks * kNst * 8), "stats rows");
+    KC_HIP(c, hipMemsetAsync(c->okeys.p, 0xFF, on * 8, s), "memset");
+    KC_HIP(c, hipMemsetAsync(c->ocounts.p, 0, on * 4 * nc, s), "memset");
+    KC_HIP(c, hipMemsetAsync(c->ovf_used.p, 0, 4, s), "memset");
+    KC_HIP(c, hipMemsetAsync(c->derr.p, 0, 4, s), "memset");
+    if (c->cfg.bloom_block_log2 < 5) {
+      KC_HIP(c, hipMemsetAsync(c->b1.p, 0, c->bloom_words64 * 8, s), "memset");
+      KC_HIP(c, hipMemsetAsync(c->b2.p, 0, c->bloom_words64 * 8, s), "memset");
+    }
+    CountArgs a{};
+    a.hc = c->hc;
+    a.segs = c->segdesc.as<SegDesc>();
+    a.nsegs = (uint32_t)hd.size();
+    a.upb_log2 = c->upb_log2;
+    a.nbw = c->nbw;
+    a.l2w = c->l2w;
+    a.probe_limit = (uint32_t)std::min<uint64_t>(cap, 128);
+    a.ovf_log2 = c->ovf_log2;
+    a.ovf_limit = (uint32_t)std::min<uint64_t>(on / 2, 0xFFFFFFFFull);
+    a.b1 = c->b1.as<uint32_t>();
+    a.b2 = c->b2.as<uint32_t>();
+    a.tkeys = c->tkeys.as<uint64_t>();
+    a.tcounts = c->tcounts.as<uint32_t>();
+    a.okeys = c->okeys.as<uint64_t>();
+    a.ocounts = c->ocounts.as<uint32_t>();
+    a.ovf_used = c->ovf_used.as<uint32_t>();
+    a.err = c->derr.as<uint32_t>();
+    a.pstats = c->pstats.as<uint64_t>();
+    {
+      StageTimer t(c, s, KC_T_COUNT);
+      KC_HIP(c, launch_count(a, 1u << c->s_log2, c->count_lds, s), "count kernel");
+      t.stop();
+    }
+    {
+      StageTimer t(c, s, KC_T_UNIFY);
+      KC_HIP(c, launch_ovf_emit(a, c->pstats_ovf.as<uint64_t>(), oblocks, s), "overflow pass");
+      KC_HIP(c, launch_reduce(c->pstats.as<uint64_t>(), 1ull << c->s_log2, c->dstat.as<uint64_t>(), s),
+             "reduce");
+      KC_HIP(c, launch_reduce(c->pstats_ovf.as<uint64_t>(), oblocks, c->dstat.as<uint64_t>() + kNst, s),
+             "reduce");
+      t.stop();
+    }
+    KC_HIP(c, hipMemcpyAsync(c->pinned, c->dstat.p, 2 * kNst * 8, hipMemcpyDeviceToHost, s), "readback");
+    KC_HIP(c, hipMemcpyAsync(c->pinned + 2 * kNst, c->derr.p, 4, hipMemcpyDeviceToHost, s), "readback");
+    KC_HIP(c, hipMemcpyAsync(c->pinned + 2 * kNst + 1, c->ovf_used.p, 4, hipMemcpyDeviceToHost, s),
+           "readback");
+    KC_HIP(c, hipStreamSynchronize(s), "stream synchronise");
+    errf = (uint32_t)c->pinned[2 * kNst];
+    for (int i = 0; i < kNst; ++i) sv[i] = c->pinned[i] + c->pinned[kNst + i];
+    if (!(errf & (ERR_OVF_FULL | ERR_OVF_LOAD))) break;
+    if (c->st.retries >= 6 || c->ovf_log2 + 3 > 34)
+      return fail(c, KC_ERR_OUT_OF_MEMORY, "overflow table kept filling up");
+    c->ovf_log2 += 3;
+    c->st.retries += 1;
+  }
+  c->st.n_pass = sv[ST_NPASS];
+  c->st.entries = sv[ST_ENTRIES];
+  c->st.sum_counts = sv[ST_SUM];
+  c->st.fp_singletons = sv[ST_FP];
+  c->st.b1_popcount = sv[ST_B1POP];
+  c->st.b2_popcount = sv[ST_B2POP];
+  c->st.passed_distinct = sv[ST_PASSED];
+  c->st.overflow_keys = (uint32_t)(c->pinned[2 * kNst] >> 32);
+  {
+    uint32_t used = 0;
+    memcpy(&used, reinterpret_cast<uint8_t*>(c->pinned + 2 * kNst + 1), 4);
+    c->st.overflow_keys = used;
+  }
+  // residency map: all resident, then spill down to the budget
+  {
+    std::vector<uint32_t> ones(nparts, 1u);
+    KC_HIP(c, hipMemcpy(c->resident.p, ones.data(), nparts * 4, hipMemcpyHostToDevice), "residency map");
+  }
+  free_spill(c);
+  c->st.spilled_partitions = 0;
+  c->st.spilled_bytes = 0;
+  c->state = FINALIZED;
+  if (budget && all_tables > budget) {
+    uint64_t moved = 0;
+    for (int64_t p = (int64_t)nparts - 1; p >= 0 && resident_bytes(c) > budget; --p) {
+      kc_status r = spill_partition(c, (uint32_t)p, s, &moved);
+      if (r != KC_OK) return r;
+    }
+  }
+  resolve_timers(c);
+  if (out) *out = c->st;
+  return KC_OK;
+}
+
+kc_status kc_query(kc_ctx* c, const uint64_t* kmers, uint64_t n, uint32_t* counts, void* hip_stream) {
+  if (!c) return KC_ERR_INVALID_ARG;
+  if (c->state != FINALIZED) return fail(c, KC_ERR_BAD_STATE, "query before finalize");
+  if (n == 0) return KC_OK;
+  if (!kmers || !counts) return fail(c, KC_ERR_INVALID_ARG, "NULL query buffer");
+  if (n > 0xFFFFFFFFull) return fail(c, KC_ERR_INVALID_ARG, "more than 2^32 queries in one call");
+  hipStream_t s = as_stream(hip_stream);
+  KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
+  const bool any_spill = !c->spill_dir.empty();
+  if (any_spill) KC_HIP(c, c->qrows.ensure(n * 4), "query rows");
+  KC_HIP(c, hipMemsetAsync(c->derr.p, 0, 4, s), "memset");
+  KC_HIP(c, hipMemsetAsync(c->qcount.p, 0, 4, s), "memset");
+  QueryArgs a{};
+  a.hc = c->hc;
+  a.tkeys = c->tkeys.as<uint64_t>();
+  a.tcounts = c->tcounts.as<uint32_t>();
+  a.resident = c->resident.as<uint32_t>();
+  a.okeys = c->okeys.as<uint64_t>();
+  a.ocounts = c->ocounts.as<uint32_t>();
+  a.ovf_used = c->ovf_used.as<uint32_t>();
+  a.ovf_log2 = c->ovf_log2;
+  a.err = c->derr.as<uint32_t>();
+  a.host_rows = any_spill ? c->qrows.as<uint32_t>() : nullptr;
+  a.host_count = c->qcount.as<uint32_t>();
+  {
+    StageTimer t(c, s, KC_T_QUERY);
+    KC_HIP(c, launch_query(a, kmers, n, counts, s), "query");
+    t.stop();
+  }
+  KC_HIP(c, hipMemcpyAsync(c->pinned, c->derr.p, 4, hipMemcpyDeviceToHost, s), "readback");
+  KC_HIP(c, hipMemcpyAsync(c->pinned + 1, c->qcount.p, 4, hipMemcpyDeviceToHost, s), "readback");
+  KC_HIP(c, hipStreamSynchronize(s), "stream synchronise");
+  const uint32_t errf = (uint32_t)c->pinned[0];
+  const uint32_t nhost = (uint32_t)c->pinned[1];
+  if (nhost) {
+    // queries on spilled partitions: answered from the pinned spill pool
+    const uint32_t nc = c->cfg.n_counters;
+    std::vector<uint32_t> rows(nhost);
+    std::vector<uint64_t> q(nhost);
+    KC_HIP(c, hipMemcpy(rows.data(), c->qrows.p, nhost * 4ull, hipMemcpyDeviceToHost), "readback");
+    std::vector<uint32_t> res(nhost * (size_t)nc, 0);
+    for (uint32_t i = 0; i < nhost; ++i)
+      KC_HIP(c, hipMemcpy(&q[i], kmers + rows[i], 8, hipMemcpyDeviceToHost), "readback");
+    for (uint32_t i = 0; i < nhost; ++i) {
+      const uint64_t v = q[i];
+      const uint64_t r = [&] {
+        uint64_t w = ~v;
+        w = ((w >> 2) & 0x3333333333333333ull) | ((w & 0x3333333333333333ull) << 2);
+        w = ((w >> 4) & 0x0F0F0F0F0F0F0F0Full) | ((w & 0x0F0F0F0F0F0F0F0Full) << 4);
+        return __builtin_bswap64(w) >> (64 - 2 * c->cfg.k);
+      }();
+      const uint64_t x = v < r ? v : r;
+      const uint64_t g = host_mix64(x ^ c->hc.salt[0]);
+      const uint32_t p = (uint32_t)(g >> (64 - c->p_log2));
+      const int32_t d = c->spill_of[p];
+      if (d < 0) continue;
+      const SpillRec& rec = c->spill_dir[d];
+      for (uint64_t j = 0; j < rec.entries; ++j) {
+        if (c->spill_keys[rec.host_offset + j] == x) {
+          for (uint32_t t = 0; t < nc; ++t)
+            res[(size_t)i * nc + t] = c->spill_counts[(rec.host_offset + j) * nc + t];
+          break;
+        }
+      }
+    }
+    for (uint32_t i = 0; i < nhost; ++i)
+      KC_HIP(c, hipMemcpy(counts + (uint64_t)rows[i] * nc, &res[(size_t)i * nc], 4ull * nc,
+                          hipMemcpyHostToDevice),
+             "spilled query results");
+  }
+  resolve_timers(c);
+  if (errf & ERR_QUERY_RANGE) return fail(c, KC_ERR_INVALID_ARG, "query k-mer code >= 4^k");
+  return KC_OK;
+}
+
+kc_status kc_spill(kc_ctx* c, int64_t partition, uint64_t* bytes_out) {
+  if (!c) return KC_ERR_INVALID_ARG;
+  if (bytes_out) *bytes_out = 0;
+  if (c->state != FINALIZED) return fail(c, KC_ERR_BAD_STATE, "spill before finalize");
+  const uint64_t nparts = 1ull << c->p_log2;
+  KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
+  hipStream_t s = nullptr;
+  if (partition >= 0) {
+    if ((uint64_t)partition >= nparts) return fail(c, KC_ERR_INVALID_ARG, "no such partition");
+    return spill_partition(c, (uint32_t)partition, s, bytes_out);
+  }
+  if (partition != -1) return fail(c, KC_ERR_INVALID_ARG, "partition must be >= -1");
+  const uint64_t budget = c->cfg.hbm_table_budget_bytes;
+  if (!budget) return KC_OK;
+  for (int64_t p = (int64_t)nparts - 1; p >= 0 && resident_bytes(c) > budget; --p) {
+    kc_status r = spill_partition(c, (uint32_t)p, s, bytes_out);
+    if (r != KC_OK) return r;
+  }
+  return KC_OK;
+}
+
+kc_status kc_export(kc_ctx* c, uint64_t* keys, uint32_t* counts, uint64_t cap, uint64_t* n_out) {
+  if (!c) return KC_ERR_INVALID_ARG;
+  if (c->state != FINALIZED) return fail(c, KC_ERR_BAD_STATE, "export before finalize");
+  if (n_out) *n_out = c->st.entries;
+  if (!keys) return KC_OK;
+  if (!counts) return fail(c, KC_ERR_INVALID_ARG, "counts is NULL");
+  if (cap < c->st.entries) return fail(c, KC_ERR_INVALID_ARG, "cap smaller than the entry count");
+  KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
+  const uint32_t nc = c->cfg.n_counters;
+  const uint64_t E = c->st.entries;
+  DevBuf ok, oc, cur;
+  KC_HIP(c, ok.ensure(E * 8), "export buffer");
+  KC_HIP(c, oc.ensure(E * 4 * nc), "export buffer");
+  KC_HIP(c, cur.ensure(8), "export cursor");
+  hipStream_t s = nullptr;
+  KC_HIP(c, hipMemsetAsync(cur.p, 0, 8, s), "memset");
+  const uint64_t nslots = 1ull << (c->p_log2 + c->cap_log2);
+  KC_HIP(c, launch_export(c->tkeys.as<uint64_t>(), c->tcounts.as<uint32_t>(), nslots,
+                          c->resident.as<uint32_t>(), c->cap_log2, nc, ok.as<uint64_t>(),
+                          oc.as<uint32_t>(), E, cur.as<uint64_t>(), s),
+         "export");
+  KC_HIP(c, launch_export(c->okeys.as<uint64_t>(), c->ocounts.as<uint32_t>(), 1ull << c->ovf_log2,
+                          nullptr, 0, nc, ok.as<uint64_t>(), oc.as<uint32_t>(), E,
+                          cur.as<uint64_t>(), s),
+         "export");
+  uint64_t got = 0;
+  kc_status r = sync_read(c, s, cur.p, 8, &got);
+  if (r != KC_OK) return r;
+  uint64_t spilled = 0;
+  for (const SpillRec& rec : c->spill_dir) spilled += rec.entries;
+  if (got + spilled != E) return fail(c, KC_ERR_DEVICE, "export count mismatch");
+  KC_HIP(c, hipMemcpy(keys, ok.p, got * 8, hipMemcpyDeviceToHost), "export copy");
+  KC_HIP(c, hipMemcpy(counts, oc.p, got * 4 * nc, hipMemcpyDeviceToHost), "export copy");
+  uint64_t at = got;
+  for (const SpillRec& rec : c->spill_dir) {
+    memcpy(keys + at, c->spill_keys + rec.host_offset, rec.entries * 8);
+    memcpy(counts + at * nc, c->spill_counts + rec.host_offset * nc, rec.entries * 4 * nc);
+    at += rec.entries;
+  }
+  return KC_OK;
+}
+
+kc_status kc_export_bloom(kc_ctx* c, uint64_t* b1, uint64_t* b2, uint64_t words) {
+  if (!c) return KC_ERR_INVALID_ARG;
+  if (c->state != FINALIZED) return fail(c, KC_ERR_BAD_STATE, "Bloom export before finalize");
+  if (words != c->bloom_words64) return fail(c, KC_ERR_INVALID_ARG, "words must equal the Bloom size / 64");
+  KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
+  if (b1) KC_HIP(c, hipMemcpy(b1, c->b1.p, words * 8, hipMemcpyDeviceToHost), "Bloom copy");
+  if (b2) KC_HIP(c, hipMemcpy(b2, c->b2.p, words * 8, hipMemcpyDeviceToHost), "Bloom copy");
+  return KC_OK;
+}
+
+kc_status kc_debug_keys(kc_ctx* c, uint64_t* keys, uint32_t* part, uint64_t cap, uint64_t* n_out) {
+  if (!c) return KC_ERR_INVALID_ARG;
+  uint64_t n = 0;
+  for (const Segment& g : c->segs) n += g.n;
+  if (n_out) *n_out = n;
+  if (!keys) return KC_OK;
+  if (cap < n) return fail(c, KC_ERR_INVALID_ARG, "cap smaller than the stored key count");
+  KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
+  KC_HIP(c, hipDeviceSynchronize(), "synchronise");
+  uint64_t at = 0;
+  for (const Segment& g : c->segs) {
+    KC_HIP(c, hipMemcpy(keys + at, g.keys.p, g.n * 8, hipMemcpyDeviceToHost), "key copy");
+    if (part) {
+      DevBuf pb;
+      KC_HIP(c, pb.ensure(g.n * 4), "partition buffer");
+      SegDesc sd{g.keys.as<uint64_t>(), g.bucket_off.as<uint64_t>(), g.tile_first.as<uint32_t>(),
+                 g.meta2.as<uint32_t>(), c->a1, c->a2};
+      KC_HIP(c, launch_debug_part(sd, g.n, pb.as<uint32_t>(), nullptr), "partition view");
+      KC_HIP(c, hipMemcpy(part + at, pb.p, g.n * 4, hipMemcpyDeviceToHost), "partition copy");
+    }
+    at += g.n;
+  }
+  return KC_OK;
+}
+
+kc_status kc_get_stats(const kc_ctx* cc, kc_stats* out) {
+  if (!cc || !out) return KC_ERR_INVALID_ARG;
+  kc_ctx* c = const_cast<kc_ctx*>(cc);
+  resolve_timers(c);
+  *out = c->st;
+  return KC_OK;
+}
+
+kc_status kc_reset(kc_ctx* c) {
+  if (!c) return KC_ERR_INVALID_ARG;
+  KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
+  KC_HIP(c, hipDeviceSynchronize(), "synchronise");
+  for (Segment& g : c->segs) c->spare_segs.push_back(g);
+  c->segs.clear();
+  // keep at most a few spare segment allocations
+  std::sort(c->spare_segs.begin(), c->spare_segs.end(),
+            [](const Segment& a, const Segment& b) { return a.keys.bytes > b.keys.bytes; });
+  while (c->spare_segs.size() > 4) {
+    c->spare_segs.back().release();
+    c->spare_segs.pop_back();
+  }
+  free_spill(c);
+  resolve_timers(c);
+  const uint32_t pl = c->p_log2, tl = c->cap_log2;
+  c->st = kc_stats{};
+  c->st.partitions_log2 = pl;
+  c->st.table_log2 = tl;
+  c->insert_done_valid = false;
+  c->state = CREATED;
+  c->err.clear();
+  return KC_OK;
+}
+
+void kc_destroy(kc_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (Segment& g : c->segs) g.release();
+  for (Segment& g : c->spare_segs) g.release();
+  DevBuf* bufs[] = {&c->b1, &c->b2, &c->dstat, &c->derr, &c->packed, &c->flags, &c->hist1,
+                    &c->off1, &c->parts, &c->segdesc, &c->tkeys, &c->tcounts, &c->resident,
+                    &c->pstats, &c->pstats_ovf, &c->okeys, &c->ocounts, &c->ovf_used, &c->qrows,
+                    &c->qcount};
+  for (DevBuf* b : bufs) b->release();
+  free_spill(c);
+  for (auto& t : c->pending) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->insert_done) (void)hipEventDestroy(c->insert_done);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+"""The C-ABI library loads on any host and exports every symbol kc.h declares.
+
+No compute call is made here: these tests run without a GPU.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1712_03254_amd as kc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = kc.load()
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(kc.EXPORTED) == names
+
+
+def test_abi_version_and_status_strings():
+    assert kc.kc_abi_version() == 1
+    lib = kc.load()
+    assert lib.kc_status_str(0) == b"KC_OK"
+    assert lib.kc_status_str(-5) == b"KC_ERR_OVER_BUDGET"
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "lay.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "kc.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(kc_config), offsetof(kc_config, seed),
+         offsetof(kc_config, hbm_table_budget_bytes), sizeof(kc_stats),
+         offsetof(kc_stats, kernel_ms), offsetof(kc_stats, kernel_launches));
+  return 0;
+}
+''')
+    exe = tmp_path / "lay"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(kc.KcConfig), kc.KcConfig.seed.offset,
+            kc.KcConfig.hbm_table_budget_bytes.offset, ctypes.sizeof(kc.KcStats),
+            kc.KcStats.kernel_ms.offset, kc.KcStats.kernel_launches.offset]
+    assert got == want
+
+
+@pytest.mark.parametrize("field,value", [("k", 0), ("k", 32), ("n_counters", 3),
+                                         ("min_count", 1), ("bloom_hashes", 9),
+                                         ("bloom_block_log2", 20), ("bloom_bits_log2", 41)])
+def test_config_validation_without_device(field, value):
+    cfg = kc.Config(k=21, bloom_bits_log2=20, bloom_hashes=3, bloom_block_log2=12)
+    setattr(cfg, field, value)
+    with pytest.raises(kc.KcError) as e:
+        kc.kc_create(cfg.c(), 0)
+    assert e.value.status == kc.KC_ERR_INVALID_ARG
+
+
+def test_null_context_calls_are_rejected():
+    lib = kc.load()
+    assert lib.kc_finalize(None, None, None) == kc.KC_ERR_INVALID_ARG
+    assert lib.kc_reset(None) == kc.KC_ERR_INVALID_ARG
+    lib.kc_destroy(None)

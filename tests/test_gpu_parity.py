@@ -1,0 +1,242 @@
+"""GPU path vs the CPU oracle, element by element, through the C ABI.
+
+Every case prints its name, seed and shape before touching the GPU.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1712_03254_amd as kc
+from kc_cases import (assert_parity, assert_same_table, note, oracle_params, pack_reads,
+                      random_reads, run_gpu, to_device, workload_chunks, workload_config)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    kc.load()
+    yield
+
+
+def test_minimum_slice_keys_and_partitions():
+    """Pass 1 alone: the stored key multiset equals the oracle's canonical
+    windows, and every key sits in the partition given by the top bits of g."""
+    note("case: minimum slice, plain_1mbp first 5000 reads")
+    w, _, b, o = workload_chunks("plain_1mbp", n_reads=5000)
+    cfg = workload_config(w)
+    db, do = to_device(b, o)
+    with kc.KmerCounter(cfg) as c:
+        c.insert_reads(db, do)
+        keys, part = c.debug_keys()
+        st = c.stats()
+    want = np.sort(oracle.enumerate_keys(oracle_params(cfg), b, o) >> np.uint64(1))
+    got = keys & np.uint64((1 << 62) - 1)
+    assert st["n_valid"] == want.size
+    assert np.array_equal(np.sort(got), want)
+    p_log2 = st["partitions_log2"]
+    s0 = oracle.mix64(cfg.seed + 0x9E3779B97F4A7C15)
+    sample = np.arange(0, got.size, 97)
+    for i in sample:
+        g = oracle.mix64(int(got[i]) ^ s0)
+        assert int(part[i]) == g >> (64 - p_log2)
+    assert part.max() < (1 << p_log2)
+
+
+def test_plain_1mbp_full_parity():
+    note("case: plain_1mbp full (20k reads x 100bp, k=31, m=2^24, h=3)")
+    w, _, b, o = workload_chunks("plain_1mbp")
+    cfg = workload_config(w)
+    g, ref = assert_parity(cfg, [(b, o)])
+    assert ref.stats["n_valid"] == 1_400_000
+    note("stats: %s" % {k: g["stats"][k] for k in ("entries", "fp_singletons", "overflow_keys")})
+
+
+PARAMS = [
+    # k, m_log2, h, bl, p_log2, table_log2, nc, min_count, seed
+    (31, 20, 4, 12, 0, 0, 1, 2, 1),
+    (21, 22, 3, 19, 6, 0, 1, 2, 2),
+    (15, 16, 2, 4, 0, 0, 1, 2, 3),      # Bloom blocks smaller than a word
+    (9, 12, 8, 2, 0, 0, 1, 2, 4),       # h > block bits: repeated positions in S(x)
+    (31, 24, 3, 19, 10, 0, 1, 3, 5),    # min_count 3, first-level fan-out 2^10
+    (27, 26, 4, 16, 14, 0, 2, 2, 6),    # joint counters, two shuffle levels
+    (1, 8, 2, 3, 0, 0, 1, 2, 7),
+    (13, 10, 3, 5, 0, 4, 1, 2, 8),      # 16-slot tables: overflow path and its regrowth
+    (31, 22, 4, 12, 12, 5, 1, 2, 9),    # 32-slot tables at 2^12 partitions
+]
+
+
+@pytest.mark.parametrize("k,m,h,bl,pl,tl,nc,mc,seed", PARAMS)
+def test_parameter_grid_parity(k, m, h, bl, pl, tl, nc, mc, seed):
+    note("case: grid k=%d m=%d h=%d bl=%d p=%d t=%d nc=%d min=%d seed=%d"
+         % (k, m, h, bl, pl, tl, nc, mc, seed))
+    reads = random_reads(seed, 3000, 0, 160, genome_len=6000)
+    cfg = kc.Config(k=k, bloom_bits_log2=m, bloom_hashes=h, bloom_block_log2=bl,
+                    partitions_log2=pl, table_log2=tl, n_counters=nc, min_count=mc, seed=seed)
+    b, o = pack_reads(reads)
+    counters = None
+    chunks = [(b, o)]
+    if nc == 2:
+        half = len(reads) // 2
+        chunks = [pack_reads(reads[:half]), pack_reads(reads[half:])]
+        counters = [0, 1]
+    g, ref = assert_parity(cfg, chunks, counters)
+    if tl == 4:
+        assert g["stats"]["overflow_keys"] > 0
+
+
+def test_chunking_and_order_invariance():
+    note("case: chunking invariance, 7 calls vs 1, plus shuffled read order")
+    reads = random_reads(11, 4000, 20, 150, genome_len=5000)
+    cfg = kc.Config(k=25, bloom_bits_log2=22, bloom_hashes=4, bloom_block_log2=16,
+                    partitions_log2=9, seed=11)
+    one = run_gpu(cfg, [pack_reads(reads)])
+    cuts = [0, 1, 500, 501, 1700, 2900, 3999, 4000]
+    many = run_gpu(cfg, [pack_reads(reads[a:b]) for a, b in zip(cuts[:-1], cuts[1:])])
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(len(reads))
+    shuf = run_gpu(cfg, [pack_reads([reads[i] for i in perm])])
+    for other in (many, shuf):
+        assert_same_table(other["keys"], other["counts"], one["keys"], one["counts"])
+        assert np.array_equal(other["b1"], one["b1"]) and np.array_equal(other["b2"], one["b2"])
+        for key in ("n_valid", "n_pass", "entries", "sum_counts", "fp_singletons"):
+            assert other["stats"][key] == one["stats"][key]
+
+
+def test_result_neutral_parameters():
+    note("case: partitions / table size / fan-out change nothing")
+    reads = random_reads(12, 3000, 30, 120, genome_len=4000)
+    base = dict(k=19, bloom_bits_log2=20, bloom_hashes=3, bloom_block_log2=14, seed=12)
+    runs = [run_gpu(kc.Config(**base, partitions_log2=p, table_log2=t, scatter_bits=sb),
+                    [pack_reads(reads)])
+            for p, t, sb in [(0, 0, 0), (9, 0, 0), (12, 6, 0), (12, 0, 4), (6, 5, 3)]]
+    for r in runs[1:]:
+        assert_same_table(r["keys"], r["counts"], runs[0]["keys"], runs[0]["counts"])
+        assert np.array_equal(r["b1"], runs[0]["b1"]) and np.array_equal(r["b2"], runs[0]["b2"])
+        assert r["stats"]["fp_singletons"] == runs[0]["stats"]["fp_singletons"]
+
+
+def test_reverse_complement_invariance_on_gpu():
+    note("case: reverse-complemented reads give the same table")
+    reads = random_reads(13, 2000, 40, 100, genome_len=3000, nfrac=0.0)
+    comp = str.maketrans("ACGT", "TGCA")
+    cfg = kc.Config(k=31, bloom_bits_log2=20, bloom_hashes=4, bloom_block_log2=19, seed=13)
+    a = run_gpu(cfg, [pack_reads(reads)])
+    b = run_gpu(cfg, [pack_reads([r[::-1].translate(comp) for r in reads])])
+    assert_same_table(a["keys"], a["counts"], b["keys"], b["counts"])
+    assert np.array_equal(a["b2"], b["b2"])
+
+
+def test_query_both_orientations_and_absent():
+    import torch
+    note("case: query, plain_1mbp 5000 reads")
+    w, _, b, o = workload_chunks("plain_1mbp", n_reads=5000)
+    cfg = workload_config(w)
+    ref = oracle.count(oracle_params(cfg), b, o, want_bloom=False)
+    table = dict(zip(ref.keys.tolist(), ref.counts[:, 0].tolist()))
+    rng = np.random.default_rng(5)
+    k = cfg.k
+    present = ref.keys[rng.integers(0, ref.keys.size, 3000)]
+
+    def rc(x):
+        y = 0
+        for j in range(k):
+            y = (y << 2) | (3 - ((int(x) >> (2 * j)) & 3))
+        return y
+    flipped = np.array([rc(x) for x in present[:500]], np.uint64)
+    rand = rng.integers(0, 1 << 62, 3000, dtype=np.uint64)
+    q = np.concatenate([present, flipped, rand])
+    db, do = to_device(b, o)
+    with kc.KmerCounter(cfg) as c:
+        c.insert_reads(db, do)
+        c.finalize()
+        out = c.query(torch.from_numpy(q.view(np.int64)).cuda()).cpu().numpy()
+        for i, x in enumerate(q):
+            xi = int(x)
+            canon = min(xi, rc(xi))
+            assert int(out[i, 0]) == table.get(canon, 0), (i, hex(xi))
+        bad = torch.tensor([1 << 62], dtype=torch.int64, device="cuda")
+        with pytest.raises(kc.KcError) as e:
+            c.query(bad)
+        assert e.value.status == kc.KC_ERR_INVALID_ARG
+
+
+def test_joint_query_and_counters():
+    import torch
+    note("case: joint counters, query returns (normal, tumour)")
+    normal = random_reads(21, 1500, 60, 100, genome_len=3000, nfrac=0.0)
+    tumour = random_reads(22, 1500, 60, 100, genome_len=3000, nfrac=0.0)
+    cfg = kc.Config(k=23, n_counters=2, bloom_bits_log2=20, bloom_hashes=4,
+                    bloom_block_log2=15, seed=21)
+    g, ref = assert_parity(cfg, [pack_reads(normal), pack_reads(tumour)], counters=[0, 1])
+    with kc.KmerCounter(cfg) as c:
+        for reads, t in ((normal, 0), (tumour, 1)):
+            db, do = to_device(*pack_reads(reads))
+            c.insert_reads(db, do, counter=t)
+        c.finalize()
+        out = c.query(torch.from_numpy(ref.keys[:2000].view(np.int64)).cuda()).cpu().numpy()
+        assert np.array_equal(out.astype(np.uint32), ref.counts[:2000])
+
+
+def test_forced_spill_keeps_results():
+    import torch
+    note("case: table budget forces spill of partitions to pinned host")
+    reads = random_reads(31, 3000, 50, 120, genome_len=6000)
+    cfg = kc.Config(k=27, bloom_bits_log2=20, bloom_hashes=3, bloom_block_log2=14,
+                    partitions_log2=8, table_log2=8, seed=31)
+    full = run_gpu(cfg, [pack_reads(reads)])
+    per_table = (1 << 8) * 12
+    cfg.hbm_table_budget_bytes = per_table * 100  # 100 of 256 partitions stay in HBM
+    b, o = pack_reads(reads)
+    db, do = to_device(b, o)
+    with kc.KmerCounter(cfg) as c:
+        c.insert_reads(db, do)
+        st = c.finalize()
+        assert st["spilled_partitions"] == 156
+        keys, counts = c.export()
+        assert_same_table(keys, counts, full["keys"], full["counts"])
+        q = torch.from_numpy(full["keys"].view(np.int64)).cuda()
+        out = c.query(q).cpu().numpy().astype(np.uint32)
+        assert np.array_equal(out, full["counts"])
+        moved = c.spill(3)
+        assert moved >= 0
+        out = c.query(q).cpu().numpy().astype(np.uint32)
+        assert np.array_equal(out, full["counts"])
+
+
+def test_edge_inputs():
+    note("case: empty reads, reads shorter than k, all-invalid reads, empty insert")
+    cfg = kc.Config(k=11, bloom_bits_log2=16, bloom_hashes=3, bloom_block_log2=12, seed=41)
+    reads = ["", "ACG", "", "NNNNNNNNNNNNNNNNNNNN", "ACGTACGTACGTACGT", "", "ACGTACGTACGTACGTT",
+             "acgtacgtacgtacgt", "A" * 50, "T" * 40, ""]
+    assert_parity(cfg, [pack_reads(reads), pack_reads([]), pack_reads([""])])
+    assert_parity(cfg, [])
+
+
+def test_bad_offsets_and_state_errors():
+    import torch
+    note("case: invalid offsets and out-of-order calls are rejected")
+    cfg = kc.Config(k=11, bloom_bits_log2=16, bloom_hashes=3, bloom_block_log2=12, seed=42)
+    b, o = pack_reads(["ACGTACGTACGTAC", "GGGGCCCCAAAATTTT"])
+    with kc.KmerCounter(cfg) as c:
+        db = torch.from_numpy(b).cuda()
+        for bad in (np.array([0, 20, 10], np.int64), np.array([1, 5, 30], np.int64),
+                    np.array([0, 5, 29], np.int64)):
+            with pytest.raises(kc.KcError) as e:
+                c.insert_reads(db, torch.from_numpy(bad).cuda())
+            assert e.value.status == kc.KC_ERR_INVALID_ARG
+        c.insert_reads(db, torch.from_numpy(o.view(np.int64)).cuda())
+        with pytest.raises(kc.KcError) as e:
+            c.export()
+        assert e.value.status == kc.KC_ERR_BAD_STATE
+        c.finalize()
+        with pytest.raises(kc.KcError) as e:
+            c.insert_reads(db, torch.from_numpy(o.view(np.int64)).cuda())
+        assert e.value.status == kc.KC_ERR_BAD_STATE
+        c.reset()
+        c.insert_reads(db, torch.from_numpy(o.view(np.int64)).cuda())
+        st = c.finalize()
+        assert st["n_valid"] == (14 - 11 + 1) + (16 - 11 + 1)
