@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X k-mer counter on the 100 Mbp plain workload.
+
+One step = one pass of the whole counting path over the workload's reads,
+already resident in HBM: reset, insert (pack, extraction, two-level partition
+shuffle), finalize (Bloom levels, screen, exact per-partition count, unify)
+and one query batch.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "plain_100mbp"
+METRIC = "k-mers/sec + HBM GB/s (plain vs batched/served); p50/p99 request latency"
+HBM_PEAK_GBS = 8000.0
+QUERY_BATCH = 1 << 20
+
+
+def stage_bytes(stage: str, w, st: dict, cfg_eff: dict) -> float:
+    """Algorithmic HBM bytes of one launch of a stage (what the algorithm must
+    move at least once), from the workload shape and the run's statistics."""
+    total_bases = w.n_reads * w.lmax
+    nwords = (total_bases + 31) // 32
+    n = st["n_valid"]
+    if stage == "pack":      # ASCII in, 2-bit words + flag words out, offsets in
+        return total_bases + nwords * 16 + (w.n_reads + 1) * 8
+    if stage == "level1":    # packed + flags in, 8 B keys out
+        return nwords * 16 + n * 8
+    if stage == "level2":    # keys in and out
+        return n * 16
+    if stage == "count":     # keys in, both Bloom levels out, partition tables out
+        m_bytes = (1 << w.bloom_bits_log2) // 8
+        tables = (1 << cfg_eff["partitions_log2"]) * cfg_eff["table_slots"] * (8 + 4 * w.n_counters)
+        return n * 8 + 2 * m_bytes + tables
+    if stage == "query":
+        return QUERY_BATCH * (8 + 4 * w.n_counters)
+    return 0.0
+
+
+def cpu_baseline(w, genome, n_reads=300_000):
+    import oracle
+    b, o = w.make_reads(genome, first=0, n=n_reads)
+    p = oracle.Params(k=w.k, n_counters=w.n_counters, min_count=w.min_count,
+                      m_log2=w.bloom_bits_log2, h=w.bloom_hashes, block_log2=w.bloom_block_log2,
+                      seed=w.seed)
+    t0 = time.perf_counter()
+    r = oracle.count(p, b, o, want_bloom=False)
+    dt = time.perf_counter() - t0
+    return {"value": r.stats["n_valid"] / dt, "unit": "k-mers/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d reads of %s (%d k-mers): sort + run-length count, Bloom levels, "
+                      "screen and table in %.1f s on one host core"
+                      % (n_reads, WORKLOAD, r.stats["n_valid"], dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default=WORKLOAD)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the counting path of this build runs on a single "
+              "MI355X (multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_1712_03254_amd as kc
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    kc.load()
+    w = synth.WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    genome = w.make_genome()
+    bases, offsets = w.make_reads(genome)
+    gen_s = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    pinned_b = torch.from_numpy(bases).pin_memory()
+    pinned_o = torch.from_numpy(offsets.view(np.int64)).pin_memory()
+    db = pinned_b.to(dev, non_blocking=True)
+    do = pinned_o.to(dev, non_blocking=True)
+    torch.cuda.synchronize()
+    cfg = kc.Config(k=w.k, n_counters=w.n_counters, min_count=w.min_count,
+                    bloom_bits_log2=w.bloom_bits_log2, bloom_hashes=w.bloom_hashes,
+                    bloom_block_log2=w.bloom_block_log2, seed=w.seed,
+                    partitions_log2=w.partitions_log2, hbm_table_budget_bytes=w.table_budget)
+    counter = kc.KmerCounter(cfg)
+    stream = torch.cuda.current_stream()
+
+    def step(q=None):
+        counter.reset()
+        counter.insert_reads(db, do, stream=stream)
+        st = counter.finalize(stream=stream)
+        if q is not None:
+            counter.query(q, stream=stream)
+        return counter.stats() if q is not None else st
+
+    # query batch: half present (from the table), half random codes
+    step()
+    keys, _ = counter.export()
+    rng = np.random.default_rng(1)
+    half = QUERY_BATCH // 2
+    qk = np.concatenate([keys[rng.integers(0, keys.size, half)],
+                         rng.integers(0, 1 << (2 * w.k), QUERY_BATCH - half, dtype=np.uint64)])
+    q = torch.from_numpy(qk.view(np.int64)).to(dev)
+    for _ in range(args.warmup):
+        step(q)
+    torch.cuda.synchronize()
+    per_stage_ms = {}
+    per_stage_n = {}
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(args.steps):
+        last = step(q)
+        for s, v in last["kernel_ms"].items():
+            per_stage_ms[s] = per_stage_ms.get(s, 0.0) + v
+            per_stage_n[s] = per_stage_n.get(s, 0) + last["kernel_launches"][s]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    n_valid = last["n_valid"]
+    value = n_valid * args.steps / elapsed
+
+    # end-to-end figure with the reads crossing PCIe from pinned host memory
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    db2 = pinned_b.to(dev, non_blocking=True)
+    do2 = pinned_o.to(dev, non_blocking=True)
+    counter.reset()
+    counter.insert_reads(db2, do2, stream=stream)
+    counter.finalize(stream=stream)
+    torch.cuda.synchronize()
+    e2e = n_valid / (time.perf_counter() - t1)
+    del db2, do2
+
+    cfg_eff = {"partitions_log2": last["partitions_log2"], "table_slots": last["table_slots"]}
+    stages = {}
+    for s in per_stage_ms:
+        if per_stage_n.get(s):
+            avg = per_stage_ms[s] / per_stage_n[s]
+            b = stage_bytes(s, w, last, cfg_eff)
+            stages[s] = {"avg_ms": round(avg, 4), "launches_per_step": per_stage_n[s] / args.steps,
+                         "alg_bytes": b,
+                         "gbs": round(b / (avg * 1e-3) / 1e9, 1) if b and avg > 0 else None}
+    dom = max(stages, key=lambda s: stages[s]["avg_ms"] * stages[s]["launches_per_step"])
+    d = stages[dom]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4) if d["gbs"] else None,
+                "traffic": None}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "k-mers/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": args.workload, "genome_bp": w.genome_len, "reads": w.n_reads,
+                   "read_len": w.lmax, "sub_rate": w.err, "n_rate": w.nrate, "k": w.k,
+                   "bloom_bits_log2": w.bloom_bits_log2, "bloom_hashes": w.bloom_hashes,
+                   "bloom_block_log2": w.bloom_block_log2,
+                   "partitions": 1 << cfg_eff["partitions_log2"],
+                   "table_slots": cfg_eff["table_slots"], "query_batch": QUERY_BATCH},
+        "roofline": roofline,
+        "stages": stages,
+        "counts": {k: last[k] for k in ("n_valid", "n_pass", "entries", "sum_counts",
+                                        "fp_singletons", "b1_popcount", "b2_popcount",
+                                        "overflow_keys")},
+        "pcie_inclusive_kmers_per_s": e2e,
+        "input_gen_s": round(gen_s, 2),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, genome)
+    counter.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

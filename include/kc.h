@@ -80,8 +80,9 @@ typedef struct kc_config {
   uint64_t seed;             /* derives s_0 .. s_h */
   /* result-neutral */
   uint32_t partitions_log2;  /* hash partitions = top bits of g; raised to
-                                bloom_bits_log2 - bloom_block_log2 when lower; <= 24 */
-  uint32_t table_log2;       /* slots per partition table; 0 = largest that fits LDS */
+                                bloom_bits_log2 - bloom_block_log2 when lower; <= 21 */
+  uint32_t table_slots;      /* slots per partition table, rounded down to a multiple of
+                                64 (>= 64); 0 = the largest that fits LDS */
   uint32_t scatter_bits;     /* first-level shuffle fan-out bits; 0 = automatic */
   uint32_t flags;            /* must be 0 */
   uint64_t hbm_table_budget_bytes; /* device bytes the partition tables may use; 0 = unlimited */
@@ -89,15 +90,14 @@ typedef struct kc_config {
 
 /* Per-stage timers (kernel_ms indexes): sums of HIP-event durations. */
 enum {
-  KC_T_PACK = 0,     /* ASCII -> 2-bit stream, invalid and read-start bits */
-  KC_T_HIST = 1,     /* window extraction + first-level histogram */
-  KC_T_SCAN = 2,     /* exclusive prefix sum of the histogram */
-  KC_T_SCATTER1 = 3, /* first-level partition scatter */
-  KC_T_SCATTER2 = 4, /* second-level (in place) partition scatter */
-  KC_T_COUNT = 5,    /* per Bloom block: B1/B2 build, screen, exact count */
-  KC_T_UNIFY = 6,    /* overflow table pass, statistics reduction */
-  KC_T_QUERY = 7,
-  KC_T_SPILL = 8,    /* device -> pinned host copies of spilled partitions */
+  KC_T_PACK = 0,   /* ASCII -> 2-bit stream, invalid and read-start bits */
+  KC_T_LEVEL1 = 1, /* extraction + first-level shuffle (one pass per tile) */
+  KC_T_SCAN = 2,   /* exclusive prefix sum of the first-level histogram */
+  KC_T_LEVEL2 = 3, /* second-level shuffle into partition-sorted tiles */
+  KC_T_COUNT = 4,  /* per Bloom block: B1/B2 build, screen, exact count */
+  KC_T_UNIFY = 5,  /* overflow table pass, statistics reduction */
+  KC_T_QUERY = 6,
+  KC_T_SPILL = 7,  /* device -> pinned host copies of spilled partitions */
   KC_T_COUNT_OF = 16
 };
 
@@ -114,7 +114,7 @@ typedef struct kc_stats {
   uint64_t overflow_keys;      /* distinct keys counted in the device overflow table */
   uint64_t passed_distinct;    /* distinct keys that passed the screen */
   uint32_t partitions_log2;    /* effective partition count (log2) */
-  uint32_t table_log2;         /* effective slots per partition table (log2) */
+  uint32_t table_slots;        /* effective slots per partition table */
   uint32_t n_segments;         /* kc_insert_reads calls since the last reset */
   uint32_t retries;            /* finalize re-runs after an overflow-table fill */
   double kernel_ms[KC_T_COUNT_OF]; /* per-stage device time, milliseconds */

@@ -28,7 +28,7 @@ KC_ERR_BAD_STATE = -3
 KC_ERR_DEVICE = -4
 KC_ERR_OVER_BUDGET = -5
 
-STAGES = ["pack", "hist", "scan", "scatter1", "scatter2", "count", "unify", "query", "spill"]
+STAGES = ["pack", "level1", "scan", "level2", "count", "unify", "query", "spill"]
 
 EXPORTED = ["kc_abi_version", "kc_status_str", "kc_create", "kc_insert_reads", "kc_finalize",
             "kc_query", "kc_spill", "kc_export", "kc_export_bloom", "kc_debug_keys",
@@ -46,7 +46,7 @@ class KcConfig(ctypes.Structure):
                 ("min_count", ctypes.c_uint32), ("bloom_bits_log2", ctypes.c_uint32),
                 ("bloom_hashes", ctypes.c_uint32), ("bloom_block_log2", ctypes.c_uint32),
                 ("seed", ctypes.c_uint64), ("partitions_log2", ctypes.c_uint32),
-                ("table_log2", ctypes.c_uint32), ("scatter_bits", ctypes.c_uint32),
+                ("table_slots", ctypes.c_uint32), ("scatter_bits", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("hbm_table_budget_bytes", ctypes.c_uint64)]
 
 
@@ -55,7 +55,7 @@ class KcStats(ctypes.Structure):
         "n_valid", "n_pass", "entries", "sum_counts", "fp_singletons", "b1_popcount",
         "b2_popcount", "spilled_partitions", "spilled_bytes", "overflow_keys",
         "passed_distinct")] + [
-        ("partitions_log2", ctypes.c_uint32), ("table_log2", ctypes.c_uint32),
+        ("partitions_log2", ctypes.c_uint32), ("table_slots", ctypes.c_uint32),
         ("n_segments", ctypes.c_uint32), ("retries", ctypes.c_uint32),
         ("kernel_ms", ctypes.c_double * 16), ("kernel_launches", ctypes.c_uint64 * 16)]
 
@@ -208,14 +208,14 @@ class Config:
     bloom_block_log2: int = 19
     seed: int = 0
     partitions_log2: int = 0
-    table_log2: int = 0
+    table_slots: int = 0
     scatter_bits: int = 0
     hbm_table_budget_bytes: int = 0
 
     def c(self) -> KcConfig:
         return KcConfig(self.k, self.n_counters, self.min_count, self.bloom_bits_log2,
                         self.bloom_hashes, min(self.bloom_block_log2, self.bloom_bits_log2),
-                        self.seed & ((1 << 64) - 1), self.partitions_log2, self.table_log2,
+                        self.seed & ((1 << 64) - 1), self.partitions_log2, self.table_slots,
                         self.scatter_bits, 0, self.hbm_table_budget_bytes)
 
 

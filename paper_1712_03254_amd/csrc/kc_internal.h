@@ -17,8 +17,10 @@ constexpr int kTilePos = kTileWords * 32;       // = 16384 window positions
 constexpr int kT2 = 16384;                      // second-level tile: keys per workgroup
 constexpr int kMaxA1 = 10;                      // first-level fan-out limit (bits)
 constexpr int kMaxA2 = 11;                      // second-level fan-out limit (bits)
+constexpr int kMaxPartLog2 = kMaxA1 + kMaxA2;    // partitions (log2) two levels can reach
 constexpr int kLdsMax = 163840;                 // gfx950 LDS per workgroup
 constexpr int kNst = 8;                         // statistics slots
+constexpr int kQueueBytes = kWaves * 64 * 12;   // per-wave miss queues of the count kernel
 
 enum Stat { ST_NPASS = 0, ST_ENTRIES, ST_SUM, ST_FP, ST_B1POP, ST_B2POP, ST_PASSED, ST_OVF };
 enum Err : uint32_t { ERR_OFFSETS = 1, ERR_OVF_FULL = 2, ERR_OVF_LOAD = 4, ERR_QUERY_RANGE = 8 };
@@ -38,7 +40,7 @@ struct SegDesc {
 
 struct HashCfg {
   uint64_t salt[9];   // s_0 .. s_h
-  uint32_t k, h, bl, s_log2, p_log2, nc, min_count, cap_log2;
+  uint32_t k, h, bl, s_log2, p_log2, nc, min_count, pad;
 };
 
 struct CountArgs {
@@ -48,6 +50,7 @@ struct CountArgs {
   uint32_t upb_log2;     // partitions per Bloom block (log2)
   uint32_t nbw;          // u32 words per Bloom block and level
   uint32_t l2w;          // LDS words reserved for level 2 (even)
+  uint32_t cap;          // slots per partition table (multiple of 64)
   uint32_t probe_limit;
   uint32_t ovf_log2;
   uint32_t ovf_limit;
@@ -64,6 +67,7 @@ struct CountArgs {
 
 struct QueryArgs {
   HashCfg hc;
+  uint64_t cap;            // slots per partition table
   const uint64_t* tkeys;
   const uint32_t* tcounts;
   const uint32_t* resident; // partition -> 1 if its table is in HBM
@@ -81,22 +85,22 @@ hipError_t launch_pack(const uint8_t* bases, uint64_t total, uint64_t nwords, ui
                        uint64_t* flags, hipStream_t s);
 hipError_t launch_rstart(const uint64_t* offsets, uint64_t n_reads, uint64_t total,
                          uint64_t* flags, uint32_t* err, hipStream_t s);
-hipError_t launch_hist1(const uint64_t* packed, const uint64_t* flags, uint64_t nwords,
-                        uint32_t k, uint64_t s0, uint32_t a1, uint32_t* hist, uint64_t ntiles,
-                        hipStream_t s);
 hipError_t launch_scan(const uint32_t* in, uint64_t n, uint64_t* out, uint64_t* parts,
                        hipStream_t s);
 size_t scan_parts(uint64_t n);
 hipError_t launch_bucket_off(const uint64_t* off1, uint64_t ntiles, uint32_t nb1,
                              uint64_t* bucket_off, hipStream_t s);
-hipError_t launch_scatter1(const uint64_t* packed, const uint64_t* flags, uint64_t nwords,
-                           uint32_t k, uint64_t s0, uint32_t a1, const uint64_t* off1,
-                           uint64_t ntiles, uint64_t tag, uint64_t* out, hipStream_t s);
+size_t level1_lds(uint32_t a1);
+size_t level2_lds(uint32_t a2);
+hipError_t launch_level1(const uint64_t* packed, const uint64_t* flags, uint64_t nwords,
+                         uint32_t k, uint64_t s0, uint32_t a1, uint64_t tag, uint32_t* hist,
+                         uint32_t* lstart, uint64_t ntiles, uint64_t* out, hipStream_t s);
 hipError_t launch_tiles2(const uint64_t* bucket_off, uint32_t nb1, uint32_t* tile_first,
                          hipStream_t s);
-hipError_t launch_scatter2(uint64_t* keys, const uint64_t* bucket_off, const uint32_t* tile_first,
-                           uint32_t a1, uint32_t a2, uint64_t s0, uint32_t* meta2,
-                           uint64_t grid, hipStream_t s);
+hipError_t launch_level2(const uint64_t* keys1, const uint64_t* off1, const uint32_t* lstart,
+                         uint64_t ntiles1, const uint64_t* bucket_off, const uint32_t* tile_first,
+                         uint32_t* tile_run, uint32_t a1, uint32_t a2, uint64_t s0,
+                         uint64_t* keys2, uint32_t* meta2, uint64_t grid, hipStream_t s);
 hipError_t launch_count(const CountArgs& a, uint32_t blocks, size_t lds, hipStream_t s);
 hipError_t launch_ovf_emit(const CountArgs& a, uint64_t* pstats_ovf, uint32_t blocks,
                            hipStream_t s);
@@ -104,7 +108,7 @@ hipError_t launch_reduce(const uint64_t* rows, uint64_t nrows, uint64_t* out, hi
 hipError_t launch_query(const QueryArgs& a, const uint64_t* kmers, uint64_t n, uint32_t* out,
                         hipStream_t s);
 hipError_t launch_export(const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,
-                         const uint32_t* resident, uint32_t cap_log2, uint32_t nc,
+                         const uint32_t* resident, uint32_t cap, uint32_t nc,
                          uint64_t* out_keys, uint32_t* out_counts, uint64_t out_cap,
                          uint64_t* cursor, hipStream_t s);
 hipError_t launch_debug_part(const SegDesc& sd, uint64_t n, uint32_t* part, hipStream_t s);

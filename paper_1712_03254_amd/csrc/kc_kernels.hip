@@ -180,27 +180,57 @@ __device__ __forceinline__ bool window_key(const WordCtx& c, uint32_t k, int j, 
 
 // --------------------------------------------------- first-level shuffle
 
-__global__ void __launch_bounds__(kThreads) k_hist1(const uint64_t* __restrict__ packed,
-                                                    const uint64_t* __restrict__ flags,
-                                                    uint64_t nwords, uint32_t k, uint64_t s0,
-                                                    uint32_t a1, uint32_t* __restrict__ hist,
-                                                    uint64_t ntiles) {
-  extern __shared__ uint32_t sh[];
+// One pass per tile of kTilePos window positions: extract the canonical keys,
+// counting-sort them by the top a1 bits of g in LDS, and write the sorted tile
+// to its own region of the tile-major buffer (every store is contiguous).  The
+// tile's bucket counts go out bucket-major (for the prefix sum that places
+// buckets) and its bucket starts tile-major (for the second level's gather).
+__global__ void __launch_bounds__(kThreads) k_level1(const uint64_t* __restrict__ packed,
+                                                     const uint64_t* __restrict__ flags,
+                                                     uint64_t nwords, uint32_t k, uint64_t s0,
+                                                     uint32_t a1, uint64_t tag,
+                                                     uint32_t* __restrict__ hist,
+                                                     uint32_t* __restrict__ lstart,
+                                                     uint64_t ntiles,
+                                                     uint64_t* __restrict__ out) {
+  extern __shared__ uint64_t lds64[];
   const uint32_t nb = 1u << a1;
-  for (uint32_t i = threadIdx.x; i < nb; i += kThreads) sh[i] = 0;
+  uint64_t* stage = lds64;                                  // kTilePos keys
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(stage + kTilePos);
+  uint32_t* start = cnt + nb;                               // nb + 1
+  uint32_t* scratch = start + nb + 1;                       // kWaves
+  for (uint32_t i = threadIdx.x; i < nb; i += kThreads) cnt[i] = 0;
   __syncthreads();
   const uint64_t w = (uint64_t)blockIdx.x * kTileWords + (threadIdx.x >> 1);
+  uint64_t key[16];
+  uint32_t meta[16];
+  uint32_t valid = 0;
   if (w < nwords) {
     const WordCtx c = load_word(packed, flags, w);
     const int j0 = (threadIdx.x & 1) * 16;
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) {
       uint64_t x;
-      if (window_key(c, k, j0 + jj, &x)) atomicAdd(&sh[mix64(x ^ s0) >> (64 - a1)], 1u);
+      if (window_key(c, k, j0 + jj, &x)) {
+        const uint32_t b = (uint32_t)(mix64(x ^ s0) >> (64 - a1));
+        meta[jj] = (b << 16) | atomicAdd(&cnt[b], 1u);
+        key[jj] = x | tag;
+        valid |= 1u << jj;
+      }
     }
   }
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < nb; i += kThreads) hist[(uint64_t)i * ntiles + blockIdx.x] = sh[i];
+  block_exclusive_scan(cnt, start, nb, scratch);
+  for (uint32_t i = threadIdx.x; i < nb; i += kThreads) hist[(uint64_t)i * ntiles + blockIdx.x] = cnt[i];
+  for (uint32_t i = threadIdx.x; i <= nb; i += kThreads)
+    lstart[(uint64_t)blockIdx.x * (nb + 1) + i] = start[i];
+#pragma unroll
+  for (int jj = 0; jj < 16; ++jj)
+    if (valid & (1u << jj)) stage[start[meta[jj] >> 16] + (meta[jj] & 0xFFFF)] = key[jj];
+  __syncthreads();
+  const uint32_t total = start[nb];
+  uint64_t* dst = out + (uint64_t)blockIdx.x * kTilePos;
+  for (uint32_t i = threadIdx.x; i < total; i += kThreads) dst[i] = stage[i];
 }
 
 // Exclusive scan u32 -> u64 in three phases over chunks of 8192 elements.
@@ -290,62 +320,6 @@ __global__ void k_bucket_off(const uint64_t* __restrict__ off1, uint64_t ntiles,
   if (c <= nb1) bucket_off[c] = off1[(uint64_t)c * ntiles];
 }
 
-// Re-extracts the tile's keys, sorts them by first-level bucket in LDS and
-// writes each bucket's run to its place (bucket-major, tiles in order).
-__global__ void __launch_bounds__(kThreads) k_scatter1(const uint64_t* __restrict__ packed,
-                                                       const uint64_t* __restrict__ flags,
-                                                       uint64_t nwords, uint32_t k, uint64_t s0,
-                                                       uint32_t a1,
-                                                       const uint64_t* __restrict__ off1,
-                                                       uint64_t ntiles, uint64_t tag,
-                                                       uint64_t* __restrict__ out) {
-  extern __shared__ uint64_t lds64[];
-  const uint32_t nb = 1u << a1;
-  uint64_t* stage = lds64;                         // kTilePos keys
-  uint64_t* dst = stage + kTilePos;                // nb global bases (minus local start)
-  uint32_t* cnt = reinterpret_cast<uint32_t*>(dst + nb);
-  uint32_t* start = cnt + nb;                      // nb + 1
-  uint32_t* scratch = start + nb + 1;              // kWaves
-  for (uint32_t i = threadIdx.x; i < nb; i += kThreads) cnt[i] = 0;
-  __syncthreads();
-  const uint64_t w = (uint64_t)blockIdx.x * kTileWords + (threadIdx.x >> 1);
-  uint64_t key[16];
-  uint32_t meta[16];
-  uint32_t valid = 0;
-  if (w < nwords) {
-    const WordCtx c = load_word(packed, flags, w);
-    const int j0 = (threadIdx.x & 1) * 16;
-#pragma unroll
-    for (int jj = 0; jj < 16; ++jj) {
-      uint64_t x;
-      if (window_key(c, k, j0 + jj, &x)) {
-        uint32_t b = (uint32_t)(mix64(x ^ s0) >> (64 - a1));
-        uint32_t rank = atomicAdd(&cnt[b], 1u);
-        key[jj] = x | tag;
-        meta[jj] = (b << 16) | rank;
-        valid |= 1u << jj;
-      }
-    }
-  }
-  __syncthreads();
-  block_exclusive_scan(cnt, start, nb, scratch);
-  for (uint32_t i = threadIdx.x; i < nb; i += kThreads)
-    dst[i] = off1[(uint64_t)i * ntiles + blockIdx.x] - start[i];
-#pragma unroll
-  for (int jj = 0; jj < 16; ++jj)
-    if (valid & (1u << jj)) stage[start[meta[jj] >> 16] + (meta[jj] & 0xFFFF)] = key[jj];
-  __syncthreads();
-  const uint32_t total = start[nb];
-  for (uint32_t i = threadIdx.x; i < total; i += kThreads) {
-    uint32_t lo = 0, hi = nb;  // largest b with start[b] <= i
-    while (hi - lo > 1) {
-      uint32_t mid = (lo + hi) >> 1;
-      if (start[mid] <= i) lo = mid; else hi = mid;
-    }
-    out[dst[lo] + i] = stage[i];
-  }
-}
-
 // tile_first[c] = sum over c' < c of ceil(n_c' / kT2); tile_first[nb1] = total.
 __global__ void __launch_bounds__(kThreads) k_tiles2(const uint64_t* __restrict__ bucket_off,
                                                      uint32_t nb1,
@@ -360,41 +334,123 @@ __global__ void __launch_bounds__(kThreads) k_tiles2(const uint64_t* __restrict_
   block_exclusive_scan(cnt, tile_first, nb1, scratch);
 }
 
-// In place: each workgroup loads one tile of a first-level bucket, sorts it by
-// the next a2 bits of g in LDS and writes it back; meta2 records the offsets.
-__global__ void __launch_bounds__(kThreads) k_scatter2(uint64_t* __restrict__ keys,
-                                                       const uint64_t* __restrict__ bucket_off,
-                                                       const uint32_t* __restrict__ tile_first,
-                                                       uint32_t a1, uint32_t a2, uint64_t s0,
-                                                       uint32_t* __restrict__ meta2) {
+// For every second-level tile: the first-level tile whose run of the tile's
+// bucket holds the tile's first key (largest t with off1[c][t] <= start).
+__global__ void __launch_bounds__(256) k_tile_runs(const uint64_t* __restrict__ off1,
+                                                   uint64_t ntiles1,
+                                                   const uint64_t* __restrict__ bucket_off,
+                                                   const uint32_t* __restrict__ tile_first,
+                                                   uint32_t nb1, uint32_t* __restrict__ tile_run) {
+  const uint32_t tt = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tt >= tile_first[nb1]) return;
+  uint32_t lo = 0, hi = nb1;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (tile_first[mid] <= tt) lo = mid; else hi = mid;
+  }
+  const uint32_t c = lo;
+  const uint64_t want = bucket_off[c] + (uint64_t)(tt - tile_first[c]) * kT2;
+  const uint64_t* offc = off1 + (uint64_t)c * ntiles1;
+  uint64_t a = 0, b = ntiles1;  // largest t in [0, ntiles1) with offc[t] <= want
+  while (b - a > 1) {
+    const uint64_t mid = (a + b) >> 1;
+    if (offc[mid] <= want) a = mid; else b = mid;
+  }
+  tile_run[tt] = (uint32_t)a;
+}
+
+// Second level: each workgroup takes kT2 consecutive keys of one first-level
+// bucket, gathered from that bucket's run in every first-level tile, sorts them
+// by the next a2 bits of g in LDS and writes them contiguously into the
+// bucket's region; meta2 records where each sub-bucket starts in the tile.
+__global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict__ keys1,
+                                                     const uint64_t* __restrict__ off1,
+                                                     const uint32_t* __restrict__ lstart,
+                                                     uint64_t ntiles1,
+                                                     const uint64_t* __restrict__ bucket_off,
+                                                     const uint32_t* __restrict__ tile_first,
+                                                     const uint32_t* __restrict__ tile_run,
+                                                     uint32_t a1, uint32_t a2, uint64_t s0,
+                                                     uint64_t* __restrict__ keys2,
+                                                     uint32_t* __restrict__ meta2) {
   extern __shared__ uint64_t lds64[];
   const uint32_t nb1 = 1u << a1, nb2 = 1u << a2;
   const uint32_t tt = blockIdx.x;
   if (tt >= tile_first[nb1]) return;
-  uint32_t lo = 0, hi = nb1;  // largest c with tile_first[c] <= tt
+  uint32_t lo = 0, hi = nb1;
   while (hi - lo > 1) {
-    uint32_t mid = (lo + hi) >> 1;
+    const uint32_t mid = (lo + hi) >> 1;
     if (tile_first[mid] <= tt) lo = mid; else hi = mid;
   }
   const uint32_t c = lo;
-  const uint64_t r0 = bucket_off[c] + (uint64_t)(tt - tile_first[c]) * kT2;
-  const uint64_t r1 = min(r0 + (uint64_t)kT2, bucket_off[c + 1]);
-  const uint32_t n = (uint32_t)(r1 - r0);
-  uint64_t* stage = lds64;
-  uint32_t* cnt = reinterpret_cast<uint32_t*>(stage + kT2);
-  uint32_t* start = cnt + nb2;
-  uint32_t* scratch = start + nb2 + 1;
+  const uint64_t bo = bucket_off[c];
+  const uint32_t p0 = (tt - tile_first[c]) * (uint32_t)kT2;  // bucket-relative start
+  const uint32_t n = (uint32_t)min((uint64_t)kT2, bucket_off[c + 1] - bo - p0);
+  uint64_t* stage = lds64;                                            // kT2
+  uint64_t* wsb = stage + kT2;                                        // kThreads
+  uint32_t* wrel = reinterpret_cast<uint32_t*>(wsb + kThreads);       // kThreads
+  uint32_t* cnt = wrel + kThreads;                                    // nb2
+  uint32_t* start = cnt + nb2;                                        // nb2 + 1
+  uint32_t* scratch = start + nb2 + 1;                                // kWaves + 1
   for (uint32_t i = threadIdx.x; i < nb2; i += kThreads) cnt[i] = 0;
-  __syncthreads();
+  const uint64_t* offc = off1 + (uint64_t)c * ntiles1;
+
+  // gather: windows of kThreads first-level runs, binary search per key
+  uint64_t tw = tile_run[tt];
+  uint32_t got = 0;
+  while (got < n) {
+    const uint64_t t = tw + threadIdx.x;
+    if (t < ntiles1) {
+      const uint32_t rel = (uint32_t)(offc[t] - bo);
+      wrel[threadIdx.x] = rel;
+      wsb[threadIdx.x] = t * kTilePos + lstart[t * (nb1 + 1) + c] - rel;
+    } else {
+      wrel[threadIdx.x] = 0xFFFFFFFFu;
+    }
+    if (threadIdx.x == 0) {
+      const uint64_t tn = tw + kThreads;
+      scratch[kWaves] = tn < ntiles1 ? (uint32_t)(offc[tn] - bo) : (uint32_t)(bucket_off[c + 1] - bo);
+    }
+    __syncthreads();
+    const uint32_t upto = min(n, scratch[kWaves] - p0);
+    // each thread's kT2/kThreads positions: all run searches, then all loads,
+    // then the LDS stores, so the loads are in flight together
+    constexpr int kPer = kT2 / kThreads;
+    uint64_t src[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const uint32_t p = got + threadIdx.x + q * kThreads;
+      const uint32_t P = p0 + p;
+      uint32_t r = 0;
+#pragma unroll
+      for (uint32_t step = kThreads / 2; step >= 1; step >>= 1)
+        if (wrel[r + step] <= P) r += step;
+      src[q] = wsb[r] + P;
+    }
+    uint64_t v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+      v[q] = (got + threadIdx.x + q * kThreads < upto) ? keys1[src[q]] : 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const uint32_t p = got + threadIdx.x + q * kThreads;
+      if (p < upto) stage[p] = v[q];
+    }
+    got = upto;
+    tw += kThreads;
+    __syncthreads();
+  }
+
+  // sort by sub-bucket
   uint64_t kv[kT2 / kThreads];
   uint32_t meta[kT2 / kThreads];
 #pragma unroll
   for (int r = 0; r < kT2 / kThreads; ++r) {
-    uint32_t i = threadIdx.x + r * kThreads;
+    const uint32_t i = threadIdx.x + r * kThreads;
     if (i < n) {
-      kv[r] = keys[r0 + i];
-      uint64_t g = mix64((kv[r] & kKeyMask) ^ s0);
-      uint32_t sub = (uint32_t)((g >> (64 - a1 - a2)) & (nb2 - 1));
+      kv[r] = stage[i];
+      const uint64_t g = mix64((kv[r] & kKeyMask) ^ s0);
+      const uint32_t sub = (uint32_t)((g >> (64 - a1 - a2)) & (nb2 - 1));
       meta[r] = (sub << 16) | atomicAdd(&cnt[sub], 1u);
     }
   }
@@ -402,69 +458,129 @@ __global__ void __launch_bounds__(kThreads) k_scatter2(uint64_t* __restrict__ ke
   block_exclusive_scan(cnt, start, nb2, scratch);
 #pragma unroll
   for (int r = 0; r < kT2 / kThreads; ++r) {
-    uint32_t i = threadIdx.x + r * kThreads;
+    const uint32_t i = threadIdx.x + r * kThreads;
     if (i < n) stage[start[meta[r] >> 16] + (meta[r] & 0xFFFF)] = kv[r];
   }
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < n; i += kThreads) keys[r0 + i] = stage[i];
+  uint64_t* dst = keys2 + bo + p0;
+  for (uint32_t i = threadIdx.x; i < n; i += kThreads) dst[i] = stage[i];
   for (uint32_t s = threadIdx.x; s <= nb2; s += kThreads)
     meta2[(uint64_t)tt * (nb2 + 1) + s] = start[s];
 }
 
 // ----------------------------------------- per-block Bloom + exact count
 
-// Calls fn(key) for every stored occurrence of partition u, across segments.
-// The whole block must call it (ranges are split between waves / threads).
-template <typename F>
-__device__ __forceinline__ void for_partition(const CountArgs& A, uint32_t u, F&& fn) {
+// Calls fn(kv, vmask, nbat) for the stored occurrences of partitions
+// [u_lo, u_hi), across segments: kv[b] holds one key per lane for b < nbat,
+// valid where bit b of the lane's vmask is set (lanes past the end of a run
+// are not).  Every lane of a wave reaches every call.  The whole block must
+// call it.  The range's run inside a second-level tile is contiguous.  Wave w
+// takes tiles g0 + w + kWaves*j (j = lane), reads their run bounds once into
+// its lanes, then walks the runs in chunks of 64 keys with wave-uniform
+// bookkeeping.  Loads of the next B chunks are issued before the current B
+// are handed to fn, so one batch is always in flight behind the one in use.
+template <int B>
+struct RunBatch {
+  uint64_t kv[B];
+  uint32_t vmask;  // bit b: kv[b] holds a key for this lane
+  uint32_t n;      // chunks in the batch (wave-uniform)
+};
+
+template <int B, typename F>
+__device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint32_t u_hi,
+                                         F&& fn) {
   for (uint32_t s = 0; s < A.nsegs; ++s) {
     const SegDesc sd = A.segs[s];
-    const uint32_t c = u >> sd.a2;
-    if (sd.a2 == 0) {
-      const uint64_t lo = sd.bucket_off[c], hi = sd.bucket_off[c + 1];
-      for (uint64_t i = lo + threadIdx.x; i < hi; i += kThreads) fn(sd.keys[i]);
-    } else {
-      const uint32_t nb2 = 1u << sd.a2;
-      const uint32_t sub = u & (nb2 - 1);
-      const uint32_t t0 = sd.tile_first[c], t1 = sd.tile_first[c + 1];
-      const uint64_t bo = sd.bucket_off[c];
-      for (uint32_t tt = t0 + wave_id(); tt < t1; tt += kWaves) {
-        const uint64_t base = bo + (uint64_t)(tt - t0) * kT2;
-        const uint32_t* m = sd.meta2 + (uint64_t)tt * (nb2 + 1) + sub;
-        const uint32_t m0 = m[0], m1 = m[1];
-        for (uint32_t i = m0 + lane_id(); i < m1; i += 64) fn(sd.keys[base + i]);
+    const uint32_t nb2 = 1u << sd.a2;
+    const uint32_t c_lo = u_lo >> sd.a2, c_hi = (u_hi - 1) >> sd.a2;
+    for (uint32_t c = c_lo; c <= c_hi; ++c) {
+      const uint32_t s_lo = max(u_lo, c << sd.a2) - (c << sd.a2);
+      const uint32_t s_hi = min(u_hi, (c + 1) << sd.a2) - (c << sd.a2);
+      const uint32_t t0 = sd.tile_first[c], nt = sd.tile_first[c + 1] - t0;
+      const uint64_t* keys = sd.keys + sd.bucket_off[c];
+      for (uint32_t g0 = 0; g0 < nt; g0 += kWaves * 64) {
+        const uint32_t tw = g0 + wave_id();  // this wave's first tile (bucket-relative)
+        if (tw >= nt) break;
+        const uint32_t nj = min(64u, (nt - tw + kWaves - 1) / kWaves);
+        const uint32_t ti = tw + kWaves * lane_id();
+        uint32_t mm0 = 0, mm1 = 0;
+        if (lane_id() < nj) {
+          const uint32_t* m = sd.meta2 + (uint64_t)(t0 + ti) * (nb2 + 1);
+          mm0 = m[s_lo];
+          mm1 = m[s_hi];
+        }
+        uint32_t j = 0;
+        uint32_t i = __builtin_amdgcn_readlane(mm0, 0), e = __builtin_amdgcn_readlane(mm1, 0);
+        // next B chunks of the walk (wave-uniform), their loads issued
+        auto next = [&](RunBatch<B>& r) {
+          r.n = 0;
+          r.vmask = 0;
+#pragma unroll
+          for (int b = 0; b < B; ++b) {
+            while (j < nj && i >= e) {
+              ++j;
+              if (j < nj) {
+                i = __builtin_amdgcn_readlane(mm0, j);
+                e = __builtin_amdgcn_readlane(mm1, j);
+              }
+            }
+            r.kv[b] = 0;
+            if (j < nj) {
+              const uint32_t idx = i + lane_id();
+              if (idx < e) {
+                r.kv[b] = keys[(uint64_t)(tw + kWaves * j) * kT2 + idx];
+                r.vmask |= 1u << b;
+              }
+              i += 64;
+              r.n = b + 1;
+            }
+          }
+        };
+        RunBatch<B> cur;
+        next(cur);
+        while (cur.n) {
+          RunBatch<B> ahead;
+          next(ahead);
+          fn(cur.kv, cur.vmask, cur.n);
+          cur = ahead;
+        }
       }
     }
   }
 }
 
-// Distinct in-block bit positions of S(x): pos[i] valid where mask bit i set.
-__device__ __forceinline__ uint32_t bloom_positions(const HashCfg& hc, uint64_t x,
-                                                    uint32_t pos[8]) {
-  uint32_t mask = 0;
+// In-block bit positions of S(x), i = 1..H; dup[i] marks a position equal to
+// an earlier one (S(x) is a set: one hit per occurrence per distinct bit).
+template <int H>
+__device__ __forceinline__ void bloom_positions(const HashCfg& hc, uint64_t x, uint32_t pos[H],
+                                                bool dup[H]) {
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    if (i < (int)hc.h) {
-      pos[i] = (uint32_t)(mix64(x ^ hc.salt[i + 1]) >> (64 - hc.bl));
-      bool dup = false;
+  for (int i = 0; i < H; ++i) {
+    pos[i] = (uint32_t)(mix64(x ^ hc.salt[i + 1]) >> (64 - hc.bl));
+    bool d = false;
 #pragma unroll
-      for (int j = 0; j < i; ++j) dup |= ((mask >> j) & 1u) && pos[j] == pos[i];
-      if (!dup) mask |= 1u << i;
-    }
+    for (int j = 0; j < i; ++j) d |= pos[j] == pos[i];
+    dup[i] = d;
   }
-  return mask;
 }
 
+// Level-2 test of x against the block's level-2 bits held in LDS.
+template <int H>
 __device__ __forceinline__ bool bloom_screen(const HashCfg& hc, const uint32_t* L2, uint64_t x) {
+  uint32_t w[H], p[H];
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    p[i] = (uint32_t)(mix64(x ^ hc.salt[i + 1]) >> (64 - hc.bl));
+    w[i] = L2[p[i] >> 5];
+  }
   bool pass = true;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    if (i < (int)hc.h) {
-      uint32_t p = (uint32_t)(mix64(x ^ hc.salt[i + 1]) >> (64 - hc.bl));
-      pass &= ((L2[p >> 5] >> (p & 31)) & 1u) != 0;
-    }
-  }
+  for (int i = 0; i < H; ++i) pass &= ((w[i] >> (p[i] & 31)) & 1u) != 0;
   return pass;
+}
+
+__device__ __forceinline__ uint32_t home_slot(uint64_t th, uint32_t cap) {
+  return (uint32_t)(((th >> 32) * (uint64_t)cap) >> 32);
 }
 
 __device__ void overflow_add(const CountArgs& A, uint64_t x, uint32_t tag, uint64_t th) {
@@ -477,7 +593,7 @@ __device__ void overflow_add(const CountArgs& A, uint64_t x, uint32_t tag, uint6
       cur = atomicCAS(reinterpret_cast<unsigned long long*>(&A.okeys[slot]),
                       (unsigned long long)kEmpty, (unsigned long long)x);
       if (cur == kEmpty) {
-        uint32_t used = atomicAdd(A.ovf_used, 1u) + 1;
+        const uint32_t used = atomicAdd(A.ovf_used, 1u) + 1;
         if (used > A.ovf_limit) atomicOr(A.err, (uint32_t)ERR_OVF_LOAD);
         cur = x;
       }
@@ -491,40 +607,67 @@ __device__ void overflow_add(const CountArgs& A, uint64_t x, uint32_t tag, uint6
   atomicOr(A.err, (uint32_t)ERR_OVF_FULL);
 }
 
+// One workgroup per Bloom block.  Pass 1 builds the block's two Bloom levels
+// in LDS from every occurrence of its partitions (level 1 records a first hit
+// of a bit, level 2 a second) and writes them out.  Pass 2, per partition:
+// every occurrence probes an LDS open-addressing table; hits count at once,
+// misses (keys not yet in the table) queue per wave and are screened against
+// level 2 (kept in LDS) densely, 64 at a time; passing keys are inserted (CAS on the key,
+// add on the count), failing ones dropped.  A key whose probe sequence fills
+// up goes, with all its occurrences, to the device overflow table.  The table
+// is then written to HBM with counts below min_count zeroed.
+template <int H>
 __global__ void __launch_bounds__(kThreads) k_count(const CountArgs A) {
   extern __shared__ uint32_t lds[];
   const HashCfg& hc = A.hc;
   const uint32_t blk = blockIdx.x;
   const uint32_t nbw = A.nbw;
-  uint32_t* L2 = lds;
-  uint32_t* L1 = lds + A.l2w;
-  uint64_t* tk = reinterpret_cast<uint64_t*>(lds + A.l2w);
-  const uint32_t cap = 1u << hc.cap_log2;
-  uint32_t* tc = reinterpret_cast<uint32_t*>(tk + cap);
+  const uint32_t cap = A.cap;
   const uint32_t nc = hc.nc;
   const uint32_t u0 = blk << A.upb_log2, nu = 1u << A.upb_log2;
+  const uint64_t bit0 = (uint64_t)blk << hc.bl;
+  uint32_t* L2 = lds;
+  uint32_t* L1 = lds + A.l2w;
+  uint64_t* tk = reinterpret_cast<uint64_t*>(lds + A.l2w);  // pass 2 table overlays level 1
+  uint32_t* tc = reinterpret_cast<uint32_t*>(tk + cap);
+  uint64_t* qk = reinterpret_cast<uint64_t*>(tc + (size_t)cap * nc) + wave_id() * 64;
+  uint32_t* qs = reinterpret_cast<uint32_t*>(reinterpret_cast<uint64_t*>(tc + (size_t)cap * nc) +
+                                             kWaves * 64) + wave_id() * 64;
 
   uint64_t st[kNst];
 #pragma unroll
   for (int i = 0; i < kNst; ++i) st[i] = 0;
 
-  // Bloom levels of this block: every occurrence hits each distinct bit of
-  // S(x) once; level 1 records a first hit, level 2 a second one.
+  // ---- pass 1: Bloom levels of this block
   for (uint32_t i = threadIdx.x; i < A.l2w + nbw; i += kThreads) lds[i] = 0;
   __syncthreads();
-  for (uint32_t uu = 0; uu < nu; ++uu) {
-    for_partition(A, u0 + uu, [&](uint64_t key) {
-      uint32_t pos[8];
-      const uint32_t m = bloom_positions(hc, key & kKeyMask, pos);
+  for_runs<8>(A, u0, u0 + nu, [&](const uint64_t (&kv)[8], uint32_t vmask, uint32_t nbat) {
+    constexpr int G = 2;  // keys whose level-1 updates are in flight together
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        if ((m >> i) & 1u) {
-          const uint32_t bit = 1u << (pos[i] & 31);
-          if (atomicOr(&L1[pos[i] >> 5], bit) & bit) atomicOr(&L2[pos[i] >> 5], bit);
-        }
+    for (int g = 0; g < 8 / G; ++g) {
+      if (g * G >= (int)nbat) break;
+      uint32_t pos[G][H], old[G][H];
+      bool dup[G][H];
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        bloom_positions<H>(hc, kv[g * G + q] & kKeyMask, pos[q], dup[q]);
+#pragma unroll
+        for (int i = 0; i < H; ++i) dup[q][i] |= !((vmask >> (g * G + q)) & 1u);
       }
-    });
-  }
+#pragma unroll
+      for (int q = 0; q < G; ++q)
+#pragma unroll
+        for (int i = 0; i < H; ++i)
+          old[q][i] = dup[q][i] ? 0u : atomicOr(&L1[pos[q][i] >> 5], 1u << (pos[q][i] & 31));
+#pragma unroll
+      for (int q = 0; q < G; ++q)
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+          const uint32_t bit = 1u << (pos[q][i] & 31);
+          if (old[q][i] & bit) atomicOr(&L2[pos[q][i] >> 5], bit);
+        }
+    }
+  });
   __syncthreads();
   if (hc.bl >= 5) {
     for (uint32_t i = threadIdx.x; i < nbw; i += kThreads) {
@@ -535,7 +678,6 @@ __global__ void __launch_bounds__(kThreads) k_count(const CountArgs A) {
       st[ST_B2POP] += __popc(b);
     }
   } else if (threadIdx.x == 0) {
-    const uint64_t bit0 = (uint64_t)blk << hc.bl;
     const uint32_t msk = (1u << (1u << hc.bl)) - 1u;
     const uint32_t a = L1[0] & msk, b = L2[0] & msk;
     atomicOr(&A.b1[bit0 >> 5], a << (bit0 & 31));
@@ -545,41 +687,118 @@ __global__ void __launch_bounds__(kThreads) k_count(const CountArgs A) {
   }
   __syncthreads();  // level 1 is dead from here: its LDS holds the count table
 
-  for (uint32_t uu = 0; uu < nu; ++uu) {
-    const uint32_t u = u0 + uu;
-    for (uint32_t i = threadIdx.x; i < cap; i += kThreads) tk[i] = kEmpty;
-    for (uint32_t i = threadIdx.x; i < cap * nc; i += kThreads) tc[i] = 0;
-    __syncthreads();
-    for_partition(A, u, [&](uint64_t key) {
-      const uint64_t x = key & kKeyMask;
-      const uint32_t tag = (uint32_t)(key >> 62);
+  // ---- pass 2: screen and exact count, one partition at a time
+  const uint32_t limit = A.probe_limit;
+  auto drain = [&](uint32_t n) {
+    const bool have = lane_id() < n;
+    uint64_t key = 0;
+    uint32_t at = 0;
+    if (have) {
+      key = qk[lane_id()];
+      at = qs[lane_id()];
+    }
+    const uint64_t x = key & kKeyMask;
+    const uint32_t tag = (uint32_t)(key >> 62);
+    if (have && bloom_screen<H>(hc, L2, x)) {
+      uint32_t slot = at & 0xFFFF, probes = at >> 16;
       const uint64_t th = (x ^ hc.salt[0]) * kTableMul;
-      uint32_t slot = (uint32_t)(th >> (64 - hc.cap_log2));
-      int screened = 0;  // 0 unknown, 1 passes, -1 fails
-      for (uint32_t probe = 0; probe < A.probe_limit; ++probe) {
-        uint64_t cur = __hip_atomic_load(&tk[slot], __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+      for (;;) {
+        if (probes >= limit) {
+          st[ST_OVF] += 1;
+          overflow_add(A, x, tag, mix64(th));
+          break;
+        }
+        uint64_t cur = __hip_atomic_load(&tk[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (cur == kEmpty) {
-          if (!screened) screened = bloom_screen(hc, L2, x) ? 1 : -1;
-          if (screened < 0) return;  // dropped by the level-2 screen
           cur = atomicCAS(reinterpret_cast<unsigned long long*>(&tk[slot]),
                           (unsigned long long)kEmpty, (unsigned long long)x);
           if (cur == kEmpty) cur = x;
         }
         if (cur == x) {
           atomicAdd(&tc[slot * nc + tag], 1u);
-          return;
+          break;
         }
-        slot = (slot + 1) & (cap - 1);
+        slot = slot + 1 == cap ? 0 : slot + 1;
+        ++probes;
       }
-      if (!screened) screened = bloom_screen(hc, L2, x) ? 1 : -1;
-      if (screened > 0) {
-        st[ST_OVF] += 1;
-        overflow_add(A, x, tag, mix64(th));  // re-mixed: the LDS slot used th's top bits
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  };
+
+  for (uint32_t uu = 0; uu < nu; ++uu) {
+    const uint32_t u = u0 + uu;
+    for (uint32_t i = threadIdx.x; i < cap; i += kThreads) tk[i] = kEmpty;
+    for (uint32_t i = threadIdx.x; i < cap * nc; i += kThreads) tc[i] = 0;
+    __syncthreads();
+    uint32_t qn = 0;  // wave-uniform queue length
+    constexpr int B2 = 4;  // chunks per batch in pass 2 (register budget)
+    for_runs<B2>(A, u, u + 1, [&](const uint64_t (&kv)[B2], uint32_t vmask, uint32_t nbat) {
+      // first probe of every key of the batch, issued before any is resolved
+      uint64_t cur[B2];
+      uint32_t slot0[B2];
+#pragma unroll
+      for (int b = 0; b < B2; ++b) {
+        const uint64_t x = kv[b] & kKeyMask;
+        slot0[b] = home_slot((x ^ hc.salt[0]) * kTableMul, cap);
+        cur[b] = ((vmask >> b) & 1u) ? __hip_atomic_load(&tk[slot0[b]], __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_WORKGROUP)
+                                     : 0;
+      }
+#pragma unroll
+      for (int b = 0; b < B2; ++b) {
+        if (b >= (int)nbat) break;
+        const uint64_t key = kv[b];
+        const uint64_t x = key & kKeyMask;
+        const uint32_t tag = (uint32_t)(key >> 62);
+        bool miss = false;
+        uint32_t at = 0;
+        if ((vmask >> b) & 1u) {
+          uint32_t slot = slot0[b], probes = 0;
+          uint64_t c = cur[b];
+          for (;;) {
+            if (c == x) {
+              atomicAdd(&tc[slot * nc + tag], 1u);
+              break;
+            }
+            if (c == kEmpty) {
+              miss = true;
+              break;
+            }
+            slot = slot + 1 == cap ? 0 : slot + 1;
+            if (++probes >= limit) {
+              miss = true;
+              break;
+            }
+            c = __hip_atomic_load(&tk[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+          at = slot | (probes << 16);
+        }
+        const uint64_t mb = __ballot(miss);
+        const uint32_t nm = (uint32_t)__popcll(mb);
+        if (!nm) continue;
+        const uint32_t rank = (uint32_t)__popcll(mb & ((1ull << lane_id()) - 1));
+        const uint32_t room = 64 - qn;
+        if (miss && rank < room) {
+          qk[qn + rank] = key;
+          qs[qn + rank] = at;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (nm >= room) {
+          drain(64);
+          if (miss && rank >= room) {
+            qk[rank - room] = key;
+            qs[rank - room] = at;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          qn = nm - room;
+        } else {
+          qn += nm;
+        }
       }
     });
+    if (qn) drain(qn);
     __syncthreads();
-    const uint64_t base = (uint64_t)u << hc.cap_log2;
+    const uint64_t base = (uint64_t)u * cap;
     for (uint32_t i = threadIdx.x; i < cap; i += kThreads) {
       const uint64_t key = tk[i];
       uint32_t c0 = tc[i * nc], c1 = nc > 1 ? tc[i * nc + 1] : 0;
@@ -611,9 +830,9 @@ __global__ void __launch_bounds__(kThreads) k_count(const CountArgs A) {
   }
   __syncthreads();
   if (threadIdx.x < kNst) {
-    uint64_t s = 0;
-    for (int w = 0; w < kWaves; ++w) s += red[w * kNst + threadIdx.x];
-    A.pstats[(uint64_t)blk * kNst + threadIdx.x] = s;
+    uint64_t sum = 0;
+    for (int w = 0; w < kWaves; ++w) sum += red[w * kNst + threadIdx.x];
+    A.pstats[(uint64_t)blk * kNst + threadIdx.x] = sum;
   }
 }
 
@@ -674,18 +893,18 @@ __global__ void __launch_bounds__(kThreads) k_reduce(const uint64_t* __restrict_
 
 // ----------------------------------------------------------------- query
 
-__device__ __forceinline__ bool probe_table(const uint64_t* keys, uint64_t base, uint32_t log2n,
-                                            uint64_t x, uint64_t th, uint64_t* at) {
-  const uint64_t mask = (1ull << log2n) - 1;
-  uint64_t slot = th >> (64 - log2n);
-  for (uint64_t p = 0; p <= mask; ++p) {
+// Linear probing in a table of n slots starting at `slot`; true with the
+// slot index when x is present.
+__device__ __forceinline__ bool probe_table(const uint64_t* keys, uint64_t base, uint64_t n,
+                                            uint64_t slot, uint64_t x, uint64_t* at) {
+  for (uint64_t p = 0; p < n; ++p) {
     const uint64_t cur = keys[base + slot];
     if (cur == x) {
       *at = base + slot;
       return true;
     }
     if (cur == kEmpty) return false;
-    slot = (slot + 1) & mask;
+    slot = slot + 1 == n ? 0 : slot + 1;
   }
   return false;
 }
@@ -710,10 +929,12 @@ __global__ void __launch_bounds__(256) k_query(const QueryArgs A, const uint64_t
       A.host_rows[at] = (uint32_t)i;
     } else {
       uint64_t at;
-      if (probe_table(A.tkeys, u << hc.cap_log2, hc.cap_log2, x, th, &at)) {
+      const uint64_t th2 = mix64(th);
+      if (probe_table(A.tkeys, u * A.cap, A.cap, home_slot(th, A.cap), x, &at)) {
         c0 = A.tcounts[at * nc];
         if (nc > 1) c1 = A.tcounts[at * nc + 1];
-      } else if (*A.ovf_used && probe_table(A.okeys, 0, A.ovf_log2, x, mix64(th), &at)) {
+      } else if (*A.ovf_used && probe_table(A.okeys, 0, 1ull << A.ovf_log2,
+                                            th2 >> (64 - A.ovf_log2), x, &at)) {
         c0 = A.ocounts[at * nc];
         if (nc > 1) c1 = A.ocounts[at * nc + 1];
       }
@@ -728,7 +949,7 @@ __global__ void __launch_bounds__(256) k_export(const uint64_t* __restrict__ tke
                                                 const uint32_t* __restrict__ tcounts,
                                                 uint64_t nslots,
                                                 const uint32_t* __restrict__ resident,
-                                                uint32_t cap_log2, uint32_t nc,
+                                                uint32_t cap, uint32_t nc,
                                                 uint64_t* __restrict__ out_keys,
                                                 uint32_t* __restrict__ out_counts,
                                                 uint64_t out_cap,
@@ -737,7 +958,7 @@ __global__ void __launch_bounds__(256) k_export(const uint64_t* __restrict__ tke
   bool take = false;
   uint64_t key = 0;
   uint32_t c0 = 0, c1 = 0;
-  if (i < nslots && (resident == nullptr || resident[i >> cap_log2])) {
+  if (i < nslots && (resident == nullptr || resident[i / cap])) {
     key = tkeys[i];
     c0 = tcounts[i * nc];
     c1 = nc > 1 ? tcounts[i * nc + 1] : 0;
@@ -841,14 +1062,6 @@ hipError_t launch_rstart(const uint64_t* offsets, uint64_t n_reads, uint64_t tot
   return hipGetLastError();
 }
 
-hipError_t launch_hist1(const uint64_t* packed, const uint64_t* flags, uint64_t nwords,
-                        uint32_t k, uint64_t s0, uint32_t a1, uint32_t* hist, uint64_t ntiles,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_hist1, dim3((uint32_t)ntiles), dim3(kThreads), (1u << a1) * 4, s, packed,
-                     flags, nwords, k, s0, a1, hist, ntiles);
-  return hipGetLastError();
-}
-
 size_t scan_parts(uint64_t n) { return (n + kScanChunk - 1) / kScanChunk + 1; }
 
 hipError_t launch_scan(const uint32_t* in, uint64_t n, uint64_t* out, uint64_t* parts,
@@ -871,25 +1084,27 @@ hipError_t launch_bucket_off(const uint64_t* off1, uint64_t ntiles, uint32_t nb1
   return hipGetLastError();
 }
 
-static size_t scatter1_lds(uint32_t a1) {
+size_t level1_lds(uint32_t a1) {
   const uint32_t nb = 1u << a1;
-  return (size_t)kTilePos * 8 + (size_t)nb * 8 + (size_t)nb * 4 + (size_t)(nb + 1) * 4 + kWaves * 4;
+  return (size_t)kTilePos * 8 + (size_t)nb * 4 + (size_t)(nb + 1) * 4 + kWaves * 4;
 }
 
-static size_t scatter2_lds(uint32_t a2) {
+size_t level2_lds(uint32_t a2) {
   const uint32_t nb = 1u << a2;
-  return (size_t)kT2 * 8 + (size_t)nb * 4 + (size_t)(nb + 1) * 4 + kWaves * 4;
+  return (size_t)kT2 * 8 + (size_t)kThreads * 12 + (size_t)nb * 4 + (size_t)(nb + 1) * 4 +
+         (kWaves + 1) * 4;
 }
 
-hipError_t launch_scatter1(const uint64_t* packed, const uint64_t* flags, uint64_t nwords,
-                           uint32_t k, uint64_t s0, uint32_t a1, const uint64_t* off1,
-                           uint64_t ntiles, uint64_t tag, uint64_t* out, hipStream_t s) {
-  const size_t lds = scatter1_lds(a1);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_scatter1),
+hipError_t launch_level1(const uint64_t* packed, const uint64_t* flags, uint64_t nwords,
+                         uint32_t k, uint64_t s0, uint32_t a1, uint64_t tag, uint32_t* hist,
+                         uint32_t* lstart, uint64_t ntiles, uint64_t* out, hipStream_t s) {
+  if (!ntiles) return hipSuccess;
+  const size_t lds = level1_lds(a1);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_level1),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scatter1, dim3((uint32_t)ntiles), dim3(kThreads), lds, s, packed, flags,
-                     nwords, k, s0, a1, off1, ntiles, tag, out);
+  hipLaunchKernelGGL(k_level1, dim3((uint32_t)ntiles), dim3(kThreads), lds, s, packed, flags,
+                     nwords, k, s0, a1, tag, hist, lstart, ntiles, out);
   return hipGetLastError();
 }
 
@@ -899,24 +1114,43 @@ hipError_t launch_tiles2(const uint64_t* bucket_off, uint32_t nb1, uint32_t* til
   return hipGetLastError();
 }
 
-hipError_t launch_scatter2(uint64_t* keys, const uint64_t* bucket_off, const uint32_t* tile_first,
-                           uint32_t a1, uint32_t a2, uint64_t s0, uint32_t* meta2, uint64_t grid,
-                           hipStream_t s) {
-  const size_t lds = scatter2_lds(a2);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_scatter2),
+hipError_t launch_level2(const uint64_t* keys1, const uint64_t* off1, const uint32_t* lstart,
+                         uint64_t ntiles1, const uint64_t* bucket_off, const uint32_t* tile_first,
+                         uint32_t* tile_run, uint32_t a1, uint32_t a2, uint64_t s0,
+                         uint64_t* keys2, uint32_t* meta2, uint64_t grid, hipStream_t s) {
+  if (!grid) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_runs, dim3(div_up(grid, 256)), dim3(256), 0, s, off1, ntiles1,
+                     bucket_off, tile_first, 1u << a1, tile_run);
+  const size_t lds = level2_lds(a2);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_level2),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scatter2, dim3((uint32_t)grid), dim3(kThreads), lds, s, keys, bucket_off,
-                     tile_first, a1, a2, s0, meta2);
+  hipLaunchKernelGGL(k_level2, dim3((uint32_t)grid), dim3(kThreads), lds, s, keys1, off1, lstart,
+                     ntiles1, bucket_off, tile_first, tile_run, a1, a2, s0, keys2, meta2);
+  return hipGetLastError();
+}
+
+template <int H>
+hipError_t launch_count_h(const CountArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_count<H>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_count<H>, dim3(blocks), dim3(kThreads), lds, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_count(const CountArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_count),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_count, dim3(blocks), dim3(kThreads), lds, s, a);
-  return hipGetLastError();
+  switch (a.hc.h) {
+    case 1: return launch_count_h<1>(a, blocks, lds, s);
+    case 2: return launch_count_h<2>(a, blocks, lds, s);
+    case 3: return launch_count_h<3>(a, blocks, lds, s);
+    case 4: return launch_count_h<4>(a, blocks, lds, s);
+    case 5: return launch_count_h<5>(a, blocks, lds, s);
+    case 6: return launch_count_h<6>(a, blocks, lds, s);
+    case 7: return launch_count_h<7>(a, blocks, lds, s);
+    case 8: return launch_count_h<8>(a, blocks, lds, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_ovf_emit(const CountArgs& a, uint64_t* pstats_ovf, uint32_t blocks,
@@ -938,12 +1172,12 @@ hipError_t launch_query(const QueryArgs& a, const uint64_t* kmers, uint64_t n, u
 }
 
 hipError_t launch_export(const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,
-                         const uint32_t* resident, uint32_t cap_log2, uint32_t nc,
+                         const uint32_t* resident, uint32_t cap, uint32_t nc,
                          uint64_t* out_keys, uint32_t* out_counts, uint64_t out_cap,
                          uint64_t* cursor, hipStream_t s) {
   if (!nslots) return hipSuccess;
   hipLaunchKernelGGL(k_export, dim3(div_up(nslots, 256)), dim3(256), 0, s, tkeys, tcounts, nslots,
-                     resident, cap_log2, nc, out_keys, out_counts, out_cap, cursor);
+                     resident, cap, nc, out_keys, out_counts, out_cap, cursor);
   return hipGetLastError();
 }
 

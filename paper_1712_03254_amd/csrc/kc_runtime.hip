@@ -94,7 +94,7 @@ struct kc_ctx {
 
   // derived layout
   HashCfg hc{};
-  uint32_t s_log2 = 0, p_log2 = 0, cap_log2 = 0, a1 = 0, a2 = 0, upb_log2 = 0;
+  uint32_t s_log2 = 0, p_log2 = 0, cap = 0, a1 = 0, a2 = 0, upb_log2 = 0;
   uint32_t nbw = 1, l2w = 2, slot_bytes = 12;
   size_t count_lds = 0;
   uint64_t bloom_words64 = 1;
@@ -102,7 +102,7 @@ struct kc_ctx {
   DevBuf b1, b2;
   DevBuf dstat;   // kNst u64 stats, then ovf stats scratch
   DevBuf derr;    // u32 error flags
-  DevBuf packed, flags, hist1, off1, parts;
+  DevBuf packed, flags, hist1, lstart1, off1, parts, keys1, tile_run;
   DevBuf segdesc;
   DevBuf tkeys, tcounts, resident, pstats, pstats_ovf;
   DevBuf okeys, ocounts, ovf_used;
@@ -221,9 +221,9 @@ kc_status validate(const kc_config* cfg, std::string* why) {
     return bad("bloom_block_log2 must be in 1..19");
   if (cfg->bloom_bits_log2 < cfg->bloom_block_log2 || cfg->bloom_bits_log2 > 40)
     return bad("bloom_bits_log2 must be in bloom_block_log2..40");
-  if (cfg->bloom_bits_log2 - cfg->bloom_block_log2 > 24)
-    return bad("more than 2^24 Bloom blocks (raise bloom_block_log2)");
-  if (cfg->partitions_log2 > 24) return bad("partitions_log2 must be <= 24");
+  if (cfg->bloom_bits_log2 - cfg->bloom_block_log2 > kMaxPartLog2)
+    return bad("more than 2^21 Bloom blocks (raise bloom_block_log2)");
+  if (cfg->partitions_log2 > kMaxPartLog2) return bad("partitions_log2 must be <= 21");
   if (cfg->flags != 0) return bad("flags must be 0");
   if (cfg->scatter_bits > kMaxA1) {
     snprintf(buf, sizeof buf, "scatter_bits must be <= %d", kMaxA1);
@@ -243,38 +243,37 @@ kc_status derive(kc_ctx* c) {
   hc.nc = f.n_counters;
   hc.min_count = f.min_count;
   c->s_log2 = f.bloom_bits_log2 - f.bloom_block_log2;
-  c->p_log2 = std::max<uint32_t>(std::max<uint32_t>(f.partitions_log2, c->s_log2), 1);
-  if (c->p_log2 > 24) return fail(c, KC_ERR_INVALID_ARG, "more than 2^24 partitions");
+  c->p_log2 = std::max<uint32_t>(std::max<uint32_t>(f.partitions_log2, c->s_log2), 2);
+  if (c->p_log2 > (uint32_t)kMaxPartLog2)
+    return fail(c, KC_ERR_INVALID_ARG, "more than 2^21 partitions");
   c->upb_log2 = c->p_log2 - c->s_log2;
   hc.s_log2 = c->s_log2;
   hc.p_log2 = c->p_log2;
   c->nbw = f.bloom_block_log2 >= 5 ? (1u << (f.bloom_block_log2 - 5)) : 1u;
   c->l2w = (c->nbw + 1) & ~1u;
   c->slot_bytes = 8 + 4 * f.n_counters;
-  const size_t table_room = (size_t)kLdsMax - 4 * (size_t)c->l2w;
-  uint32_t cap_max = 0;
-  while ((((size_t)1) << (cap_max + 1)) * c->slot_bytes <= table_room) ++cap_max;
-  if (cap_max < 4) return fail(c, KC_ERR_INVALID_ARG, "Bloom block leaves no LDS for a table");
-  if (f.table_log2) {
-    if (f.table_log2 > cap_max || f.table_log2 < 4)
+  // pass 2 of the count kernel: table (cap slots) + per-wave miss queues in LDS
+  const uint32_t cap_max =
+      (uint32_t)(((size_t)kLdsMax - 4 * (size_t)c->l2w - kQueueBytes) / c->slot_bytes / 64 * 64);
+  if (cap_max < 64) return fail(c, KC_ERR_INVALID_ARG, "Bloom block leaves no LDS for a table");
+  if (f.table_slots) {
+    const uint32_t want = f.table_slots / 64 * 64;
+    if (want < 64 || want > cap_max)
       return fail(c, KC_ERR_INVALID_ARG,
-                  "table_log2 must be in 4.." + std::to_string(cap_max) + " for this Bloom block");
-    c->cap_log2 = f.table_log2;
+                  "table_slots must be in 64.." + std::to_string(cap_max));
+    c->cap = want;
   } else {
-    c->cap_log2 = cap_max;
+    c->cap = cap_max;
   }
-  hc.cap_log2 = c->cap_log2;
-  const size_t table_bytes = ((size_t)1 << c->cap_log2) * c->slot_bytes;
   c->count_lds = 4 * (size_t)c->l2w +
-                 std::max(std::max((size_t)4 * c->nbw, table_bytes), (size_t)kWaves * kNst * 8);
+                 std::max(std::max((size_t)4 * c->nbw, (size_t)c->cap * c->slot_bytes + kQueueBytes),
+                          (size_t)kWaves * kNst * 8);
   if (c->count_lds > (size_t)kLdsMax) return fail(c, KC_ERR_INVALID_ARG, "LDS layout too large");
-  if (f.scatter_bits) {
-    c->a1 = std::min<uint32_t>(f.scatter_bits, c->p_log2);
-  } else {
-    c->a1 = c->p_log2 <= 8 ? c->p_log2 : c->p_log2 / 2;
-  }
+  // two shuffle levels: a1 bits in the first, the rest in the second
+  c->a1 = f.scatter_bits ? std::min<uint32_t>(f.scatter_bits, c->p_log2 - 1)
+                         : std::min<uint32_t>((c->p_log2 + 1) / 2, kMaxA1);
   c->a2 = c->p_log2 - c->a1;
-  if (c->a1 > (uint32_t)kMaxA1 || c->a2 > (uint32_t)kMaxA2)
+  if (c->a1 < 1 || c->a1 > (uint32_t)kMaxA1 || c->a2 < 1 || c->a2 > (uint32_t)kMaxA2)
     return fail(c, KC_ERR_INVALID_ARG, "partition count needs a wider shuffle (set scatter_bits)");
   c->bloom_words64 = f.bloom_bits_log2 >= 6 ? (1ull << (f.bloom_bits_log2 - 6)) : 1ull;
   return KC_OK;
@@ -328,7 +327,7 @@ kc_status sync_read(kc_ctx* c, hipStream_t s, const void* dev, size_t bytes, voi
 // pinned spill pool and marks it non-resident.
 kc_status spill_partition(kc_ctx* c, uint32_t p, hipStream_t s, uint64_t* bytes) {
   if (c->spill_of[p] >= 0) return KC_OK;
-  const uint64_t cap = 1ull << c->cap_log2;
+  const uint64_t cap = c->cap;
   const uint32_t nc = c->cfg.n_counters;
   DevBuf tmpk, tmpc, cur;
   KC_HIP(c, tmpk.ensure(cap * 8), "spill staging");
@@ -337,7 +336,7 @@ kc_status spill_partition(kc_ctx* c, uint32_t p, hipStream_t s, uint64_t* bytes)
   KC_HIP(c, hipMemsetAsync(cur.p, 0, 8, s), "memset");
   StageTimer tm(c, s, KC_T_SPILL);
   KC_HIP(c, launch_gather_part(c->tkeys.as<uint64_t>(), c->tcounts.as<uint32_t>(),
-                               (uint64_t)p << c->cap_log2, cap, nc, tmpk.as<uint64_t>(),
+                               (uint64_t)p * cap, cap, nc, tmpk.as<uint64_t>(),
                                tmpc.as<uint32_t>(), cur.as<uint64_t>(), s),
          "gather");
   uint64_t n = 0;
@@ -375,14 +374,14 @@ kc_status spill_partition(kc_ctx* c, uint32_t p, hipStream_t s, uint64_t* bytes)
 }
 
 uint64_t table_bytes_total(const kc_ctx* c) {
-  return (1ull << (c->p_log2 + c->cap_log2)) * c->slot_bytes;
+  return (1ull << c->p_log2) * c->cap * c->slot_bytes;
 }
 
 uint64_t resident_bytes(const kc_ctx* c) {
   uint64_t n = 0;
   for (size_t p = 0; p < c->spill_of.size(); ++p)
     if (c->spill_of[p] < 0) ++n;
-  return n * (1ull << c->cap_log2) * c->slot_bytes;
+  return n * c->cap * c->slot_bytes;
 }
 
 }  // namespace
@@ -458,7 +457,7 @@ kc_status kc_create(const kc_config* cfg, int device, kc_ctx** out) {
     return bail(KC_ERR_DEVICE, "event creation failed");
   c->spill_of.assign(1ull << c->p_log2, -1);
   c->st.partitions_log2 = c->p_log2;
-  c->st.table_log2 = c->cap_log2;
+  c->st.table_slots = c->cap;
   *out = c;
   return KC_OK;
 }
@@ -471,7 +470,8 @@ kc_status kc_insert_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offse
   if (counter >= c->cfg.n_counters) return fail(c, KC_ERR_INVALID_ARG, "counter >= n_counters");
   if (!offsets) return fail(c, KC_ERR_INVALID_ARG, "offsets is NULL");
   if (total_bases && !bases) return fail(c, KC_ERR_INVALID_ARG, "bases is NULL");
-  if (total_bases >= (1ull << 40)) return fail(c, KC_ERR_INVALID_ARG, "more than 2^40 bases in one call");
+  if (total_bases >= (1ull << 32))
+    return fail(c, KC_ERR_INVALID_ARG, "more than 2^32 - 1 bases in one call (split the reads)");
   hipStream_t s = as_stream(hip_stream);
   KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
   if (c->insert_done_valid) KC_HIP(c, hipStreamWaitEvent(s, c->insert_done, 0), "stream wait");
@@ -484,11 +484,14 @@ kc_status kc_insert_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offse
   KC_HIP(c, c->packed.ensure(nwords * 8), "packed buffer");
   KC_HIP(c, c->flags.ensure(nwords * 8), "flag buffer");
   KC_HIP(c, c->hist1.ensure(nhist * 4), "histogram buffer");
+  KC_HIP(c, c->lstart1.ensure(ntiles * (nb1 + 1) * 4), "tile start buffer");
   KC_HIP(c, c->off1.ensure((nhist + 1) * 8), "offset buffer");
   KC_HIP(c, c->parts.ensure(scan_parts(nhist) * 8), "scan buffer");
+  KC_HIP(c, c->keys1.ensure(ntiles * kTilePos * 8), "first-level key buffer");
   KC_HIP(c, hipMemsetAsync(c->derr.p, 0, 4, s), "memset");
 
   const uint64_t s0 = c->hc.salt[0];
+  const uint64_t tag = (uint64_t)counter << 62;
   {
     StageTimer t(c, s, KC_T_PACK);
     KC_HIP(c, launch_pack(bases, total_bases, nwords, c->packed.as<uint64_t>(),
@@ -499,11 +502,12 @@ kc_status kc_insert_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offse
            "read starts");
     t.stop();
   }
-  if (ntiles) {
-    StageTimer t(c, s, KC_T_HIST);
-    KC_HIP(c, launch_hist1(c->packed.as<uint64_t>(), c->flags.as<uint64_t>(), nwords, c->cfg.k,
-                           s0, c->a1, c->hist1.as<uint32_t>(), ntiles, s),
-           "histogram");
+  {
+    StageTimer t(c, s, KC_T_LEVEL1);
+    KC_HIP(c, launch_level1(c->packed.as<uint64_t>(), c->flags.as<uint64_t>(), nwords, c->cfg.k,
+                            s0, c->a1, tag, c->hist1.as<uint32_t>(), c->lstart1.as<uint32_t>(),
+                            ntiles, c->keys1.as<uint64_t>(), s),
+           "first-level shuffle");
     t.stop();
   }
   {
@@ -536,7 +540,7 @@ kc_status kc_insert_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offse
   seg.n = n;
   seg.counter = counter;
   const uint32_t nb2 = 1u << c->a2;
-  const uint64_t tiles2 = c->a2 ? (n + kT2 - 1) / kT2 + nb1 : 0;
+  const uint64_t tiles2 = (n + kT2 - 1) / kT2 + nb1;
   hipError_t e;
   if ((e = seg.keys.ensure(n * 8)) != hipSuccess || (e = seg.bucket_off.ensure((nb1 + 1) * 8)) != hipSuccess ||
       (e = seg.tile_first.ensure((nb1 + 1) * 4)) != hipSuccess ||
@@ -544,24 +548,19 @@ kc_status kc_insert_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offse
     seg.release();
     return hip_fail(c, e, "segment allocation");
   }
-  KC_HIP(c, launch_bucket_off(c->off1.as<uint64_t>(), ntiles, nb1, seg.bucket_off.as<uint64_t>(), s),
-         "bucket offsets");
+  KC_HIP(c, c->tile_run.ensure(tiles2 * 4), "tile run buffer");
   {
-    StageTimer t(c, s, KC_T_SCATTER1);
-    KC_HIP(c, launch_scatter1(c->packed.as<uint64_t>(), c->flags.as<uint64_t>(), nwords, c->cfg.k,
-                              s0, c->a1, c->off1.as<uint64_t>(), ntiles, (uint64_t)counter << 62,
-                              seg.keys.as<uint64_t>(), s),
-           "scatter");
-    t.stop();
-  }
-  if (c->a2) {
-    StageTimer t(c, s, KC_T_SCATTER2);
+    StageTimer t(c, s, KC_T_LEVEL2);
+    KC_HIP(c, launch_bucket_off(c->off1.as<uint64_t>(), ntiles, nb1, seg.bucket_off.as<uint64_t>(), s),
+           "bucket offsets");
     KC_HIP(c, launch_tiles2(seg.bucket_off.as<uint64_t>(), nb1, seg.tile_first.as<uint32_t>(), s),
            "tiles");
-    KC_HIP(c, launch_scatter2(seg.keys.as<uint64_t>(), seg.bucket_off.as<uint64_t>(),
-                              seg.tile_first.as<uint32_t>(), c->a1, c->a2, s0,
-                              seg.meta2.as<uint32_t>(), tiles2, s),
-           "scatter level 2");
+    KC_HIP(c, launch_level2(c->keys1.as<uint64_t>(), c->off1.as<uint64_t>(),
+                            c->lstart1.as<uint32_t>(), ntiles, seg.bucket_off.as<uint64_t>(),
+                            seg.tile_first.as<uint32_t>(), c->tile_run.as<uint32_t>(), c->a1,
+                            c->a2, s0, seg.keys.as<uint64_t>(), seg.meta2.as<uint32_t>(), tiles2,
+                            s),
+           "second-level shuffle");
     t.stop();
   }
   KC_HIP(c, hipEventRecord(c->insert_done, s), "event record");
@@ -580,7 +579,7 @@ kc_status kc_finalize(kc_ctx* c, void* hip_stream, kc_stats* out) {
   if (c->insert_done_valid) KC_HIP(c, hipStreamWaitEvent(s, c->insert_done, 0), "stream wait");
   const uint32_t nc = c->cfg.n_counters;
   const uint64_t nparts = 1ull << c->p_log2;
-  const uint64_t cap = 1ull << c->cap_log2;
+  const uint64_t cap = c->cap;
   const uint64_t all_tables = table_bytes_total(c);
   const uint64_t budget = c->cfg.hbm_table_budget_bytes;
   const uint64_t per_table = cap * c->slot_bytes;
@@ -635,6 +634,7 @@ kc_status kc_finalize(kc_ctx* c, void* hip_stream, kc_stats* out) {
     a.upb_log2 = c->upb_log2;
     a.nbw = c->nbw;
     a.l2w = c->l2w;
+    a.cap = c->cap;
     a.probe_limit = (uint32_t)std::min<uint64_t>(cap, 128);
     a.ovf_log2 = c->ovf_log2;
     a.ovf_limit = (uint32_t)std::min<uint64_t>(on / 2, 0xFFFFFFFFull);
@@ -722,6 +722,7 @@ kc_status kc_query(kc_ctx* c, const uint64_t* kmers, uint64_t n, uint32_t* count
   KC_HIP(c, hipMemsetAsync(c->qcount.p, 0, 4, s), "memset");
   QueryArgs a{};
   a.hc = c->hc;
+  a.cap = c->cap;
   a.tkeys = c->tkeys.as<uint64_t>();
   a.tcounts = c->tcounts.as<uint32_t>();
   a.resident = c->resident.as<uint32_t>();
@@ -820,9 +821,9 @@ kc_status kc_export(kc_ctx* c, uint64_t* keys, uint32_t* counts, uint64_t cap, u
   KC_HIP(c, cur.ensure(8), "export cursor");
   hipStream_t s = nullptr;
   KC_HIP(c, hipMemsetAsync(cur.p, 0, 8, s), "memset");
-  const uint64_t nslots = 1ull << (c->p_log2 + c->cap_log2);
+  const uint64_t nslots = (1ull << c->p_log2) * c->cap;
   KC_HIP(c, launch_export(c->tkeys.as<uint64_t>(), c->tcounts.as<uint32_t>(), nslots,
-                          c->resident.as<uint32_t>(), c->cap_log2, nc, ok.as<uint64_t>(),
+                          c->resident.as<uint32_t>(), c->cap, nc, ok.as<uint64_t>(),
                           oc.as<uint32_t>(), E, cur.as<uint64_t>(), s),
          "export");
   KC_HIP(c, launch_export(c->okeys.as<uint64_t>(), c->ocounts.as<uint32_t>(), 1ull << c->ovf_log2,
@@ -904,10 +905,10 @@ kc_status kc_reset(kc_ctx* c) {
   }
   free_spill(c);
   resolve_timers(c);
-  const uint32_t pl = c->p_log2, tl = c->cap_log2;
+  const uint32_t pl = c->p_log2, tl = c->cap;
   c->st = kc_stats{};
   c->st.partitions_log2 = pl;
-  c->st.table_log2 = tl;
+  c->st.table_slots = tl;
   c->insert_done_valid = false;
   c->state = CREATED;
   c->err.clear();
@@ -921,7 +922,7 @@ void kc_destroy(kc_ctx* c) {
   for (Segment& g : c->segs) g.release();
   for (Segment& g : c->spare_segs) g.release();
   DevBuf* bufs[] = {&c->b1, &c->b2, &c->dstat, &c->derr, &c->packed, &c->flags, &c->hist1,
-                    &c->off1, &c->parts, &c->segdesc, &c->tkeys, &c->tcounts, &c->resident,
+                    &c->lstart1, &c->off1, &c->parts, &c->keys1, &c->tile_run, &c->segdesc, &c->tkeys, &c->tcounts, &c->resident,
                     &c->pstats, &c->pstats_ovf, &c->okeys, &c->ocounts, &c->ovf_used, &c->qrows,
                     &c->qcount};
   for (DevBuf* b : bufs) b->release();

@@ -165,7 +165,7 @@ WORKLOADS = {
     "plain_100mbp": Workload("plain_100mbp", 2, 100_000_000, 10_000_000, 100, 100, 0.005, 0.001,
                              31, 32, 4, 19, 15),
     "batched_200mbp": Workload("batched_200mbp", 3, 200_000_000, 0, 100, 250, 0.005, 0.0,
-                               31, 35, 4, 19, 18),
+                               31, 35, 4, 19, 16),
     "served_300mbp": Workload("served_300mbp", 4, 300_000_000, 30_000_000, 100, 100, 0.005, 0.0,
                               31, 32, 4, 19, 16, n_counters=2),
     "spill_3gbp": Workload("spill_3gbp", 5, 3_000_000_000, 200_000_000, 100, 100, 0.01, 0.0,

@@ -56,7 +56,7 @@ def test_plain_1mbp_full_parity():
 
 
 PARAMS = [
-    # k, m_log2, h, bl, p_log2, table_log2, nc, min_count, seed
+    # k, m_log2, h, bl, p_log2, table_slots, nc, min_count, seed
     (31, 20, 4, 12, 0, 0, 1, 2, 1),
     (21, 22, 3, 19, 6, 0, 1, 2, 2),
     (15, 16, 2, 4, 0, 0, 1, 2, 3),      # Bloom blocks smaller than a word
@@ -64,8 +64,8 @@ PARAMS = [
     (31, 24, 3, 19, 10, 0, 1, 3, 5),    # min_count 3, first-level fan-out 2^10
     (27, 26, 4, 16, 14, 0, 2, 2, 6),    # joint counters, two shuffle levels
     (1, 8, 2, 3, 0, 0, 1, 2, 7),
-    (13, 10, 3, 5, 0, 4, 1, 2, 8),      # 16-slot tables: overflow path and its regrowth
-    (31, 22, 4, 12, 12, 5, 1, 2, 9),    # 32-slot tables at 2^12 partitions
+    (13, 10, 3, 5, 0, 64, 1, 2, 8),     # 64-slot tables: overflow path and its regrowth
+    (31, 22, 4, 12, 12, 128, 1, 2, 9),  # 128-slot tables at 2^12 partitions
 ]
 
 
@@ -75,7 +75,7 @@ def test_parameter_grid_parity(k, m, h, bl, pl, tl, nc, mc, seed):
          % (k, m, h, bl, pl, tl, nc, mc, seed))
     reads = random_reads(seed, 3000, 0, 160, genome_len=6000)
     cfg = kc.Config(k=k, bloom_bits_log2=m, bloom_hashes=h, bloom_block_log2=bl,
-                    partitions_log2=pl, table_log2=tl, n_counters=nc, min_count=mc, seed=seed)
+                    partitions_log2=pl, table_slots=tl, n_counters=nc, min_count=mc, seed=seed)
     b, o = pack_reads(reads)
     counters = None
     chunks = [(b, o)]
@@ -84,7 +84,7 @@ def test_parameter_grid_parity(k, m, h, bl, pl, tl, nc, mc, seed):
         chunks = [pack_reads(reads[:half]), pack_reads(reads[half:])]
         counters = [0, 1]
     g, ref = assert_parity(cfg, chunks, counters)
-    if tl == 4:
+    if tl == 64:
         assert g["stats"]["overflow_keys"] > 0
 
 
@@ -110,9 +110,9 @@ def test_result_neutral_parameters():
     note("case: partitions / table size / fan-out change nothing")
     reads = random_reads(12, 3000, 30, 120, genome_len=4000)
     base = dict(k=19, bloom_bits_log2=20, bloom_hashes=3, bloom_block_log2=14, seed=12)
-    runs = [run_gpu(kc.Config(**base, partitions_log2=p, table_log2=t, scatter_bits=sb),
+    runs = [run_gpu(kc.Config(**base, partitions_log2=p, table_slots=t, scatter_bits=sb),
                     [pack_reads(reads)])
-            for p, t, sb in [(0, 0, 0), (9, 0, 0), (12, 6, 0), (12, 0, 4), (6, 5, 3)]]
+            for p, t, sb in [(0, 0, 0), (9, 0, 0), (12, 64, 0), (12, 0, 4), (6, 128, 3)]]
     for r in runs[1:]:
         assert_same_table(r["keys"], r["counts"], runs[0]["keys"], runs[0]["counts"])
         assert np.array_equal(r["b1"], runs[0]["b1"]) and np.array_equal(r["b2"], runs[0]["b2"])
@@ -186,7 +186,7 @@ def test_forced_spill_keeps_results():
     note("case: table budget forces spill of partitions to pinned host")
     reads = random_reads(31, 3000, 50, 120, genome_len=6000)
     cfg = kc.Config(k=27, bloom_bits_log2=20, bloom_hashes=3, bloom_block_log2=14,
-                    partitions_log2=8, table_log2=8, seed=31)
+                    partitions_log2=8, table_slots=256, seed=31)
     full = run_gpu(cfg, [pack_reads(reads)])
     per_table = (1 << 8) * 12
     cfg.hbm_table_budget_bytes = per_table * 100  # 100 of 256 partitions stay in HBM
