@@ -24,7 +24,31 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "plain_100mbp"
 METRIC = "k-mers/sec + HBM GB/s (plain vs batched/served); p50/p99 request latency"
 HBM_PEAK_GBS = 8000.0
+# 256 CUs x 64 integer lanes per clock x 2.4 GHz (32-bit integer VALU issue rate)
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+MIX64_OPS = 17          # VALU instructions of one SplitMix64 output function on gfx950
+SLOT_HASH_OPS = 6       # table slot hash: xor, 64-bit multiply (4), multiply-high
 QUERY_BATCH = 1 << 20
+COPY_BYTES = 1 << 30
+KERNEL_SRC = os.path.join(ROOT, "paper_1712_03254_amd", "csrc", "kc_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "count_traffic.json")
+STAGE_KERNEL = {"pack": "k_pack", "level1": "k_level1", "level2": "k_level2", "count": "k_count",
+                "query": "k_query"}
+
+
+def src_hash() -> str:
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def count_alu_ops(w, st: dict) -> float:
+    """Algorithmic integer ops of one count-kernel launch: h hashes per occurrence
+    (Bloom build), h per screened key (misses: occurrences of failing keys plus
+    the first arrival of each passing key), one slot hash per occurrence."""
+    n = st["n_valid"]
+    screened = (n - st["n_pass"]) + st["passed_distinct"]
+    return MIX64_OPS * w.bloom_hashes * (n + screened) + SLOT_HASH_OPS * n
 
 
 def stage_bytes(stage: str, w, st: dict, cfg_eff: dict) -> float:
@@ -63,6 +87,88 @@ def cpu_baseline(w, genome, n_reads=300_000):
                       % (n_reads, WORKLOAD, r.stats["n_valid"], dt)}
 
 
+def load_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when it is missing or was taken on different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel") != kernel or t.get("src_sha256") != src_hash():
+        return None
+    return t.get("traffic_bytes")
+
+
+def _pmc_rows(directory: str):
+    import csv
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            rows += list(csv.DictReader(f))
+    return rows
+
+
+def pmc_summary(fetch_dir: str, write_dir: str, command: str):
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of k_count and of the
+    calibration copy; writes profiles/count_traffic.json and a markdown note."""
+    res = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        per = {}
+        for r in _pmc_rows(d):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"]
+            key = "k_count" if "k_count" in name else ("copy" if "copy" in name.lower() else None)
+            if key:
+                per.setdefault(key, []).append(float(r["Counter_Value"]) * 1024.0)
+        res[counter] = per
+    copy_f = max(res["FETCH_SIZE"]["copy"])
+    copy_w = max(res["WRITE_SIZE"]["copy"])
+    f_factor, w_factor = copy_f / COPY_BYTES, copy_w / COPY_BYTES
+    kf = np.median(res["FETCH_SIZE"]["k_count"]) / f_factor
+    kw = np.median(res["WRITE_SIZE"]["k_count"]) / w_factor
+    out = {"kernel": "k_count", "workload": WORKLOAD, "src_sha256": src_hash(),
+           "fetch_bytes": kf, "write_bytes": kw, "traffic_bytes": kf + kw,
+           "copy_fetch_factor": f_factor, "copy_write_factor": w_factor,
+           "launches": len(res["FETCH_SIZE"]["k_count"]), "command": command}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    md = os.path.join(ROOT, "profiles", "k_count_plain_100mbp_hbm_traffic.md")
+    with open(md, "w") as f:
+        f.write("# k_count HBM traffic, %s workload\n\n" % WORKLOAD)
+        f.write("Commands (FETCH_SIZE run, then WRITE_SIZE run):\n\n```\n%s\n```\n\n" % command)
+        f.write("| counter | k_count per launch (raw) | %d-byte copy (raw) | factor | k_count bytes |\n"
+                % COPY_BYTES)
+        f.write("|---|---|---|---|---|\n")
+        f.write("| FETCH_SIZE | %.3e | %.3e | %.4f | %.3e |\n"
+                % (np.median(res["FETCH_SIZE"]["k_count"]), copy_f, f_factor, kf))
+        f.write("| WRITE_SIZE | %.3e | %.3e | %.4f | %.3e |\n"
+                % (np.median(res["WRITE_SIZE"]["k_count"]), copy_w, w_factor, kw))
+        f.write("\nkc_kernels.hip sha256: `%s`\n" % out["src_sha256"])
+    print(json.dumps(out))
+
+
+def trace_summary(trace_dir: str, command: str):
+    import csv
+    import glob
+    paths = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    rows = list(csv.DictReader(open(paths[0])))
+    md = os.path.join(ROOT, "profiles", "plain_100mbp_kernel_stats.md")
+    with open(md, "w") as f:
+        f.write("# Kernel time, %s workload (rocprofv3 --kernel-trace --stats)\n\n" % WORKLOAD)
+        f.write("Command:\n\n```\n%s\n```\n\n" % command)
+        f.write("| kernel | calls | total ms | average us | share % |\n|---|---|---|---|---|\n")
+        for r in rows:
+            f.write("| %s | %s | %.3f | %.1f | %.2f |\n" % (
+                r["Name"][:60], r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+                float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+        f.write("\nkc_kernels.hip sha256: `%s`\n" % src_hash())
+    print(open(md).read())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,7 +176,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run %d-byte device copies (counter calibration)" % COPY_BYTES)
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="offline: turn two rocprofv3 --pmc runs into profiles/ files")
+    ap.add_argument("--trace-summary", metavar="TRACE_DIR",
+                    help="offline: turn a rocprofv3 --kernel-trace --stats run into a profiles/ file")
+    ap.add_argument("--command", default="", help="command line recorded in the offline summaries")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.command)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary, args.command)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the counting path of this build runs on a single "
               "MI355X (multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
@@ -158,9 +277,22 @@ def main():
                          "gbs": round(b / (avg * 1e-3) / 1e9, 1) if b and avg > 0 else None}
     dom = max(stages, key=lambda s: stages[s]["avg_ms"] * stages[s]["launches_per_step"])
     d = stages[dom]
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4) if d["gbs"] else None,
-                "traffic": None}
+    hbm_frac = d["gbs"] / HBM_PEAK_GBS if d["gbs"] else 0.0
+    roofline = {"bound": "hbm", "kernel": STAGE_KERNEL.get(dom, dom), "achieved": d["gbs"],
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(hbm_frac, 4), "traffic": None}
+    if dom == "count":
+        tops = count_alu_ops(w, last) / (d["avg_ms"] * 1e-3) / 1e12
+        roofline["alu_tops"] = round(tops, 3)
+        roofline["alu_frac"] = round(tops / ALU_PEAK_TOPS, 4)
+        roofline["hbm_gbs"] = d["gbs"]
+        roofline["hbm_frac"] = round(hbm_frac, 4)
+        if tops / ALU_PEAK_TOPS > hbm_frac:
+            roofline.update({"bound": "alu", "achieved": round(tops, 3), "peak": round(ALU_PEAK_TOPS, 2),
+                             "unit": "T int-ops/s", "frac": round(tops / ALU_PEAK_TOPS, 4)})
+    traffic = load_traffic(roofline["kernel"])
+    if traffic is not None:
+        roofline["traffic"] = traffic
+    total_alg = sum(v["alg_bytes"] * v["launches_per_step"] for v in stages.values())
 
     out = {
         "metric": METRIC, "value": value, "unit": "k-mers/s", "n_gpus": 1,
@@ -179,8 +311,17 @@ def main():
                                         "fp_singletons", "b1_popcount", "b2_popcount",
                                         "overflow_keys")},
         "pcie_inclusive_kmers_per_s": e2e,
+        "step_alg_bytes_per_kmer": round(total_alg / n_valid, 2),
+        "step_hbm_gbs": round(total_alg * args.steps / elapsed / 1e9, 1),
         "input_gen_s": round(gen_s, 2),
     }
+    if args.copy_probe:
+        src = torch.empty(COPY_BYTES, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, genome)
     counter.close()

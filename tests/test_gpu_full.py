@@ -1,0 +1,86 @@
+"""Full-size parity on the 100 Mbp / 10M-read workload, in the configuration
+bench.py times.  The whole table is too large to sort on the host, so the
+oracle computes sampled outputs exactly (threaded scans over every window):
+counts of sampled keys and saturating hits of sampled Bloom bits.  Properties
+that hold at any size are checked on the full outputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1712_03254_amd as kc
+from kc_cases import note, oracle_params, to_device, workload_chunks, workload_config
+from oracle import brute
+
+pytestmark = pytest.mark.gpu
+
+
+def _popcount(words):
+    v = words.view(np.uint8)
+    return int(np.unpackbits(v).sum())
+
+
+def test_plain_100mbp_sampled_parity():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    note("case: plain_100mbp full size (1e7 reads x 100 bp), sampled parity")
+    w, _, b, o = workload_chunks("plain_100mbp")
+    cfg = workload_config(w)
+    db, do = to_device(b, o)
+    rng = np.random.default_rng(2024)
+    with kc.KmerCounter(cfg) as c:
+        c.insert_reads(db, do)
+        st = c.finalize()
+        keys, counts = c.export()
+        b1, b2 = c.export_bloom()
+        # sampled keys: from the table, from random windows of the reads, random codes
+        from_table = keys[rng.integers(0, keys.size, 3000)]
+        wins = []
+        starts = rng.integers(0, w.n_reads, 4000)
+        for r in starts:
+            lo = int(o[r])
+            j = int(rng.integers(0, 100 - w.k + 1))
+            s = bytes(b[lo + j:lo + j + w.k]).decode()
+            if all(ch in "ACGT" for ch in s):
+                wins.append(brute.encode(brute.canonical(s)))
+        rand = rng.integers(0, 1 << (2 * w.k), 1000, dtype=np.uint64)
+        sample = np.unique(np.concatenate([from_table, np.array(wins, np.uint64), rand]))
+        q = torch.from_numpy(sample.view(np.int64)).cuda()
+        got = c.query(q).cpu().numpy().astype(np.uint32)[:, 0]
+    note("sample keys: %d; oracle scan over all windows" % sample.size)
+    p = oracle_params(cfg)
+    ks, cs, nv = oracle.sample_counts(p, b, o, sample, threads=16)
+    assert np.array_equal(ks, sample)
+    want = np.where(cs[:, 0] >= cfg.min_count, cs[:, 0], 0)
+    assert nv == st["n_valid"]
+    assert np.array_equal(got, want)
+    # the exported table agrees with the sample
+    order = np.argsort(keys)
+    sk, sc = keys[order], counts[order, 0]
+    at = np.searchsorted(sk, sample)
+    present = (at < sk.size) & (sk[np.minimum(at, sk.size - 1)] == sample)
+    assert np.array_equal(present, want > 0)
+    assert np.array_equal(sc[at[present]], want[present])
+
+    # sampled Bloom bits: random positions plus the positions of sampled keys
+    m = 1 << cfg.bloom_bits_log2
+    bits = list(rng.integers(0, m, 3000, dtype=np.uint64))
+    for x in sample[:300]:
+        bits += oracle.bloom_bits(p, int(x))
+    bs, hs = oracle.sample_hits(p, b, o, np.array(bits, np.uint64), threads=16)
+    g1 = (b1[bs >> np.uint64(6)] >> (bs & np.uint64(63))) & np.uint64(1)
+    g2 = (b2[bs >> np.uint64(6)] >> (bs & np.uint64(63))) & np.uint64(1)
+    assert np.array_equal(g1.astype(bool), hs >= 1)
+    assert np.array_equal(g2.astype(bool), hs >= 2)
+
+    # properties that hold at any size
+    assert keys.size == st["entries"] == np.unique(keys).size
+    assert int(counts.sum()) == st["sum_counts"]
+    assert counts.min() >= cfg.min_count
+    assert st["n_pass"] == st["sum_counts"] + st["fp_singletons"]
+    assert _popcount(b1) == st["b1_popcount"] and _popcount(b2) == st["b2_popcount"]
+    assert st["b2_popcount"] <= st["b1_popcount"]
+    assert int(keys.max()) < (1 << (2 * cfg.k))
+    note("entries %d, F %d, overflow keys %d" % (st["entries"], st["fp_singletons"],
+                                                st["overflow_keys"]))
