@@ -32,8 +32,8 @@ QUERY_BATCH = 1 << 20
 COPY_BYTES = 1 << 30
 KERNEL_SRC = os.path.join(ROOT, "paper_1712_03254_amd", "csrc", "kc_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "count_traffic.json")
-STAGE_KERNEL = {"pack": "k_pack", "level1": "k_level1", "level2": "k_level2", "count": "k_count",
-                "query": "k_query"}
+STAGE_KERNEL = {"pack": "k_pack", "level1": "k_level1", "level2": "k_level2", "bloom": "k_bloom",
+                "tally": "k_tally", "query": "k_query"}
 
 
 def src_hash() -> str:
@@ -42,13 +42,20 @@ def src_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def count_alu_ops(w, st: dict) -> float:
-    """Algorithmic integer ops of one count-kernel launch: h hashes per occurrence
-    (Bloom build), h per screened key (misses: occurrences of failing keys plus
-    the first arrival of each passing key), one slot hash per occurrence."""
+def stage_alu_ops(stage: str, w, st: dict) -> float:
+    """Algorithmic integer ops of one launch: k_bloom evaluates h hashes per
+    occurrence; k_tally one slot hash per occurrence and h hashes per screened
+    key (occurrences of failing keys plus the first arrival of each passing
+    key); the shuffle levels one hash per occurrence."""
     n = st["n_valid"]
-    screened = (n - st["n_pass"]) + st["passed_distinct"]
-    return MIX64_OPS * w.bloom_hashes * (n + screened) + SLOT_HASH_OPS * n
+    if stage == "bloom":
+        return MIX64_OPS * w.bloom_hashes * n
+    if stage == "tally":
+        screened = (n - st["n_pass"]) + st["passed_distinct"]
+        return MIX64_OPS * w.bloom_hashes * screened + SLOT_HASH_OPS * n
+    if stage in ("level1", "level2"):
+        return MIX64_OPS * n
+    return 0.0
 
 
 def stage_bytes(stage: str, w, st: dict, cfg_eff: dict) -> float:
@@ -63,10 +70,11 @@ def stage_bytes(stage: str, w, st: dict, cfg_eff: dict) -> float:
         return nwords * 16 + n * 8
     if stage == "level2":    # keys in and out
         return n * 16
-    if stage == "count":     # keys in, both Bloom levels out, partition tables out
-        m_bytes = (1 << w.bloom_bits_log2) // 8
+    if stage == "bloom":     # keys in, both Bloom levels out
+        return n * 8 + 2 * (1 << w.bloom_bits_log2) // 8
+    if stage == "tally":     # keys in, partition tables out
         tables = (1 << cfg_eff["partitions_log2"]) * cfg_eff["table_slots"] * (8 + 4 * w.n_counters)
-        return n * 8 + 2 * m_bytes + tables
+        return n * 8 + tables
     if stage == "query":
         return QUERY_BATCH * (8 + 4 * w.n_counters)
     return 0.0
@@ -95,9 +103,10 @@ def load_traffic(kernel: str):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel") != kernel or t.get("src_sha256") != src_hash():
+    if t.get("src_sha256") != src_hash():
         return None
-    return t.get("traffic_bytes")
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("traffic_bytes")
 
 
 def _pmc_rows(directory: str):
@@ -110,43 +119,58 @@ def _pmc_rows(directory: str):
     return rows
 
 
+def _kernel_key(name: str):
+    for k in STAGE_KERNEL.values():
+        if k + "<" in name or k + "(" in name or name.endswith(k):
+            return k
+    return "copy" if "copy" in name.lower() else None
+
+
 def pmc_summary(fetch_dir: str, write_dir: str, command: str):
-    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of k_count and of the
-    calibration copy; writes profiles/count_traffic.json and a markdown note."""
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the stage kernels and of
+    the calibration copy; writes profiles/count_traffic.json and a markdown
+    note.  Each counter is scaled by what it reads for a copy of known size."""
     res = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         per = {}
         for r in _pmc_rows(d):
             if r["Counter_Name"] != counter:
                 continue
-            name = r["Kernel_Name"]
-            key = "k_count" if "k_count" in name else ("copy" if "copy" in name.lower() else None)
+            key = _kernel_key(r["Kernel_Name"])
             if key:
                 per.setdefault(key, []).append(float(r["Counter_Value"]) * 1024.0)
         res[counter] = per
     copy_f = max(res["FETCH_SIZE"]["copy"])
     copy_w = max(res["WRITE_SIZE"]["copy"])
     f_factor, w_factor = copy_f / COPY_BYTES, copy_w / COPY_BYTES
-    kf = np.median(res["FETCH_SIZE"]["k_count"]) / f_factor
-    kw = np.median(res["WRITE_SIZE"]["k_count"]) / w_factor
-    out = {"kernel": "k_count", "workload": WORKLOAD, "src_sha256": src_hash(),
-           "fetch_bytes": kf, "write_bytes": kw, "traffic_bytes": kf + kw,
+    kernels = {}
+    for k in STAGE_KERNEL.values():
+        if k in res["FETCH_SIZE"] and k in res["WRITE_SIZE"]:
+            rf, rw = np.median(res["FETCH_SIZE"][k]), np.median(res["WRITE_SIZE"][k])
+            kernels[k] = {"fetch_raw": rf, "write_raw": rw, "fetch_bytes": rf / f_factor,
+                          "write_bytes": rw / w_factor,
+                          "traffic_bytes": rf / f_factor + rw / w_factor,
+                          "launches": len(res["FETCH_SIZE"][k])}
+    out = {"workload": WORKLOAD, "src_sha256": src_hash(), "copy_bytes": COPY_BYTES,
+           "copy_fetch_raw": copy_f, "copy_write_raw": copy_w,
            "copy_fetch_factor": f_factor, "copy_write_factor": w_factor,
-           "launches": len(res["FETCH_SIZE"]["k_count"]), "command": command}
+           "kernels": kernels, "command": command}
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
-    md = os.path.join(ROOT, "profiles", "k_count_plain_100mbp_hbm_traffic.md")
+    md = os.path.join(ROOT, "profiles", "%s_hbm_traffic.md" % WORKLOAD)
     with open(md, "w") as f:
-        f.write("# k_count HBM traffic, %s workload\n\n" % WORKLOAD)
+        f.write("# HBM traffic per launch, %s workload (rocprofv3 --pmc)\n\n" % WORKLOAD)
         f.write("Commands (FETCH_SIZE run, then WRITE_SIZE run):\n\n```\n%s\n```\n\n" % command)
-        f.write("| counter | k_count per launch (raw) | %d-byte copy (raw) | factor | k_count bytes |\n"
-                % COPY_BYTES)
-        f.write("|---|---|---|---|---|\n")
-        f.write("| FETCH_SIZE | %.3e | %.3e | %.4f | %.3e |\n"
-                % (np.median(res["FETCH_SIZE"]["k_count"]), copy_f, f_factor, kf))
-        f.write("| WRITE_SIZE | %.3e | %.3e | %.4f | %.3e |\n"
-                % (np.median(res["WRITE_SIZE"]["k_count"]), copy_w, w_factor, kw))
+        f.write("Calibration: a %d-byte device copy reads FETCH_SIZE %.4e B and WRITE_SIZE %.4e B, "
+                "so the factors are %.4f and %.4f.\n\n" % (COPY_BYTES, copy_f, copy_w, f_factor,
+                                                            w_factor))
+        f.write("| kernel | FETCH raw | WRITE raw | read bytes | written bytes | total |\n"
+                "|---|---|---|---|---|---|\n")
+        for k, v in kernels.items():
+            f.write("| %s | %.3e | %.3e | %.3e | %.3e | %.3e |\n" % (
+                k, v["fetch_raw"], v["write_raw"], v["fetch_bytes"], v["write_bytes"],
+                v["traffic_bytes"]))
         f.write("\nkc_kernels.hip sha256: `%s`\n" % out["src_sha256"])
     print(json.dumps(out))
 
@@ -272,16 +296,19 @@ def main():
         if per_stage_n.get(s):
             avg = per_stage_ms[s] / per_stage_n[s]
             b = stage_bytes(s, w, last, cfg_eff)
+            ops = stage_alu_ops(s, w, last)
             stages[s] = {"avg_ms": round(avg, 4), "launches_per_step": per_stage_n[s] / args.steps,
                          "alg_bytes": b,
-                         "gbs": round(b / (avg * 1e-3) / 1e9, 1) if b and avg > 0 else None}
+                         "gbs": round(b / (avg * 1e-3) / 1e9, 1) if b and avg > 0 else None,
+                         "alu_tops": round(ops / (avg * 1e-3) / 1e12, 3) if ops and avg > 0 else None}
     dom = max(stages, key=lambda s: stages[s]["avg_ms"] * stages[s]["launches_per_step"])
     d = stages[dom]
     hbm_frac = d["gbs"] / HBM_PEAK_GBS if d["gbs"] else 0.0
     roofline = {"bound": "hbm", "kernel": STAGE_KERNEL.get(dom, dom), "achieved": d["gbs"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(hbm_frac, 4), "traffic": None}
-    if dom == "count":
-        tops = count_alu_ops(w, last) / (d["avg_ms"] * 1e-3) / 1e12
+    ops = stage_alu_ops(dom, w, last)
+    if ops:
+        tops = ops / (d["avg_ms"] * 1e-3) / 1e12
         roofline["alu_tops"] = round(tops, 3)
         roofline["alu_frac"] = round(tops / ALU_PEAK_TOPS, 4)
         roofline["hbm_gbs"] = d["gbs"]

@@ -94,10 +94,11 @@ enum {
   KC_T_LEVEL1 = 1, /* extraction + first-level shuffle (one pass per tile) */
   KC_T_SCAN = 2,   /* exclusive prefix sum of the first-level histogram */
   KC_T_LEVEL2 = 3, /* second-level shuffle into partition-sorted tiles */
-  KC_T_COUNT = 4,  /* per Bloom block: B1/B2 build, screen, exact count */
-  KC_T_UNIFY = 5,  /* overflow table pass, statistics reduction */
-  KC_T_QUERY = 6,
-  KC_T_SPILL = 7,  /* device -> pinned host copies of spilled partitions */
+  KC_T_BLOOM = 4,  /* per Bloom block: B1/B2 built from every occurrence */
+  KC_T_TALLY = 5,  /* per partition: screen against B2 and exact count */
+  KC_T_UNIFY = 6,  /* overflow table pass, statistics reduction */
+  KC_T_QUERY = 7,
+  KC_T_SPILL = 8,  /* device -> pinned host copies of spilled partitions */
   KC_T_COUNT_OF = 16
 };
 

@@ -28,7 +28,7 @@ KC_ERR_BAD_STATE = -3
 KC_ERR_DEVICE = -4
 KC_ERR_OVER_BUDGET = -5
 
-STAGES = ["pack", "level1", "scan", "level2", "count", "unify", "query", "spill"]
+STAGES = ["pack", "level1", "scan", "level2", "bloom", "tally", "unify", "query", "spill"]
 
 EXPORTED = ["kc_abi_version", "kc_status_str", "kc_create", "kc_insert_reads", "kc_finalize",
             "kc_query", "kc_spill", "kc_export", "kc_export_bloom", "kc_debug_keys",

@@ -20,7 +20,8 @@ constexpr int kMaxA2 = 11;                      // second-level fan-out limit (b
 constexpr int kMaxPartLog2 = kMaxA1 + kMaxA2;    // partitions (log2) two levels can reach
 constexpr int kLdsMax = 163840;                 // gfx950 LDS per workgroup
 constexpr int kNst = 8;                         // statistics slots
-constexpr int kQueueBytes = kWaves * 64 * 12;   // per-wave miss queues of the count kernel
+constexpr int kTallyWaves = 8;                  // waves per k_tally workgroup
+constexpr int kQueueBytes = kTallyWaves * 64 * 12;  // per-wave miss queues of k_tally
 
 enum Stat { ST_NPASS = 0, ST_ENTRIES, ST_SUM, ST_FP, ST_B1POP, ST_B2POP, ST_PASSED, ST_OVF };
 enum Err : uint32_t { ERR_OFFSETS = 1, ERR_OVF_FULL = 2, ERR_OVF_LOAD = 4, ERR_QUERY_RANGE = 8 };
@@ -62,7 +63,8 @@ struct CountArgs {
   uint32_t* ocounts;
   uint32_t* ovf_used;
   uint32_t* err;
-  uint64_t* pstats;      // [blocks * kNst]
+  uint64_t* pstats;      // [Bloom blocks * kNst]: level popcounts
+  uint64_t* pstats2;     // [partitions * kNst]: count statistics
 };
 
 struct QueryArgs {
@@ -101,7 +103,9 @@ hipError_t launch_level2(const uint64_t* keys1, const uint64_t* off1, const uint
                          uint64_t ntiles1, const uint64_t* bucket_off, const uint32_t* tile_first,
                          uint32_t* tile_run, uint32_t a1, uint32_t a2, uint64_t s0,
                          uint64_t* keys2, uint32_t* meta2, uint64_t grid, hipStream_t s);
-hipError_t launch_count(const CountArgs& a, uint32_t blocks, size_t lds, hipStream_t s);
+hipError_t launch_bloom(const CountArgs& a, uint32_t blocks, size_t lds, hipStream_t s);
+hipError_t launch_tally(const CountArgs& a, uint32_t parts, size_t lds, hipStream_t s);
+int tally_threads();
 hipError_t launch_ovf_emit(const CountArgs& a, uint64_t* pstats_ovf, uint32_t blocks,
                            hipStream_t s);
 hipError_t launch_reduce(const uint64_t* rows, uint64_t nrows, uint64_t* out, hipStream_t s);

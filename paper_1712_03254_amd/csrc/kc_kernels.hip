@@ -35,7 +35,26 @@ __device__ __forceinline__ uint64_t top_bits(uint64_t g, uint32_t n) {
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
-__device__ __forceinline__ uint32_t wave_id() { return threadIdx.x >> 6; }
+// Wave index in the block, in a scalar register (the compiler cannot tell on
+// its own that threadIdx.x >> 6 is the same in every lane of a wave).
+__device__ __forceinline__ uint32_t wave_id() {
+  return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+// Address-space views of device pointers.  Pointers read out of memory (a
+// segment descriptor) are generic to the compiler, which then emits flat
+// loads; flat loads also count against the LDS wait counter, so an LDS wait
+// would hold until every key load in flight had landed.  gview() restores
+// global loads.  cview() marks data no kernel writes while this one runs;
+// loads from it at wave-uniform addresses become scalar loads.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gview(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* cview(const T* p) {
+  return (const __attribute__((address_space(4))) T*)p;
+}
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -475,10 +494,14 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
 // valid where bit b of the lane's vmask is set (lanes past the end of a run
 // are not).  Every lane of a wave reaches every call.  The whole block must
 // call it.  The range's run inside a second-level tile is contiguous.  Wave w
-// takes tiles g0 + w + kWaves*j (j = lane), reads their run bounds once into
+// takes tiles g0 + w + NW*j (j = lane; NW waves per workgroup), reads their
+// run bounds once into
 // its lanes, then walks the runs in chunks of 64 keys with wave-uniform
 // bookkeeping.  Loads of the next B chunks are issued before the current B
 // are handed to fn, so one batch is always in flight behind the one in use.
+// s_waitcnt immediate (gfx9 encoding): vmcnt 0, expcnt and lgkmcnt unbounded.
+constexpr int kWaitVm0 = 0x0F70;
+
 template <int B>
 struct RunBatch {
   uint64_t kv[B];
@@ -486,33 +509,43 @@ struct RunBatch {
   uint32_t n;      // chunks in the batch (wave-uniform)
 };
 
-template <int B, typename F>
+template <int NW, int B, typename F>
 __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint32_t u_hi,
                                          F&& fn) {
+  const auto segs = cview(A.segs);
   for (uint32_t s = 0; s < A.nsegs; ++s) {
-    const SegDesc sd = A.segs[s];
-    const uint32_t nb2 = 1u << sd.a2;
-    const uint32_t c_lo = u_lo >> sd.a2, c_hi = (u_hi - 1) >> sd.a2;
+    const uint32_t a2 = segs[s].a2;
+    const uint32_t nb2 = 1u << a2;
+    const uint32_t c_lo = u_lo >> a2, c_hi = (u_hi - 1) >> a2;
+    const auto tile_first = cview(segs[s].tile_first);
+    const auto bucket_off = cview(segs[s].bucket_off);
+    const auto meta2 = gview(segs[s].meta2);
+    const auto seg_keys = gview(segs[s].keys);
     for (uint32_t c = c_lo; c <= c_hi; ++c) {
-      const uint32_t s_lo = max(u_lo, c << sd.a2) - (c << sd.a2);
-      const uint32_t s_hi = min(u_hi, (c + 1) << sd.a2) - (c << sd.a2);
-      const uint32_t t0 = sd.tile_first[c], nt = sd.tile_first[c + 1] - t0;
-      const uint64_t* keys = sd.keys + sd.bucket_off[c];
-      for (uint32_t g0 = 0; g0 < nt; g0 += kWaves * 64) {
+      const uint32_t s_lo = max(u_lo, c << a2) - (c << a2);
+      const uint32_t s_hi = min(u_hi, (c + 1) << a2) - (c << a2);
+      const uint32_t t0 = tile_first[c], nt = tile_first[c + 1] - t0;
+      const auto keys = seg_keys + bucket_off[c];
+      for (uint32_t g0 = 0; g0 < nt; g0 += NW * 64) {
         const uint32_t tw = g0 + wave_id();  // this wave's first tile (bucket-relative)
         if (tw >= nt) break;
-        const uint32_t nj = min(64u, (nt - tw + kWaves - 1) / kWaves);
-        const uint32_t ti = tw + kWaves * lane_id();
+        const uint32_t nj = min(64u, (nt - tw + NW - 1) / NW);
+        const uint32_t ti = tw + NW * lane_id();
         uint32_t mm0 = 0, mm1 = 0;
         if (lane_id() < nj) {
-          const uint32_t* m = sd.meta2 + (uint64_t)(t0 + ti) * (nb2 + 1);
+          const auto m = meta2 + (uint64_t)(t0 + ti) * (nb2 + 1);
           mm0 = m[s_lo];
           mm1 = m[s_hi];
         }
         uint32_t j = 0;
         uint32_t i = __builtin_amdgcn_readlane(mm0, 0), e = __builtin_amdgcn_readlane(mm1, 0);
         // next B chunks of the walk (wave-uniform), their loads issued
+        // The B loads are issued unconditionally, after the bookkeeping, so
+        // that the compiler can count them and wait for the older batch only.
+        // Lanes without a key load the bucket's first key (the bucket holds
+        // at least one, as it has a tile) and are masked off in vmask.
         auto next = [&](RunBatch<B>& r) {
+          uint32_t off[B];
           r.n = 0;
           r.vmask = 0;
 #pragma unroll
@@ -524,26 +557,33 @@ __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint
                 e = __builtin_amdgcn_readlane(mm1, j);
               }
             }
-            r.kv[b] = 0;
+            off[b] = 0;
             if (j < nj) {
               const uint32_t idx = i + lane_id();
-              if (idx < e) {
-                r.kv[b] = keys[(uint64_t)(tw + kWaves * j) * kT2 + idx];
-                r.vmask |= 1u << b;
-              }
+              const bool ok = idx < e;
+              off[b] = ok ? (tw + NW * j) * kT2 + idx : 0u;
+              r.vmask |= (uint32_t)ok << b;
               i += 64;
               r.n = b + 1;
             }
           }
+#pragma unroll
+          for (int b = 0; b < B; ++b) r.kv[b] = keys[off[b]];
         };
-        RunBatch<B> cur;
-        next(cur);
-        while (cur.n) {
-          RunBatch<B> ahead;
-          next(ahead);
-          fn(cur.kv, cur.vmask, cur.n);
-          cur = ahead;
+        // Two batches alternate roles (no copy of registers whose loads are
+        // still in flight, which would have to wait for them).
+        RunBatch<B> x, y;
+        next(x);
+        while (x.n) {
+          next(y);
+          fn(x.kv, x.vmask, x.n);
+          if (!y.n) break;
+          next(x);
+          fn(y.kv, y.vmask, y.n);
         }
+        // The last batch's (masked) loads land here, once per group of
+        // tiles, instead of at the loop head on every pass.
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
       }
     }
   }
@@ -562,21 +602,6 @@ __device__ __forceinline__ void bloom_positions(const HashCfg& hc, uint64_t x, u
     for (int j = 0; j < i; ++j) d |= pos[j] == pos[i];
     dup[i] = d;
   }
-}
-
-// Level-2 test of x against the block's level-2 bits held in LDS.
-template <int H>
-__device__ __forceinline__ bool bloom_screen(const HashCfg& hc, const uint32_t* L2, uint64_t x) {
-  uint32_t w[H], p[H];
-#pragma unroll
-  for (int i = 0; i < H; ++i) {
-    p[i] = (uint32_t)(mix64(x ^ hc.salt[i + 1]) >> (64 - hc.bl));
-    w[i] = L2[p[i] >> 5];
-  }
-  bool pass = true;
-#pragma unroll
-  for (int i = 0; i < H; ++i) pass &= ((w[i] >> (p[i] & 31)) & 1u) != 0;
-  return pass;
 }
 
 __device__ __forceinline__ uint32_t home_slot(uint64_t th, uint32_t cap) {
@@ -607,41 +632,22 @@ __device__ void overflow_add(const CountArgs& A, uint64_t x, uint32_t tag, uint6
   atomicOr(A.err, (uint32_t)ERR_OVF_FULL);
 }
 
-// One workgroup per Bloom block.  Pass 1 builds the block's two Bloom levels
-// in LDS from every occurrence of its partitions (level 1 records a first hit
-// of a bit, level 2 a second) and writes them out.  Pass 2, per partition:
-// every occurrence probes an LDS open-addressing table; hits count at once,
-// misses (keys not yet in the table) queue per wave and are screened against
-// level 2 (kept in LDS) densely, 64 at a time; passing keys are inserted (CAS on the key,
-// add on the count), failing ones dropped.  A key whose probe sequence fills
-// up goes, with all its occurrences, to the device overflow table.  The table
-// is then written to HBM with counts below min_count zeroed.
+// Pass 1 (Prune), one workgroup per Bloom block: the block's two levels are
+// built in LDS from every occurrence of its partitions (every occurrence hits
+// each distinct bit of S(x) once; level 1 records a first hit of a bit, level
+// 2 a second one) and written out with their popcounts.
 template <int H>
-__global__ void __launch_bounds__(kThreads) k_count(const CountArgs A) {
+__global__ void __launch_bounds__(kThreads) k_bloom(const CountArgs A) {
   extern __shared__ uint32_t lds[];
   const HashCfg& hc = A.hc;
   const uint32_t blk = blockIdx.x;
   const uint32_t nbw = A.nbw;
-  const uint32_t cap = A.cap;
-  const uint32_t nc = hc.nc;
   const uint32_t u0 = blk << A.upb_log2, nu = 1u << A.upb_log2;
-  const uint64_t bit0 = (uint64_t)blk << hc.bl;
   uint32_t* L2 = lds;
   uint32_t* L1 = lds + A.l2w;
-  uint64_t* tk = reinterpret_cast<uint64_t*>(lds + A.l2w);  // pass 2 table overlays level 1
-  uint32_t* tc = reinterpret_cast<uint32_t*>(tk + cap);
-  uint64_t* qk = reinterpret_cast<uint64_t*>(tc + (size_t)cap * nc) + wave_id() * 64;
-  uint32_t* qs = reinterpret_cast<uint32_t*>(reinterpret_cast<uint64_t*>(tc + (size_t)cap * nc) +
-                                             kWaves * 64) + wave_id() * 64;
-
-  uint64_t st[kNst];
-#pragma unroll
-  for (int i = 0; i < kNst; ++i) st[i] = 0;
-
-  // ---- pass 1: Bloom levels of this block
   for (uint32_t i = threadIdx.x; i < A.l2w + nbw; i += kThreads) lds[i] = 0;
   __syncthreads();
-  for_runs<8>(A, u0, u0 + nu, [&](const uint64_t (&kv)[8], uint32_t vmask, uint32_t nbat) {
+  for_runs<kWaves, 8>(A, u0, u0 + nu, [&](const uint64_t (&kv)[8], uint32_t vmask, uint32_t nbat) {
     constexpr int G = 2;  // keys whose level-1 updates are in flight together
 #pragma unroll
     for (int g = 0; g < 8 / G; ++g) {
@@ -669,27 +675,86 @@ __global__ void __launch_bounds__(kThreads) k_count(const CountArgs A) {
     }
   });
   __syncthreads();
+  uint64_t p1 = 0, p2 = 0;
   if (hc.bl >= 5) {
     for (uint32_t i = threadIdx.x; i < nbw; i += kThreads) {
       const uint32_t a = L1[i], b = L2[i];
       A.b1[(uint64_t)blk * nbw + i] = a;
       A.b2[(uint64_t)blk * nbw + i] = b;
-      st[ST_B1POP] += __popc(a);
-      st[ST_B2POP] += __popc(b);
+      p1 += __popc(a);
+      p2 += __popc(b);
     }
   } else if (threadIdx.x == 0) {
+    const uint64_t bit0 = (uint64_t)blk << hc.bl;
     const uint32_t msk = (1u << (1u << hc.bl)) - 1u;
     const uint32_t a = L1[0] & msk, b = L2[0] & msk;
     atomicOr(&A.b1[bit0 >> 5], a << (bit0 & 31));
     atomicOr(&A.b2[bit0 >> 5], b << (bit0 & 31));
-    st[ST_B1POP] += __popc(a);
-    st[ST_B2POP] += __popc(b);
+    p1 += __popc(a);
+    p2 += __popc(b);
   }
-  __syncthreads();  // level 1 is dead from here: its LDS holds the count table
+  p1 = wave_sum(p1);
+  p2 = wave_sum(p2);
+  __syncthreads();
+  uint64_t* red = reinterpret_cast<uint64_t*>(lds);
+  if (lane_id() == 0) {
+    red[wave_id() * 2] = p1;
+    red[wave_id() * 2 + 1] = p2;
+  }
+  __syncthreads();
+  if (threadIdx.x < kNst) {
+    uint64_t v = 0;
+    if (threadIdx.x == ST_B1POP || threadIdx.x == ST_B2POP)
+      for (int w = 0; w < kWaves; ++w) v += red[w * 2 + (threadIdx.x == ST_B2POP)];
+    A.pstats[(uint64_t)blk * kNst + threadIdx.x] = v;
+  }
+}
 
-  // ---- pass 2: screen and exact count, one partition at a time
+// Partition handled by workgroup i.  The hardware hands consecutive
+// workgroups to the 8 XCDs in turn; this mapping gives the partitions of one
+// Bloom block to workgroups of one XCD, launched close together, so that
+// block's level-2 words are read through one L2.
+__device__ __forceinline__ uint32_t tally_partition(uint32_t i, uint32_t upb_log2, uint32_t p_log2) {
+  const uint32_t upb = 1u << upb_log2;
+  if (p_log2 < upb_log2 + 3) return i;
+  const uint32_t xcd = i & 7, slot = i >> 3;
+  return (slot & (upb - 1)) + upb * (xcd + 8 * (slot >> upb_log2));
+}
+
+constexpr int kTallyThreads = kTallyWaves * 64;
+
+// Pass 2 (Count) and Unify, one workgroup per partition.  Every occurrence
+// probes the partition's LDS open-addressing table; hits count at once; misses
+// (keys not yet in the table) queue per wave and are screened against level 2
+// densely, 64 at a time; passing keys are inserted (CAS on the key, add on the
+// count), failing ones dropped.  A key whose probe sequence fills up goes,
+// with all its occurrences, to the device overflow table.  The table is then
+// written to HBM with counts below min_count zeroed.
+template <int H>
+__global__ void __launch_bounds__(kTallyThreads)
+k_tally(const CountArgs A) {
+  extern __shared__ uint32_t lds[];
+  const HashCfg& hc = A.hc;
+  const uint32_t u = tally_partition(blockIdx.x, A.upb_log2, hc.p_log2);
+  const uint32_t cap = A.cap;
+  const uint32_t nc = hc.nc;
+  const uint32_t blk = u >> A.upb_log2;
+  const uint64_t bit0 = (uint64_t)blk << hc.bl;
+  const uint32_t* b2 = A.b2;
+  uint64_t* tk = reinterpret_cast<uint64_t*>(lds);
+  uint32_t* tc = reinterpret_cast<uint32_t*>(tk + cap);
+  uint64_t* qk = reinterpret_cast<uint64_t*>(tc + (size_t)cap * nc) + wave_id() * 64;
+  uint32_t* qs = reinterpret_cast<uint32_t*>(reinterpret_cast<uint64_t*>(tc + (size_t)cap * nc) +
+                                             kTallyWaves * 64) + wave_id() * 64;
+  uint32_t n_ovf = 0;  // occurrences counted in the overflow table
   const uint32_t limit = A.probe_limit;
+
+  for (uint32_t i = threadIdx.x; i < cap; i += kTallyThreads) tk[i] = kEmpty;
+  for (uint32_t i = threadIdx.x; i < cap * nc; i += kTallyThreads) tc[i] = 0;
+  __syncthreads();
+
   auto drain = [&](uint32_t n) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     const bool have = lane_id() < n;
     uint64_t key = 0;
     uint32_t at = 0;
@@ -699,12 +764,25 @@ __global__ void __launch_bounds__(kThreads) k_count(const CountArgs A) {
     }
     const uint64_t x = key & kKeyMask;
     const uint32_t tag = (uint32_t)(key >> 62);
-    if (have && bloom_screen<H>(hc, L2, x)) {
+    bool pass = false;
+    if (have) {
+      uint32_t w[H], p[H];
+#pragma unroll
+      for (int i = 0; i < H; ++i) {
+        const uint64_t g = bit0 + (mix64(x ^ hc.salt[i + 1]) >> (64 - hc.bl));
+        p[i] = (uint32_t)(g & 31);
+        w[i] = b2[g >> 5];
+      }
+      pass = true;
+#pragma unroll
+      for (int i = 0; i < H; ++i) pass &= ((w[i] >> p[i]) & 1u) != 0;
+    }
+    if (pass) {
       uint32_t slot = at & 0xFFFF, probes = at >> 16;
       const uint64_t th = (x ^ hc.salt[0]) * kTableMul;
       for (;;) {
         if (probes >= limit) {
-          st[ST_OVF] += 1;
+          ++n_ovf;
           overflow_add(A, x, tag, mix64(th));
           break;
         }
@@ -725,104 +803,100 @@ __global__ void __launch_bounds__(kThreads) k_count(const CountArgs A) {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   };
 
-  for (uint32_t uu = 0; uu < nu; ++uu) {
-    const uint32_t u = u0 + uu;
-    for (uint32_t i = threadIdx.x; i < cap; i += kThreads) tk[i] = kEmpty;
-    for (uint32_t i = threadIdx.x; i < cap * nc; i += kThreads) tc[i] = 0;
-    __syncthreads();
-    uint32_t qn = 0;  // wave-uniform queue length
-    constexpr int B2 = 4;  // chunks per batch in pass 2 (register budget)
-    for_runs<B2>(A, u, u + 1, [&](const uint64_t (&kv)[B2], uint32_t vmask, uint32_t nbat) {
-      // first probe of every key of the batch, issued before any is resolved
-      uint64_t cur[B2];
-      uint32_t slot0[B2];
+  uint32_t qn = 0;  // wave-uniform queue length
+  constexpr int B2 = 2;
+  for_runs<kTallyWaves, B2>(A, u, u + 1, [&](const uint64_t (&kv)[B2], uint32_t vmask,
+                                            uint32_t nbat) {
+    // first probe of every key of the batch, issued before any is resolved
+    uint64_t cur[B2];
+    uint32_t slot0[B2];
 #pragma unroll
-      for (int b = 0; b < B2; ++b) {
-        const uint64_t x = kv[b] & kKeyMask;
-        slot0[b] = home_slot((x ^ hc.salt[0]) * kTableMul, cap);
-        cur[b] = ((vmask >> b) & 1u) ? __hip_atomic_load(&tk[slot0[b]], __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_WORKGROUP)
-                                     : 0;
-      }
-#pragma unroll
-      for (int b = 0; b < B2; ++b) {
-        if (b >= (int)nbat) break;
-        const uint64_t key = kv[b];
-        const uint64_t x = key & kKeyMask;
-        const uint32_t tag = (uint32_t)(key >> 62);
-        bool miss = false;
-        uint32_t at = 0;
-        if ((vmask >> b) & 1u) {
-          uint32_t slot = slot0[b], probes = 0;
-          uint64_t c = cur[b];
-          for (;;) {
-            if (c == x) {
-              atomicAdd(&tc[slot * nc + tag], 1u);
-              break;
-            }
-            if (c == kEmpty) {
-              miss = true;
-              break;
-            }
-            slot = slot + 1 == cap ? 0 : slot + 1;
-            if (++probes >= limit) {
-              miss = true;
-              break;
-            }
-            c = __hip_atomic_load(&tk[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          }
-          at = slot | (probes << 16);
-        }
-        const uint64_t mb = __ballot(miss);
-        const uint32_t nm = (uint32_t)__popcll(mb);
-        if (!nm) continue;
-        const uint32_t rank = (uint32_t)__popcll(mb & ((1ull << lane_id()) - 1));
-        const uint32_t room = 64 - qn;
-        if (miss && rank < room) {
-          qk[qn + rank] = key;
-          qs[qn + rank] = at;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        if (nm >= room) {
-          drain(64);
-          if (miss && rank >= room) {
-            qk[rank - room] = key;
-            qs[rank - room] = at;
-          }
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-          qn = nm - room;
-        } else {
-          qn += nm;
-        }
-      }
-    });
-    if (qn) drain(qn);
-    __syncthreads();
-    const uint64_t base = (uint64_t)u * cap;
-    for (uint32_t i = threadIdx.x; i < cap; i += kThreads) {
-      const uint64_t key = tk[i];
-      uint32_t c0 = tc[i * nc], c1 = nc > 1 ? tc[i * nc + 1] : 0;
-      if (key != kEmpty) {
-        const uint64_t tot = (uint64_t)c0 + c1;
-        st[ST_PASSED] += 1;
-        st[ST_NPASS] += tot;
-        st[ST_FP] += (tot == 1);
-        if (tot >= hc.min_count) {
-          st[ST_ENTRIES] += 1;
-          st[ST_SUM] += tot;
-        } else {
-          c0 = c1 = 0;
-        }
-      }
-      A.tkeys[base + i] = key;
-      A.tcounts[(base + i) * nc] = c0;
-      if (nc > 1) A.tcounts[(base + i) * nc + 1] = c1;
+    for (int b = 0; b < B2; ++b) {
+      const uint64_t x = kv[b] & kKeyMask;
+      slot0[b] = home_slot((x ^ hc.salt[0]) * kTableMul, cap);
+      cur[b] = ((vmask >> b) & 1u) ? __hip_atomic_load(&tk[slot0[b]], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_WORKGROUP)
+                                   : 0;
     }
-    __syncthreads();
-  }
+#pragma unroll
+    for (int b = 0; b < B2; ++b) {
+      if (b >= (int)nbat) break;
+      const uint64_t key = kv[b];
+      const uint64_t x = key & kKeyMask;
+      const uint32_t tag = (uint32_t)(key >> 62);
+      bool miss = false;
+      uint32_t at = 0;
+      if ((vmask >> b) & 1u) {
+        uint32_t slot = slot0[b], probes = 0;
+        uint64_t c = cur[b];
+        for (;;) {
+          if (c == x) {
+            atomicAdd(&tc[slot * nc + tag], 1u);
+            break;
+          }
+          if (c == kEmpty) {
+            miss = true;
+            break;
+          }
+          slot = slot + 1 == cap ? 0 : slot + 1;
+          if (++probes >= limit) {
+            miss = true;
+            break;
+          }
+          c = __hip_atomic_load(&tk[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        at = slot | (probes << 16);
+      }
+      const uint64_t mb = __ballot(miss);
+      const uint32_t nm = (uint32_t)__popcll(mb);
+      if (!nm) continue;
+      const uint32_t rank = (uint32_t)__popcll(mb & ((1ull << lane_id()) - 1));
+      const uint32_t room = 64 - qn;
+      if (miss && rank < room) {
+        qk[qn + rank] = key;
+        qs[qn + rank] = at;
+      }
+      if (nm >= room) {
+        drain(64);
+        if (miss && rank >= room) {
+          qk[rank - room] = key;
+          qs[rank - room] = at;
+        }
+        qn = nm - room;
+      } else {
+        qn += nm;
+      }
+    }
+  });
+  if (qn) drain(qn);
+  __syncthreads();
 
-  // block statistics: wave sums, then one row per block (LDS table is free)
-  uint64_t* red = reinterpret_cast<uint64_t*>(lds + A.l2w);
+  uint64_t st[kNst];
+#pragma unroll
+  for (int i = 0; i < kNst; ++i) st[i] = 0;
+  st[ST_OVF] = n_ovf;
+  const uint64_t base = (uint64_t)u * cap;
+  for (uint32_t i = threadIdx.x; i < cap; i += kTallyThreads) {
+    const uint64_t key = tk[i];
+    uint32_t c0 = tc[i * nc], c1 = nc > 1 ? tc[i * nc + 1] : 0;
+    if (key != kEmpty) {
+      const uint64_t tot = (uint64_t)c0 + c1;
+      st[ST_PASSED] += 1;
+      st[ST_NPASS] += tot;
+      st[ST_FP] += (tot == 1);
+      if (tot >= hc.min_count) {
+        st[ST_ENTRIES] += 1;
+        st[ST_SUM] += tot;
+      } else {
+        c0 = c1 = 0;
+      }
+    }
+    A.tkeys[base + i] = key;
+    A.tcounts[(base + i) * nc] = c0;
+    if (nc > 1) A.tcounts[(base + i) * nc + 1] = c1;
+  }
+  __syncthreads();
+  uint64_t* red = reinterpret_cast<uint64_t*>(lds);
 #pragma unroll
   for (int i = 0; i < kNst; ++i) {
     const uint64_t v = wave_sum(st[i]);
@@ -831,8 +905,8 @@ __global__ void __launch_bounds__(kThreads) k_count(const CountArgs A) {
   __syncthreads();
   if (threadIdx.x < kNst) {
     uint64_t sum = 0;
-    for (int w = 0; w < kWaves; ++w) sum += red[w * kNst + threadIdx.x];
-    A.pstats[(uint64_t)blk * kNst + threadIdx.x] = sum;
+    for (int w = 0; w < kTallyWaves; ++w) sum += red[w * kNst + threadIdx.x];
+    A.pstats2[(uint64_t)u * kNst + threadIdx.x] = sum;
   }
 }
 
@@ -1131,27 +1205,45 @@ hipError_t launch_level2(const uint64_t* keys1, const uint64_t* off1, const uint
 }
 
 template <int H>
-hipError_t launch_count_h(const CountArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_count<H>),
+hipError_t launch_bloom_h(const CountArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bloom<H>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_count<H>, dim3(blocks), dim3(kThreads), lds, s, a);
+  hipLaunchKernelGGL(k_bloom<H>, dim3(blocks), dim3(kThreads), lds, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_count(const CountArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
-  switch (a.hc.h) {
-    case 1: return launch_count_h<1>(a, blocks, lds, s);
-    case 2: return launch_count_h<2>(a, blocks, lds, s);
-    case 3: return launch_count_h<3>(a, blocks, lds, s);
-    case 4: return launch_count_h<4>(a, blocks, lds, s);
-    case 5: return launch_count_h<5>(a, blocks, lds, s);
-    case 6: return launch_count_h<6>(a, blocks, lds, s);
-    case 7: return launch_count_h<7>(a, blocks, lds, s);
-    case 8: return launch_count_h<8>(a, blocks, lds, s);
-  }
-  return hipErrorInvalidValue;
+template <int H>
+hipError_t launch_tally_h(const CountArgs& a, uint32_t parts, size_t lds, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_tally<H>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tally<H>, dim3(parts), dim3(kTallyThreads), lds, s, a);
+  return hipGetLastError();
 }
+
+#define KC_DISPATCH_H(fn, ...)                     \
+  switch (a.hc.h) {                                \
+    case 1: return fn<1>(__VA_ARGS__);             \
+    case 2: return fn<2>(__VA_ARGS__);             \
+    case 3: return fn<3>(__VA_ARGS__);             \
+    case 4: return fn<4>(__VA_ARGS__);             \
+    case 5: return fn<5>(__VA_ARGS__);             \
+    case 6: return fn<6>(__VA_ARGS__);             \
+    case 7: return fn<7>(__VA_ARGS__);             \
+    case 8: return fn<8>(__VA_ARGS__);             \
+  }                                                \
+  return hipErrorInvalidValue;
+
+hipError_t launch_bloom(const CountArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
+  KC_DISPATCH_H(launch_bloom_h, a, blocks, lds, s)
+}
+
+hipError_t launch_tally(const CountArgs& a, uint32_t parts, size_t lds, hipStream_t s) {
+  KC_DISPATCH_H(launch_tally_h, a, parts, lds, s)
+}
+
+int tally_threads() { return kTallyThreads; }
 
 hipError_t launch_ovf_emit(const CountArgs& a, uint64_t* pstats_ovf, uint32_t blocks,
                            hipStream_t s) {

@@ -96,7 +96,7 @@ struct kc_ctx {
   HashCfg hc{};
   uint32_t s_log2 = 0, p_log2 = 0, cap = 0, a1 = 0, a2 = 0, upb_log2 = 0;
   uint32_t nbw = 1, l2w = 2, slot_bytes = 12;
-  size_t count_lds = 0;
+  size_t count_lds = 0, tally_lds = 0;
   uint64_t bloom_words64 = 1;
 
   DevBuf b1, b2;
@@ -104,7 +104,7 @@ struct kc_ctx {
   DevBuf derr;    // u32 error flags
   DevBuf packed, flags, hist1, lstart1, off1, parts, keys1, tile_run;
   DevBuf segdesc;
-  DevBuf tkeys, tcounts, resident, pstats, pstats_ovf;
+  DevBuf tkeys, tcounts, resident, pstats, pstats2, pstats_ovf;
   DevBuf okeys, ocounts, ovf_used;
   DevBuf qrows, qcount;
   uint32_t ovf_log2 = 12;
@@ -252,10 +252,11 @@ kc_status derive(kc_ctx* c) {
   c->nbw = f.bloom_block_log2 >= 5 ? (1u << (f.bloom_block_log2 - 5)) : 1u;
   c->l2w = (c->nbw + 1) & ~1u;
   c->slot_bytes = 8 + 4 * f.n_counters;
-  // pass 2 of the count kernel: table (cap slots) + per-wave miss queues in LDS
-  const uint32_t cap_max =
-      (uint32_t)(((size_t)kLdsMax - 4 * (size_t)c->l2w - kQueueBytes) / c->slot_bytes / 64 * 64);
-  if (cap_max < 64) return fail(c, KC_ERR_INVALID_ARG, "Bloom block leaves no LDS for a table");
+  // k_bloom: the block's two levels in LDS.  k_tally: a partition table (cap
+  // slots) plus per-wave miss queues; by default three workgroups fit a CU.
+  const uint32_t cap_max = (uint32_t)(((size_t)kLdsMax - kQueueBytes) / c->slot_bytes / 64 * 64);
+  const uint32_t cap_def =
+      (uint32_t)(((size_t)kLdsMax / 3 - kQueueBytes) / c->slot_bytes / 64 * 64);
   if (f.table_slots) {
     const uint32_t want = f.table_slots / 64 * 64;
     if (want < 64 || want > cap_max)
@@ -263,12 +264,13 @@ kc_status derive(kc_ctx* c) {
                   "table_slots must be in 64.." + std::to_string(cap_max));
     c->cap = want;
   } else {
-    c->cap = cap_max;
+    c->cap = cap_def;
   }
-  c->count_lds = 4 * (size_t)c->l2w +
-                 std::max(std::max((size_t)4 * c->nbw, (size_t)c->cap * c->slot_bytes + kQueueBytes),
-                          (size_t)kWaves * kNst * 8);
-  if (c->count_lds > (size_t)kLdsMax) return fail(c, KC_ERR_INVALID_ARG, "LDS layout too large");
+  c->count_lds = std::max((size_t)4 * (c->l2w + c->nbw), (size_t)kWaves * 2 * 8);
+  c->tally_lds = std::max((size_t)c->cap * c->slot_bytes + kQueueBytes,
+                          (size_t)kTallyWaves * kNst * 8);
+  if (c->count_lds > (size_t)kLdsMax || c->tally_lds > (size_t)kLdsMax)
+    return fail(c, KC_ERR_INVALID_ARG, "LDS layout too large");
   // two shuffle levels: a1 bits in the first, the rest in the second
   c->a1 = f.scatter_bits ? std::min<uint32_t>(f.scatter_bits, c->p_log2 - 1)
                          : std::min<uint32_t>((c->p_log2 + 1) / 2, kMaxA1);
@@ -445,7 +447,7 @@ kc_status kc_create(const kc_config* cfg, int device, kc_ctx** out) {
   const size_t bloom_bytes = c->bloom_words64 * 8;
   if (c->b1.ensure(bloom_bytes) != hipSuccess || c->b2.ensure(bloom_bytes) != hipSuccess)
     return bail(KC_ERR_OUT_OF_MEMORY, "Bloom level allocation failed");
-  if (c->dstat.ensure(kNst * 8 * 2) != hipSuccess || c->derr.ensure(8) != hipSuccess ||
+  if (c->dstat.ensure(kNst * 8 * 3) != hipSuccess || c->derr.ensure(8) != hipSuccess ||
       c->ovf_used.ensure(8) != hipSuccess || c->qcount.ensure(8) != hipSuccess)
     return bail(KC_ERR_OUT_OF_MEMORY, "device allocation failed");
   if (hipHostMalloc(reinterpret_cast<void**>(&c->pinned), 4096, hipHostMallocDefault) != hipSuccess) {
@@ -591,6 +593,7 @@ kc_status kc_finalize(kc_ctx* c, void* hip_stream, kc_stats* out) {
   KC_HIP(c, c->tcounts.ensure(nparts * cap * 4 * nc), "table allocation");
   KC_HIP(c, c->resident.ensure(nparts * 4), "residency map");
   KC_HIP(c, c->pstats.ensure((1ull << c->s_log2) * kNst * 8), "stats rows");
+  KC_HIP(c, c->pstats2.ensure(nparts * kNst * 8), "stats rows");
 
   std::vector<SegDesc> hd(c->segs.size());
   for (size_t i = 0; i < c->segs.size(); ++i) {
@@ -647,9 +650,15 @@ kc_status kc_finalize(kc_ctx* c, void* hip_stream, kc_stats* out) {
     a.ovf_used = c->ovf_used.as<uint32_t>();
     a.err = c->derr.as<uint32_t>();
     a.pstats = c->pstats.as<uint64_t>();
+    a.pstats2 = c->pstats2.as<uint64_t>();
     {
-      StageTimer t(c, s, KC_T_COUNT);
-      KC_HIP(c, launch_count(a, 1u << c->s_log2, c->count_lds, s), "count kernel");
+      StageTimer t(c, s, KC_T_BLOOM);
+      KC_HIP(c, launch_bloom(a, 1u << c->s_log2, c->count_lds, s), "Bloom kernel");
+      t.stop();
+    }
+    {
+      StageTimer t(c, s, KC_T_TALLY);
+      KC_HIP(c, launch_tally(a, (uint32_t)nparts, c->tally_lds, s), "count kernel");
       t.stop();
     }
     {
@@ -659,15 +668,17 @@ kc_status kc_finalize(kc_ctx* c, void* hip_stream, kc_stats* out) {
              "reduce");
       KC_HIP(c, launch_reduce(c->pstats_ovf.as<uint64_t>(), oblocks, c->dstat.as<uint64_t>() + kNst, s),
              "reduce");
+      KC_HIP(c, launch_reduce(c->pstats2.as<uint64_t>(), nparts, c->dstat.as<uint64_t>() + 2 * kNst, s),
+             "reduce");
       t.stop();
     }
-    KC_HIP(c, hipMemcpyAsync(c->pinned, c->dstat.p, 2 * kNst * 8, hipMemcpyDeviceToHost, s), "readback");
-    KC_HIP(c, hipMemcpyAsync(c->pinned + 2 * kNst, c->derr.p, 4, hipMemcpyDeviceToHost, s), "readback");
-    KC_HIP(c, hipMemcpyAsync(c->pinned + 2 * kNst + 1, c->ovf_used.p, 4, hipMemcpyDeviceToHost, s),
+    KC_HIP(c, hipMemcpyAsync(c->pinned, c->dstat.p, 3 * kNst * 8, hipMemcpyDeviceToHost, s), "readback");
+    KC_HIP(c, hipMemcpyAsync(c->pinned + 3 * kNst, c->derr.p, 4, hipMemcpyDeviceToHost, s), "readback");
+    KC_HIP(c, hipMemcpyAsync(c->pinned + 3 * kNst + 1, c->ovf_used.p, 4, hipMemcpyDeviceToHost, s),
            "readback");
     KC_HIP(c, hipStreamSynchronize(s), "stream synchronise");
-    errf = (uint32_t)c->pinned[2 * kNst];
-    for (int i = 0; i < kNst; ++i) sv[i] = c->pinned[i] + c->pinned[kNst + i];
+    errf = (uint32_t)c->pinned[3 * kNst];
+    for (int i = 0; i < kNst; ++i) sv[i] = c->pinned[i] + c->pinned[kNst + i] + c->pinned[2 * kNst + i];
     if (!(errf & (ERR_OVF_FULL | ERR_OVF_LOAD))) break;
     if (c->st.retries >= 6 || c->ovf_log2 + 3 > 34)
       return fail(c, KC_ERR_OUT_OF_MEMORY, "overflow table kept filling up");
@@ -681,10 +692,9 @@ kc_status kc_finalize(kc_ctx* c, void* hip_stream, kc_stats* out) {
   c->st.b1_popcount = sv[ST_B1POP];
   c->st.b2_popcount = sv[ST_B2POP];
   c->st.passed_distinct = sv[ST_PASSED];
-  c->st.overflow_keys = (uint32_t)(c->pinned[2 * kNst] >> 32);
   {
     uint32_t used = 0;
-    memcpy(&used, reinterpret_cast<uint8_t*>(c->pinned + 2 * kNst + 1), 4);
+    memcpy(&used, reinterpret_cast<uint8_t*>(c->pinned + 3 * kNst + 1), 4);
     c->st.overflow_keys = used;
   }
   // residency map: all resident, then spill down to the budget
@@ -923,7 +933,7 @@ void kc_destroy(kc_ctx* c) {
   for (Segment& g : c->spare_segs) g.release();
   DevBuf* bufs[] = {&c->b1, &c->b2, &c->dstat, &c->derr, &c->packed, &c->flags, &c->hist1,
                     &c->lstart1, &c->off1, &c->parts, &c->keys1, &c->tile_run, &c->segdesc, &c->tkeys, &c->tcounts, &c->resident,
-                    &c->pstats, &c->pstats_ovf, &c->okeys, &c->ocounts, &c->ovf_used, &c->qrows,
+                    &c->pstats, &c->pstats2, &c->pstats_ovf, &c->okeys, &c->ocounts, &c->ovf_used, &c->qrows,
                     &c->qcount};
   for (DevBuf* b : bufs) b->release();
   free_spill(c);

@@ -161,9 +161,9 @@ class Workload:
 # count is set from the expected distinct k-mers per Bloom block).
 WORKLOADS = {
     "plain_1mbp": Workload("plain_1mbp", 1, 1_000_000, 20_000, 100, 100, 0.01, 0.0,
-                           31, 24, 3, 19, 7),
+                           31, 24, 3, 19, 8),
     "plain_100mbp": Workload("plain_100mbp", 2, 100_000_000, 10_000_000, 100, 100, 0.005, 0.001,
-                             31, 32, 4, 19, 15),
+                             31, 32, 4, 19, 16),
     "batched_200mbp": Workload("batched_200mbp", 3, 200_000_000, 0, 100, 250, 0.005, 0.0,
                                31, 35, 4, 19, 16),
     "served_300mbp": Workload("served_300mbp", 4, 300_000_000, 30_000_000, 100, 100, 0.005, 0.0,
