@@ -10,6 +10,8 @@ namespace kc {
 constexpr uint64_t kEmpty = ~0ull;              // empty table slot (no key reaches it: x < 2^62)
 constexpr uint64_t kKeyMask = (1ull << 62) - 1; // key bits; bit 62 carries the counter tag
 constexpr uint64_t kTableMul = 0xD6E8FEB86659FD93ull; // odd multiplier of the table slot hash
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;          // partition table not in HBM (spilled)
+constexpr uint32_t kProbeLimit = 128;              // probes before a key goes to the overflow table
 constexpr int kThreads = 1024;                  // block size of the tile kernels
 constexpr int kWaves = kThreads / 64;
 constexpr int kTileWords = 512;                 // first-level tile: 512 packed words
@@ -49,6 +51,9 @@ struct CountArgs {
   const SegDesc* segs;
   uint32_t nsegs;
   uint32_t upb_log2;     // partitions per Bloom block (log2)
+  uint32_t part_base;    // k_tally: first partition of this launch
+  uint32_t part_n;       // k_tally: partitions in this launch (= grid size)
+  uint32_t slot_base;    // k_tally: table slot of partition part_base
   uint32_t nbw;          // u32 words per Bloom block and level
   uint32_t l2w;          // LDS words reserved for level 2 (even)
   uint32_t cap;          // slots per partition table (multiple of 64)
@@ -72,13 +77,14 @@ struct QueryArgs {
   uint64_t cap;            // slots per partition table
   const uint64_t* tkeys;
   const uint32_t* tcounts;
-  const uint32_t* resident; // partition -> 1 if its table is in HBM
+  const uint32_t* slot_of;  // partition -> its table slot in HBM, or kNoSlot if spilled
   const uint64_t* okeys;
   const uint32_t* ocounts;
   const uint32_t* ovf_used;
   uint32_t ovf_log2;
   uint32_t* err;
   uint32_t* host_rows;     // indices of queries on spilled partitions
+  uint64_t* host_keys;     // their canonical keys (same order)
   uint32_t* host_count;
 };
 
@@ -112,12 +118,12 @@ hipError_t launch_reduce(const uint64_t* rows, uint64_t nrows, uint64_t* out, hi
 hipError_t launch_query(const QueryArgs& a, const uint64_t* kmers, uint64_t n, uint32_t* out,
                         hipStream_t s);
 hipError_t launch_export(const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,
-                         const uint32_t* resident, uint32_t cap, uint32_t nc,
+                         const uint32_t* live, uint32_t cap, uint32_t nc,
                          uint64_t* out_keys, uint32_t* out_counts, uint64_t out_cap,
                          uint64_t* cursor, hipStream_t s);
 hipError_t launch_debug_part(const SegDesc& sd, uint64_t n, uint32_t* part, hipStream_t s);
-hipError_t launch_gather_part(const uint64_t* tkeys, const uint32_t* tcounts, uint64_t base,
-                              uint64_t cap, uint32_t nc, uint64_t* out_keys, uint32_t* out_counts,
-                              uint64_t* cursor, hipStream_t s);
+hipError_t launch_slot_map(uint32_t* slot_of, uint32_t n, uint32_t first, hipStream_t s);
+hipError_t launch_scatter_rows(const uint32_t* rows, const uint32_t* vals, uint32_t n,
+                               uint32_t nc, uint32_t* out, hipStream_t s);
 
 }  // namespace kc

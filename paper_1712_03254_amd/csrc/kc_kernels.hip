@@ -714,9 +714,12 @@ __global__ void __launch_bounds__(kThreads) k_bloom(const CountArgs A) {
 // workgroups to the 8 XCDs in turn; this mapping gives the partitions of one
 // Bloom block to workgroups of one XCD, launched close together, so that
 // block's level-2 words are read through one L2.
-__device__ __forceinline__ uint32_t tally_partition(uint32_t i, uint32_t upb_log2, uint32_t p_log2) {
+// The launch covers n partitions starting at a Bloom-block boundary; the
+// mapping applies when n is a whole number of 8-block groups (otherwise the
+// identity).  Returns the partition's index within the launch.
+__device__ __forceinline__ uint32_t tally_partition(uint32_t i, uint32_t upb_log2, uint32_t n) {
   const uint32_t upb = 1u << upb_log2;
-  if (p_log2 < upb_log2 + 3) return i;
+  if (n & (8 * upb - 1)) return i;
   const uint32_t xcd = i & 7, slot = i >> 3;
   return (slot & (upb - 1)) + upb * (xcd + 8 * (slot >> upb_log2));
 }
@@ -735,7 +738,8 @@ __global__ void __launch_bounds__(kTallyThreads)
 k_tally(const CountArgs A) {
   extern __shared__ uint32_t lds[];
   const HashCfg& hc = A.hc;
-  const uint32_t u = tally_partition(blockIdx.x, A.upb_log2, hc.p_log2);
+  const uint32_t lu = tally_partition(blockIdx.x, A.upb_log2, A.part_n);
+  const uint32_t u = A.part_base + lu;
   const uint32_t cap = A.cap;
   const uint32_t nc = hc.nc;
   const uint32_t blk = u >> A.upb_log2;
@@ -875,7 +879,7 @@ k_tally(const CountArgs A) {
 #pragma unroll
   for (int i = 0; i < kNst; ++i) st[i] = 0;
   st[ST_OVF] = n_ovf;
-  const uint64_t base = (uint64_t)u * cap;
+  const uint64_t base = (uint64_t)(A.slot_base + lu) * cap;
   for (uint32_t i = threadIdx.x; i < cap; i += kTallyThreads) {
     const uint64_t key = tk[i];
     uint32_t c0 = tc[i * nc], c1 = nc > 1 ? tc[i * nc + 1] : 0;
@@ -998,20 +1002,21 @@ __global__ void __launch_bounds__(256) k_query(const QueryArgs A, const uint64_t
     const uint64_t x = q < r ? q : r;
     const uint64_t u = top_bits(mix64(x ^ hc.salt[0]), hc.p_log2);
     const uint64_t th = (x ^ hc.salt[0]) * kTableMul;
-    if (!A.resident[u]) {
-      const uint32_t at = atomicAdd(A.host_count, 1u);
-      A.host_rows[at] = (uint32_t)i;
-    } else {
-      uint64_t at;
-      const uint64_t th2 = mix64(th);
-      if (probe_table(A.tkeys, u * A.cap, A.cap, home_slot(th, A.cap), x, &at)) {
-        c0 = A.tcounts[at * nc];
-        if (nc > 1) c1 = A.tcounts[at * nc + 1];
-      } else if (*A.ovf_used && probe_table(A.okeys, 0, 1ull << A.ovf_log2,
-                                            th2 >> (64 - A.ovf_log2), x, &at)) {
-        c0 = A.ocounts[at * nc];
-        if (nc > 1) c1 = A.ocounts[at * nc + 1];
-      }
+    const uint32_t slot = A.slot_of[u];
+    uint64_t at;
+    // A key lives in its partition table or in the overflow table, never both.
+    if (slot != kNoSlot &&
+        probe_table(A.tkeys, (uint64_t)slot * A.cap, A.cap, home_slot(th, A.cap), x, &at)) {
+      c0 = A.tcounts[at * nc];
+      if (nc > 1) c1 = A.tcounts[at * nc + 1];
+    } else if (*A.ovf_used && probe_table(A.okeys, 0, 1ull << A.ovf_log2,
+                                          mix64(th) >> (64 - A.ovf_log2), x, &at)) {
+      c0 = A.ocounts[at * nc];
+      if (nc > 1) c1 = A.ocounts[at * nc + 1];
+    } else if (slot == kNoSlot) {
+      const uint32_t r = atomicAdd(A.host_count, 1u);  // answered from the host copy
+      A.host_rows[r] = (uint32_t)i;
+      A.host_keys[r] = x;
     }
   }
   out[i * nc] = c0;
@@ -1022,7 +1027,7 @@ __global__ void __launch_bounds__(256) k_query(const QueryArgs A, const uint64_t
 __global__ void __launch_bounds__(256) k_export(const uint64_t* __restrict__ tkeys,
                                                 const uint32_t* __restrict__ tcounts,
                                                 uint64_t nslots,
-                                                const uint32_t* __restrict__ resident,
+                                                const uint32_t* __restrict__ live,
                                                 uint32_t cap, uint32_t nc,
                                                 uint64_t* __restrict__ out_keys,
                                                 uint32_t* __restrict__ out_counts,
@@ -1032,7 +1037,7 @@ __global__ void __launch_bounds__(256) k_export(const uint64_t* __restrict__ tke
   bool take = false;
   uint64_t key = 0;
   uint32_t c0 = 0, c1 = 0;
-  if (i < nslots && (resident == nullptr || resident[i / cap])) {
+  if (i < nslots && (live == nullptr || live[i / cap])) {
     key = tkeys[i];
     c0 = tcounts[i * nc];
     c1 = nc > 1 ? tcounts[i * nc + 1] : 0;
@@ -1083,35 +1088,21 @@ __global__ void __launch_bounds__(256) k_debug_part(const SegDesc sd, uint64_t n
   part[i] = (c << sd.a2) | sub;
 }
 
-// Compacts one partition table (entries with a nonzero count) in slot order.
-__global__ void __launch_bounds__(256) k_gather_part(const uint64_t* __restrict__ tkeys,
-                                                     const uint32_t* __restrict__ tcounts,
-                                                     uint64_t base, uint64_t cap, uint32_t nc,
-                                                     uint64_t* __restrict__ out_keys,
-                                                     uint32_t* __restrict__ out_counts,
-                                                     uint64_t* __restrict__ cursor) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool take = false;
-  uint64_t key = 0;
-  uint32_t c0 = 0, c1 = 0;
-  if (i < cap) {
-    key = tkeys[base + i];
-    c0 = tcounts[(base + i) * nc];
-    c1 = nc > 1 ? tcounts[(base + i) * nc + 1] : 0;
-    take = key != kEmpty && (c0 | c1) != 0;
-  }
-  const uint64_t bal = __ballot(take);
-  if (!bal) return;
-  uint64_t b = 0;
-  if (lane_id() == (uint32_t)(__ffsll((unsigned long long)bal) - 1))
-    b = atomicAdd(reinterpret_cast<unsigned long long*>(cursor), (unsigned long long)__popcll(bal));
-  b = __shfl(b, __ffsll((unsigned long long)bal) - 1, 64);
-  if (take) {
-    const uint64_t at = b + __popcll(bal & ((1ull << lane_id()) - 1));
-    out_keys[at] = key;
-    out_counts[at * nc] = c0;
-    if (nc > 1) out_counts[at * nc + 1] = c1;
-  }
+// slot_of[u] = u - first for partitions u >= first (their tables sit in HBM
+// slots 0..), kNoSlot below (spilled to host memory).
+__global__ void __launch_bounds__(256) k_slot_map(uint32_t* __restrict__ slot_of, uint32_t n,
+                                                  uint32_t first) {
+  const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) slot_of[u] = u >= first ? u - first : kNoSlot;
+}
+
+// out[rows[i] * nc + t] = vals[i * nc + t]: results of queries answered on the host.
+__global__ void __launch_bounds__(256) k_scatter_rows(const uint32_t* __restrict__ rows,
+                                                      const uint32_t* __restrict__ vals, uint32_t n,
+                                                      uint32_t nc, uint32_t* __restrict__ out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (uint32_t t = 0; t < nc; ++t) out[(uint64_t)rows[i] * nc + t] = vals[(uint64_t)i * nc + t];
 }
 
 inline uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
@@ -1264,12 +1255,12 @@ hipError_t launch_query(const QueryArgs& a, const uint64_t* kmers, uint64_t n, u
 }
 
 hipError_t launch_export(const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,
-                         const uint32_t* resident, uint32_t cap, uint32_t nc,
+                         const uint32_t* live, uint32_t cap, uint32_t nc,
                          uint64_t* out_keys, uint32_t* out_counts, uint64_t out_cap,
                          uint64_t* cursor, hipStream_t s) {
   if (!nslots) return hipSuccess;
   hipLaunchKernelGGL(k_export, dim3(div_up(nslots, 256)), dim3(256), 0, s, tkeys, tcounts, nslots,
-                     resident, cap, nc, out_keys, out_counts, out_cap, cursor);
+                     live, cap, nc, out_keys, out_counts, out_cap, cursor);
   return hipGetLastError();
 }
 
@@ -1279,11 +1270,15 @@ hipError_t launch_debug_part(const SegDesc& sd, uint64_t n, uint32_t* part, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_gather_part(const uint64_t* tkeys, const uint32_t* tcounts, uint64_t base,
-                              uint64_t cap, uint32_t nc, uint64_t* out_keys, uint32_t* out_counts,
-                              uint64_t* cursor, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_part, dim3(div_up(cap, 256)), dim3(256), 0, s, tkeys, tcounts, base,
-                     cap, nc, out_keys, out_counts, cursor);
+hipError_t launch_slot_map(uint32_t* slot_of, uint32_t n, uint32_t first, hipStream_t s) {
+  hipLaunchKernelGGL(k_slot_map, dim3(div_up(n, 256)), dim3(256), 0, s, slot_of, n, first);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(const uint32_t* rows, const uint32_t* vals, uint32_t n,
+                               uint32_t nc, uint32_t* out, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_rows, dim3(div_up(n, 256)), dim3(256), 0, s, rows, vals, n, nc, out);
   return hipGetLastError();
 }
 

@@ -70,14 +70,14 @@ struct Segment {
   }
 };
 
-// One spilled partition: its entries (keys ascending by slot, counts) in
-// pinned host memory.  Mirrors the paper's swap metadata record (partition,
+// One spilled partition: its table (keys and counts in slot order) in pinned
+// host memory.  Mirrors the paper's swap metadata record (partition,
 // stale flag, byte offset, item count; Sec. III-D).
 struct SpillRec {
   uint32_t partition = 0;
   bool stale = false;
-  uint64_t host_offset = 0;  // entry index into the spill pool
-  uint64_t entries = 0;
+  uint64_t host_offset = 0;  // first slot of the table in the spill pool
+  uint64_t entries = 0;      // keys with a count at or above min_count
 };
 
 enum State { CREATED = 0, INSERTING = 1, FINALIZED = 2 };
@@ -104,9 +104,14 @@ struct kc_ctx {
   DevBuf derr;    // u32 error flags
   DevBuf packed, flags, hist1, lstart1, off1, parts, keys1, tile_run;
   DevBuf segdesc;
-  DevBuf tkeys, tcounts, resident, pstats, pstats2, pstats_ovf;
+  DevBuf tkeys, tcounts, pstats, pstats2, pstats_ovf;
+  DevBuf slot_of, slot_live;  // partition -> HBM table slot; slot -> holds a live table
   DevBuf okeys, ocounts, ovf_used;
-  DevBuf qrows, qcount;
+  DevBuf qrows, qkeys, qcount;
+  uint32_t pool_slots = 0;            // partition tables held in HBM (the budget's share)
+  std::vector<uint32_t> slot_of_h;    // host mirror of slot_of
+  hipStream_t copy_stream = nullptr;  // device-to-host spill copies
+  hipEvent_t ev_tally[2] = {nullptr, nullptr}, ev_copy[2] = {nullptr, nullptr};
   uint32_t ovf_log2 = 12;
   std::vector<Segment> segs, spare_segs;
   hipEvent_t insert_done = nullptr;
@@ -114,12 +119,14 @@ struct kc_ctx {
 
   uint64_t* pinned = nullptr;  // small pinned staging area (4 KiB)
 
-  // spill directory + pool (pinned host)
+  // spill directory + pool (pinned host).  The pool holds whole partition
+  // tables in their HBM layout (cap slots each), so host lookups probe them
+  // with the table's own slot function.
   std::vector<SpillRec> spill_dir;
   std::vector<int32_t> spill_of;  // partition -> index into spill_dir or -1
   uint64_t* spill_keys = nullptr;
   uint32_t* spill_counts = nullptr;
-  uint64_t spill_cap = 0, spill_used = 0;
+  uint64_t spill_cap = 0, spill_used = 0;  // in tables
 
   kc_stats st{};
 
@@ -283,38 +290,47 @@ kc_status derive(kc_ctx* c) {
 
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
+// Forgets the spill directory; the pinned pool stays for the next finalize.
 void free_spill(kc_ctx* c) {
-  if (c->spill_keys) (void)hipHostFree(c->spill_keys);
-  if (c->spill_counts) (void)hipHostFree(c->spill_counts);
-  c->spill_keys = nullptr;
-  c->spill_counts = nullptr;
-  c->spill_cap = c->spill_used = 0;
+  c->spill_used = 0;
   c->spill_dir.clear();
   c->spill_of.assign(1ull << c->p_log2, -1);
 }
 
-kc_status ensure_spill_pool(kc_ctx* c, uint64_t need) {
-  if (c->spill_used + need <= c->spill_cap) return KC_OK;
-  uint64_t cap = std::max<uint64_t>(c->spill_cap * 2, c->spill_used + need);
-  cap = std::max<uint64_t>(cap, 1 << 16);
+void release_spill_pool(kc_ctx* c) {
+  if (c->spill_keys) (void)hipHostFree(c->spill_keys);
+  if (c->spill_counts) (void)hipHostFree(c->spill_counts);
+  c->spill_keys = nullptr;
+  c->spill_counts = nullptr;
+  c->spill_cap = 0;
+  free_spill(c);
+}
+
+// Room for `tables` more partition tables in the pinned pool.  Growing keeps
+// the tables already there (a copy); finalize sizes the pool once per run.
+kc_status ensure_spill_pool(kc_ctx* c, uint64_t tables) {
+  if (c->spill_used + tables <= c->spill_cap) return KC_OK;
+  const uint64_t cap = c->cap, nc = c->cfg.n_counters;
+  const uint64_t want = std::max<uint64_t>(c->spill_used + tables,
+                                           c->spill_used ? c->spill_cap * 2 : 0);
   uint64_t* nk = nullptr;
   uint32_t* ncs = nullptr;
-  if (hipHostMalloc(reinterpret_cast<void**>(&nk), cap * 8, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&ncs), cap * 4 * c->cfg.n_counters,
-                    hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc(reinterpret_cast<void**>(&nk), want * cap * 8, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&ncs), want * cap * 4 * nc, hipHostMallocDefault) !=
+          hipSuccess) {
     (void)hipGetLastError();
     if (nk) (void)hipHostFree(nk);
     return fail(c, KC_ERR_OUT_OF_MEMORY, "pinned spill pool allocation failed");
   }
   if (c->spill_used) {
-    memcpy(nk, c->spill_keys, c->spill_used * 8);
-    memcpy(ncs, c->spill_counts, c->spill_used * 4 * c->cfg.n_counters);
+    memcpy(nk, c->spill_keys, c->spill_used * cap * 8);
+    memcpy(ncs, c->spill_counts, c->spill_used * cap * 4 * nc);
   }
   if (c->spill_keys) (void)hipHostFree(c->spill_keys);
   if (c->spill_counts) (void)hipHostFree(c->spill_counts);
   c->spill_keys = nk;
   c->spill_counts = ncs;
-  c->spill_cap = cap;
+  c->spill_cap = want;
   return KC_OK;
 }
 
@@ -325,64 +341,57 @@ kc_status sync_read(kc_ctx* c, hipStream_t s, const void* dev, size_t bytes, voi
   return KC_OK;
 }
 
-// Moves partition p's table (entries with a nonzero count, slot order) to the
-// pinned spill pool and marks it non-resident.
-kc_status spill_partition(kc_ctx* c, uint32_t p, hipStream_t s, uint64_t* bytes) {
-  if (c->spill_of[p] >= 0) return KC_OK;
-  const uint64_t cap = c->cap;
-  const uint32_t nc = c->cfg.n_counters;
-  DevBuf tmpk, tmpc, cur;
-  KC_HIP(c, tmpk.ensure(cap * 8), "spill staging");
-  KC_HIP(c, tmpc.ensure(cap * 4 * nc), "spill staging");
-  KC_HIP(c, cur.ensure(8), "spill cursor");
-  KC_HIP(c, hipMemsetAsync(cur.p, 0, 8, s), "memset");
-  StageTimer tm(c, s, KC_T_SPILL);
-  KC_HIP(c, launch_gather_part(c->tkeys.as<uint64_t>(), c->tcounts.as<uint32_t>(),
-                               (uint64_t)p * cap, cap, nc, tmpk.as<uint64_t>(),
-                               tmpc.as<uint32_t>(), cur.as<uint64_t>(), s),
-         "gather");
-  uint64_t n = 0;
-  kc_status r = sync_read(c, s, cur.p, 8, &n);
-  if (r != KC_OK) return r;
-  r = ensure_spill_pool(c, n);
-  if (r != KC_OK) return r;
-  if (n) {
-    KC_HIP(c, hipMemcpyAsync(c->spill_keys + c->spill_used, tmpk.p, n * 8, hipMemcpyDeviceToHost, s),
-           "spill copy");
-    KC_HIP(c, hipMemcpyAsync(c->spill_counts + c->spill_used * nc, tmpc.p, n * 4 * nc,
-                             hipMemcpyDeviceToHost, s),
-           "spill copy");
-  }
-  const uint32_t zero = 0;
-  KC_HIP(c, hipMemcpyAsync(c->resident.as<uint32_t>() + p, &zero, 4, hipMemcpyHostToDevice, s),
-         "resident flag");
-  tm.stop();
-  KC_HIP(c, hipStreamSynchronize(s), "spill synchronise");
-  tmpk.release();
-  tmpc.release();
-  cur.release();
+// Directory record for the table of partition p, already copied to pool
+// table t; entries come from the partition's statistics row.
+void add_spill_record(kc_ctx* c, uint32_t p, uint64_t t, uint64_t entries) {
   SpillRec rec;
   rec.partition = p;
   rec.stale = false;
-  rec.host_offset = c->spill_used;
-  rec.entries = n;
+  rec.host_offset = t * c->cap;
+  rec.entries = entries;
   c->spill_of[p] = (int32_t)c->spill_dir.size();
   c->spill_dir.push_back(rec);
-  c->spill_used += n;
   c->st.spilled_partitions += 1;
-  c->st.spilled_bytes += n * (8 + 4ull * nc);
-  if (bytes) *bytes += n * (8 + 4ull * nc);
-  return KC_OK;
+  c->st.spilled_bytes += (uint64_t)c->cap * c->slot_bytes;
 }
 
-uint64_t table_bytes_total(const kc_ctx* c) {
-  return (1ull << c->p_log2) * c->cap * c->slot_bytes;
+// Moves the HBM table of a resident partition p to the pinned pool; its slot
+// is then free (no longer exported or probed on the device).
+kc_status spill_partition(kc_ctx* c, uint32_t p, hipStream_t s, uint64_t* bytes) {
+  const uint32_t slot = c->slot_of_h[p];
+  if (slot == kNoSlot) return KC_OK;
+  const uint64_t cap = c->cap;
+  const uint32_t nc = c->cfg.n_counters;
+  kc_status r = ensure_spill_pool(c, 1);
+  if (r != KC_OK) return r;
+  const uint64_t t = c->spill_used;
+  StageTimer tm(c, s, KC_T_SPILL);
+  KC_HIP(c, hipMemcpyAsync(c->spill_keys + t * cap, c->tkeys.as<uint64_t>() + slot * cap, cap * 8,
+                           hipMemcpyDeviceToHost, s),
+         "spill copy");
+  KC_HIP(c, hipMemcpyAsync(c->spill_counts + t * cap * nc, c->tcounts.as<uint32_t>() + slot * cap * nc,
+                           cap * 4 * nc, hipMemcpyDeviceToHost, s),
+         "spill copy");
+  KC_HIP(c, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(c->slot_of.as<uint32_t>() + p),
+                              kNoSlot, 1, s),
+         "slot map");
+  KC_HIP(c, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(c->slot_live.as<uint32_t>() + slot),
+                              0, 1, s),
+         "slot map");
+  tm.stop();
+  uint64_t row[kNst];
+  r = sync_read(c, s, c->pstats2.as<uint64_t>() + (uint64_t)p * kNst, sizeof(row), row);
+  if (r != KC_OK) return r;
+  c->spill_used += 1;
+  c->slot_of_h[p] = kNoSlot;
+  add_spill_record(c, p, t, row[ST_ENTRIES]);
+  if (bytes) *bytes += cap * c->slot_bytes;
+  return KC_OK;
 }
 
 uint64_t resident_bytes(const kc_ctx* c) {
   uint64_t n = 0;
-  for (size_t p = 0; p < c->spill_of.size(); ++p)
-    if (c->spill_of[p] < 0) ++n;
+  for (uint32_t v : c->slot_of_h) n += v != kNoSlot;
   return n * c->cap * c->slot_bytes;
 }
 
@@ -582,18 +591,45 @@ kc_status kc_finalize(kc_ctx* c, void* hip_stream, kc_stats* out) {
   const uint32_t nc = c->cfg.n_counters;
   const uint64_t nparts = 1ull << c->p_log2;
   const uint64_t cap = c->cap;
-  const uint64_t all_tables = table_bytes_total(c);
   const uint64_t budget = c->cfg.hbm_table_budget_bytes;
   const uint64_t per_table = cap * c->slot_bytes;
   if (budget && budget < per_table)
     return fail(c, KC_ERR_OVER_BUDGET, "table budget smaller than one partition table");
-  // Every partition table is computed in HBM; partitions beyond the budget are
-  // moved to pinned host memory right after (highest index first).
-  KC_HIP(c, c->tkeys.ensure(nparts * cap * 8), "table allocation");
-  KC_HIP(c, c->tcounts.ensure(nparts * cap * 4 * nc), "table allocation");
-  KC_HIP(c, c->resident.ensure(nparts * 4), "residency map");
+  // HBM holds R partition tables (all of them, or what the budget pays for).
+  // The last R partitions are counted straight into their slots; the others
+  // are counted in waves through two staging halves of the same slots, and
+  // each wave's tables are copied to the pinned pool while the next wave runs.
+  // Table memory in HBM never exceeds R tables.
+  const uint64_t R = budget ? std::min<uint64_t>(nparts, budget / per_table) : nparts;
+  const uint64_t n_spill = nparts - R;
+  c->pool_slots = (uint32_t)R;
+  KC_HIP(c, c->tkeys.ensure(R * cap * 8), "table allocation");
+  KC_HIP(c, c->tcounts.ensure(R * cap * 4 * nc), "table allocation");
+  KC_HIP(c, c->slot_of.ensure(nparts * 4), "slot map");
+  KC_HIP(c, c->slot_live.ensure(R * 4), "slot map");
   KC_HIP(c, c->pstats.ensure((1ull << c->s_log2) * kNst * 8), "stats rows");
   KC_HIP(c, c->pstats2.ensure(nparts * kNst * 8), "stats rows");
+  free_spill(c);
+  c->st.spilled_partitions = 0;
+  c->st.spilled_bytes = 0;
+  uint64_t wave = 0, nbuf = 1;
+  if (n_spill) {
+    kc_status r = ensure_spill_pool(c, n_spill);
+    if (r != KC_OK) return r;
+    if (!c->copy_stream) KC_HIP(c, hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking),
+                                "copy stream");
+    for (int b = 0; b < 2; ++b) {
+      if (!c->ev_tally[b])
+        KC_HIP(c, hipEventCreateWithFlags(&c->ev_tally[b], hipEventDisableTiming), "event");
+      if (!c->ev_copy[b])
+        KC_HIP(c, hipEventCreateWithFlags(&c->ev_copy[b], hipEventDisableTiming), "event");
+    }
+    nbuf = R >= 2 ? 2 : 1;
+    wave = R / nbuf;
+    // whole groups of 8 Bloom blocks keep the XCD-aware partition order
+    const uint64_t group = 8ull << c->upb_log2;
+    if (wave >= group) wave -= wave % group;
+  }
 
   std::vector<SegDesc> hd(c->segs.size());
   for (size_t i = 0; i < c->segs.size(); ++i) {
@@ -638,7 +674,7 @@ kc_status kc_finalize(kc_ctx* c, void* hip_stream, kc_stats* out) {
     a.nbw = c->nbw;
     a.l2w = c->l2w;
     a.cap = c->cap;
-    a.probe_limit = (uint32_t)std::min<uint64_t>(cap, 128);
+    a.probe_limit = (uint32_t)std::min<uint64_t>(cap, kProbeLimit);
     a.ovf_log2 = c->ovf_log2;
     a.ovf_limit = (uint32_t)std::min<uint64_t>(on / 2, 0xFFFFFFFFull);
     a.b1 = c->b1.as<uint32_t>();
@@ -656,9 +692,45 @@ kc_status kc_finalize(kc_ctx* c, void* hip_stream, kc_stats* out) {
       KC_HIP(c, launch_bloom(a, 1u << c->s_log2, c->count_lds, s), "Bloom kernel");
       t.stop();
     }
+    // waves of spilled partitions
+    for (uint64_t first = 0, w = 0; first < n_spill; first += wave, ++w) {
+      const uint64_t n = std::min<uint64_t>(wave, n_spill - first);
+      const int b = (int)(w % nbuf);
+      const uint64_t slot0 = (uint64_t)b * wave;
+      if (w >= nbuf) KC_HIP(c, hipStreamWaitEvent(s, c->ev_copy[b], 0), "stream wait");
+      a.part_base = (uint32_t)first;
+      a.part_n = (uint32_t)n;
+      a.slot_base = (uint32_t)slot0;
+      {
+        StageTimer t(c, s, KC_T_TALLY);
+        KC_HIP(c, launch_tally(a, (uint32_t)n, c->tally_lds, s), "count kernel");
+        t.stop();
+      }
+      KC_HIP(c, hipEventRecord(c->ev_tally[b], s), "event");
+      KC_HIP(c, hipStreamWaitEvent(c->copy_stream, c->ev_tally[b], 0), "stream wait");
+      {
+        StageTimer t(c, c->copy_stream, KC_T_SPILL);
+        KC_HIP(c, hipMemcpyAsync(c->spill_keys + first * cap, c->tkeys.as<uint64_t>() + slot0 * cap,
+                                 n * cap * 8, hipMemcpyDeviceToHost, c->copy_stream),
+               "spill copy");
+        KC_HIP(c, hipMemcpyAsync(c->spill_counts + first * cap * nc,
+                                 c->tcounts.as<uint32_t>() + slot0 * cap * nc, n * cap * 4 * nc,
+                                 hipMemcpyDeviceToHost, c->copy_stream),
+               "spill copy");
+        t.stop();
+      }
+      KC_HIP(c, hipEventRecord(c->ev_copy[b], c->copy_stream), "event");
+    }
+    if (n_spill) {
+      for (uint64_t b = 0; b < nbuf; ++b) KC_HIP(c, hipStreamWaitEvent(s, c->ev_copy[b], 0), "stream wait");
+    }
+    // resident partitions, straight into their slots
+    a.part_base = (uint32_t)n_spill;
+    a.part_n = (uint32_t)R;
+    a.slot_base = 0;
     {
       StageTimer t(c, s, KC_T_TALLY);
-      KC_HIP(c, launch_tally(a, (uint32_t)nparts, c->tally_lds, s), "count kernel");
+      KC_HIP(c, launch_tally(a, (uint32_t)R, c->tally_lds, s), "count kernel");
       t.stop();
     }
     {
@@ -697,25 +769,44 @@ kc_status kc_finalize(kc_ctx* c, void* hip_stream, kc_stats* out) {
     memcpy(&used, reinterpret_cast<uint8_t*>(c->pinned + 3 * kNst + 1), 4);
     c->st.overflow_keys = used;
   }
-  // residency map: all resident, then spill down to the budget
-  {
-    std::vector<uint32_t> ones(nparts, 1u);
-    KC_HIP(c, hipMemcpy(c->resident.p, ones.data(), nparts * 4, hipMemcpyHostToDevice), "residency map");
+  // slot map: partitions below n_spill live in the pool, the rest in slots 0..R
+  KC_HIP(c, launch_slot_map(c->slot_of.as<uint32_t>(), (uint32_t)nparts, (uint32_t)n_spill, s), "slot map");
+  KC_HIP(c, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(c->slot_live.p), 1, R, s), "slot map");
+  c->slot_of_h.resize(nparts);
+  for (uint64_t u = 0; u < nparts; ++u) c->slot_of_h[u] = u < n_spill ? kNoSlot : (uint32_t)(u - n_spill);
+  if (n_spill) {
+    std::vector<uint64_t> rows(n_spill * kNst);
+    KC_HIP(c, hipMemcpyAsync(rows.data(), c->pstats2.p, rows.size() * 8, hipMemcpyDeviceToHost, s),
+           "readback");
+    KC_HIP(c, hipStreamSynchronize(s), "stream synchronise");
+    for (uint64_t u = 0; u < n_spill; ++u) add_spill_record(c, (uint32_t)u, u, rows[u * kNst + ST_ENTRIES]);
+    c->spill_used = n_spill;
   }
-  free_spill(c);
-  c->st.spilled_partitions = 0;
-  c->st.spilled_bytes = 0;
+  KC_HIP(c, hipStreamSynchronize(s), "stream synchronise");
   c->state = FINALIZED;
-  if (budget && all_tables > budget) {
-    uint64_t moved = 0;
-    for (int64_t p = (int64_t)nparts - 1; p >= 0 && resident_bytes(c) > budget; --p) {
-      kc_status r = spill_partition(c, (uint32_t)p, s, &moved);
-      if (r != KC_OK) return r;
-    }
-  }
   resolve_timers(c);
   if (out) *out = c->st;
   return KC_OK;
+}
+
+// Host lookup of a canonical key in the pinned copy of its partition table:
+// the same home slot and linear probing as on the device.
+void host_probe(const kc_ctx* c, const SpillRec& rec, uint64_t x, uint32_t* out) {
+  const uint64_t cap = c->cap;
+  const uint32_t nc = c->cfg.n_counters;
+  const uint64_t th = (x ^ c->hc.salt[0]) * kTableMul;
+  uint64_t slot = ((th >> 32) * cap) >> 32;
+  const uint64_t* keys = c->spill_keys + rec.host_offset;
+  const uint32_t* counts = c->spill_counts + rec.host_offset * nc;
+  for (uint64_t n = 0; n < cap; ++n) {
+    const uint64_t k = keys[slot];
+    if (k == x) {
+      for (uint32_t t = 0; t < nc; ++t) out[t] = counts[slot * nc + t];
+      return;
+    }
+    if (k == kEmpty) return;
+    slot = slot + 1 == cap ? 0 : slot + 1;
+  }
 }
 
 kc_status kc_query(kc_ctx* c, const uint64_t* kmers, uint64_t n, uint32_t* counts, void* hip_stream) {
@@ -727,7 +818,10 @@ kc_status kc_query(kc_ctx* c, const uint64_t* kmers, uint64_t n, uint32_t* count
   hipStream_t s = as_stream(hip_stream);
   KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
   const bool any_spill = !c->spill_dir.empty();
-  if (any_spill) KC_HIP(c, c->qrows.ensure(n * 4), "query rows");
+  if (any_spill) {
+    KC_HIP(c, c->qrows.ensure(n * 4), "query rows");
+    KC_HIP(c, c->qkeys.ensure(n * 8), "query keys");
+  }
   KC_HIP(c, hipMemsetAsync(c->derr.p, 0, 4, s), "memset");
   KC_HIP(c, hipMemsetAsync(c->qcount.p, 0, 4, s), "memset");
   QueryArgs a{};
@@ -735,13 +829,14 @@ kc_status kc_query(kc_ctx* c, const uint64_t* kmers, uint64_t n, uint32_t* count
   a.cap = c->cap;
   a.tkeys = c->tkeys.as<uint64_t>();
   a.tcounts = c->tcounts.as<uint32_t>();
-  a.resident = c->resident.as<uint32_t>();
+  a.slot_of = c->slot_of.as<uint32_t>();
   a.okeys = c->okeys.as<uint64_t>();
   a.ocounts = c->ocounts.as<uint32_t>();
   a.ovf_used = c->ovf_used.as<uint32_t>();
   a.ovf_log2 = c->ovf_log2;
   a.err = c->derr.as<uint32_t>();
   a.host_rows = any_spill ? c->qrows.as<uint32_t>() : nullptr;
+  a.host_keys = any_spill ? c->qkeys.as<uint64_t>() : nullptr;
   a.host_count = c->qcount.as<uint32_t>();
   {
     StageTimer t(c, s, KC_T_QUERY);
@@ -753,44 +848,32 @@ kc_status kc_query(kc_ctx* c, const uint64_t* kmers, uint64_t n, uint32_t* count
   KC_HIP(c, hipStreamSynchronize(s), "stream synchronise");
   const uint32_t errf = (uint32_t)c->pinned[0];
   const uint32_t nhost = (uint32_t)c->pinned[1];
+  if (errf & ERR_QUERY_RANGE) {
+    resolve_timers(c);
+    return fail(c, KC_ERR_INVALID_ARG, "query k-mer code >= 4^k");
+  }
   if (nhost) {
-    // queries on spilled partitions: answered from the pinned spill pool
+    // keys on spilled partitions: probed in the pinned table copies, results
+    // scattered back to their rows by one kernel
     const uint32_t nc = c->cfg.n_counters;
-    std::vector<uint32_t> rows(nhost);
     std::vector<uint64_t> q(nhost);
-    KC_HIP(c, hipMemcpy(rows.data(), c->qrows.p, nhost * 4ull, hipMemcpyDeviceToHost), "readback");
-    std::vector<uint32_t> res(nhost * (size_t)nc, 0);
-    for (uint32_t i = 0; i < nhost; ++i)
-      KC_HIP(c, hipMemcpy(&q[i], kmers + rows[i], 8, hipMemcpyDeviceToHost), "readback");
+    KC_HIP(c, hipMemcpyAsync(q.data(), c->qkeys.p, nhost * 8ull, hipMemcpyDeviceToHost, s), "readback");
+    KC_HIP(c, hipStreamSynchronize(s), "stream synchronise");
+    std::vector<uint32_t> res((size_t)nhost * nc, 0);
     for (uint32_t i = 0; i < nhost; ++i) {
-      const uint64_t v = q[i];
-      const uint64_t r = [&] {
-        uint64_t w = ~v;
-        w = ((w >> 2) & 0x3333333333333333ull) | ((w & 0x3333333333333333ull) << 2);
-        w = ((w >> 4) & 0x0F0F0F0F0F0F0F0Full) | ((w & 0x0F0F0F0F0F0F0F0Full) << 4);
-        return __builtin_bswap64(w) >> (64 - 2 * c->cfg.k);
-      }();
-      const uint64_t x = v < r ? v : r;
-      const uint64_t g = host_mix64(x ^ c->hc.salt[0]);
-      const uint32_t p = (uint32_t)(g >> (64 - c->p_log2));
+      const uint64_t x = q[i];
+      const uint32_t p = (uint32_t)(host_mix64(x ^ c->hc.salt[0]) >> (64 - c->p_log2));
       const int32_t d = c->spill_of[p];
-      if (d < 0) continue;
-      const SpillRec& rec = c->spill_dir[d];
-      for (uint64_t j = 0; j < rec.entries; ++j) {
-        if (c->spill_keys[rec.host_offset + j] == x) {
-          for (uint32_t t = 0; t < nc; ++t)
-            res[(size_t)i * nc + t] = c->spill_counts[(rec.host_offset + j) * nc + t];
-          break;
-        }
-      }
+      if (d >= 0) host_probe(c, c->spill_dir[d], x, &res[(size_t)i * nc]);
     }
-    for (uint32_t i = 0; i < nhost; ++i)
-      KC_HIP(c, hipMemcpy(counts + (uint64_t)rows[i] * nc, &res[(size_t)i * nc], 4ull * nc,
-                          hipMemcpyHostToDevice),
-             "spilled query results");
+    DevBuf vals;
+    KC_HIP(c, vals.ensure(res.size() * 4), "query results");
+    KC_HIP(c, hipMemcpyAsync(vals.p, res.data(), res.size() * 4, hipMemcpyHostToDevice, s), "results");
+    KC_HIP(c, launch_scatter_rows(c->qrows.as<uint32_t>(), vals.as<uint32_t>(), nhost, nc, counts, s),
+           "scatter");
+    KC_HIP(c, hipStreamSynchronize(s), "stream synchronise");
   }
   resolve_timers(c);
-  if (errf & ERR_QUERY_RANGE) return fail(c, KC_ERR_INVALID_ARG, "query k-mer code >= 4^k");
   return KC_OK;
 }
 
@@ -808,9 +891,13 @@ kc_status kc_spill(kc_ctx* c, int64_t partition, uint64_t* bytes_out) {
   if (partition != -1) return fail(c, KC_ERR_INVALID_ARG, "partition must be >= -1");
   const uint64_t budget = c->cfg.hbm_table_budget_bytes;
   if (!budget) return KC_OK;
-  for (int64_t p = (int64_t)nparts - 1; p >= 0 && resident_bytes(c) > budget; --p) {
+  uint64_t held = resident_bytes(c);
+  const uint64_t per_table = (uint64_t)c->cap * c->slot_bytes;
+  for (int64_t p = (int64_t)nparts - 1; p >= 0 && held > budget; --p) {
+    if (c->slot_of_h[p] == kNoSlot) continue;
     kc_status r = spill_partition(c, (uint32_t)p, s, bytes_out);
     if (r != KC_OK) return r;
+    held -= per_table;
   }
   return KC_OK;
 }
@@ -831,9 +918,9 @@ kc_status kc_export(kc_ctx* c, uint64_t* keys, uint32_t* counts, uint64_t cap, u
   KC_HIP(c, cur.ensure(8), "export cursor");
   hipStream_t s = nullptr;
   KC_HIP(c, hipMemsetAsync(cur.p, 0, 8, s), "memset");
-  const uint64_t nslots = (1ull << c->p_log2) * c->cap;
+  const uint64_t nslots = (uint64_t)c->pool_slots * c->cap;
   KC_HIP(c, launch_export(c->tkeys.as<uint64_t>(), c->tcounts.as<uint32_t>(), nslots,
-                          c->resident.as<uint32_t>(), c->cap, nc, ok.as<uint64_t>(),
+                          c->slot_live.as<uint32_t>(), c->cap, nc, ok.as<uint64_t>(),
                           oc.as<uint32_t>(), E, cur.as<uint64_t>(), s),
          "export");
   KC_HIP(c, launch_export(c->okeys.as<uint64_t>(), c->ocounts.as<uint32_t>(), 1ull << c->ovf_log2,
@@ -850,9 +937,19 @@ kc_status kc_export(kc_ctx* c, uint64_t* keys, uint32_t* counts, uint64_t cap, u
   KC_HIP(c, hipMemcpy(counts, oc.p, got * 4 * nc, hipMemcpyDeviceToHost), "export copy");
   uint64_t at = got;
   for (const SpillRec& rec : c->spill_dir) {
-    memcpy(keys + at, c->spill_keys + rec.host_offset, rec.entries * 8);
-    memcpy(counts + at * nc, c->spill_counts + rec.host_offset * nc, rec.entries * 4 * nc);
-    at += rec.entries;
+    const uint64_t* tk = c->spill_keys + rec.host_offset;
+    const uint32_t* tc = c->spill_counts + rec.host_offset * nc;
+    uint64_t taken = 0;
+    for (uint64_t i = 0; i < c->cap; ++i) {
+      uint32_t any = 0;
+      for (uint32_t t = 0; t < nc; ++t) any |= tc[i * nc + t];
+      if (tk[i] == kEmpty || !any) continue;
+      keys[at] = tk[i];
+      for (uint32_t t = 0; t < nc; ++t) counts[at * nc + t] = tc[i * nc + t];
+      ++at;
+      ++taken;
+    }
+    if (taken != rec.entries) return fail(c, KC_ERR_DEVICE, "spilled partition entry count mismatch");
   }
   return KC_OK;
 }
@@ -932,11 +1029,17 @@ void kc_destroy(kc_ctx* c) {
   for (Segment& g : c->segs) g.release();
   for (Segment& g : c->spare_segs) g.release();
   DevBuf* bufs[] = {&c->b1, &c->b2, &c->dstat, &c->derr, &c->packed, &c->flags, &c->hist1,
-                    &c->lstart1, &c->off1, &c->parts, &c->keys1, &c->tile_run, &c->segdesc, &c->tkeys, &c->tcounts, &c->resident,
-                    &c->pstats, &c->pstats2, &c->pstats_ovf, &c->okeys, &c->ocounts, &c->ovf_used, &c->qrows,
+                    &c->lstart1, &c->off1, &c->parts, &c->keys1, &c->tile_run, &c->segdesc,
+                    &c->tkeys, &c->tcounts, &c->slot_of, &c->slot_live, &c->pstats, &c->pstats2,
+                    &c->pstats_ovf, &c->okeys, &c->ocounts, &c->ovf_used, &c->qrows, &c->qkeys,
                     &c->qcount};
   for (DevBuf* b : bufs) b->release();
-  free_spill(c);
+  release_spill_pool(c);
+  for (int b = 0; b < 2; ++b) {
+    if (c->ev_tally[b]) (void)hipEventDestroy(c->ev_tally[b]);
+    if (c->ev_copy[b]) (void)hipEventDestroy(c->ev_copy[b]);
+  }
+  if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
   for (auto& t : c->pending) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);

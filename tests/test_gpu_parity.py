@@ -181,30 +181,51 @@ def test_joint_query_and_counters():
         assert np.array_equal(out.astype(np.uint32), ref.counts[:2000])
 
 
-def test_forced_spill_keeps_results():
+@pytest.mark.parametrize("tables,nc", [(100, 1), (1, 1), (3, 2), (255, 2)])
+def test_forced_spill_keeps_results(tables, nc):
+    """A table budget of `tables` partition tables: the other partitions are
+    counted in waves and copied to pinned host memory, and every result (the
+    exported table, queries on resident and spilled partitions, absent keys)
+    matches the run without a budget."""
     import torch
-    note("case: table budget forces spill of partitions to pinned host")
+    note("case: table budget of %d tables (of 256), %d counter(s): spill in waves" % (tables, nc))
     reads = random_reads(31, 3000, 50, 120, genome_len=6000)
-    cfg = kc.Config(k=27, bloom_bits_log2=20, bloom_hashes=3, bloom_block_log2=14,
+    cfg = kc.Config(k=27, n_counters=nc, bloom_bits_log2=20, bloom_hashes=3, bloom_block_log2=14,
                     partitions_log2=8, table_slots=256, seed=31)
-    full = run_gpu(cfg, [pack_reads(reads)])
-    per_table = (1 << 8) * 12
-    cfg.hbm_table_budget_bytes = per_table * 100  # 100 of 256 partitions stay in HBM
-    b, o = pack_reads(reads)
-    db, do = to_device(b, o)
+    chunks = [pack_reads(reads[:1500]), pack_reads(reads[1500:])]
+    counters = [0, 1] if nc == 2 else [0, 0]
+    per_table = 256 * (8 + 4 * nc)
+    cfg.hbm_table_budget_bytes = per_table * tables
+    # table, Bloom levels and statistics of the budgeted run against the oracle
+    _, ref = assert_parity(cfg, chunks, counters=counters)
+    full = {"keys": ref.keys, "counts": ref.counts.reshape(-1, nc)}
+    rng = np.random.default_rng(tables)
+    absent = rng.integers(0, 1 << (2 * cfg.k), 4000, dtype=np.uint64)
+    absent = absent[~np.isin(absent, full["keys"])]
+    qk = np.concatenate([full["keys"], absent])
+    want = np.zeros((qk.size, nc), np.uint32)
+    want[:full["keys"].size] = full["counts"]
     with kc.KmerCounter(cfg) as c:
-        c.insert_reads(db, do)
+        for (b, o), t in zip(chunks, counters):
+            db, do = to_device(b, o)
+            c.insert_reads(db, do, counter=t)
         st = c.finalize()
-        assert st["spilled_partitions"] == 156
+        assert st["spilled_partitions"] == 256 - tables
+        assert st["spilled_bytes"] == (256 - tables) * per_table
         keys, counts = c.export()
         assert_same_table(keys, counts, full["keys"], full["counts"])
-        q = torch.from_numpy(full["keys"].view(np.int64)).cuda()
-        out = c.query(q).cpu().numpy().astype(np.uint32)
-        assert np.array_equal(out, full["counts"])
-        moved = c.spill(3)
-        assert moved >= 0
-        out = c.query(q).cpu().numpy().astype(np.uint32)
-        assert np.array_equal(out, full["counts"])
+        q = torch.from_numpy(qk.view(np.int64)).cuda()
+        out = c.query(q).cpu().numpy().astype(np.uint32).reshape(-1, nc)
+        assert np.array_equal(out, want)
+        # explicit spill of a resident partition (the highest ones stay in HBM)
+        moved = c.spill(255)
+        assert moved == per_table
+        assert c.spill(255) == 0 and c.spill(0) == 0
+        out = c.query(q).cpu().numpy().astype(np.uint32).reshape(-1, nc)
+        assert np.array_equal(out, want)
+        keys, counts = c.export()
+        assert_same_table(keys, counts, full["keys"], full["counts"])
+        assert c.stats()["spilled_partitions"] == 257 - tables
 
 
 def test_edge_inputs():
