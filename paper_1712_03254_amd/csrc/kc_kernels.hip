@@ -491,14 +491,19 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
 
 // Calls fn(kv, vmask, nbat) for the stored occurrences of partitions
 // [u_lo, u_hi), across segments: kv[b] holds one key per lane for b < nbat,
-// valid where bit b of the lane's vmask is set (lanes past the end of a run
-// are not).  Every lane of a wave reaches every call.  The whole block must
-// call it.  The range's run inside a second-level tile is contiguous.  Wave w
-// takes tiles g0 + w + NW*j (j = lane; NW waves per workgroup), reads their
-// run bounds once into
-// its lanes, then walks the runs in chunks of 64 keys with wave-uniform
-// bookkeeping.  Loads of the next B chunks are issued before the current B
-// are handed to fn, so one batch is always in flight behind the one in use.
+// valid where bit b of the lane's vmask is set.  Every lane of a wave reaches
+// every call.  The whole block must call it.  The range's run inside a
+// second-level tile is contiguous.  Wave w takes tiles g0 + w + NW*j (j =
+// lane; NW waves per workgroup) and reads their run bounds once into its
+// lanes.  Loads of the next B chunks are issued before the current B are
+// handed to fn, so one batch is always in flight behind the one in use.
+//
+// FLAT = false walks run by run in chunks of 64 keys (a run's last chunk is
+// partly empty), with wave-uniform bookkeeping: right for long runs.
+// FLAT = true walks the concatenation of the wave's runs in full chunks of
+// 64: the wave prefix-sums the run lengths, and each lane finds the run that
+// holds its position by binary search over the sums (cross-lane reads):
+// right for short runs, where partly empty chunks would dominate.
 // s_waitcnt immediate (gfx9 encoding): vmcnt 0, expcnt and lgkmcnt unbounded.
 constexpr int kWaitVm0 = 0x0F70;
 
@@ -509,7 +514,17 @@ struct RunBatch {
   uint32_t n;      // chunks in the batch (wave-uniform)
 };
 
-template <int NW, int B, typename F>
+// Inclusive prefix sum across the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(v, d, 64);
+    if ((int)lane_id() >= d) v += o;
+  }
+  return v;
+}
+
+template <int NW, int B, bool FLAT, typename F>
 __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint32_t u_hi,
                                          F&& fn) {
   const auto segs = cview(A.segs);
@@ -537,14 +552,45 @@ __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint
           mm0 = m[s_lo];
           mm1 = m[s_hi];
         }
+        // Next B chunks of the walk, their loads issued.  The B loads are
+        // issued unconditionally, after the bookkeeping, so that the compiler
+        // can count them and wait for the older batch only.  Lanes without a
+        // key load the bucket's first key (the bucket holds at least one, as
+        // it has a tile) and are masked off in vmask.
         uint32_t j = 0;
         uint32_t i = __builtin_amdgcn_readlane(mm0, 0), e = __builtin_amdgcn_readlane(mm1, 0);
-        // next B chunks of the walk (wave-uniform), their loads issued
-        // The B loads are issued unconditionally, after the bookkeeping, so
-        // that the compiler can count them and wait for the older batch only.
-        // Lanes without a key load the bucket's first key (the bucket holds
-        // at least one, as it has a tile) and are masked off in vmask.
-        auto next = [&](RunBatch<B>& r) {
+        // FLAT: lane j's run starts at position excl of the concatenation
+        // (lanes past nj hold the total, which no position reaches)
+        const uint32_t len = mm1 - mm0;
+        const uint32_t incl = FLAT ? wave_incl_scan(len) : 0u;
+        const uint32_t total = FLAT ? __builtin_amdgcn_readlane(incl, 63) : 0u;
+        const uint32_t excl = lane_id() < nj ? incl - len : total;
+        uint32_t v0 = 0;  // FLAT: next position of the concatenation
+        auto next_flat = [&](RunBatch<B>& r) {
+          uint32_t off[B];
+          r.vmask = 0;
+          r.n = v0 < total ? min((uint32_t)B, (total - v0 + 63) >> 6) : 0u;
+#pragma unroll
+          for (int b = 0; b < B; ++b) {
+            const uint32_t v = v0 + 64 * b + lane_id();
+            const bool ok = v < total;
+            const uint32_t vc = ok ? v : 0u;
+            // largest run index jj with excl[jj] <= vc (excl is non-decreasing)
+            uint32_t jj = 0;
+#pragma unroll
+            for (int st = 32; st >= 1; st >>= 1) {
+              const uint32_t ex = __shfl(excl, jj + st, 64);
+              jj = ex <= vc ? jj + st : jj;
+            }
+            const uint32_t start = __shfl(mm0, jj, 64), ex = __shfl(excl, jj, 64);
+            off[b] = ok ? (tw + NW * jj) * kT2 + start + (vc - ex) : 0u;
+            r.vmask |= (uint32_t)ok << b;
+          }
+          v0 += 64 * B;
+#pragma unroll
+          for (int b = 0; b < B; ++b) r.kv[b] = keys[off[b]];
+        };
+        auto next_runs = [&](RunBatch<B>& r) {
           uint32_t off[B];
           r.n = 0;
           r.vmask = 0;
@@ -569,6 +615,12 @@ __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint
           }
 #pragma unroll
           for (int b = 0; b < B; ++b) r.kv[b] = keys[off[b]];
+        };
+        auto next = [&](RunBatch<B>& r) {
+          if constexpr (FLAT)
+            next_flat(r);
+          else
+            next_runs(r);
         };
         // Two batches alternate roles (no copy of registers whose loads are
         // still in flight, which would have to wait for them).
@@ -647,7 +699,7 @@ __global__ void __launch_bounds__(kThreads) k_bloom(const CountArgs A) {
   uint32_t* L1 = lds + A.l2w;
   for (uint32_t i = threadIdx.x; i < A.l2w + nbw; i += kThreads) lds[i] = 0;
   __syncthreads();
-  for_runs<kWaves, 8>(A, u0, u0 + nu, [&](const uint64_t (&kv)[8], uint32_t vmask, uint32_t nbat) {
+  for_runs<kWaves, 8, false>(A, u0, u0 + nu, [&](const uint64_t (&kv)[8], uint32_t vmask, uint32_t nbat) {
     constexpr int G = 2;  // keys whose level-1 updates are in flight together
 #pragma unroll
     for (int g = 0; g < 8 / G; ++g) {
@@ -809,7 +861,7 @@ k_tally(const CountArgs A) {
 
   uint32_t qn = 0;  // wave-uniform queue length
   constexpr int B2 = 2;
-  for_runs<kTallyWaves, B2>(A, u, u + 1, [&](const uint64_t (&kv)[B2], uint32_t vmask,
+  for_runs<kTallyWaves, B2, true>(A, u, u + 1, [&](const uint64_t (&kv)[B2], uint32_t vmask,
                                             uint32_t nbat) {
     // first probe of every key of the batch, issued before any is resolved
     uint64_t cur[B2];
