@@ -299,6 +299,8 @@ typedef struct {
   uint64_t n_valid;
   uint64_t lo, hi;
   const uint64_t* salt;
+  const uint64_t* blocks; /* mode 1: sorted Bloom blocks of the sampled bits */
+  uint64_t n_blocks;
   int mode; /* 0 = key counts, 1 = bit hits */
 } or_scan_job;
 
@@ -327,6 +329,10 @@ static void* or_scan_main(void* arg) {
         int64_t at = or_find(j->sample, j->n_sample, x);
         if (at >= 0) j->counts[at * p->n_counters + (j->tags ? j->tags[r] : 0)] += 1;
       } else {
+        /* every bit of S(x) lies in x's block: skip keys of other blocks */
+        uint32_t sb = p->m_log2 - p->block_log2;
+        uint64_t block = sb ? (or_mix64(x ^ j->salt[0]) >> (64 - sb)) : 0;
+        if (or_find(j->blocks, j->n_blocks, block) < 0) continue;
         uint32_t np = or_bloom_positions(p, j->salt, x, pos);
         for (uint32_t q = 0; q < np; ++q) {
           int64_t at = or_find(j->sample, j->n_sample, pos[q]);
@@ -349,6 +355,12 @@ static int or_scan(const or_params* p, const uint8_t* bases, const uint64_t* off
   uint64_t salt[9];
   or_salts(p, salt);
   uint64_t width = mode == 0 ? p->n_counters : 1;
+  uint64_t* blocks = (uint64_t*)malloc((n_sample ? n_sample : 1) * sizeof(uint64_t));
+  uint64_t n_blocks = 0;
+  for (uint64_t i = 0; i < n_sample; ++i) { /* sample is sorted, so are its blocks */
+    uint64_t b = sample[i] >> p->block_log2;
+    if (!n_blocks || blocks[n_blocks - 1] != b) blocks[n_blocks++] = b;
+  }
   or_scan_job jobs[128];
   pthread_t tid[128];
   for (int t = 0; t < threads; ++t) {
@@ -356,6 +368,7 @@ static int or_scan(const or_params* p, const uint8_t* bases, const uint64_t* off
     memset(j, 0, sizeof(*j));
     j->p = p; j->bases = bases; j->offsets = offsets; j->tags = tags;
     j->sample = sample; j->n_sample = n_sample; j->salt = salt; j->mode = mode;
+    j->blocks = blocks; j->n_blocks = n_blocks;
     j->counts = (uint32_t*)calloc((n_sample ? n_sample : 1) * width, sizeof(uint32_t));
     j->lo = n_reads * (uint64_t)t / (uint64_t)threads;
     j->hi = n_reads * (uint64_t)(t + 1) / (uint64_t)threads;
@@ -372,6 +385,7 @@ static int or_scan(const or_params* p, const uint8_t* bases, const uint64_t* off
     }
     free(jobs[t].counts);
   }
+  free(blocks);
   if (n_valid) *n_valid = nv;
   return 0;
 }

@@ -21,6 +21,7 @@ constexpr int kMaxA1 = 10;                      // first-level fan-out limit (bi
 constexpr int kMaxA2 = 11;                      // second-level fan-out limit (bits)
 constexpr int kMaxPartLog2 = kMaxA1 + kMaxA2;    // partitions (log2) two levels can reach
 constexpr int kLdsMax = 163840;                 // gfx950 LDS per workgroup
+constexpr int kLdsSlack = 2048;                 // LDS left unused per k_tally workgroup
 constexpr int kNst = 8;                         // statistics slots
 constexpr int kTallyWaves = 8;                  // waves per k_tally workgroup
 constexpr int kQueueBytes = kTallyWaves * 64 * 12;  // per-wave miss queues of k_tally

@@ -809,19 +809,47 @@ k_tally(const CountArgs A) {
   for (uint32_t i = threadIdx.x; i < cap * nc; i += kTallyThreads) tc[i] = 0;
   __syncthreads();
 
+  // Resolves the queued occurrences densely, 64 at a time.  Each walks its
+  // probe chain from the home slot: a key already in the table is counted
+  // there.  A key that reaches an empty slot (or the probe limit) is new: it
+  // is screened against level 2 and, if it passes, inserted from that slot on
+  // (CAS on the key, add on the count; a lost CAS continues the walk) or, at
+  // the probe limit, counted in the overflow table.  A failing key is
+  // dropped.
   auto drain = [&](uint32_t n) {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     const bool have = lane_id() < n;
     uint64_t key = 0;
-    uint32_t at = 0;
+    uint32_t slot = 0;
     if (have) {
       key = qk[lane_id()];
-      at = qs[lane_id()];
+      slot = qs[lane_id()];
     }
     const uint64_t x = key & kKeyMask;
     const uint32_t tag = (uint32_t)(key >> 62);
-    bool pass = false;
+    uint32_t probes = 0;
+    bool fresh = false;  // not in the table: needs the screen
     if (have) {
+      for (;;) {
+        const uint64_t c =
+            __hip_atomic_load(&tk[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (c == x) {
+          atomicAdd(&tc[slot * nc + tag], 1u);
+          break;
+        }
+        if (c == kEmpty) {
+          fresh = true;
+          break;
+        }
+        slot = slot + 1 == cap ? 0 : slot + 1;
+        if (++probes >= limit) {
+          fresh = true;
+          break;
+        }
+      }
+    }
+    bool pass = false;
+    if (fresh) {
       uint32_t w[H], p[H];
 #pragma unroll
       for (int i = 0; i < H; ++i) {
@@ -834,7 +862,6 @@ k_tally(const CountArgs A) {
       for (int i = 0; i < H; ++i) pass &= ((w[i] >> p[i]) & 1u) != 0;
     }
     if (pass) {
-      uint32_t slot = at & 0xFFFF, probes = at >> 16;
       const uint64_t th = (x ^ hc.salt[0]) * kTableMul;
       for (;;) {
         if (probes >= limit) {
@@ -862,8 +889,9 @@ k_tally(const CountArgs A) {
   uint32_t qn = 0;  // wave-uniform queue length
   constexpr int B2 = 2;
   for_runs<kTallyWaves, B2, true>(A, u, u + 1, [&](const uint64_t (&kv)[B2], uint32_t vmask,
-                                            uint32_t nbat) {
-    // first probe of every key of the batch, issued before any is resolved
+                                                  uint32_t nbat) {
+    // One probe at the home slot per occurrence: a hit counts at once; any
+    // other outcome (a new key, or a key further along its chain) is queued.
     uint64_t cur[B2];
     uint32_t slot0[B2];
 #pragma unroll
@@ -880,29 +908,10 @@ k_tally(const CountArgs A) {
       const uint64_t key = kv[b];
       const uint64_t x = key & kKeyMask;
       const uint32_t tag = (uint32_t)(key >> 62);
-      bool miss = false;
-      uint32_t at = 0;
-      if ((vmask >> b) & 1u) {
-        uint32_t slot = slot0[b], probes = 0;
-        uint64_t c = cur[b];
-        for (;;) {
-          if (c == x) {
-            atomicAdd(&tc[slot * nc + tag], 1u);
-            break;
-          }
-          if (c == kEmpty) {
-            miss = true;
-            break;
-          }
-          slot = slot + 1 == cap ? 0 : slot + 1;
-          if (++probes >= limit) {
-            miss = true;
-            break;
-          }
-          c = __hip_atomic_load(&tk[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-        at = slot | (probes << 16);
-      }
+      const bool valid = (vmask >> b) & 1u;
+      const bool hit = valid && cur[b] == x;
+      if (hit) atomicAdd(&tc[slot0[b] * nc + tag], 1u);
+      const bool miss = valid && !hit;
       const uint64_t mb = __ballot(miss);
       const uint32_t nm = (uint32_t)__popcll(mb);
       if (!nm) continue;
@@ -910,13 +919,13 @@ k_tally(const CountArgs A) {
       const uint32_t room = 64 - qn;
       if (miss && rank < room) {
         qk[qn + rank] = key;
-        qs[qn + rank] = at;
+        qs[qn + rank] = slot0[b];
       }
       if (nm >= room) {
         drain(64);
         if (miss && rank >= room) {
           qk[rank - room] = key;
-          qs[rank - room] = at;
+          qs[rank - room] = slot0[b];
         }
         qn = nm - room;
       } else {

@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/kc.h"
+#include "kc.h"
 #include "kc_internal.h"
 
 using namespace kc;
@@ -260,10 +260,12 @@ kc_status derive(kc_ctx* c) {
   c->l2w = (c->nbw + 1) & ~1u;
   c->slot_bytes = 8 + 4 * f.n_counters;
   // k_bloom: the block's two levels in LDS.  k_tally: a partition table (cap
-  // slots) plus per-wave miss queues; by default three workgroups fit a CU.
+  // slots) plus per-wave miss queues; by default three workgroups fit a CU,
+  // with kLdsSlack bytes to spare each (a table sized to the last byte of a
+  // third of the LDS measured as if only two fitted).
   const uint32_t cap_max = (uint32_t)(((size_t)kLdsMax - kQueueBytes) / c->slot_bytes / 64 * 64);
   const uint32_t cap_def =
-      (uint32_t)(((size_t)kLdsMax / 3 - kQueueBytes) / c->slot_bytes / 64 * 64);
+      (uint32_t)(((size_t)kLdsMax / 3 - kLdsSlack - kQueueBytes) / c->slot_bytes / 64 * 64);
   if (f.table_slots) {
     const uint32_t want = f.table_slots / 64 * 64;
     if (want < 64 || want > cap_max)

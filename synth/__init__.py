@@ -169,5 +169,5 @@ WORKLOADS = {
     "served_300mbp": Workload("served_300mbp", 4, 300_000_000, 30_000_000, 100, 100, 0.005, 0.0,
                               31, 32, 4, 19, 16, n_counters=2),
     "spill_3gbp": Workload("spill_3gbp", 5, 3_000_000_000, 200_000_000, 100, 100, 0.01, 0.0,
-                           31, 36, 4, 19, 19, table_budget=64 << 30),
+                           31, 36, 4, 19, 20, table_budget=64 << 30),
 }

@@ -67,6 +67,8 @@ PARAMS = [
     (13, 10, 3, 5, 0, 64, 1, 2, 8),     # 64-slot tables: overflow path and its regrowth
     (31, 22, 4, 12, 12, 128, 1, 2, 9),  # 128-slot tables at 2^12 partitions
     (31, 24, 4, 10, 18, 64, 1, 2, 10),  # 2^18 partitions: runs of 0-1 keys per tile
+    (31, 26, 4, 6, 20, 64, 1, 2, 12),   # 2^20 partitions: widest first level (2^10)
+    (31, 27, 3, 6, 21, 64, 2, 2, 13),   # 2^21 partitions: widest second level (2^11)
 ]
 
 

@@ -326,10 +326,15 @@ def test_sampled_counts_and_hits_match_full():
         assert int(c[0]) == int(np.count_nonzero(enum == x))
         if int(x) in t:
             assert t[int(x)] == (int(c[0]),)
-    bits = np.arange(0, 1 << 12, 5, dtype=np.uint64)
-    bs, hs = oracle.sample_hits(p, b, o, bits, threads=2)
     b1, b2 = bits_of(res.b1), bits_of(res.b2)
-    for bit, hcount in zip(bs, hs):
-        assert (int(hcount) >= 1) == (int(bit) in b1)
-        assert (int(hcount) >= 2) == (int(bit) in b2)
+    # every block sampled, then bits of two blocks only (keys of the other
+    # blocks are skipped by the scan and must not change the result)
+    for bits in (np.arange(0, 1 << 12, 5, dtype=np.uint64),
+                 np.concatenate([np.arange(3 * 64, 4 * 64, dtype=np.uint64),
+                                 np.arange(40 * 64 + 1, 41 * 64, 3, dtype=np.uint64)])):
+        bs, hs = oracle.sample_hits(p, b, o, bits, threads=2)
+        assert np.array_equal(bs, np.unique(bits))
+        for bit, hcount in zip(bs, hs):
+            assert (int(hcount) >= 1) == (int(bit) in b1)
+            assert (int(hcount) >= 2) == (int(bit) in b2)
     del full
