@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define KC_ABI_VERSION 1u
+#define KC_ABI_VERSION 2u
 
 typedef struct kc_ctx kc_ctx;
 
@@ -84,7 +84,8 @@ typedef struct kc_config {
   uint32_t table_slots;      /* slots per partition table, rounded down to a multiple of
                                 64 (>= 64); 0 = the largest that fits LDS */
   uint32_t scatter_bits;     /* first-level shuffle fan-out bits; 0 = automatic */
-  uint32_t flags;            /* must be 0 */
+  uint32_t group_bases_log2; /* kc_count_batch: at most 2^this bases (with padding) per key
+                                segment; 0 = 2^32 - 64, else 10..32 */
   uint64_t hbm_table_budget_bytes; /* device bytes the partition tables may use; 0 = unlimited */
 } kc_config;
 
@@ -99,6 +100,7 @@ enum {
   KC_T_UNIFY = 6,  /* overflow table pass, statistics reduction */
   KC_T_QUERY = 7,
   KC_T_SPILL = 8,  /* device -> pinned host copies of spilled partitions */
+  KC_T_GRAPH = 9,  /* kc_count_batch: the whole batch as one graph launch */
   KC_T_COUNT_OF = 16
 };
 
@@ -153,9 +155,12 @@ kc_status kc_insert_reads(kc_ctx* ctx, const uint8_t* bases_dev, const uint64_t*
  * Pass 2 and Unify (Sec. III): builds the Bloom levels, screens every
  * occurrence against level 2, counts the passing keys exactly per partition,
  * drops keys below min_count (false-positive singletons are counted in
- * fp_singletons) and leaves one open-addressing table per partition in HBM
- * (or in pinned host memory for partitions spilled under the table budget).
- * Synchronises.  out_host (may be NULL) receives the statistics.
+ * fp_singletons) and leaves one open-addressing table per partition.  With a
+ * table budget smaller than all tables, HBM holds only the tables the budget
+ * pays for (the highest partitions); the others are counted in waves and
+ * their tables copied to pinned host memory as each wave finishes (Sec.
+ * III-D's swap of full tables), so table memory in HBM never exceeds the
+ * budget.  Synchronises.  out_host (may be NULL) receives the statistics.
  */
 kc_status kc_finalize(kc_ctx* ctx, void* hip_stream, kc_stats* out_host);
 
@@ -206,6 +211,58 @@ kc_status kc_get_stats(const kc_ctx* ctx, kc_stats* out_host);
 /* Drops inserted reads, tables and spilled partitions; keeps allocations for
  * reuse.  Back to CREATED.  Synchronises the device. */
 kc_status kc_reset(kc_ctx* ctx);
+
+/*
+ * Batched form.  A chunk is a set of reads laid out as for kc_insert_reads.
+ */
+typedef struct kc_chunk {
+  const uint8_t* bases_dev;
+  const uint64_t* offsets_dev; /* n_reads + 1 entries */
+  uint64_t n_reads;
+  uint64_t total_bases;
+} kc_chunk;
+
+/*
+ * Counts a batch of read chunks into the shared Bloom levels and tables:
+ * the same result as kc_insert_reads on every chunk (in order, all with
+ * `counter`) followed by kc_finalize, produced by one hipGraph launch on
+ * hip_stream.  Consecutive chunks are packed side by side into key segments
+ * of at most 2^group_bases_log2 bases, each segment shuffled once; the graph
+ * (every kernel of every segment, then Bloom, count and Unify) is captured on
+ * the first call for a given chunk list and replayed by later calls with the
+ * same chunks (pointers and sizes), after kc_reset.  The context must be in
+ * CREATED state; afterwards it is FINALIZED.  Every partition table stays in
+ * HBM: a budget smaller than all tables returns KC_ERR_OVER_BUDGET.  Offsets
+ * that break kc_insert_reads' rules return KC_ERR_INVALID_ARG.  chunks_host
+ * is read during the call only.  Synchronises.
+ */
+kc_status kc_count_batch(kc_ctx* ctx, const kc_chunk* chunks_host, uint32_t n_chunks,
+                         uint32_t counter, void* hip_stream, kc_stats* out_host);
+
+/* One configuration timed by kc_autotune_batch. */
+typedef struct kc_tune_trial {
+  uint32_t partitions_log2;
+  uint32_t table_slots;
+  uint32_t scatter_bits;
+  int32_t status;          /* kc_status of the trial */
+  double ms;               /* fastest of the timed kc_count_batch calls */
+  uint64_t overflow_keys;
+} kc_tune_trial;
+
+/*
+ * Chooses the result-neutral parameters of kc_count_batch for a batch by
+ * measurement: partition count (around one partition per 2^13 key
+ * positions), table slots (load factor) and first-level fan-out (the shuffle's
+ * tile split).  Each candidate runs kc_count_batch on the batch itself on a
+ * context of its own; the fastest configuration without errors is written to
+ * *best_out (base's result-defining fields unchanged).  trials_host (may be
+ * NULL) receives up to max_trials records and *n_trials_out their number.
+ * Needs the memory of one batched count at a time.  Synchronises.
+ */
+kc_status kc_autotune_batch(const kc_config* base, int device, const kc_chunk* chunks_host,
+                            uint32_t n_chunks, uint32_t counter, void* hip_stream,
+                            kc_config* best_out, kc_tune_trial* trials_host,
+                            uint32_t max_trials, uint32_t* n_trials_out);
 
 /* Frees everything the context owns.  NULL is ignored. */
 void kc_destroy(kc_ctx* ctx);

@@ -28,11 +28,12 @@ KC_ERR_BAD_STATE = -3
 KC_ERR_DEVICE = -4
 KC_ERR_OVER_BUDGET = -5
 
-STAGES = ["pack", "level1", "scan", "level2", "bloom", "tally", "unify", "query", "spill"]
+STAGES = ["pack", "level1", "scan", "level2", "bloom", "tally", "unify", "query", "spill", "graph"]
 
 EXPORTED = ["kc_abi_version", "kc_status_str", "kc_create", "kc_insert_reads", "kc_finalize",
             "kc_query", "kc_spill", "kc_export", "kc_export_bloom", "kc_debug_keys",
-            "kc_get_stats", "kc_reset", "kc_destroy", "kc_last_error"]
+            "kc_get_stats", "kc_reset", "kc_destroy", "kc_last_error", "kc_count_batch",
+            "kc_autotune_batch"]
 
 
 class KcError(RuntimeError):
@@ -47,7 +48,22 @@ class KcConfig(ctypes.Structure):
                 ("bloom_hashes", ctypes.c_uint32), ("bloom_block_log2", ctypes.c_uint32),
                 ("seed", ctypes.c_uint64), ("partitions_log2", ctypes.c_uint32),
                 ("table_slots", ctypes.c_uint32), ("scatter_bits", ctypes.c_uint32),
-                ("flags", ctypes.c_uint32), ("hbm_table_budget_bytes", ctypes.c_uint64)]
+                ("group_bases_log2", ctypes.c_uint32),
+                ("hbm_table_budget_bytes", ctypes.c_uint64)]
+
+
+class KcChunk(ctypes.Structure):
+    _fields_ = [("bases_dev", ctypes.c_void_p), ("offsets_dev", ctypes.c_void_p),
+                ("n_reads", ctypes.c_uint64), ("total_bases", ctypes.c_uint64)]
+
+
+class KcTuneTrial(ctypes.Structure):
+    _fields_ = [("partitions_log2", ctypes.c_uint32), ("table_slots", ctypes.c_uint32),
+                ("scatter_bits", ctypes.c_uint32), ("status", ctypes.c_int32),
+                ("ms", ctypes.c_double), ("overflow_keys", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
 
 
 class KcStats(ctypes.Structure):
@@ -98,6 +114,9 @@ def load():
         "kc_reset": ([V], st),
         "kc_destroy": ([V], None),
         "kc_last_error": ([V], ctypes.c_char_p),
+        "kc_count_batch": ([V, P(KcChunk), U32, U32, V, P(KcStats)], st),
+        "kc_autotune_batch": ([P(KcConfig), ctypes.c_int, P(KcChunk), U32, U32, V, P(KcConfig),
+                               P(KcTuneTrial), U32, P(U32)], st),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -176,6 +195,33 @@ def kc_debug_keys(ctx):
     return keys[:e], part[:e]
 
 
+def _chunk_array(chunks):
+    arr = (KcChunk * max(1, len(chunks)))()
+    for i, (b, o, n, t) in enumerate(chunks):
+        arr[i] = KcChunk(b, o, n, t)
+    return arr
+
+
+def kc_count_batch(ctx, chunks, counter: int, stream_ptr: int) -> KcStats:
+    """chunks: list of (bases_ptr, offsets_ptr, n_reads, total_bases)."""
+    s = KcStats()
+    arr = _chunk_array(chunks)
+    _check(ctx, load().kc_count_batch(ctx, arr, len(chunks), counter, stream_ptr, ctypes.byref(s)))
+    return s
+
+
+def kc_autotune_batch(cfg: KcConfig, device: int, chunks, counter: int, stream_ptr: int):
+    """Returns (best KcConfig, list of trial dicts)."""
+    arr = _chunk_array(chunks)
+    best = KcConfig()
+    trials = (KcTuneTrial * 64)()
+    n = ctypes.c_uint32(0)
+    _check(None, load().kc_autotune_batch(ctypes.byref(cfg), device, arr, len(chunks), counter,
+                                          stream_ptr, ctypes.byref(best), trials, 64,
+                                          ctypes.byref(n)))
+    return best, [trials[i].as_dict() for i in range(min(n.value, 64))]
+
+
 def kc_get_stats(ctx) -> KcStats:
     s = KcStats()
     _check(ctx, load().kc_get_stats(ctx, ctypes.byref(s)))
@@ -211,12 +257,19 @@ class Config:
     table_slots: int = 0
     scatter_bits: int = 0
     hbm_table_budget_bytes: int = 0
+    group_bases_log2: int = 0
 
     def c(self) -> KcConfig:
         return KcConfig(self.k, self.n_counters, self.min_count, self.bloom_bits_log2,
                         self.bloom_hashes, min(self.bloom_block_log2, self.bloom_bits_log2),
                         self.seed & ((1 << 64) - 1), self.partitions_log2, self.table_slots,
-                        self.scatter_bits, 0, self.hbm_table_budget_bytes)
+                        self.scatter_bits, self.group_bases_log2, self.hbm_table_budget_bytes)
+
+    @staticmethod
+    def from_c(c: KcConfig) -> "Config":
+        return Config(c.k, c.n_counters, c.min_count, c.bloom_bits_log2, c.bloom_hashes,
+                      c.bloom_block_log2, c.seed, c.partitions_log2, c.table_slots,
+                      c.scatter_bits, c.hbm_table_budget_bytes, c.group_bases_log2)
 
 
 def _stream_ptr(stream) -> int:
@@ -224,6 +277,22 @@ def _stream_ptr(stream) -> int:
     if stream is None:
         stream = torch.cuda.current_stream()
     return int(stream.cuda_stream)
+
+
+def chunk_list(chunks):
+    """(bases, offsets) device tensor pairs -> kc_chunk tuples."""
+    out = []
+    for b, o in chunks:
+        out.append((b.data_ptr() if b.numel() else 0, o.data_ptr(), o.numel() - 1, b.numel()))
+    return out
+
+
+def autotune_batch(cfg: Config, chunks, counter: int = 0, device: int = 0, stream=None):
+    """Measured choice of partitions, table slots and shuffle split for a batch
+    (kc_autotune_batch).  Returns (best Config, trial records)."""
+    best, trials = kc_autotune_batch(cfg.c(), device, chunk_list(chunks), counter,
+                                     _stream_ptr(stream))
+    return Config.from_c(best), trials
 
 
 class KmerCounter:
@@ -269,6 +338,11 @@ class KmerCounter:
                           device=kmers.device)
         kc_query(self.ctx, kmers.data_ptr(), kmers.numel(), out.data_ptr(), _stream_ptr(stream))
         return out
+
+    def count_batch(self, chunks, counter: int = 0, stream=None) -> dict:
+        """chunks: list of (bases, offsets) device tensor pairs; inserts them all
+        and finalizes, as one graph launch (kc_count_batch)."""
+        return kc_count_batch(self.ctx, chunk_list(chunks), counter, _stream_ptr(stream)).as_dict()
 
     def spill(self, partition: int = -1) -> int:
         return kc_spill(self.ctx, partition)

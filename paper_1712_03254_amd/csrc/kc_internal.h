@@ -42,6 +42,19 @@ struct SegDesc {
   uint32_t a1, a2;
 };
 
+// One read chunk of a batch, placed in its group's position stream at
+// packed word word0 (chunks start on 32-base boundaries; the gap before the
+// next chunk holds invalid bases).  read0: exclusive prefix of (n_reads + 1)
+// over the group's chunks (one check slot per chunk end).
+struct ChunkDesc {
+  const uint8_t* bases;
+  const uint64_t* offsets;
+  uint64_t total;
+  uint64_t n_reads;
+  uint64_t word0;
+  uint64_t read0;
+};
+
 struct HashCfg {
   uint64_t salt[9];   // s_0 .. s_h
   uint32_t k, h, bl, s_log2, p_log2, nc, min_count, pad;
@@ -123,6 +136,13 @@ hipError_t launch_export(const uint64_t* tkeys, const uint32_t* tcounts, uint64_
                          uint64_t* out_keys, uint32_t* out_counts, uint64_t out_cap,
                          uint64_t* cursor, hipStream_t s);
 hipError_t launch_debug_part(const SegDesc& sd, uint64_t n, uint32_t* part, hipStream_t s);
+hipError_t launch_pack_batch(const ChunkDesc* cd, uint32_t nchunks, uint64_t nwords,
+                             uint64_t* packed, uint64_t* flags, hipStream_t s);
+hipError_t launch_rstart_batch(const ChunkDesc* cd, uint32_t nchunks, uint64_t nslots,
+                               uint64_t* flags, uint32_t* err, hipStream_t s);
+hipError_t launch_fill64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_fill32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_copy64(const uint64_t* src, uint64_t* dst, hipStream_t s);
 hipError_t launch_slot_map(uint32_t* slot_of, uint32_t n, uint32_t first, hipStream_t s);
 hipError_t launch_scatter_rows(const uint32_t* rows, const uint32_t* vals, uint32_t n,
                                uint32_t nc, uint32_t* out, hipStream_t s);

@@ -156,6 +156,90 @@ __global__ void __launch_bounds__(256) k_rstart(const uint64_t* __restrict__ off
              1ull << (32 + (o & 31)));
 }
 
+// Largest j < n with key(j) <= v, for a non-decreasing key (chunks with no
+// words or reads share their successor's start and are skipped).
+template <typename K>
+__device__ __forceinline__ uint32_t chunk_of(const ChunkDesc* cd, uint32_t n, uint64_t v, K key) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (key(cd[mid]) <= v) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// k_pack over the chunks of a batch group: word w of the group stream is word
+// w - word0 of its chunk (positions past the chunk's end are invalid).
+__global__ void __launch_bounds__(256) k_pack_batch(const ChunkDesc* __restrict__ cd,
+                                                    uint32_t nchunks, uint64_t nwords,
+                                                    uint64_t* __restrict__ packed,
+                                                    uint64_t* __restrict__ flags) {
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords;
+       w += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t j = chunk_of(cd, nchunks, w, [](const ChunkDesc& d) { return d.word0; });
+    const uint8_t* bases = cd[j].bases;
+    const uint64_t total = cd[j].total;
+    const uint64_t p0 = (w - cd[j].word0) * 32;
+    uint64_t code = 0;
+    uint32_t inv = 0;
+#pragma unroll 8
+    for (int i = 0; i < 32; ++i) {
+      const uint32_t c = p0 + i < total ? bases[p0 + i] : (uint32_t)'N';
+      const bool ok = (c == 'A') | (c == 'C') | (c == 'G') | (c == 'T');
+      const uint32_t cdv = ((c >> 1) ^ (c >> 2)) & 3u;  // A->0 C->1 G->2 T->3
+      code = (code << 2) | (ok ? cdv : 0u);
+      inv |= (ok ? 0u : 1u) << i;
+    }
+    packed[w] = code;
+    flags[w] = inv;
+  }
+}
+
+// k_rstart over the chunks of a batch group: slot i is read i - read0 of its
+// chunk, or the chunk's end check when that equals the chunk's read count.
+__global__ void __launch_bounds__(256) k_rstart_batch(const ChunkDesc* __restrict__ cd,
+                                                      uint32_t nchunks, uint64_t nslots,
+                                                      uint64_t* __restrict__ flags,
+                                                      uint32_t* __restrict__ err) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t j = chunk_of(cd, nchunks, i, [](const ChunkDesc& d) { return d.read0; });
+    const uint64_t r = i - cd[j].read0, n = cd[j].n_reads, total = cd[j].total;
+    const uint64_t* offsets = cd[j].offsets;
+    const uint64_t o = offsets[r];
+    if (r == 0 && o != 0) atomicOr(err, (uint32_t)ERR_OFFSETS);
+    if (r == n) {
+      if (o != total) atomicOr(err, (uint32_t)ERR_OFFSETS);
+      continue;
+    }
+    const uint64_t o1 = offsets[r + 1];
+    if (o1 < o || o1 > total) {
+      atomicOr(err, (uint32_t)ERR_OFFSETS);
+      continue;
+    }
+    if (o1 > o && o < total) {
+      const uint64_t at = cd[j].word0 * 32 + o;
+      atomicOr(reinterpret_cast<unsigned long long*>(&flags[at >> 5]), 1ull << (32 + (at & 31)));
+    }
+  }
+}
+
+// Fills and a one-word copy, for work that may be captured in a graph
+// (where memset nodes are avoided).
+__global__ void __launch_bounds__(256) k_fill64(uint64_t* __restrict__ p, uint64_t n, uint64_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void __launch_bounds__(256) k_fill32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_copy64(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst) {
+  if (threadIdx.x == 0) *dst = *src;
+}
+
 // ----------------------------------------------------- window extraction
 
 struct WordCtx {
@@ -1328,6 +1412,44 @@ hipError_t launch_export(const uint64_t* tkeys, const uint32_t* tcounts, uint64_
 hipError_t launch_debug_part(const SegDesc& sd, uint64_t n, uint32_t* part, hipStream_t s) {
   if (!n) return hipSuccess;
   hipLaunchKernelGGL(k_debug_part, dim3(div_up(n, 256)), dim3(256), 0, s, sd, n, part);
+  return hipGetLastError();
+}
+
+// grid-stride launches: enough workgroups to fill the chip, at most one per 256 items
+static uint32_t stride_grid(uint64_t n) {
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(n, 256), 8192));
+}
+
+hipError_t launch_pack_batch(const ChunkDesc* cd, uint32_t nchunks, uint64_t nwords,
+                             uint64_t* packed, uint64_t* flags, hipStream_t s) {
+  if (!nwords || !nchunks) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_batch, dim3(stride_grid(nwords)), dim3(256), 0, s, cd, nchunks, nwords,
+                     packed, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_rstart_batch(const ChunkDesc* cd, uint32_t nchunks, uint64_t nslots,
+                               uint64_t* flags, uint32_t* err, hipStream_t s) {
+  if (!nslots || !nchunks) return hipSuccess;
+  hipLaunchKernelGGL(k_rstart_batch, dim3(stride_grid(nslots)), dim3(256), 0, s, cd, nchunks,
+                     nslots, flags, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_fill64, dim3(stride_grid(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_fill32, dim3(stride_grid(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy64(const uint64_t* src, uint64_t* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy64, dim3(1), dim3(64), 0, s, src, dst);
   return hipGetLastError();
 }
 

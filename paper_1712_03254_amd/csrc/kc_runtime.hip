@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -82,6 +83,39 @@ struct SpillRec {
 
 enum State { CREATED = 0, INSERTING = 1, FINALIZED = 2 };
 
+// kc_count_batch: consecutive chunks packed side by side into one key segment.
+struct BatchGroup {
+  uint32_t c0 = 0, nc = 0;  // chunk range
+  uint64_t nwords = 0;      // packed words of the group stream
+  uint64_t nslots = 0;      // read slots (sum of n_reads + 1)
+  uint64_t ntiles = 0, nhist = 0, tiles2 = 0;
+  DevBuf cdesc;             // ChunkDesc[nc]
+  Segment seg;              // key segment; upper-bound sized (graph replays reuse it)
+};
+
+// The captured graph of one chunk list and everything its nodes point to.
+struct BatchPlan {
+  std::vector<kc_chunk> chunks;
+  uint32_t counter = 0;
+  std::vector<BatchGroup> groups;
+  DevBuf counts;  // keys per group (u64), written by the graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    for (BatchGroup& g : groups) {
+      g.cdesc.release();
+      g.seg.release();
+    }
+    groups.clear();
+    chunks.clear();
+    counts.release();
+  }
+};
+
 thread_local std::string g_create_error;
 
 }  // namespace
@@ -114,6 +148,9 @@ struct kc_ctx {
   hipEvent_t ev_tally[2] = {nullptr, nullptr}, ev_copy[2] = {nullptr, nullptr};
   uint32_t ovf_log2 = 12;
   std::vector<Segment> segs, spare_segs;
+  bool segs_borrowed = false;  // segs are views of the batch plan's segments
+  BatchPlan batch;
+  hipStream_t capture_stream = nullptr;
   hipEvent_t insert_done = nullptr;
   bool insert_done_valid = false;
 
@@ -231,7 +268,8 @@ kc_status validate(const kc_config* cfg, std::string* why) {
   if (cfg->bloom_bits_log2 - cfg->bloom_block_log2 > kMaxPartLog2)
     return bad("more than 2^21 Bloom blocks (raise bloom_block_log2)");
   if (cfg->partitions_log2 > kMaxPartLog2) return bad("partitions_log2 must be <= 21");
-  if (cfg->flags != 0) return bad("flags must be 0");
+  if (cfg->group_bases_log2 != 0 && (cfg->group_bases_log2 < 10 || cfg->group_bases_log2 > 32))
+    return bad("group_bases_log2 must be 0 or in 10..32");
   if (cfg->scatter_bits > kMaxA1) {
     snprintf(buf, sizeof buf, "scatter_bits must be <= %d", kMaxA1);
     *why = buf;
@@ -391,6 +429,47 @@ kc_status spill_partition(kc_ctx* c, uint32_t p, hipStream_t s, uint64_t* bytes)
   return KC_OK;
 }
 
+// Arguments of the count kernels over the context's current buffers (the
+// launch range fields part_base / part_n / slot_base are the caller's).
+CountArgs count_args(kc_ctx* c, uint32_t nsegs) {
+  const uint64_t on = 1ull << c->ovf_log2;
+  CountArgs a{};
+  a.hc = c->hc;
+  a.segs = c->segdesc.as<SegDesc>();
+  a.nsegs = nsegs;
+  a.upb_log2 = c->upb_log2;
+  a.nbw = c->nbw;
+  a.l2w = c->l2w;
+  a.cap = c->cap;
+  a.probe_limit = std::min<uint32_t>(c->cap, kProbeLimit);
+  a.ovf_log2 = c->ovf_log2;
+  a.ovf_limit = (uint32_t)std::min<uint64_t>(on / 2, 0xFFFFFFFFull);
+  a.b1 = c->b1.as<uint32_t>();
+  a.b2 = c->b2.as<uint32_t>();
+  a.tkeys = c->tkeys.as<uint64_t>();
+  a.tcounts = c->tcounts.as<uint32_t>();
+  a.okeys = c->okeys.as<uint64_t>();
+  a.ocounts = c->ocounts.as<uint32_t>();
+  a.ovf_used = c->ovf_used.as<uint32_t>();
+  a.err = c->derr.as<uint32_t>();
+  a.pstats = c->pstats.as<uint64_t>();
+  a.pstats2 = c->pstats2.as<uint64_t>();
+  return a;
+}
+
+// A captured batch graph points at buffers that an eager insert or finalize
+// may reallocate: those calls drop the graph (the next kc_count_batch
+// captures it again).  The plan's segments stay until that rebuild, since
+// the context may still be reading them.
+void invalidate_batch_graph(kc_ctx* c) {
+  BatchPlan& b = c->batch;
+  if (b.exec) (void)hipGraphExecDestroy(b.exec);
+  if (b.graph) (void)hipGraphDestroy(b.graph);
+  b.exec = nullptr;
+  b.graph = nullptr;
+  b.chunks.clear();
+}
+
 uint64_t resident_bytes(const kc_ctx* c) {
   uint64_t n = 0;
   for (uint32_t v : c->slot_of_h) n += v != kNoSlot;
@@ -488,6 +567,7 @@ kc_status kc_insert_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offse
   hipStream_t s = as_stream(hip_stream);
   KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
   if (c->insert_done_valid) KC_HIP(c, hipStreamWaitEvent(s, c->insert_done, 0), "stream wait");
+  invalidate_batch_graph(c);
   c->state = INSERTING;
 
   const uint64_t nwords = (total_bases + 31) / 32;
@@ -588,6 +668,7 @@ kc_status kc_finalize(kc_ctx* c, void* hip_stream, kc_stats* out) {
   if (!c) return KC_ERR_INVALID_ARG;
   if (c->state == FINALIZED) return fail(c, KC_ERR_BAD_STATE, "already finalized");
   hipStream_t s = as_stream(hip_stream);
+  invalidate_batch_graph(c);
   KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
   if (c->insert_done_valid) KC_HIP(c, hipStreamWaitEvent(s, c->insert_done, 0), "stream wait");
   const uint32_t nc = c->cfg.n_counters;
@@ -668,27 +749,7 @@ kc_status kc_finalize(kc_ctx* c, void* hip_stream, kc_stats* out) {
       KC_HIP(c, hipMemsetAsync(c->b1.p, 0, c->bloom_words64 * 8, s), "memset");
       KC_HIP(c, hipMemsetAsync(c->b2.p, 0, c->bloom_words64 * 8, s), "memset");
     }
-    CountArgs a{};
-    a.hc = c->hc;
-    a.segs = c->segdesc.as<SegDesc>();
-    a.nsegs = (uint32_t)hd.size();
-    a.upb_log2 = c->upb_log2;
-    a.nbw = c->nbw;
-    a.l2w = c->l2w;
-    a.cap = c->cap;
-    a.probe_limit = (uint32_t)std::min<uint64_t>(cap, kProbeLimit);
-    a.ovf_log2 = c->ovf_log2;
-    a.ovf_limit = (uint32_t)std::min<uint64_t>(on / 2, 0xFFFFFFFFull);
-    a.b1 = c->b1.as<uint32_t>();
-    a.b2 = c->b2.as<uint32_t>();
-    a.tkeys = c->tkeys.as<uint64_t>();
-    a.tcounts = c->tcounts.as<uint32_t>();
-    a.okeys = c->okeys.as<uint64_t>();
-    a.ocounts = c->ocounts.as<uint32_t>();
-    a.ovf_used = c->ovf_used.as<uint32_t>();
-    a.err = c->derr.as<uint32_t>();
-    a.pstats = c->pstats.as<uint64_t>();
-    a.pstats2 = c->pstats2.as<uint64_t>();
+    CountArgs a = count_args(c, (uint32_t)hd.size());
     {
       StageTimer t(c, s, KC_T_BLOOM);
       KC_HIP(c, launch_bloom(a, 1u << c->s_log2, c->count_lds, s), "Bloom kernel");
@@ -1003,8 +1064,10 @@ kc_status kc_reset(kc_ctx* c) {
   if (!c) return KC_ERR_INVALID_ARG;
   KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
   KC_HIP(c, hipDeviceSynchronize(), "synchronise");
-  for (Segment& g : c->segs) c->spare_segs.push_back(g);
+  if (!c->segs_borrowed)
+    for (Segment& g : c->segs) c->spare_segs.push_back(g);
   c->segs.clear();
+  c->segs_borrowed = false;
   // keep at most a few spare segment allocations
   std::sort(c->spare_segs.begin(), c->spare_segs.end(),
             [](const Segment& a, const Segment& b) { return a.keys.bytes > b.keys.bytes; });
@@ -1028,8 +1091,11 @@ void kc_destroy(kc_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
-  for (Segment& g : c->segs) g.release();
+  if (!c->segs_borrowed)
+    for (Segment& g : c->segs) g.release();
   for (Segment& g : c->spare_segs) g.release();
+  c->batch.release();
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   DevBuf* bufs[] = {&c->b1, &c->b2, &c->dstat, &c->derr, &c->packed, &c->flags, &c->hist1,
                     &c->lstart1, &c->off1, &c->parts, &c->keys1, &c->tile_run, &c->segdesc,
                     &c->tkeys, &c->tcounts, &c->slot_of, &c->slot_live, &c->pstats, &c->pstats2,
@@ -1050,6 +1116,388 @@ void kc_destroy(kc_ctx* c) {
   if (c->insert_done) (void)hipEventDestroy(c->insert_done);
   if (c->pinned) (void)hipHostFree(c->pinned);
   delete c;
+}
+
+
+// ------------------------------------------------------------ batched form
+
+namespace {
+
+bool same_batch(const BatchPlan& b, const kc_chunk* ch, uint32_t n, uint32_t counter) {
+  if (!b.exec || b.counter != counter || b.chunks.size() != n) return false;
+  for (uint32_t i = 0; i < n; ++i) {
+    const kc_chunk& a = b.chunks[i];
+    if (a.bases_dev != ch[i].bases_dev || a.offsets_dev != ch[i].offsets_dev ||
+        a.n_reads != ch[i].n_reads || a.total_bases != ch[i].total_bases)
+      return false;
+  }
+  return true;
+}
+
+// Groups the chunks into segments, sizes every buffer for the largest
+// possible key count (every position a key), and captures the graph: per
+// segment pack, read starts, first level, scan, second level; then the Bloom
+// levels, the count, Unify and the slot map.  Fills replace memsets.
+kc_status build_batch(kc_ctx* c, const kc_chunk* ch, uint32_t n, uint32_t counter) {
+  c->batch.release();
+  BatchPlan& b = c->batch;
+  const uint64_t limit = c->cfg.group_bases_log2 ? (1ull << c->cfg.group_bases_log2)
+                                                 : (1ull << 32) - 64;
+  std::vector<std::vector<ChunkDesc>> descs;
+  {
+    std::vector<ChunkDesc> d;
+    uint64_t words = 0, slots = 0;
+    uint32_t c0 = 0;
+    auto close = [&](uint32_t end) {
+      BatchGroup g;
+      g.c0 = c0;
+      g.nc = end - c0;
+      g.nwords = words;
+      g.nslots = slots;
+      b.groups.push_back(g);
+      descs.push_back(d);
+      d.clear();
+      words = slots = 0;
+      c0 = end;
+    };
+    for (uint32_t i = 0; i < n; ++i) {
+      const uint64_t w = (ch[i].total_bases + 31) / 32;
+      if (w * 32 > limit) return fail(c, KC_ERR_INVALID_ARG, "a chunk holds more bases than a segment");
+      if (!d.empty() && (words + w) * 32 > limit) close(i);
+      ChunkDesc cd{ch[i].bases_dev, ch[i].offsets_dev, ch[i].total_bases, ch[i].n_reads, words, slots};
+      d.push_back(cd);
+      words += w;
+      slots += ch[i].n_reads + 1;
+    }
+    if (!d.empty()) close(n);
+  }
+  const uint32_t nb1 = 1u << c->a1, nb2 = 1u << c->a2;
+  uint64_t max_words = 0, max_tiles = 0, max_hist = 0, max_tiles2 = 0, bound_total = 0;
+  for (BatchGroup& g : b.groups) {
+    g.ntiles = (g.nwords + kTileWords - 1) / kTileWords;
+    g.nhist = (uint64_t)nb1 * g.ntiles;
+    const uint64_t bound = g.nwords * 32;  // keys <= positions
+    g.tiles2 = (bound + kT2 - 1) / kT2 + nb1;
+    max_words = std::max(max_words, g.nwords);
+    max_tiles = std::max(max_tiles, g.ntiles);
+    max_hist = std::max(max_hist, g.nhist);
+    max_tiles2 = std::max(max_tiles2, g.tiles2);
+    bound_total += bound;
+  }
+  // shared first-level scratch, per-segment outputs, chunk tables
+  KC_HIP(c, c->packed.ensure(max_words * 8), "packed buffer");
+  KC_HIP(c, c->flags.ensure(max_words * 8), "flag buffer");
+  KC_HIP(c, c->hist1.ensure(max_hist * 4), "histogram buffer");
+  KC_HIP(c, c->lstart1.ensure(max_tiles * (nb1 + 1) * 4), "tile start buffer");
+  KC_HIP(c, c->off1.ensure((max_hist + 1) * 8), "offset buffer");
+  KC_HIP(c, c->parts.ensure(scan_parts(max_hist) * 8), "scan buffer");
+  KC_HIP(c, c->keys1.ensure(max_tiles * kTilePos * 8), "first-level key buffer");
+  KC_HIP(c, c->tile_run.ensure(max_tiles2 * 4), "tile run buffer");
+  KC_HIP(c, b.counts.ensure(std::max<size_t>(1, b.groups.size()) * 8), "segment counts");
+  std::vector<SegDesc> hd;
+  for (size_t gi = 0; gi < b.groups.size(); ++gi) {
+    BatchGroup& g = b.groups[gi];
+    KC_HIP(c, g.cdesc.ensure(std::max<size_t>(1, g.nc) * sizeof(ChunkDesc)), "chunk table");
+    if (g.nc)
+      KC_HIP(c, hipMemcpy(g.cdesc.p, descs[gi].data(), g.nc * sizeof(ChunkDesc), hipMemcpyHostToDevice),
+             "chunk table copy");
+    if (!g.nwords) continue;
+    hipError_t e;
+    if ((e = g.seg.keys.ensure(g.nwords * 32 * 8)) != hipSuccess ||
+        (e = g.seg.bucket_off.ensure((nb1 + 1) * 8)) != hipSuccess ||
+        (e = g.seg.tile_first.ensure((nb1 + 1) * 4)) != hipSuccess ||
+        (e = g.seg.meta2.ensure(g.tiles2 * (nb2 + 1) * 4)) != hipSuccess)
+      return hip_fail(c, e, "segment allocation");
+    g.seg.counter = counter;
+    SegDesc sd;
+    sd.keys = g.seg.keys.as<uint64_t>();
+    sd.bucket_off = g.seg.bucket_off.as<uint64_t>();
+    sd.tile_first = g.seg.tile_first.as<uint32_t>();
+    sd.meta2 = g.seg.meta2.as<uint32_t>();
+    sd.a1 = c->a1;
+    sd.a2 = c->a2;
+    hd.push_back(sd);
+  }
+  KC_HIP(c, c->segdesc.ensure(std::max<size_t>(1, hd.size()) * sizeof(SegDesc)), "segment table");
+  if (!hd.empty())
+    KC_HIP(c, hipMemcpy(c->segdesc.p, hd.data(), hd.size() * sizeof(SegDesc), hipMemcpyHostToDevice),
+           "segment table copy");
+  // count buffers: every table resident
+  const uint64_t nparts = 1ull << c->p_log2, cap = c->cap, nc = c->cfg.n_counters;
+  c->pool_slots = (uint32_t)nparts;
+  KC_HIP(c, c->tkeys.ensure(nparts * cap * 8), "table allocation");
+  KC_HIP(c, c->tcounts.ensure(nparts * cap * 4 * nc), "table allocation");
+  KC_HIP(c, c->slot_of.ensure(nparts * 4), "slot map");
+  KC_HIP(c, c->slot_live.ensure(nparts * 4), "slot map");
+  KC_HIP(c, c->pstats.ensure((1ull << c->s_log2) * kNst * 8), "stats rows");
+  KC_HIP(c, c->pstats2.ensure(nparts * kNst * 8), "stats rows");
+  c->ovf_log2 = std::max<uint32_t>(12, std::min<uint32_t>(30, ceil_log2(bound_total / 256 + 1)));
+  const uint64_t on = 1ull << c->ovf_log2;
+  const uint32_t oblocks = (uint32_t)std::min<uint64_t>(1024, (on + 255) / 256);
+  KC_HIP(c, c->okeys.ensure(on * 8), "overflow table");
+  KC_HIP(c, c->ocounts.ensure(on * 4 * nc), "overflow table");
+  KC_HIP(c, c->pstats_ovf.ensure((uint64_t)oblocks * kNst * 8), "stats rows");
+  KC_HIP(c, hipDeviceSynchronize(), "synchronise");
+
+  if (!c->capture_stream)
+    KC_HIP(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking), "capture stream");
+  hipStream_t cs = c->capture_stream;
+  KC_HIP(c, hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed), "begin capture");
+  auto record = [&]() -> hipError_t {
+    hipError_t e;
+#define KC_REC(x) \
+  if ((e = (x)) != hipSuccess) return e
+    const uint64_t s0 = c->hc.salt[0];
+    const uint64_t tag = (uint64_t)counter << 62;
+    KC_REC(launch_fill32(c->derr.as<uint32_t>(), 1, 0, cs));
+    for (size_t gi = 0; gi < b.groups.size(); ++gi) {
+      BatchGroup& g = b.groups[gi];
+      const ChunkDesc* cd = g.cdesc.as<ChunkDesc>();
+      KC_REC(launch_pack_batch(cd, g.nc, g.nwords, c->packed.as<uint64_t>(), c->flags.as<uint64_t>(), cs));
+      KC_REC(launch_rstart_batch(cd, g.nc, g.nslots, c->flags.as<uint64_t>(), c->derr.as<uint32_t>(), cs));
+      if (!g.nwords) {
+        KC_REC(launch_fill64(b.counts.as<uint64_t>() + gi, 1, 0, cs));
+        continue;
+      }
+      KC_REC(launch_level1(c->packed.as<uint64_t>(), c->flags.as<uint64_t>(), g.nwords, c->cfg.k, s0,
+                           c->a1, tag, c->hist1.as<uint32_t>(), c->lstart1.as<uint32_t>(), g.ntiles,
+                           c->keys1.as<uint64_t>(), cs));
+      KC_REC(launch_scan(c->hist1.as<uint32_t>(), g.nhist, c->off1.as<uint64_t>(),
+                         c->parts.as<uint64_t>(), cs));
+      KC_REC(launch_copy64(c->off1.as<uint64_t>() + g.nhist, b.counts.as<uint64_t>() + gi, cs));
+      KC_REC(launch_bucket_off(c->off1.as<uint64_t>(), g.ntiles, nb1, g.seg.bucket_off.as<uint64_t>(), cs));
+      KC_REC(launch_tiles2(g.seg.bucket_off.as<uint64_t>(), nb1, g.seg.tile_first.as<uint32_t>(), cs));
+      KC_REC(launch_level2(c->keys1.as<uint64_t>(), c->off1.as<uint64_t>(), c->lstart1.as<uint32_t>(),
+                           g.ntiles, g.seg.bucket_off.as<uint64_t>(), g.seg.tile_first.as<uint32_t>(),
+                           c->tile_run.as<uint32_t>(), c->a1, c->a2, s0, g.seg.keys.as<uint64_t>(),
+                           g.seg.meta2.as<uint32_t>(), g.tiles2, cs));
+    }
+    KC_REC(launch_fill64(c->okeys.as<uint64_t>(), on, kEmpty, cs));
+    KC_REC(launch_fill32(c->ocounts.as<uint32_t>(), on * nc, 0, cs));
+    KC_REC(launch_fill32(c->ovf_used.as<uint32_t>(), 1, 0, cs));
+    if (c->cfg.bloom_block_log2 < 5) {
+      KC_REC(launch_fill64(c->b1.as<uint64_t>(), c->bloom_words64, 0, cs));
+      KC_REC(launch_fill64(c->b2.as<uint64_t>(), c->bloom_words64, 0, cs));
+    }
+    CountArgs a = count_args(c, (uint32_t)hd.size());
+    a.part_base = 0;
+    a.part_n = (uint32_t)nparts;
+    a.slot_base = 0;
+    KC_REC(launch_bloom(a, 1u << c->s_log2, c->count_lds, cs));
+    KC_REC(launch_tally(a, (uint32_t)nparts, c->tally_lds, cs));
+    KC_REC(launch_ovf_emit(a, c->pstats_ovf.as<uint64_t>(), oblocks, cs));
+    KC_REC(launch_reduce(c->pstats.as<uint64_t>(), 1ull << c->s_log2, c->dstat.as<uint64_t>(), cs));
+    KC_REC(launch_reduce(c->pstats_ovf.as<uint64_t>(), oblocks, c->dstat.as<uint64_t>() + kNst, cs));
+    KC_REC(launch_reduce(c->pstats2.as<uint64_t>(), nparts, c->dstat.as<uint64_t>() + 2 * kNst, cs));
+    KC_REC(launch_slot_map(c->slot_of.as<uint32_t>(), (uint32_t)nparts, 0, cs));
+    KC_REC(launch_fill32(c->slot_live.as<uint32_t>(), nparts, 1, cs));
+#undef KC_REC
+    return hipSuccess;
+  };
+  const hipError_t rec = record();
+  const hipError_t end = hipStreamEndCapture(cs, &b.graph);
+  if (rec != hipSuccess) return hip_fail(c, rec, "graph capture");
+  if (end != hipSuccess) return hip_fail(c, end, "end capture");
+  KC_HIP(c, hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0), "graph instantiate");
+  b.chunks.assign(ch, ch + n);
+  b.counter = counter;
+  return KC_OK;
+}
+
+}  // namespace
+
+kc_status kc_count_batch(kc_ctx* c, const kc_chunk* chunks, uint32_t n_chunks, uint32_t counter,
+                         void* hip_stream, kc_stats* out) {
+  if (!c) return KC_ERR_INVALID_ARG;
+  if (c->state != CREATED) return fail(c, KC_ERR_BAD_STATE, "batch count needs a fresh or reset context");
+  if (counter >= c->cfg.n_counters) return fail(c, KC_ERR_INVALID_ARG, "counter >= n_counters");
+  if (n_chunks && !chunks) return fail(c, KC_ERR_INVALID_ARG, "chunks is NULL");
+  for (uint32_t i = 0; i < n_chunks; ++i) {
+    if (!chunks[i].offsets_dev) return fail(c, KC_ERR_INVALID_ARG, "a chunk's offsets are NULL");
+    if (chunks[i].total_bases && !chunks[i].bases_dev)
+      return fail(c, KC_ERR_INVALID_ARG, "a chunk's bases are NULL");
+  }
+  const uint64_t nparts = 1ull << c->p_log2;
+  const uint64_t per_table = (uint64_t)c->cap * c->slot_bytes;
+  if (c->cfg.hbm_table_budget_bytes && c->cfg.hbm_table_budget_bytes < nparts * per_table)
+    return fail(c, KC_ERR_OVER_BUDGET, "batch counting keeps every partition table in HBM");
+  hipStream_t s = as_stream(hip_stream);
+  KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
+  if (!same_batch(c->batch, chunks, n_chunks, counter)) {
+    kc_status r = build_batch(c, chunks, n_chunks, counter);
+    if (r != KC_OK) {
+      c->batch.release();
+      return r;
+    }
+  }
+  BatchPlan& b = c->batch;
+  free_spill(c);
+  {
+    StageTimer t(c, s, KC_T_GRAPH);
+    KC_HIP(c, hipGraphLaunch(b.exec, s), "graph launch");
+    t.stop();
+  }
+  const size_t ng = b.groups.size();
+  std::vector<uint64_t> counts(std::max<size_t>(1, ng), 0);
+  if (ng)
+    KC_HIP(c, hipMemcpyAsync(counts.data(), b.counts.p, ng * 8, hipMemcpyDeviceToHost, s), "readback");
+  KC_HIP(c, hipMemcpyAsync(c->pinned, c->dstat.p, 3 * kNst * 8, hipMemcpyDeviceToHost, s), "readback");
+  KC_HIP(c, hipMemcpyAsync(c->pinned + 3 * kNst, c->derr.p, 4, hipMemcpyDeviceToHost, s), "readback");
+  KC_HIP(c, hipMemcpyAsync(c->pinned + 3 * kNst + 1, c->ovf_used.p, 4, hipMemcpyDeviceToHost, s),
+         "readback");
+  KC_HIP(c, hipStreamSynchronize(s), "stream synchronise");
+  const uint32_t errf = (uint32_t)c->pinned[3 * kNst];
+  if (errf & ERR_OFFSETS) {
+    resolve_timers(c);
+    return fail(c, KC_ERR_INVALID_ARG,
+                "offsets must start at 0, be non-decreasing and end at total_bases");
+  }
+  uint64_t nv = 0;
+  c->segs.clear();
+  c->segs_borrowed = true;
+  for (size_t gi = 0; gi < ng; ++gi) {
+    nv += counts[gi];
+    if (!b.groups[gi].nwords) continue;
+    Segment view = b.groups[gi].seg;  // shallow: the plan owns the memory
+    view.n = counts[gi];
+    c->segs.push_back(view);
+  }
+  c->st.n_valid = nv;
+  c->st.n_segments = (uint32_t)c->segs.size();
+  if (errf & (ERR_OVF_FULL | ERR_OVF_LOAD)) {
+    // the overflow table filled up: count again with the eager path, which
+    // grows it (and drops this graph, whose buffers it may reallocate)
+    c->state = INSERTING;
+    return kc_finalize(c, hip_stream, out);
+  }
+  uint64_t sv[kNst];
+  for (int i = 0; i < kNst; ++i) sv[i] = c->pinned[i] + c->pinned[kNst + i] + c->pinned[2 * kNst + i];
+  c->st.n_pass = sv[ST_NPASS];
+  c->st.entries = sv[ST_ENTRIES];
+  c->st.sum_counts = sv[ST_SUM];
+  c->st.fp_singletons = sv[ST_FP];
+  c->st.b1_popcount = sv[ST_B1POP];
+  c->st.b2_popcount = sv[ST_B2POP];
+  c->st.passed_distinct = sv[ST_PASSED];
+  {
+    uint32_t used = 0;
+    memcpy(&used, reinterpret_cast<uint8_t*>(c->pinned + 3 * kNst + 1), 4);
+    c->st.overflow_keys = used;
+  }
+  c->st.spilled_partitions = 0;
+  c->st.spilled_bytes = 0;
+  c->pool_slots = (uint32_t)nparts;
+  c->slot_of_h.resize(nparts);
+  for (uint64_t u = 0; u < nparts; ++u) c->slot_of_h[u] = (uint32_t)u;
+  c->state = FINALIZED;
+  resolve_timers(c);
+  if (out) *out = c->st;
+  return KC_OK;
+}
+
+kc_status kc_autotune_batch(const kc_config* base, int device, const kc_chunk* chunks,
+                            uint32_t n_chunks, uint32_t counter, void* hip_stream,
+                            kc_config* best_out, kc_tune_trial* trials, uint32_t max_trials,
+                            uint32_t* n_trials_out) {
+  if (n_trials_out) *n_trials_out = 0;
+  if (!base || !best_out) {
+    g_create_error = "base or best_out is NULL";
+    return KC_ERR_INVALID_ARG;
+  }
+  std::string why;
+  if (validate(base, &why) != KC_OK) {
+    g_create_error = why;
+    return KC_ERR_INVALID_ARG;
+  }
+  uint64_t positions = 0;
+  for (uint32_t i = 0; i < n_chunks; ++i) positions += chunks[i].total_bases;
+  const uint32_t s_log2 = base->bloom_bits_log2 - base->bloom_block_log2;
+  const uint32_t lo = std::max<uint32_t>(std::max<uint32_t>(s_log2, 2), 2);
+  auto clampp = [&](int64_t v) {
+    return (uint32_t)std::min<int64_t>(kMaxPartLog2, std::max<int64_t>(lo, v));
+  };
+  // about one partition per 2^13 key positions, and its two neighbours
+  const int64_t pc = (int64_t)std::llround(std::log2((double)std::max<uint64_t>(positions, 1)) - 13.0);
+  // (three distinct counts: a centre clamped at either end shifts the set)
+  const uint32_t centre = std::min<uint32_t>(std::max<uint32_t>(clampp(pc), lo + 1),
+                                             (uint32_t)kMaxPartLog2 - 1);
+  std::vector<uint32_t> plist;
+  for (int64_t d = -1; d <= 1; ++d) {
+    const uint32_t v = clampp((int64_t)centre + d);
+    if (std::find(plist.begin(), plist.end(), v) == plist.end()) plist.push_back(v);
+  }
+  // table slots: the default (three workgroups per CU) and two lower load-room sizes
+  const uint32_t slot_bytes = 8 + 4 * base->n_counters;
+  const uint32_t cap_def =
+      (uint32_t)(((size_t)kLdsMax / 3 - kLdsSlack - kQueueBytes) / slot_bytes / 64 * 64);
+  const uint32_t slist[3] = {cap_def, cap_def * 4 / 5 / 64 * 64, cap_def * 2 / 3 / 64 * 64};
+  std::vector<kc_tune_trial> got;
+  kc_config best = *base;
+  double best_ms = 1e300;
+  auto trial = [&](kc_config cfg) {
+    kc_tune_trial t{};
+    t.partitions_log2 = cfg.partitions_log2;
+    t.table_slots = cfg.table_slots;
+    t.scatter_bits = cfg.scatter_bits;
+    t.ms = -1.0;
+    kc_ctx* c = nullptr;
+    kc_status r = kc_create(&cfg, device, &c);
+    if (r == KC_OK) {
+      t.table_slots = c->cap;
+      t.scatter_bits = c->a1;
+      kc_stats st{};
+      double ms = 1e300;
+      for (int rep = 0; rep < 3 && r == KC_OK; ++rep) {
+        if (rep) r = kc_reset(c);
+        if (r != KC_OK) break;
+        r = kc_count_batch(c, chunks, n_chunks, counter, hip_stream, &st);
+        if (r == KC_OK && rep) ms = std::min(ms, st.kernel_ms[KC_T_GRAPH]);
+      }
+      if (r == KC_OK) {
+        t.ms = ms;
+        t.overflow_keys = st.overflow_keys;
+      }
+      kc_destroy(c);
+    }
+    t.status = r;
+    got.push_back(t);
+    if (r == KC_OK && t.ms < best_ms) {
+      best_ms = t.ms;
+      best = cfg;
+      best.table_slots = t.table_slots;
+      best.scatter_bits = t.scatter_bits;
+    }
+  };
+  for (uint32_t pl : plist)
+    for (uint32_t sl : slist) {
+      kc_config cfg = *base;
+      cfg.partitions_log2 = pl;
+      cfg.table_slots = sl;
+      cfg.scatter_bits = 0;
+      trial(cfg);
+    }
+  if (best_ms < 1e300) {
+    // the shuffle's split between its two levels, around the automatic one
+    const uint32_t p = std::max<uint32_t>(best.partitions_log2, lo);
+    const uint32_t a_def = best.scatter_bits;
+    for (int d : {-1, 1}) {
+      const int64_t a1 = (int64_t)a_def + d;
+      const int64_t a2 = (int64_t)p - a1;
+      if (a1 < 1 || a1 > kMaxA1 || a2 < 1 || a2 > kMaxA2) continue;
+      kc_config cfg = best;
+      cfg.scatter_bits = (uint32_t)a1;
+      trial(cfg);
+    }
+  }
+  if (trials)
+    for (uint32_t i = 0; i < std::min<uint32_t>(max_trials, (uint32_t)got.size()); ++i) trials[i] = got[i];
+  if (n_trials_out) *n_trials_out = (uint32_t)got.size();
+  if (best_ms >= 1e300) {
+    g_create_error = "no candidate configuration ran";
+    return got.empty() ? KC_ERR_INVALID_ARG : (kc_status)got.back().status;
+  }
+  *best_out = best;
+  return KC_OK;
 }
 
 }  // extern "C"

@@ -31,7 +31,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version_and_status_strings():
-    assert kc.kc_abi_version() == 1
+    text = open(HEADER).read() if os.path.exists(HEADER) else ""
+    want = int(re.search(r"#define KC_ABI_VERSION (\d+)u", text).group(1))
+    assert kc.kc_abi_version() == want
     lib = kc.load()
     assert lib.kc_status_str(0) == b"KC_OK"
     assert lib.kc_status_str(-5) == b"KC_ERR_OVER_BUDGET"
@@ -44,9 +46,11 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "kc.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(kc_config), offsetof(kc_config, seed),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(kc_config),
+         offsetof(kc_config, seed), offsetof(kc_config, group_bases_log2),
          offsetof(kc_config, hbm_table_budget_bytes), sizeof(kc_stats),
-         offsetof(kc_stats, kernel_ms), offsetof(kc_stats, kernel_launches));
+         offsetof(kc_stats, kernel_ms), offsetof(kc_stats, kernel_launches), sizeof(kc_chunk),
+         offsetof(kc_chunk, total_bases), sizeof(kc_tune_trial), offsetof(kc_tune_trial, ms));
   return 0;
 }
 ''')
@@ -54,14 +58,17 @@ int main(void) {
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(kc.KcConfig), kc.KcConfig.seed.offset,
-            kc.KcConfig.hbm_table_budget_bytes.offset, ctypes.sizeof(kc.KcStats),
-            kc.KcStats.kernel_ms.offset, kc.KcStats.kernel_launches.offset]
+            kc.KcConfig.group_bases_log2.offset, kc.KcConfig.hbm_table_budget_bytes.offset,
+            ctypes.sizeof(kc.KcStats), kc.KcStats.kernel_ms.offset,
+            kc.KcStats.kernel_launches.offset, ctypes.sizeof(kc.KcChunk),
+            kc.KcChunk.total_bases.offset, ctypes.sizeof(kc.KcTuneTrial), kc.KcTuneTrial.ms.offset]
     assert got == want
 
 
 @pytest.mark.parametrize("field,value", [("k", 0), ("k", 32), ("n_counters", 3),
                                          ("min_count", 1), ("bloom_hashes", 9),
-                                         ("bloom_block_log2", 20), ("bloom_bits_log2", 41)])
+                                         ("bloom_block_log2", 20), ("bloom_bits_log2", 41),
+                                         ("group_bases_log2", 9), ("group_bases_log2", 33)])
 def test_config_validation_without_device(field, value):
     cfg = kc.Config(k=21, bloom_bits_log2=20, bloom_hashes=3, bloom_block_log2=12)
     setattr(cfg, field, value)
