@@ -1,12 +1,15 @@
 #!/usr/bin/env python3
-"""Benchmark of the MI355X k-mer counter on the 100 Mbp plain workload.
+"""Benchmark of the MI355X k-mer counter (default: the 100 Mbp plain workload).
 
 One step = one pass of the whole counting path over the workload's reads,
 already resident in HBM: reset, insert (pack, extraction, two-level partition
 shuffle), finalize (Bloom levels, screen, exact per-partition count, unify)
-and one query batch.  Prints one JSON line.
+and one query batch.  With --workload batched_200mbp the step is one
+kc_count_batch graph launch over the 256 chunks (the autotuner picks the
+configuration first, untimed) plus the query batch.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+                  [--workload plain_100mbp|batched_200mbp|...]
 """
 from __future__ import annotations
 
@@ -60,12 +63,12 @@ def stage_alu_ops(stage: str, w, st: dict) -> float:
 
 def stage_bytes(stage: str, w, st: dict, cfg_eff: dict) -> float:
     """Algorithmic HBM bytes of one launch of a stage (what the algorithm must
-    move at least once), from the workload shape and the run's statistics."""
-    total_bases = w.n_reads * w.lmax
+    move at least once), from the input's shape and the run's statistics."""
+    total_bases, n_reads = cfg_eff["total_bases"], cfg_eff["n_reads"]
     nwords = (total_bases + 31) // 32
     n = st["n_valid"]
     if stage == "pack":      # ASCII in, 2-bit words + flag words out, offsets in
-        return total_bases + nwords * 16 + (w.n_reads + 1) * 8
+        return total_bases + nwords * 16 + (n_reads + 1) * 8
     if stage == "level1":    # packed + flags in, 8 B keys out
         return nwords * 16 + n * 8
     if stage == "level2":    # keys in and out
@@ -77,12 +80,15 @@ def stage_bytes(stage: str, w, st: dict, cfg_eff: dict) -> float:
         return n * 8 + tables
     if stage == "query":
         return QUERY_BATCH * (8 + 4 * w.n_counters)
+    if stage == "graph":     # every stage of the batch in one launch
+        return sum(stage_bytes(x, w, st, cfg_eff) for x in ("pack", "level1", "level2", "bloom",
+                                                             "tally"))
     return 0.0
 
 
 def cpu_baseline(w, genome, n_reads=300_000):
     import oracle
-    b, o = w.make_reads(genome, first=0, n=n_reads)
+    b, o = w.make_reads(genome, first=0, n=n_reads, threads=16)
     p = oracle.Params(k=w.k, n_counters=w.n_counters, min_count=w.min_count,
                       m_log2=w.bloom_bits_log2, h=w.bloom_hashes, block_log2=w.bloom_block_log2,
                       seed=w.seed)
@@ -228,27 +234,51 @@ def main():
         sys.exit(1)
     kc.load()
     w = synth.WORKLOADS[args.workload]
+    batched = w.batch_chunks > 0
     t0 = time.perf_counter()
-    genome = w.make_genome()
-    bases, offsets = w.make_reads(genome)
-    gen_s = time.perf_counter() - t0
+    genome = w.make_genome(threads=16)
     dev = torch.device("cuda:0")
-    pinned_b = torch.from_numpy(bases).pin_memory()
-    pinned_o = torch.from_numpy(offsets.view(np.int64)).pin_memory()
-    db = pinned_b.to(dev, non_blocking=True)
-    do = pinned_o.to(dev, non_blocking=True)
+    stream = torch.cuda.current_stream()
+    if batched:
+        sizes = w.chunk_plan()
+        host_chunks = [w.make_chunk(genome, sizes, i, threads=16) for i in range(sizes.size)]
+        n_reads = int(sizes.sum())
+        total_bases = int(sum(int(o[-1]) for _, o in host_chunks))
+    else:
+        bases, offsets = w.make_reads(genome, threads=16)
+        host_chunks = [(bases, offsets)]
+        n_reads, total_bases = w.n_reads, int(offsets[-1])
+    gen_s = time.perf_counter() - t0
+    pinned = [(torch.from_numpy(b).pin_memory(), torch.from_numpy(o.view(np.int64)).pin_memory())
+              for b, o in host_chunks]
+    chunks = [(b.to(dev, non_blocking=True), o.to(dev, non_blocking=True)) for b, o in pinned]
     torch.cuda.synchronize()
     cfg = kc.Config(k=w.k, n_counters=w.n_counters, min_count=w.min_count,
                     bloom_bits_log2=w.bloom_bits_log2, bloom_hashes=w.bloom_hashes,
                     bloom_block_log2=w.bloom_block_log2, seed=w.seed,
                     partitions_log2=w.partitions_log2, hbm_table_budget_bytes=w.table_budget)
+    tune = None
+    if batched:
+        # the autotuner's trials run here, before warm-up and outside the timed steps
+        t_tune = time.perf_counter()
+        cfg, trials = kc.autotune_batch(cfg, chunks, stream=stream)
+        tune = {"chosen": {"partitions_log2": cfg.partitions_log2, "table_slots": cfg.table_slots,
+                           "scatter_bits": cfg.scatter_bits},
+                "trials": [[t["partitions_log2"], t["table_slots"], t["scatter_bits"],
+                            round(t["ms"], 3), t["status"]] for t in trials],
+                "seconds": round(time.perf_counter() - t_tune, 1)}
     counter = kc.KmerCounter(cfg)
-    stream = torch.cuda.current_stream()
+
+    def count(src):
+        counter.reset()
+        if batched:
+            return counter.count_batch(src, stream=stream)
+        for b, o in src:
+            counter.insert_reads(b, o, stream=stream)
+        return counter.finalize(stream=stream)
 
     def step(q=None):
-        counter.reset()
-        counter.insert_reads(db, do, stream=stream)
-        st = counter.finalize(stream=stream)
+        st = count(chunks)
         if q is not None:
             counter.query(q, stream=stream)
         return counter.stats() if q is not None else st
@@ -260,6 +290,7 @@ def main():
     half = QUERY_BATCH // 2
     qk = np.concatenate([keys[rng.integers(0, keys.size, half)],
                          rng.integers(0, 1 << (2 * w.k), QUERY_BATCH - half, dtype=np.uint64)])
+    del keys
     q = torch.from_numpy(qk.view(np.int64)).to(dev)
     for _ in range(args.warmup):
         step(q)
@@ -270,9 +301,9 @@ def main():
     last = None
     for _ in range(args.steps):
         last = step(q)
-        for s, v in last["kernel_ms"].items():
-            per_stage_ms[s] = per_stage_ms.get(s, 0.0) + v
-            per_stage_n[s] = per_stage_n.get(s, 0) + last["kernel_launches"][s]
+        for s_, v in last["kernel_ms"].items():
+            per_stage_ms[s_] = per_stage_ms.get(s_, 0.0) + v
+            per_stage_n[s_] = per_stage_n.get(s_, 0) + last["kernel_launches"][s_]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     n_valid = last["n_valid"]
@@ -281,16 +312,14 @@ def main():
     # end-to-end figure with the reads crossing PCIe from pinned host memory
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    db2 = pinned_b.to(dev, non_blocking=True)
-    do2 = pinned_o.to(dev, non_blocking=True)
-    counter.reset()
-    counter.insert_reads(db2, do2, stream=stream)
-    counter.finalize(stream=stream)
+    fresh = [(b.to(dev, non_blocking=True), o.to(dev, non_blocking=True)) for b, o in pinned]
+    count(fresh)
     torch.cuda.synchronize()
     e2e = n_valid / (time.perf_counter() - t1)
-    del db2, do2
+    del fresh
 
-    cfg_eff = {"partitions_log2": last["partitions_log2"], "table_slots": last["table_slots"]}
+    cfg_eff = {"partitions_log2": last["partitions_log2"], "table_slots": last["table_slots"],
+               "total_bases": total_bases, "n_reads": n_reads}
     stages = {}
     for s in per_stage_ms:
         if per_stage_n.get(s):
@@ -326,8 +355,9 @@ def main():
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": args.workload, "genome_bp": w.genome_len, "reads": w.n_reads,
-                   "read_len": w.lmax, "sub_rate": w.err, "n_rate": w.nrate, "k": w.k,
+        "config": {"workload": args.workload, "genome_bp": w.genome_len, "reads": n_reads,
+                   "bases": total_bases, "chunks": len(host_chunks),
+                   "read_len": [w.lmin, w.lmax], "sub_rate": w.err, "n_rate": w.nrate, "k": w.k,
                    "bloom_bits_log2": w.bloom_bits_log2, "bloom_hashes": w.bloom_hashes,
                    "bloom_block_log2": w.bloom_block_log2,
                    "partitions": 1 << cfg_eff["partitions_log2"],
@@ -342,6 +372,8 @@ def main():
         "step_hbm_gbs": round(total_alg * args.steps / elapsed / 1e9, 1),
         "input_gen_s": round(gen_s, 2),
     }
+    if tune is not None:
+        out["autotune"] = tune
     if args.copy_probe:
         src = torch.empty(COPY_BYTES, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

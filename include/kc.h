@@ -251,13 +251,17 @@ typedef struct kc_tune_trial {
 
 /*
  * Chooses the result-neutral parameters of kc_count_batch for a batch by
- * measurement: partition count (around one partition per 2^13 key
- * positions), table slots (load factor) and first-level fan-out (the shuffle's
- * tile split).  Each candidate runs kc_count_batch on the batch itself on a
- * context of its own; the fastest configuration without errors is written to
- * *best_out (base's result-defining fields unchanged).  trials_host (may be
- * NULL) receives up to max_trials records and *n_trials_out their number.
- * Needs the memory of one batched count at a time.  Synchronises.
+ * measurement: partition count, table slots (load factor) and first-level
+ * fan-out (the split of the shuffle between its two tile levels).  A
+ * coordinate search starts at about one partition per 2^13 key positions,
+ * the default table and the automatic split, and steps along each dimension
+ * while a neighbour is faster (at most 24 trials).  Each trial runs
+ * kc_count_batch on the batch itself, on a context of its own (the fastest
+ * of two timed runs after one untimed).  The fastest configuration without
+ * errors is written to *best_out (base's result-defining fields unchanged).
+ * trials_host (may be NULL) receives up to max_trials records and
+ * *n_trials_out their number.  Needs the memory of one batched count at a
+ * time.  Synchronises.
  */
 kc_status kc_autotune_batch(const kc_config* base, int device, const kc_chunk* chunks_host,
                             uint32_t n_chunks, uint32_t counter, void* hip_stream,

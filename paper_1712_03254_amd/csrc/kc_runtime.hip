@@ -320,7 +320,7 @@ kc_status derive(kc_ctx* c) {
     return fail(c, KC_ERR_INVALID_ARG, "LDS layout too large");
   // two shuffle levels: a1 bits in the first, the rest in the second
   c->a1 = f.scatter_bits ? std::min<uint32_t>(f.scatter_bits, c->p_log2 - 1)
-                         : std::min<uint32_t>((c->p_log2 + 1) / 2, kMaxA1);
+                         : std::min<uint32_t>(c->p_log2 / 2, kMaxA1);
   c->a2 = c->p_log2 - c->a1;
   if (c->a1 < 1 || c->a1 > (uint32_t)kMaxA1 || c->a2 < 1 || c->a2 > (uint32_t)kMaxA2)
     return fail(c, KC_ERR_INVALID_ARG, "partition count needs a wider shuffle (set scatter_bits)");
@@ -1412,41 +1412,42 @@ kc_status kc_autotune_batch(const kc_config* base, int device, const kc_chunk* c
   uint64_t positions = 0;
   for (uint32_t i = 0; i < n_chunks; ++i) positions += chunks[i].total_bases;
   const uint32_t s_log2 = base->bloom_bits_log2 - base->bloom_block_log2;
-  const uint32_t lo = std::max<uint32_t>(std::max<uint32_t>(s_log2, 2), 2);
-  auto clampp = [&](int64_t v) {
-    return (uint32_t)std::min<int64_t>(kMaxPartLog2, std::max<int64_t>(lo, v));
-  };
-  // about one partition per 2^13 key positions, and its two neighbours
+  const uint32_t lo = std::max<uint32_t>(s_log2, 2);  // fewest partitions allowed
+  // Coordinate search from about one partition per 2^13 key positions, the
+  // default table and the automatic shuffle split: along each dimension in
+  // turn, step to a neighbour while that is faster.
   const int64_t pc = (int64_t)std::llround(std::log2((double)std::max<uint64_t>(positions, 1)) - 13.0);
-  // (three distinct counts: a centre clamped at either end shifts the set)
-  const uint32_t centre = std::min<uint32_t>(std::max<uint32_t>(clampp(pc), lo + 1),
-                                             (uint32_t)kMaxPartLog2 - 1);
-  std::vector<uint32_t> plist;
-  for (int64_t d = -1; d <= 1; ++d) {
-    const uint32_t v = clampp((int64_t)centre + d);
-    if (std::find(plist.begin(), plist.end(), v) == plist.end()) plist.push_back(v);
-  }
-  // table slots: the default (three workgroups per CU) and two lower load-room sizes
   const uint32_t slot_bytes = 8 + 4 * base->n_counters;
   const uint32_t cap_def =
       (uint32_t)(((size_t)kLdsMax / 3 - kLdsSlack - kQueueBytes) / slot_bytes / 64 * 64);
-  const uint32_t slist[3] = {cap_def, cap_def * 4 / 5 / 64 * 64, cap_def * 2 / 3 / 64 * 64};
+  // table sizes: the default (three workgroups per CU) and smaller ones in 64-slot steps
+  std::vector<uint32_t> slist;
+  for (uint32_t f = 10; f >= 5; --f) slist.push_back(std::max<uint32_t>(64, cap_def * f / 10 / 64 * 64));
   std::vector<kc_tune_trial> got;
+  struct Key {
+    uint32_t p, si, a1;
+    bool operator==(const Key& o) const { return p == o.p && si == o.si && a1 == o.a1; }
+  };
+  std::vector<std::pair<Key, double>> seen;
   kc_config best = *base;
   double best_ms = 1e300;
-  auto trial = [&](kc_config cfg) {
+  auto run = [&](Key key) -> double {
+    for (auto& kv : seen)
+      if (kv.first == key) return kv.second;
+    kc_config cfg = *base;
+    cfg.partitions_log2 = key.p;
+    cfg.table_slots = slist[key.si];
+    cfg.scatter_bits = key.a1;
     kc_tune_trial t{};
-    t.partitions_log2 = cfg.partitions_log2;
-    t.table_slots = cfg.table_slots;
-    t.scatter_bits = cfg.scatter_bits;
+    t.partitions_log2 = key.p;
+    t.table_slots = slist[key.si];
+    t.scatter_bits = key.a1;
     t.ms = -1.0;
     kc_ctx* c = nullptr;
     kc_status r = kc_create(&cfg, device, &c);
+    double ms = 1e300;
     if (r == KC_OK) {
-      t.table_slots = c->cap;
-      t.scatter_bits = c->a1;
       kc_stats st{};
-      double ms = 1e300;
       for (int rep = 0; rep < 3 && r == KC_OK; ++rep) {
         if (rep) r = kc_reset(c);
         if (r != KC_OK) break;
@@ -1459,34 +1460,49 @@ kc_status kc_autotune_batch(const kc_config* base, int device, const kc_chunk* c
       }
       kc_destroy(c);
     }
+    if (r != KC_OK) ms = 1e300;
     t.status = r;
     got.push_back(t);
-    if (r == KC_OK && t.ms < best_ms) {
-      best_ms = t.ms;
+    seen.push_back({key, ms});
+    if (ms < best_ms) {
+      best_ms = ms;
       best = cfg;
-      best.table_slots = t.table_slots;
-      best.scatter_bits = t.scatter_bits;
     }
+    return ms;
   };
-  for (uint32_t pl : plist)
-    for (uint32_t sl : slist) {
-      kc_config cfg = *base;
-      cfg.partitions_log2 = pl;
-      cfg.table_slots = sl;
-      cfg.scatter_bits = 0;
-      trial(cfg);
-    }
-  if (best_ms < 1e300) {
-    // the shuffle's split between its two levels, around the automatic one
-    const uint32_t p = std::max<uint32_t>(best.partitions_log2, lo);
-    const uint32_t a_def = best.scatter_bits;
-    for (int d : {-1, 1}) {
-      const int64_t a1 = (int64_t)a_def + d;
-      const int64_t a2 = (int64_t)p - a1;
-      if (a1 < 1 || a1 > kMaxA1 || a2 < 1 || a2 > kMaxA2) continue;
-      kc_config cfg = best;
-      cfg.scatter_bits = (uint32_t)a1;
-      trial(cfg);
+  const uint32_t p0 = std::min<uint32_t>(kMaxPartLog2, (uint32_t)std::max<int64_t>(lo, pc));
+  auto split = [&](uint32_t p) { return std::min<uint32_t>(p / 2, kMaxA1); };
+  auto valid = [&](const Key& k) {
+    if (k.p < lo || k.p > (uint32_t)kMaxPartLog2 || k.si >= slist.size()) return false;
+    const int64_t a2 = (int64_t)k.p - k.a1;
+    return k.a1 >= 1 && k.a1 <= (uint32_t)kMaxA1 && a2 >= 1 && a2 <= kMaxA2;
+  };
+  Key cur{p0, 0, split(p0)};
+  double cur_ms = run(cur);
+  const int kMaxTrials = 24;
+  bool moved = true;
+  while (moved && (int)got.size() < kMaxTrials) {
+    moved = false;
+    for (int dim = 0; dim < 3 && (int)got.size() < kMaxTrials; ++dim) {
+      for (int dir : {-1, 1}) {
+        for (;;) {
+          Key nk = cur;
+          if (dim == 0) {
+            nk.p = (uint32_t)((int64_t)cur.p + dir);
+            nk.a1 = split(nk.p);
+          } else if (dim == 1) {
+            nk.a1 = (uint32_t)((int64_t)cur.a1 + dir);
+          } else {
+            nk.si = (uint32_t)((int64_t)cur.si + dir);
+          }
+          if (!valid(nk) || (int)got.size() >= kMaxTrials) break;
+          const double ms = run(nk);
+          if (ms >= cur_ms) break;
+          cur = nk;
+          cur_ms = ms;
+          moved = true;
+        }
+      }
     }
   }
   if (trials)

@@ -146,6 +146,9 @@ class Workload:
     n_counters: int = 1
     min_count: int = 2
     table_budget: int = 0
+    batch_chunks: int = 0     # batched workloads: number of read chunks
+    chunk_lo: float = 0.0     # reads per chunk, log-uniform in [chunk_lo, chunk_hi]
+    chunk_hi: float = 0.0
 
     def make_genome(self, threads: int = 0) -> np.ndarray:
         return genome(self.seed, self.genome_len, threads)
@@ -154,6 +157,15 @@ class Workload:
         n = self.n_reads - first if n is None else n
         return reads(self.seed, genome_seq, first, n, self.lmin, self.lmax, self.err, self.nrate,
                      threads)
+
+    def chunk_plan(self) -> np.ndarray:
+        """Reads per chunk of a batched workload: floor(exp(U[ln lo, ln hi])),
+        seeded; the chunks hold consecutive reads of one read stream."""
+        return chunk_sizes(self.seed, self.batch_chunks, self.chunk_lo, self.chunk_hi)
+
+    def make_chunk(self, genome_seq, sizes: np.ndarray, i: int, threads: int = 0):
+        first = int(sizes[:i].sum())
+        return self.make_reads(genome_seq, first=first, n=int(sizes[i]), threads=threads)
 
 
 # The five workloads.  Partition counts are result-neutral; the value here is
@@ -165,7 +177,7 @@ WORKLOADS = {
     "plain_100mbp": Workload("plain_100mbp", 2, 100_000_000, 10_000_000, 100, 100, 0.005, 0.001,
                              31, 32, 4, 19, 16),
     "batched_200mbp": Workload("batched_200mbp", 3, 200_000_000, 0, 100, 250, 0.005, 0.0,
-                               31, 35, 4, 19, 16),
+                               31, 35, 4, 19, 19, batch_chunks=256, chunk_lo=1e3, chunk_hi=2e6),
     "served_300mbp": Workload("served_300mbp", 4, 300_000_000, 30_000_000, 100, 100, 0.005, 0.0,
                               31, 32, 4, 19, 16, n_counters=2),
     "spill_3gbp": Workload("spill_3gbp", 5, 3_000_000_000, 200_000_000, 100, 100, 0.01, 0.0,

@@ -185,7 +185,7 @@ def test_autotune_choice_is_result_neutral():
     best, trials = kc.autotune_batch(cfg, dev)
     note("trials: %s" % [(t["partitions_log2"], t["table_slots"], t["scatter_bits"],
                           round(t["ms"], 3), t["status"]) for t in trials])
-    assert len(trials) >= 9
+    assert len(trials) >= 5  # the start and its neighbours along each dimension
     assert all(t["status"] == 0 for t in trials)
     fastest = min(t["ms"] for t in trials)
     assert any(t["ms"] == fastest and t["partitions_log2"] == best.partitions_log2 and
