@@ -209,7 +209,8 @@ kc_status kc_debug_keys(kc_ctx* ctx, uint64_t* keys_host, uint32_t* partition_ho
 kc_status kc_get_stats(const kc_ctx* ctx, kc_stats* out_host);
 
 /* Drops inserted reads, tables and spilled partitions; keeps allocations for
- * reuse.  Back to CREATED.  Synchronises the device. */
+ * reuse.  Back to CREATED.  Waits for the context's own queued work (the last
+ * kc_insert_reads); other contexts' work on the device is not waited for. */
 kc_status kc_reset(kc_ctx* ctx);
 
 /*
@@ -267,6 +268,67 @@ kc_status kc_autotune_batch(const kc_config* base, int device, const kc_chunk* c
                             uint32_t n_chunks, uint32_t counter, void* hip_stream,
                             kc_config* best_out, kc_tune_trial* trials_host,
                             uint32_t max_trials, uint32_t* n_trials_out);
+
+/*
+ * Served form: a request server on one device.  A request is one count job
+ * (its own configuration, and up to two read chunks, chunk c counted into
+ * counter c).  Requests queue in arrival order and are admitted while the
+ * device bytes of admitted, unreleased requests stay within the server's
+ * HBM budget and a worker is free; admitted requests run concurrently (one
+ * worker thread and stream each), so their kernels overlap on the device.  A
+ * finished request keeps its context (tables, Bloom levels) resident until
+ * kc_server_release; released contexts are kept for reuse by later requests
+ * of the same configuration and are freed when the budget needs their
+ * memory.  Each request's result is exactly what kc_create + kc_insert_reads
+ * (per chunk) + kc_finalize would give alone: contexts share no state.
+ */
+typedef struct kc_server kc_server;
+
+typedef struct kc_request {
+  kc_config cfg;        /* the job's configuration (its table budget is ignored) */
+  kc_chunk parts[2];    /* parts[c] is counted into counter c */
+  uint32_t n_parts;     /* 1 or 2, at most cfg.n_counters */
+} kc_request;
+
+typedef struct kc_response {
+  int32_t status;        /* kc_status of the job */
+  uint32_t worker;       /* worker that ran it */
+  kc_stats stats;        /* kc_finalize's statistics */
+  kc_ctx* ctx;           /* FINALIZED context with the job's tables, valid until release; may be
+                            passed to kc_query / kc_export / kc_export_bloom by the waiting thread */
+  double submit_ms;      /* server clock (ms since kc_server_create) at submission */
+  double admit_ms;       /* ... when a worker took it */
+  double done_ms;        /* ... when kc_finalize returned */
+  uint64_t footprint_bytes; /* device bytes reserved for it (estimate before, actual after) */
+} kc_response;
+
+/* Starts `workers` (1..16) worker threads on `device`, admitting requests
+ * within hbm_budget_bytes of device memory (> 0). */
+kc_status kc_server_create(int device, uint64_t hbm_budget_bytes, uint32_t workers,
+                           kc_server** out);
+
+/* Queues a request (copied; its read buffers must stay valid until the
+ * request is done) and returns at once with its ticket.  A request whose
+ * estimated footprint exceeds the whole budget finishes at once with status
+ * KC_ERR_OVER_BUDGET. */
+kc_status kc_server_submit(kc_server* srv, const kc_request* req, uint64_t* ticket_out);
+
+/* Blocks until the request is done; *out receives its response.  The call
+ * itself fails only for an unknown or released ticket. */
+kc_status kc_server_wait(kc_server* srv, uint64_t ticket, kc_response* out);
+
+/* Ends a done request: its tables leave the budget (the context goes to the
+ * reuse pool) and the ticket becomes invalid. */
+kc_status kc_server_release(kc_server* srv, uint64_t ticket);
+
+/* Budget in use by admitted requests, bytes held by pooled contexts, queued
+ * and running request counts. */
+kc_status kc_server_usage(kc_server* srv, uint64_t* in_use_bytes, uint64_t* pooled_bytes,
+                          uint32_t* queued, uint32_t* running);
+
+/* Waits for running requests, drops queued ones, frees every context.  NULL
+ * is ignored. */
+void kc_server_destroy(kc_server* srv);
 
 /* Frees everything the context owns.  NULL is ignored. */
 void kc_destroy(kc_ctx* ctx);

@@ -33,7 +33,8 @@ STAGES = ["pack", "level1", "scan", "level2", "bloom", "tally", "unify", "query"
 EXPORTED = ["kc_abi_version", "kc_status_str", "kc_create", "kc_insert_reads", "kc_finalize",
             "kc_query", "kc_spill", "kc_export", "kc_export_bloom", "kc_debug_keys",
             "kc_get_stats", "kc_reset", "kc_destroy", "kc_last_error", "kc_count_batch",
-            "kc_autotune_batch"]
+            "kc_autotune_batch", "kc_server_create", "kc_server_submit", "kc_server_wait",
+            "kc_server_release", "kc_server_usage", "kc_server_destroy"]
 
 
 class KcError(RuntimeError):
@@ -52,20 +53,6 @@ class KcConfig(ctypes.Structure):
                 ("hbm_table_budget_bytes", ctypes.c_uint64)]
 
 
-class KcChunk(ctypes.Structure):
-    _fields_ = [("bases_dev", ctypes.c_void_p), ("offsets_dev", ctypes.c_void_p),
-                ("n_reads", ctypes.c_uint64), ("total_bases", ctypes.c_uint64)]
-
-
-class KcTuneTrial(ctypes.Structure):
-    _fields_ = [("partitions_log2", ctypes.c_uint32), ("table_slots", ctypes.c_uint32),
-                ("scatter_bits", ctypes.c_uint32), ("status", ctypes.c_int32),
-                ("ms", ctypes.c_double), ("overflow_keys", ctypes.c_uint64)]
-
-    def as_dict(self) -> dict:
-        return {n: getattr(self, n) for n, _ in self._fields_}
-
-
 class KcStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "n_valid", "n_pass", "entries", "sum_counts", "fp_singletons", "b1_popcount",
@@ -80,6 +67,31 @@ class KcStats(ctypes.Structure):
         d["kernel_ms"] = {STAGES[i]: self.kernel_ms[i] for i in range(len(STAGES))}
         d["kernel_launches"] = {STAGES[i]: int(self.kernel_launches[i]) for i in range(len(STAGES))}
         return d
+
+
+class KcChunk(ctypes.Structure):
+    _fields_ = [("bases_dev", ctypes.c_void_p), ("offsets_dev", ctypes.c_void_p),
+                ("n_reads", ctypes.c_uint64), ("total_bases", ctypes.c_uint64)]
+
+
+class KcRequest(ctypes.Structure):
+    _fields_ = [("cfg", KcConfig), ("parts", KcChunk * 2), ("n_parts", ctypes.c_uint32)]
+
+
+class KcResponse(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("worker", ctypes.c_uint32), ("stats", KcStats),
+                ("ctx", ctypes.c_void_p), ("submit_ms", ctypes.c_double),
+                ("admit_ms", ctypes.c_double), ("done_ms", ctypes.c_double),
+                ("footprint_bytes", ctypes.c_uint64)]
+
+
+class KcTuneTrial(ctypes.Structure):
+    _fields_ = [("partitions_log2", ctypes.c_uint32), ("table_slots", ctypes.c_uint32),
+                ("scatter_bits", ctypes.c_uint32), ("status", ctypes.c_int32),
+                ("ms", ctypes.c_double), ("overflow_keys", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
 
 
 def _status_name(s: int) -> str:
@@ -117,6 +129,12 @@ def load():
         "kc_count_batch": ([V, P(KcChunk), U32, U32, V, P(KcStats)], st),
         "kc_autotune_batch": ([P(KcConfig), ctypes.c_int, P(KcChunk), U32, U32, V, P(KcConfig),
                                P(KcTuneTrial), U32, P(U32)], st),
+        "kc_server_create": ([ctypes.c_int, U64, U32, P(V)], st),
+        "kc_server_submit": ([V, P(KcRequest), P(U64)], st),
+        "kc_server_wait": ([V, U64, P(KcResponse)], st),
+        "kc_server_release": ([V, U64], st),
+        "kc_server_usage": ([V, P(U64), P(U64), P(U32), P(U32)], st),
+        "kc_server_destroy": ([V], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -362,3 +380,69 @@ class KmerCounter:
 
     def reset(self):
         kc_reset(self.ctx)
+
+
+# ---- served form ----------------------------------------------------------------
+
+class Server:
+    """Request server (kc_server_*): jobs of their own configuration, admitted
+    under an HBM budget, run concurrently by `workers` threads."""
+
+    def __init__(self, budget_bytes: int, workers: int = 4, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("Server needs a HIP device")
+        h = ctypes.c_void_p()
+        _check(None, load().kc_server_create(device, budget_bytes, workers, ctypes.byref(h)))
+        self.h = h
+
+    def submit(self, cfg: Config, parts) -> int:
+        """parts: list of up to two (bases, offsets) device tensor pairs (part c
+        counted into counter c).  Returns the ticket at once."""
+        r = KcRequest()
+        r.cfg = cfg.c()
+        for i, (b, o, n, t) in enumerate(chunk_list(parts)):
+            r.parts[i] = KcChunk(b, o, n, t)
+        r.n_parts = len(parts)
+        t = ctypes.c_uint64(0)
+        _check(None, load().kc_server_submit(self.h, ctypes.byref(r), ctypes.byref(t)))
+        return int(t.value)
+
+    def wait(self, ticket: int) -> KcResponse:
+        out = KcResponse()
+        _check(None, load().kc_server_wait(self.h, ticket, ctypes.byref(out)))
+        return out
+
+    def release(self, ticket: int):
+        _check(None, load().kc_server_release(self.h, ticket))
+
+    def usage(self) -> dict:
+        a, b = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        q, r = ctypes.c_uint32(0), ctypes.c_uint32(0)
+        _check(None, load().kc_server_usage(self.h, ctypes.byref(a), ctypes.byref(b),
+                                            ctypes.byref(q), ctypes.byref(r)))
+        return {"in_use": a.value, "pooled": b.value, "queued": q.value, "running": r.value}
+
+    def close(self):
+        if self.h:
+            load().kc_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def response_table(resp: KcResponse, n_counters: int):
+    """(keys, counts) of a finished request, from its resident context."""
+    return kc_export(ctypes.c_void_p(resp.ctx), n_counters)
+
+
+def response_query(resp: KcResponse, kmers, n_counters: int):
+    import torch
+    out = torch.empty((kmers.numel(), n_counters), dtype=torch.int32, device=kmers.device)
+    kc_query(ctypes.c_void_p(resp.ctx), kmers.data_ptr(), kmers.numel(), out.data_ptr(),
+             _stream_ptr(None))
+    return out

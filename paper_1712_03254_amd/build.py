@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkc.so")
-SOURCES = ["kc_kernels.hip", "kc_runtime.hip"]
+SOURCES = ["kc_kernels.hip", "kc_runtime.hip", "kc_server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kc.h"
+
 namespace kc {
 
 constexpr uint64_t kEmpty = ~0ull;              // empty table slot (no key reaches it: x < 2^62)
@@ -146,5 +148,13 @@ hipError_t launch_copy64(const uint64_t* src, uint64_t* dst, hipStream_t s);
 hipError_t launch_slot_map(uint32_t* slot_of, uint32_t n, uint32_t first, hipStream_t s);
 hipError_t launch_scatter_rows(const uint32_t* rows, const uint32_t* vals, uint32_t n,
                                uint32_t nc, uint32_t* out, hipStream_t s);
+
+// ---- runtime helpers for the request server (kc_runtime.hip) ----
+// Device bytes a context holds now (every buffer it has allocated).
+uint64_t ctx_device_bytes(const kc_ctx* c);
+// Device bytes a context with configuration cfg allocates to count reads of
+// n_parts inserts of part_bases[i] bases each (an upper bound: every window
+// position a key); 0 when cfg is invalid.
+uint64_t estimate_count_bytes(const kc_config* cfg, const uint64_t* part_bases, uint32_t n_parts);
 
 }  // namespace kc

@@ -1256,6 +1256,13 @@ inline uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) /
 
 // ---------------------------------------------------------------- launchers
 
+// Lets a kernel take up to the whole LDS of a CU in dynamic shared memory.
+// Always the same value, so contexts launching from several threads cannot
+// race each other into a smaller limit than one of their launches needs.
+static hipError_t allow_lds(const void* fn) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
+}
+
 hipError_t launch_pack(const uint8_t* bases, uint64_t total, uint64_t nwords, uint64_t* packed,
                        uint64_t* flags, hipStream_t s) {
   if (!nwords) return hipSuccess;
@@ -1310,8 +1317,7 @@ hipError_t launch_level1(const uint64_t* packed, const uint64_t* flags, uint64_t
                          uint32_t* lstart, uint64_t ntiles, uint64_t* out, hipStream_t s) {
   if (!ntiles) return hipSuccess;
   const size_t lds = level1_lds(a1);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_level1),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(k_level1));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_level1, dim3((uint32_t)ntiles), dim3(kThreads), lds, s, packed, flags,
                      nwords, k, s0, a1, tag, hist, lstart, ntiles, out);
@@ -1332,8 +1338,7 @@ hipError_t launch_level2(const uint64_t* keys1, const uint64_t* off1, const uint
   hipLaunchKernelGGL(k_tile_runs, dim3(div_up(grid, 256)), dim3(256), 0, s, off1, ntiles1,
                      bucket_off, tile_first, 1u << a1, tile_run);
   const size_t lds = level2_lds(a2);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_level2),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(k_level2));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_level2, dim3((uint32_t)grid), dim3(kThreads), lds, s, keys1, off1, lstart,
                      ntiles1, bucket_off, tile_first, tile_run, a1, a2, s0, keys2, meta2);
@@ -1342,8 +1347,7 @@ hipError_t launch_level2(const uint64_t* keys1, const uint64_t* off1, const uint
 
 template <int H>
 hipError_t launch_bloom_h(const CountArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bloom<H>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(k_bloom<H>));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bloom<H>, dim3(blocks), dim3(kThreads), lds, s, a);
   return hipGetLastError();
@@ -1351,8 +1355,7 @@ hipError_t launch_bloom_h(const CountArgs& a, uint32_t blocks, size_t lds, hipSt
 
 template <int H>
 hipError_t launch_tally_h(const CountArgs& a, uint32_t parts, size_t lds, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_tally<H>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(k_tally<H>));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_tally<H>, dim3(parts), dim3(kTallyThreads), lds, s, a);
   return hipGetLastError();

@@ -478,6 +478,59 @@ uint64_t resident_bytes(const kc_ctx* c) {
 
 }  // namespace
 
+namespace kc {
+
+uint64_t ctx_device_bytes(const kc_ctx* c) {
+  const DevBuf* bufs[] = {&c->b1, &c->b2, &c->dstat, &c->derr, &c->packed, &c->flags, &c->hist1,
+                          &c->lstart1, &c->off1, &c->parts, &c->keys1, &c->tile_run, &c->segdesc,
+                          &c->tkeys, &c->tcounts, &c->slot_of, &c->slot_live, &c->pstats,
+                          &c->pstats2, &c->pstats_ovf, &c->okeys, &c->ocounts, &c->ovf_used,
+                          &c->qrows, &c->qkeys, &c->qcount};
+  uint64_t n = 0;
+  for (const DevBuf* b : bufs) n += b->bytes;
+  auto seg = [](const Segment& g) {
+    return (uint64_t)g.keys.bytes + g.bucket_off.bytes + g.tile_first.bytes + g.meta2.bytes;
+  };
+  if (!c->segs_borrowed)
+    for (const Segment& g : c->segs) n += seg(g);
+  for (const Segment& g : c->spare_segs) n += seg(g);
+  for (const BatchGroup& g : c->batch.groups) n += seg(g.seg) + g.cdesc.bytes;
+  return n + c->batch.counts.bytes;
+}
+
+uint64_t estimate_count_bytes(const kc_config* cfg, const uint64_t* part_bases, uint32_t n_parts) {
+  std::string why;
+  if (validate(cfg, &why) != KC_OK) return 0;
+  kc_ctx c;
+  c.cfg = *cfg;
+  if (derive(&c) != KC_OK) return 0;
+  const uint64_t nb1 = 1ull << c.a1, nb2 = 1ull << c.a2;
+  const uint64_t nparts = 1ull << c.p_log2, nc = cfg->n_counters;
+  uint64_t n = 2 * c.bloom_words64 * 8 + kNst * 8 * 3 + 64;  // Bloom levels, stats, flags
+  uint64_t scratch = 0, segs = 0, runs = 0, keys = 0;
+  for (uint32_t i = 0; i < n_parts; ++i) {
+    const uint64_t nwords = (part_bases[i] + 31) / 32;
+    const uint64_t ntiles = (nwords + kTileWords - 1) / kTileWords;
+    const uint64_t nhist = nb1 * ntiles;
+    const uint64_t kmax = nwords * 32;  // keys <= window positions
+    const uint64_t tiles2 = (kmax + kT2 - 1) / kT2 + nb1;
+    scratch = std::max<uint64_t>(scratch, nwords * 16 + nhist * 4 + ntiles * (nb1 + 1) * 4 +
+                                              (nhist + 1) * 8 + scan_parts(nhist) * 8 +
+                                              ntiles * kTilePos * 8);
+    runs = std::max<uint64_t>(runs, tiles2 * 4);
+    segs += kmax * 8 + (nb1 + 1) * 12 + tiles2 * (nb2 + 1) * 4;
+    keys += kmax;
+  }
+  const uint32_t ovf_log2 = std::max<uint32_t>(12, std::min<uint32_t>(30, ceil_log2(keys / 256 + 1)));
+  const uint64_t on = 1ull << ovf_log2;
+  const uint64_t tables = nparts * c.cap * c.slot_bytes + nparts * 8 +
+                          ((1ull << c.s_log2) + nparts) * kNst * 8;
+  const uint64_t ovf = on * (8 + 4 * nc) + 1024ull * kNst * 8;
+  return n + scratch + runs + segs + tables + ovf;
+}
+
+}  // namespace kc
+
 extern "C" {
 
 uint32_t kc_abi_version(void) { return KC_ABI_VERSION; }
@@ -1063,7 +1116,9 @@ kc_status kc_get_stats(const kc_ctx* cc, kc_stats* out) {
 kc_status kc_reset(kc_ctx* c) {
   if (!c) return KC_ERR_INVALID_ARG;
   KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
-  KC_HIP(c, hipDeviceSynchronize(), "synchronise");
+  // every other call has finished its device work before returning; only the
+  // last insert's shuffle may still be queued
+  if (c->insert_done_valid) KC_HIP(c, hipEventSynchronize(c->insert_done), "synchronise");
   if (!c->segs_borrowed)
     for (Segment& g : c->segs) c->spare_segs.push_back(g);
   c->segs.clear();

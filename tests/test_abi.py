@@ -51,6 +51,8 @@ int main(void) {
          offsetof(kc_config, hbm_table_budget_bytes), sizeof(kc_stats),
          offsetof(kc_stats, kernel_ms), offsetof(kc_stats, kernel_launches), sizeof(kc_chunk),
          offsetof(kc_chunk, total_bases), sizeof(kc_tune_trial), offsetof(kc_tune_trial, ms));
+  printf("%zu %zu %zu %zu %zu\n", sizeof(kc_request), offsetof(kc_request, n_parts),
+         sizeof(kc_response), offsetof(kc_response, ctx), offsetof(kc_response, footprint_bytes));
   return 0;
 }
 ''')
@@ -61,7 +63,9 @@ int main(void) {
             kc.KcConfig.group_bases_log2.offset, kc.KcConfig.hbm_table_budget_bytes.offset,
             ctypes.sizeof(kc.KcStats), kc.KcStats.kernel_ms.offset,
             kc.KcStats.kernel_launches.offset, ctypes.sizeof(kc.KcChunk),
-            kc.KcChunk.total_bases.offset, ctypes.sizeof(kc.KcTuneTrial), kc.KcTuneTrial.ms.offset]
+            kc.KcChunk.total_bases.offset, ctypes.sizeof(kc.KcTuneTrial), kc.KcTuneTrial.ms.offset,
+            ctypes.sizeof(kc.KcRequest), kc.KcRequest.n_parts.offset, ctypes.sizeof(kc.KcResponse),
+            kc.KcResponse.ctx.offset, kc.KcResponse.footprint_bytes.offset]
     assert got == want
 
 
