@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -199,6 +200,134 @@ def trace_summary(trace_dir: str, command: str):
     print(open(md).read())
 
 
+def served_main(args, w):
+    """The served workload: 512 joint (normal, tumour) count requests of
+    log-uniform size through the request server under its HBM budget.
+    "plain" = the same requests through a one-worker server (one job at a
+    time, no overlap); "served" = concurrent workers.  Reports closed-loop
+    throughput of both and p50/p99 latency under Poisson arrivals at offered
+    loads rho x the plain capacity."""
+    import threading
+    import torch
+    import paper_1712_03254_amd as kc
+
+    kc.load()
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    normal = w.make_genome(threads=16)
+    tum = w.make_tumour(normal)
+    reads = [w.make_sample_reads(normal, 0, threads=16), w.make_sample_reads(tum, 1, threads=16)]
+    del normal, tum
+    gen_s = time.perf_counter() - t0
+    L = w.lmax
+    assert w.lmin == w.lmax  # fixed-length reads: a slice's offsets are a prefix of the first
+    dev_b = [torch.from_numpy(b).to(dev) for b, _ in reads]
+    offs = torch.from_numpy(reads[0][1].view(np.int64)).to(dev)
+    del reads
+    plan = w.request_plan()
+    win = L - w.k + 1
+
+    def request(i):
+        n, s0, s1 = (int(v) for v in plan[i])
+        half = n // 2
+        kmers = n * win
+        m = int(min(34, max(20, math.ceil(math.log2(8 * kmers)))))
+        pl = max(m - w.bloom_block_log2, int(round(math.log2(max(1, n * L) / 8192))))
+        cfg = kc.Config(k=w.k, n_counters=2, min_count=w.min_count, bloom_bits_log2=m,
+                        bloom_hashes=w.bloom_hashes, bloom_block_log2=w.bloom_block_log2,
+                        seed=w.seed, partitions_log2=pl)
+        parts = [(dev_b[0][s0 * L:(s0 + half) * L], offs[:half + 1]),
+                 (dev_b[1][s1 * L:(s1 + half) * L], offs[:half + 1])]
+        return cfg, parts, kmers
+
+    reqs = [request(i) for i in range(plan.shape[0])]
+    warm, timed = reqs[:w.warmup_requests], reqs[w.warmup_requests:]
+    total_kmers = sum(r[2] for r in timed)
+    mean_kmers = total_kmers / len(timed)
+
+    def run(srv, jobs, arrivals=None):
+        """Submits jobs (at arrival offsets in seconds, or all at once);
+        collectors wait and release each as it finishes."""
+        tickets = [None] * len(jobs)
+        ready = [threading.Event() for _ in jobs]
+        out = [None] * len(jobs)
+        nxt = {"i": 0}
+        lock = threading.Lock()
+
+        def collect():
+            while True:
+                with lock:
+                    i = nxt["i"]
+                    nxt["i"] += 1
+                if i >= len(jobs):
+                    return
+                ready[i].wait()
+                r = srv.wait(tickets[i])
+                out[i] = (r.status, r.submit_ms, r.admit_ms, r.done_ms, r.worker)
+                srv.release(tickets[i])
+
+        cols = [threading.Thread(target=collect) for _ in range(2 * args.serve_workers)]
+        for c in cols:
+            c.start()
+        start = time.perf_counter()
+        for i, (cfg, parts, _) in enumerate(jobs):
+            if arrivals is not None:
+                wait = start + arrivals[i] - time.perf_counter()
+                if wait > 0:
+                    time.sleep(wait)
+            tickets[i] = srv.submit(cfg, parts)
+            ready[i].set()
+        for c in cols:
+            c.join()
+        assert all(o[0] == 0 for o in out), [o[0] for o in out if o[0]]
+        lat = np.array([o[3] - o[1] for o in out])
+        svc = np.array([o[3] - o[2] for o in out])
+        span_ms = max(o[3] for o in out) - min(o[1] for o in out)
+        u = srv.usage()
+        return {"kmers_per_s": total_kmers / (span_ms * 1e-3),
+                "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                "mean_ms": round(float(lat.mean()), 2), "span_ms": round(span_ms, 1),
+                "mean_service_ms": round(float(svc.mean()), 2),
+                "contexts": {k: u[k] for k in ("created", "reused", "grown", "evicted",
+                                               "pooled_contexts")}}
+
+    budget = w.serve_budget
+    res = {}
+    with kc.Server(budget, workers=1) as plain, kc.Server(budget, workers=args.serve_workers) as srv:
+        run(plain, warm)
+        run(srv, warm)
+        closed_plain = run(plain, timed)
+        closed = run(srv, timed)
+        cap = closed_plain["kmers_per_s"]
+        rng = np.random.default_rng(w.seed)
+        gaps = rng.exponential(1.0, len(timed))
+        for rho in args.loads:
+            lam = rho * cap / mean_kmers  # requests per second
+            arr = np.cumsum(gaps) / lam
+            res[str(rho)] = {"served": run(srv, timed, arr), "plain": run(plain, timed, arr)}
+            print("rho %.1f: %s" % (rho, res[str(rho)]), file=sys.stderr, flush=True)
+    best = max([closed] + [v["served"] for v in res.values()], key=lambda d: d["kmers_per_s"])
+    out = {
+        "metric": METRIC, "value": closed["kmers_per_s"], "unit": "k-mers/s", "n_gpus": 1,
+        "steps": len(timed), "warmup": len(warm),
+        "ms_per_step": closed["span_ms"] / len(timed), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": w.name, "genome_bp": w.genome_len, "reads_per_sample": w.n_reads,
+                   "read_len": L, "requests": len(timed), "request_reads": [w.req_lo, w.req_hi],
+                   "k": w.k, "bloom_hashes": w.bloom_hashes, "n_counters": 2,
+                   "hbm_budget_bytes": budget, "workers": args.serve_workers,
+                   "mean_request_kmers": mean_kmers},
+        "served_closed_loop": closed,
+        "plain_closed_loop": closed_plain,
+        "served_vs_plain": round(closed["kmers_per_s"] / cap, 3),
+        "latency_by_offered_load": res,
+        "best_served_kmers_per_s": best["kmers_per_s"],
+        "input_gen_s": round(gen_s, 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,6 +342,10 @@ def main():
     ap.add_argument("--trace-summary", metavar="TRACE_DIR",
                     help="offline: turn a rocprofv3 --kernel-trace --stats run into a profiles/ file")
     ap.add_argument("--command", default="", help="command line recorded in the offline summaries")
+    ap.add_argument("--serve-workers", type=int, default=4,
+                    help="served workload: concurrent jobs (server worker threads)")
+    ap.add_argument("--loads", type=float, nargs="*", default=[0.3, 0.5, 0.7, 0.9],
+                    help="served workload: offered loads as fractions of the plain capacity")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.command)
@@ -232,8 +365,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    kc.load()
     w = synth.WORKLOADS[args.workload]
+    if w.requests:
+        served_main(args, w)
+        return
+    kc.load()
     batched = w.batch_chunks > 0
     t0 = time.perf_counter()
     genome = w.make_genome(threads=16)

@@ -278,9 +278,11 @@ kc_status kc_autotune_batch(const kc_config* base, int device, const kc_chunk* c
  * worker thread and stream each), so their kernels overlap on the device.  A
  * finished request keeps its context (tables, Bloom levels) resident until
  * kc_server_release; released contexts are kept for reuse by later requests
- * of the same configuration and are freed when the budget needs their
- * memory.  Each request's result is exactly what kc_create + kc_insert_reads
- * (per chunk) + kc_finalize would give alone: contexts share no state.
+ * (of any configuration: a reused context is reconfigured and keeps its
+ * buffers, which only grow) and are freed when the budget needs their memory.
+ * Reservations are exact: the bytes the chosen context will hold after the
+ * job.  Each request's result is exactly what kc_create + kc_insert_reads (per
+ * chunk) + kc_finalize would give alone: contexts share no state.
  */
 typedef struct kc_server kc_server;
 
@@ -321,10 +323,21 @@ kc_status kc_server_wait(kc_server* srv, uint64_t ticket, kc_response* out);
  * reuse pool) and the ticket becomes invalid. */
 kc_status kc_server_release(kc_server* srv, uint64_t ticket);
 
-/* Budget in use by admitted requests, bytes held by pooled contexts, queued
- * and running request counts. */
-kc_status kc_server_usage(kc_server* srv, uint64_t* in_use_bytes, uint64_t* pooled_bytes,
-                          uint32_t* queued, uint32_t* running);
+/* State and counters of a server. */
+typedef struct kc_server_stats {
+  uint64_t in_use_bytes;     /* reserved by admitted, unreleased requests */
+  uint64_t pooled_bytes;     /* held by pooled (released) contexts */
+  uint32_t queued;           /* requests waiting for admission */
+  uint32_t running;          /* requests on a worker now */
+  uint32_t pooled_contexts;
+  uint32_t reserved_;        /* 0 */
+  uint64_t created;          /* requests given a new context */
+  uint64_t reused;           /* ... a pooled context that needed no new memory */
+  uint64_t grown;            /* ... a pooled context whose buffers had to grow */
+  uint64_t evicted;          /* pooled contexts freed to make room */
+} kc_server_stats;
+
+kc_status kc_server_usage(kc_server* srv, kc_server_stats* out);
 
 /* Waits for running requests, drops queued ones, frees every context.  NULL
  * is ignored. */

@@ -85,6 +85,14 @@ class KcResponse(ctypes.Structure):
                 ("footprint_bytes", ctypes.c_uint64)]
 
 
+class KcServerStats(ctypes.Structure):
+    _fields_ = [("in_use_bytes", ctypes.c_uint64), ("pooled_bytes", ctypes.c_uint64),
+                ("queued", ctypes.c_uint32), ("running", ctypes.c_uint32),
+                ("pooled_contexts", ctypes.c_uint32), ("reserved_", ctypes.c_uint32),
+                ("created", ctypes.c_uint64), ("reused", ctypes.c_uint64),
+                ("grown", ctypes.c_uint64), ("evicted", ctypes.c_uint64)]
+
+
 class KcTuneTrial(ctypes.Structure):
     _fields_ = [("partitions_log2", ctypes.c_uint32), ("table_slots", ctypes.c_uint32),
                 ("scatter_bits", ctypes.c_uint32), ("status", ctypes.c_int32),
@@ -133,7 +141,7 @@ def load():
         "kc_server_submit": ([V, P(KcRequest), P(U64)], st),
         "kc_server_wait": ([V, U64, P(KcResponse)], st),
         "kc_server_release": ([V, U64], st),
-        "kc_server_usage": ([V, P(U64), P(U64), P(U32), P(U32)], st),
+        "kc_server_usage": ([V, P(KcServerStats)], st),
         "kc_server_destroy": ([V], None),
     }
     for name, (args, res) in sig.items():
@@ -417,11 +425,11 @@ class Server:
         _check(None, load().kc_server_release(self.h, ticket))
 
     def usage(self) -> dict:
-        a, b = ctypes.c_uint64(0), ctypes.c_uint64(0)
-        q, r = ctypes.c_uint32(0), ctypes.c_uint32(0)
-        _check(None, load().kc_server_usage(self.h, ctypes.byref(a), ctypes.byref(b),
-                                            ctypes.byref(q), ctypes.byref(r)))
-        return {"in_use": a.value, "pooled": b.value, "queued": q.value, "running": r.value}
+        st = KcServerStats()
+        _check(None, load().kc_server_usage(self.h, ctypes.byref(st)))
+        d = {n: getattr(st, n) for n, _ in st._fields_ if n != "reserved_"}
+        d["in_use"], d["pooled"] = d["in_use_bytes"], d["pooled_bytes"]
+        return d
 
     def close(self):
         if self.h:

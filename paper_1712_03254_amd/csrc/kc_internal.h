@@ -152,9 +152,27 @@ hipError_t launch_scatter_rows(const uint32_t* rows, const uint32_t* vals, uint3
 // ---- runtime helpers for the request server (kc_runtime.hip) ----
 // Device bytes a context holds now (every buffer it has allocated).
 uint64_t ctx_device_bytes(const kc_ctx* c);
-// Device bytes a context with configuration cfg allocates to count reads of
-// n_parts inserts of part_bases[i] bases each (an upper bound: every window
-// position a key); 0 when cfg is invalid.
+// Device bytes context c (NULL: a new one) holds after counting, with
+// configuration cfg, n_parts inserts of part_bases[i] bases each: its buffers
+// only grow, so each is the larger of what it holds and what the job needs
+// (keys bounded by window positions).  0 when cfg is invalid.
+uint64_t bytes_after(const kc_ctx* c, const kc_config* cfg, const uint64_t* part_bases,
+                     uint32_t n_parts);
 uint64_t estimate_count_bytes(const kc_config* cfg, const uint64_t* part_bases, uint32_t n_parts);
+// Gives a reset (CREATED) context a new configuration, keeping its buffers
+// (new ones are allocated in order on stream s).
+kc_status reconfigure(kc_ctx* c, const kc_config* cfg, hipStream_t s);
+// While one lives, the calling thread's library allocations and frees are
+// stream-ordered on s.
+struct AllocStream {
+  explicit AllocStream(hipStream_t s);
+  ~AllocStream();
+  AllocStream(const AllocStream&) = delete;
+  AllocStream& operator=(const AllocStream&) = delete;
+  hipStream_t prev;
+  bool prev_on;
+};
+// Keeps memory freed to the device's default pool cached there (once per device).
+void keep_pool_memory(int device);
 
 }  // namespace kc

@@ -5,10 +5,12 @@
 // and the spill directory, and enqueues the kernels of kc_kernels.hip on the
 // caller's stream.
 #include <algorithm>
+#include <array>
 #include <cstdio>
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -34,27 +36,76 @@ uint32_t ceil_log2(uint64_t v) {
   return r;
 }
 
+}  // namespace
+
+namespace kc {
+
+// Allocation stream of the calling thread: set by the entry points that run
+// on a stream.  There, buffers are allocated and freed in stream order
+// (hipMallocAsync / hipFreeAsync on the device's default pool, which keeps
+// freed memory for reuse), so a growing or freed buffer does not wait for the
+// whole device; elsewhere hipMalloc / hipFree.
+thread_local bool t_async = false;
+thread_local hipStream_t t_stream = nullptr;
+
+AllocStream::AllocStream(hipStream_t s) : prev(t_stream), prev_on(t_async) {
+  t_stream = s;
+  t_async = true;
+}
+AllocStream::~AllocStream() {
+  t_stream = prev;
+  t_async = prev_on;
+}
+
+void keep_pool_memory(int device) {
+  static std::once_flag once[64];
+  if (device < 0 || device >= 64) return;
+  std::call_once(once[device], [device] {
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+      uint64_t keep = ~0ull;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    (void)hipGetLastError();
+  });
+}
+
+}  // namespace kc
+
+namespace {
+
+using kc::t_async;
+using kc::t_stream;
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool async = false;  // came from hipMallocAsync
   template <typename T>
   T* as() const { return static_cast<T*>(p); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (async && t_async)
+        (void)hipFreeAsync(p, t_stream);
+      else
+        (void)hipFree(p);
+    }
     p = nullptr;
     bytes = 0;
+    async = false;
   }
   hipError_t ensure(size_t want) {
     if (want == 0) want = 8;
     if (bytes >= want) return hipSuccess;
     release();
-    hipError_t e = hipMalloc(&p, want);
+    hipError_t e = t_async ? hipMallocAsync(&p, want, t_stream) : hipMalloc(&p, want);
     if (e != hipSuccess) {
       p = nullptr;
       (void)hipGetLastError();
       return e;
     }
     bytes = want;
+    async = t_async;
     return hipSuccess;
   }
 };
@@ -498,35 +549,111 @@ uint64_t ctx_device_bytes(const kc_ctx* c) {
   return n + c->batch.counts.bytes;
 }
 
-uint64_t estimate_count_bytes(const kc_config* cfg, const uint64_t* part_bases, uint32_t n_parts) {
+uint64_t bytes_after(const kc_ctx* c, const kc_config* cfg, const uint64_t* part_bases,
+                     uint32_t n_parts) {
   std::string why;
   if (validate(cfg, &why) != KC_OK) return 0;
-  kc_ctx c;
-  c.cfg = *cfg;
-  if (derive(&c) != KC_OK) return 0;
-  const uint64_t nb1 = 1ull << c.a1, nb2 = 1ull << c.a2;
-  const uint64_t nparts = 1ull << c.p_log2, nc = cfg->n_counters;
-  uint64_t n = 2 * c.bloom_words64 * 8 + kNst * 8 * 3 + 64;  // Bloom levels, stats, flags
-  uint64_t scratch = 0, segs = 0, runs = 0, keys = 0;
+  kc_ctx d;
+  d.cfg = *cfg;
+  if (derive(&d) != KC_OK) return 0;
+  const uint64_t nb1 = 1ull << d.a1, nb2 = 1ull << d.a2;
+  const uint64_t nparts = 1ull << d.p_log2, nc = cfg->n_counters;
+  auto mx = [&](const DevBuf kc_ctx::*buf, uint64_t need) {
+    return std::max<uint64_t>(c ? (c->*buf).bytes : 0, need);
+  };
+  // first-level scratch (largest insert) and the per-insert segments
+  uint64_t packed = 0, hist = 0, lstart = 0, off = 0, parts = 0, keys1 = 0, runs = 0, keys = 0;
+  std::vector<std::array<uint64_t, 2>> seg;  // keys bytes, other bytes of each new segment
   for (uint32_t i = 0; i < n_parts; ++i) {
     const uint64_t nwords = (part_bases[i] + 31) / 32;
     const uint64_t ntiles = (nwords + kTileWords - 1) / kTileWords;
     const uint64_t nhist = nb1 * ntiles;
     const uint64_t kmax = nwords * 32;  // keys <= window positions
     const uint64_t tiles2 = (kmax + kT2 - 1) / kT2 + nb1;
-    scratch = std::max<uint64_t>(scratch, nwords * 16 + nhist * 4 + ntiles * (nb1 + 1) * 4 +
-                                              (nhist + 1) * 8 + scan_parts(nhist) * 8 +
-                                              ntiles * kTilePos * 8);
-    runs = std::max<uint64_t>(runs, tiles2 * 4);
-    segs += kmax * 8 + (nb1 + 1) * 12 + tiles2 * (nb2 + 1) * 4;
+    packed = std::max(packed, nwords * 8);
+    hist = std::max(hist, nhist * 4);
+    lstart = std::max(lstart, ntiles * (nb1 + 1) * 4);
+    off = std::max(off, (nhist + 1) * 8);
+    parts = std::max<uint64_t>(parts, scan_parts(nhist) * 8);
+    keys1 = std::max<uint64_t>(keys1, ntiles * kTilePos * 8);
+    runs = std::max(runs, tiles2 * 4);
+    if (kmax) seg.push_back({kmax * 8, (nb1 + 1) * 12 + tiles2 * (nb2 + 1) * 4});
     keys += kmax;
   }
+  uint64_t n = mx(&kc_ctx::b1, d.bloom_words64 * 8) + mx(&kc_ctx::b2, d.bloom_words64 * 8) +
+               mx(&kc_ctx::packed, packed) + mx(&kc_ctx::flags, packed) + mx(&kc_ctx::hist1, hist) +
+               mx(&kc_ctx::lstart1, lstart) + mx(&kc_ctx::off1, off) + mx(&kc_ctx::parts, parts) +
+               mx(&kc_ctx::keys1, keys1) + mx(&kc_ctx::tile_run, runs);
   const uint32_t ovf_log2 = std::max<uint32_t>(12, std::min<uint32_t>(30, ceil_log2(keys / 256 + 1)));
   const uint64_t on = 1ull << ovf_log2;
-  const uint64_t tables = nparts * c.cap * c.slot_bytes + nparts * 8 +
-                          ((1ull << c.s_log2) + nparts) * kNst * 8;
-  const uint64_t ovf = on * (8 + 4 * nc) + 1024ull * kNst * 8;
-  return n + scratch + runs + segs + tables + ovf;
+  const uint64_t oblocks = std::min<uint64_t>(1024, (on + 255) / 256);
+  n += mx(&kc_ctx::tkeys, nparts * d.cap * 8) + mx(&kc_ctx::tcounts, nparts * d.cap * 4 * nc) +
+       mx(&kc_ctx::slot_of, nparts * 4) + mx(&kc_ctx::slot_live, nparts * 4) +
+       mx(&kc_ctx::pstats, (1ull << d.s_log2) * kNst * 8) +
+       mx(&kc_ctx::pstats2, nparts * kNst * 8) + mx(&kc_ctx::okeys, on * 8) +
+       mx(&kc_ctx::ocounts, on * 4 * nc) + mx(&kc_ctx::pstats_ovf, oblocks * kNst * 8) +
+       mx(&kc_ctx::segdesc, std::max<uint64_t>(1, n_parts) * sizeof(SegDesc)) +
+       mx(&kc_ctx::dstat, kNst * 8 * 3) + mx(&kc_ctx::derr, 8) + mx(&kc_ctx::ovf_used, 8) +
+       mx(&kc_ctx::qcount, 8) + (c ? c->qrows.bytes + c->qkeys.bytes : 0);
+  // segments: after a reset the context keeps at most four spare ones, largest
+  // first; an insert reuses the first spare whose key buffer is large enough
+  std::vector<const Segment*> spare;
+  if (c) {
+    if (!c->segs_borrowed)
+      for (const Segment& g : c->segs) spare.push_back(&g);
+    for (const Segment& g : c->spare_segs) spare.push_back(&g);
+    std::sort(spare.begin(), spare.end(),
+              [](const Segment* a, const Segment* b) { return a->keys.bytes > b->keys.bytes; });
+    if (spare.size() > 4) spare.resize(4);
+    for (const BatchGroup& g : c->batch.groups)
+      n += g.seg.keys.bytes + g.seg.bucket_off.bytes + g.seg.tile_first.bytes + g.seg.meta2.bytes +
+           g.cdesc.bytes;
+    n += c->batch.counts.bytes;
+  }
+  for (const auto& need : seg) {
+    size_t k = 0;
+    while (k < spare.size() && spare[k]->keys.bytes < need[0]) ++k;
+    if (k < spare.size()) {
+      const Segment* g = spare[k];
+      n += g->keys.bytes + std::max<uint64_t>(g->bucket_off.bytes + g->tile_first.bytes + g->meta2.bytes,
+                                              need[1]);
+      spare.erase(spare.begin() + k);
+    } else {
+      n += need[0] + need[1];
+    }
+  }
+  for (const Segment* g : spare)
+    n += g->keys.bytes + g->bucket_off.bytes + g->tile_first.bytes + g->meta2.bytes;
+  return n;
+}
+
+uint64_t estimate_count_bytes(const kc_config* cfg, const uint64_t* part_bases, uint32_t n_parts) {
+  return bytes_after(nullptr, cfg, part_bases, n_parts);
+}
+
+kc_status reconfigure(kc_ctx* c, const kc_config* cfg, hipStream_t s) {
+  if (!c) return KC_ERR_INVALID_ARG;
+  AllocStream alloc_on(s);
+  if (c->state != CREATED) return fail(c, KC_ERR_BAD_STATE, "reconfigure needs a reset context");
+  std::string why;
+  if (validate(cfg, &why) != KC_OK) return fail(c, KC_ERR_INVALID_ARG, why);
+  const kc_config old = c->cfg;
+  c->cfg = *cfg;
+  kc_status r = derive(c);
+  if (r != KC_OK) {
+    c->cfg = old;
+    (void)derive(c);
+    return r;
+  }
+  invalidate_batch_graph(c);
+  KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
+  KC_HIP(c, c->b1.ensure(c->bloom_words64 * 8), "Bloom level allocation");
+  KC_HIP(c, c->b2.ensure(c->bloom_words64 * 8), "Bloom level allocation");
+  c->spill_of.assign(1ull << c->p_log2, -1);
+  c->slot_of_h.clear();
+  c->st.partitions_log2 = c->p_log2;
+  c->st.table_slots = c->cap;
+  return KC_OK;
 }
 
 }  // namespace kc
@@ -587,6 +714,7 @@ kc_status kc_create(const kc_config* cfg, int device, kc_ctx** out) {
     return s;
   };
   if (hipSetDevice(device) != hipSuccess) return bail(KC_ERR_DEVICE, "hipSetDevice failed");
+  kc::keep_pool_memory(device);
   const size_t bloom_bytes = c->bloom_words64 * 8;
   if (c->b1.ensure(bloom_bytes) != hipSuccess || c->b2.ensure(bloom_bytes) != hipSuccess)
     return bail(KC_ERR_OUT_OF_MEMORY, "Bloom level allocation failed");
@@ -618,6 +746,7 @@ kc_status kc_insert_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offse
   if (total_bases >= (1ull << 32))
     return fail(c, KC_ERR_INVALID_ARG, "more than 2^32 - 1 bases in one call (split the reads)");
   hipStream_t s = as_stream(hip_stream);
+  kc::AllocStream alloc_on(s);
   KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
   if (c->insert_done_valid) KC_HIP(c, hipStreamWaitEvent(s, c->insert_done, 0), "stream wait");
   invalidate_batch_graph(c);
@@ -721,6 +850,7 @@ kc_status kc_finalize(kc_ctx* c, void* hip_stream, kc_stats* out) {
   if (!c) return KC_ERR_INVALID_ARG;
   if (c->state == FINALIZED) return fail(c, KC_ERR_BAD_STATE, "already finalized");
   hipStream_t s = as_stream(hip_stream);
+  kc::AllocStream alloc_on(s);
   invalidate_batch_graph(c);
   KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
   if (c->insert_done_valid) KC_HIP(c, hipStreamWaitEvent(s, c->insert_done, 0), "stream wait");
@@ -932,6 +1062,7 @@ kc_status kc_query(kc_ctx* c, const uint64_t* kmers, uint64_t n, uint32_t* count
   if (!kmers || !counts) return fail(c, KC_ERR_INVALID_ARG, "NULL query buffer");
   if (n > 0xFFFFFFFFull) return fail(c, KC_ERR_INVALID_ARG, "more than 2^32 queries in one call");
   hipStream_t s = as_stream(hip_stream);
+  kc::AllocStream alloc_on(s);
   KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
   const bool any_spill = !c->spill_dir.empty();
   if (any_spill) {
@@ -1144,8 +1275,15 @@ kc_status kc_reset(kc_ctx* c) {
 
 void kc_destroy(kc_ctx* c) {
   if (!c) return;
+  if (!kc::t_async) {
+    // buffers from stream-ordered calls are freed in order on the null stream
+    kc::AllocStream alloc_on(nullptr);
+    kc_destroy(c);
+    return;
+  }
   (void)hipSetDevice(c->device);
-  (void)hipDeviceSynchronize();
+  // only the last insert may still be queued (every other call has finished)
+  if (c->insert_done_valid) (void)hipEventSynchronize(c->insert_done);
   if (!c->segs_borrowed)
     for (Segment& g : c->segs) g.release();
   for (Segment& g : c->spare_segs) g.release();
@@ -1377,6 +1515,7 @@ kc_status kc_count_batch(kc_ctx* c, const kc_chunk* chunks, uint32_t n_chunks, u
   if (c->cfg.hbm_table_budget_bytes && c->cfg.hbm_table_budget_bytes < nparts * per_table)
     return fail(c, KC_ERR_OVER_BUDGET, "batch counting keeps every partition table in HBM");
   hipStream_t s = as_stream(hip_stream);
+  kc::AllocStream alloc_on(s);
   KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
   if (!same_batch(c->batch, chunks, n_chunks, counter)) {
     kc_status r = build_batch(c, chunks, n_chunks, counter);

@@ -3,8 +3,9 @@
 // the server's HBM budget and a worker is free.  Each worker thread runs one
 // job at a time on a stream of its own, so admitted jobs overlap on the
 // device; a finished job keeps its context (tables resident) until the client
-// releases it, after which the context is pooled for a later job of the same
-// configuration.  Host code only.
+// releases it, after which the context is pooled: a later job reconfigures it
+// and reuses its buffers, so steady serving allocates and frees nothing.  Host
+// code only.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,15 +27,17 @@ namespace {
 struct Job {
   kc_request req{};
   kc_response resp{};
-  uint64_t estimate = 0;  // estimated device bytes of a fresh context for the job
+  uint64_t bases[2] = {0, 0};
+  uint64_t estimate = 0;  // device bytes of a fresh context after the job
   uint64_t reserve = 0;   // bytes counted in the server's in_use for the job
   bool done = false;
 };
 
+// A released context, kept for reuse by any later job (contexts are
+// reconfigured per job and keep their buffers, which only grow).
 struct Pooled {
-  kc_config cfg;
   kc_ctx* ctx;
-  uint64_t bytes;
+  uint64_t bytes;  // device bytes it holds
   uint64_t stamp;  // last use, for least-recently-used eviction
 };
 
@@ -42,14 +45,6 @@ kc_config normalised(const kc_config& c) {
   kc_config n = c;
   n.hbm_table_budget_bytes = 0;  // a job's tables always stay resident
   return n;
-}
-
-bool same_cfg(const kc_config& a, const kc_config& b) {
-  return a.k == b.k && a.n_counters == b.n_counters && a.min_count == b.min_count &&
-         a.bloom_bits_log2 == b.bloom_bits_log2 && a.bloom_hashes == b.bloom_hashes &&
-         a.bloom_block_log2 == b.bloom_block_log2 && a.seed == b.seed &&
-         a.partitions_log2 == b.partitions_log2 && a.table_slots == b.table_slots &&
-         a.scatter_bits == b.scatter_bits && a.group_bases_log2 == b.group_bases_log2;
 }
 
 }  // namespace
@@ -67,6 +62,7 @@ struct kc_server {
   std::vector<Pooled> pool;
   uint64_t pooled = 0;  // bytes of pooled contexts
   uint32_t running = 0;
+  uint64_t created = 0, reused = 0, grown = 0, evicted = 0;
   bool stop = false;
   std::vector<std::thread> threads;
   std::vector<hipStream_t> streams;
@@ -75,18 +71,58 @@ struct kc_server {
   double now() const {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
-  // pooled context of the job's configuration, or -1
-  int match(const Job& j) const {
-    for (size_t i = 0; i < pool.size(); ++i)
-      if (same_cfg(pool[i].cfg, j.req.cfg)) return (int)i;
-    return -1;
+  // Context for job j, *reserve receiving its size after the job: the
+  // smallest pooled context that needs no new memory (best fit); else a new
+  // one, if it fits beside the admitted jobs and the pooled contexts; else the
+  // pooled context that grows least, or a new one, if it fits once pooled
+  // contexts are freed.  Returns its pool index, -1 for a new context, -2
+  // when none fits yet.  (New memory and freed memory both cost: a growing
+  // buffer and an eviction free device memory, which waits for the device.)
+  int choose(const Job& j, uint64_t* reserve) const {
+    int fit = -2;
+    uint64_t fit_bytes = ~0ull;
+    int grow = -2;
+    uint64_t grow_by = ~0ull, grow_after = 0;
+    for (size_t i = 0; i < pool.size(); ++i) {
+      const uint64_t after = kc::bytes_after(pool[i].ctx, &j.req.cfg, j.bases, j.req.n_parts);
+      if (after == 0 || in_use + after > budget) continue;
+      if (after <= pool[i].bytes) {
+        if (pool[i].bytes < fit_bytes) {
+          fit = (int)i;
+          fit_bytes = pool[i].bytes;
+        }
+      } else if (after - pool[i].bytes < grow_by) {
+        grow = (int)i;
+        grow_by = after - pool[i].bytes;
+        grow_after = after;
+      }
+    }
+    if (fit >= 0) {
+      *reserve = fit_bytes;
+      return fit;
+    }
+    if (in_use + pooled + j.estimate <= budget) {
+      *reserve = j.estimate;
+      return -1;
+    }
+    if (grow >= 0 && grow_by <= j.estimate) {
+      *reserve = grow_after;
+      return grow;
+    }
+    if (in_use + j.estimate <= budget) {
+      *reserve = j.estimate;
+      return -1;
+    }
+    if (grow >= 0) {
+      *reserve = grow_after;
+      return grow;
+    }
+    return -2;
   }
-  // the head job fits once other pooled contexts are freed
   bool admissible() const {
     if (queue.empty()) return false;
-    const Job& j = jobs.at(queue.front());
-    const int m = match(j);
-    return in_use + j.estimate + (m >= 0 ? pool[m].bytes : 0) <= budget;
+    uint64_t r = 0;
+    return choose(jobs.at(queue.front()), &r) != -2;
   }
 };
 
@@ -94,9 +130,11 @@ namespace {
 
 kc_status run_job(kc_server* S, uint32_t w, const kc_request& req, kc_ctx** ctx, kc_stats* st) {
   hipStream_t s = S->streams[w];
+  kc::AllocStream alloc_on(s);  // creation and growth allocate in order on the worker's stream
   kc_status r;
   if (*ctx) {
     r = kc_reset(*ctx);
+    if (r == KC_OK) r = kc::reconfigure(*ctx, &req.cfg, s);
   } else {
     r = kc_create(&req.cfg, S->device, ctx);
   }
@@ -119,31 +157,37 @@ void worker_main(kc_server* S, uint32_t w) {
     S->queue.pop_front();
     Job& j = S->jobs.at(ticket);  // element references survive rehashing
     kc_ctx* ctx = nullptr;
-    uint64_t reuse = 0;
-    const int m = S->match(j);
+    uint64_t reserve = 0;
+    const int m = S->choose(j, &reserve);
     if (m >= 0) {
       ctx = S->pool[m].ctx;
-      reuse = S->pool[m].bytes;
-      S->pooled -= reuse;
+      ++(reserve > S->pool[m].bytes ? S->grown : S->reused);
+      S->pooled -= S->pool[m].bytes;
       S->pool.erase(S->pool.begin() + m);
+    } else {
+      ++S->created;
     }
-    // free pooled contexts, least recently used first, until the job fits
+    j.reserve = reserve;  // the context's size after the job
+    S->in_use += j.reserve;
+    // free pooled contexts, least recently used first, until everything fits
     std::vector<kc_ctx*> evict;
-    while (S->in_use + S->pooled + j.estimate + reuse > S->budget && !S->pool.empty()) {
+    while (S->in_use + S->pooled > S->budget && !S->pool.empty()) {
       auto lru = std::min_element(S->pool.begin(), S->pool.end(),
                                   [](const Pooled& a, const Pooled& b) { return a.stamp < b.stamp; });
       evict.push_back(lru->ctx);
       S->pooled -= lru->bytes;
       S->pool.erase(lru);
+      ++S->evicted;
     }
-    j.reserve = j.estimate + reuse;  // a reused context keeps its buffers and may grow them
-    S->in_use += j.reserve;
     ++S->running;
     j.resp.admit_ms = S->now();
     j.resp.worker = w;
     const kc_request req = j.req;
     lk.unlock();
-    for (kc_ctx* e : evict) kc_destroy(e);
+    {
+      kc::AllocStream alloc_on(S->streams[w]);  // evicted contexts are idle: free in stream order
+      for (kc_ctx* e : evict) kc_destroy(e);
+    }
     kc_stats st{};
     kc_status r = run_job(S, w, req, &ctx, &st);
     kc_ctx* dead = nullptr;
@@ -152,7 +196,10 @@ void worker_main(kc_server* S, uint32_t w) {
       ctx = nullptr;
     }
     const uint64_t actual = ctx ? kc::ctx_device_bytes(ctx) : 0;
-    if (dead) kc_destroy(dead);
+    if (dead) {
+      kc::AllocStream alloc_on(S->streams[w]);
+      kc_destroy(dead);
+    }
     lk.lock();
     --S->running;
     j.resp.status = r;
@@ -208,8 +255,9 @@ kc_status kc_server_submit(kc_server* S, const kc_request* req, uint64_t* ticket
   Job j;
   j.req = *req;
   j.req.cfg = normalised(req->cfg);
-  uint64_t bases[2] = {req->parts[0].total_bases, req->n_parts > 1 ? req->parts[1].total_bases : 0};
-  j.estimate = kc::estimate_count_bytes(&j.req.cfg, bases, req->n_parts);
+  j.bases[0] = req->parts[0].total_bases;
+  j.bases[1] = req->n_parts > 1 ? req->parts[1].total_bases : 0;
+  j.estimate = kc::estimate_count_bytes(&j.req.cfg, j.bases, req->n_parts);
   if (j.estimate == 0) return KC_ERR_INVALID_ARG;  // configuration rejected
   std::lock_guard<std::mutex> lk(S->mu);
   const uint64_t t = S->next_ticket++;
@@ -249,7 +297,7 @@ kc_status kc_server_release(kc_server* S, uint64_t ticket) {
   Job& j = it->second;
   S->in_use -= j.reserve;
   if (j.resp.ctx) {
-    S->pool.push_back({j.req.cfg, j.resp.ctx, j.reserve, ++S->stamp});
+    S->pool.push_back({j.resp.ctx, j.reserve, ++S->stamp});
     S->pooled += j.reserve;
   }
   S->jobs.erase(it);
@@ -257,14 +305,19 @@ kc_status kc_server_release(kc_server* S, uint64_t ticket) {
   return KC_OK;
 }
 
-kc_status kc_server_usage(kc_server* S, uint64_t* in_use, uint64_t* pooled, uint32_t* queued,
-                          uint32_t* running) {
-  if (!S) return KC_ERR_INVALID_ARG;
+kc_status kc_server_usage(kc_server* S, kc_server_stats* out) {
+  if (!S || !out) return KC_ERR_INVALID_ARG;
   std::lock_guard<std::mutex> lk(S->mu);
-  if (in_use) *in_use = S->in_use;
-  if (pooled) *pooled = S->pooled;
-  if (queued) *queued = (uint32_t)S->queue.size();
-  if (running) *running = S->running;
+  out->in_use_bytes = S->in_use;
+  out->pooled_bytes = S->pooled;
+  out->queued = (uint32_t)S->queue.size();
+  out->running = S->running;
+  out->pooled_contexts = (uint32_t)S->pool.size();
+  out->reserved_ = 0;
+  out->created = S->created;
+  out->reused = S->reused;
+  out->grown = S->grown;
+  out->evicted = S->evicted;
   return KC_OK;
 }
 

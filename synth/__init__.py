@@ -149,6 +149,15 @@ class Workload:
     batch_chunks: int = 0     # batched workloads: number of read chunks
     chunk_lo: float = 0.0     # reads per chunk, log-uniform in [chunk_lo, chunk_hi]
     chunk_hi: float = 0.0
+    requests: int = 0         # served workloads: timed requests (after warm-up ones)
+    warmup_requests: int = 0
+    req_lo: float = 0.0       # reads per request, log-uniform in [req_lo, req_hi]
+    req_hi: float = 0.0
+    snv_rate: float = 0.0     # tumour genome: distinct point substitutions per base
+    n_inv: int = 0            # ... then this many inversions of inv_lo..inv_hi bases
+    inv_lo: int = 0
+    inv_hi: int = 0
+    serve_budget: int = 0     # HBM budget of the request server (bytes)
 
     def make_genome(self, threads: int = 0) -> np.ndarray:
         return genome(self.seed, self.genome_len, threads)
@@ -157,6 +166,31 @@ class Workload:
         n = self.n_reads - first if n is None else n
         return reads(self.seed, genome_seq, first, n, self.lmin, self.lmax, self.err, self.nrate,
                      threads)
+
+    def make_tumour(self, normal_seq) -> np.ndarray:
+        return tumour(self.seed, normal_seq, int(self.snv_rate * self.genome_len), self.n_inv,
+                      self.inv_lo, self.inv_hi)
+
+    def make_sample_reads(self, genome_seq, sample: int, threads: int = 0):
+        """Reads of sample 0 (normal) or 1 (tumour): disjoint index ranges of
+        one read stream, so the two samples draw independent reads."""
+        return self.make_reads(genome_seq, first=sample * self.n_reads, n=self.n_reads,
+                               threads=threads)
+
+    def request_plan(self):
+        """(reads, normal start, tumour start) per request, warm-up ones first:
+        size log-uniform in [req_lo, req_hi] (even), half from each sample, at
+        seeded starts."""
+        n = self.warmup_requests + self.requests
+        d = draws(self.seed, 1, 3 * n).reshape(n, 3)
+        u = (d[:, 0] >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+        size = np.floor(np.exp(np.log(self.req_lo) + u * (np.log(self.req_hi) -
+                                                           np.log(self.req_lo)))).astype(np.int64)
+        half = np.maximum(1, size // 2)
+        room = (self.n_reads - half + 1).astype(np.uint64)
+        s0 = (d[:, 1] % room).astype(np.int64)
+        s1 = (d[:, 2] % room).astype(np.int64)
+        return np.stack([2 * half, s0, s1], axis=1)
 
     def chunk_plan(self) -> np.ndarray:
         """Reads per chunk of a batched workload: floor(exp(U[ln lo, ln hi])),
@@ -179,7 +213,9 @@ WORKLOADS = {
     "batched_200mbp": Workload("batched_200mbp", 3, 200_000_000, 0, 100, 250, 0.005, 0.0,
                                31, 35, 4, 19, 19, batch_chunks=256, chunk_lo=1e3, chunk_hi=2e6),
     "served_300mbp": Workload("served_300mbp", 4, 300_000_000, 30_000_000, 100, 100, 0.005, 0.0,
-                              31, 32, 4, 19, 16, n_counters=2),
+                              31, 32, 4, 19, 16, n_counters=2, requests=512, warmup_requests=32,
+                              req_lo=1e4, req_hi=5e6, snv_rate=0.001, n_inv=200, inv_lo=1000,
+                              inv_hi=10000, serve_budget=32 << 30),
     "spill_3gbp": Workload("spill_3gbp", 5, 3_000_000_000, 200_000_000, 100, 100, 0.01, 0.0,
                            31, 36, 4, 19, 20, table_budget=64 << 30),
 }
