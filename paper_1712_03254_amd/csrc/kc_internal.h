@@ -16,9 +16,9 @@ constexpr uint32_t kNoSlot = 0xFFFFFFFFu;          // partition table not in HBM
 constexpr uint32_t kProbeLimit = 128;              // probes before a key goes to the overflow table
 constexpr int kThreads = 1024;                  // block size of the tile kernels
 constexpr int kWaves = kThreads / 64;
-constexpr int kTileWords = 512;                 // first-level tile: 512 packed words
-constexpr int kTilePos = kTileWords * 32;       // = 16384 window positions
-constexpr int kT2 = 16384;                      // second-level tile: keys per workgroup
+constexpr int kTileWords = 256;                 // first-level tile: 256 packed words
+constexpr int kTilePos = kTileWords * 32;       // = 8192 window positions
+constexpr int kT2 = 8192;                       // second-level tile: keys per workgroup
 constexpr int kMaxA1 = 10;                      // first-level fan-out limit (bits)
 constexpr int kMaxA2 = 11;                      // second-level fan-out limit (bits)
 constexpr int kMaxPartLog2 = kMaxA1 + kMaxA2;    // partitions (log2) two levels can reach

@@ -286,8 +286,10 @@ __device__ __forceinline__ bool window_key(const WordCtx& c, uint32_t k, int j, 
 // One pass per tile of kTilePos window positions: extract the canonical keys,
 // counting-sort them by the top a1 bits of g in LDS, and write the sorted tile
 // to its own region of the tile-major buffer (every store is contiguous).  The
-// tile's bucket counts go out bucket-major (for the prefix sum that places
-// buckets) and its bucket starts tile-major (for the second level's gather).
+// tile's bucket counts and bucket starts go out bucket-major: the counts for
+// the prefix sum that places buckets, the starts for the second level's
+// gather, which reads one bucket's starts over consecutive tiles (adjacent
+// tiles' entries share cache lines, and their writes merge in L2).
 __global__ void __launch_bounds__(kThreads) k_level1(const uint64_t* __restrict__ packed,
                                                      const uint64_t* __restrict__ flags,
                                                      uint64_t nwords, uint32_t k, uint64_t s0,
@@ -304,15 +306,19 @@ __global__ void __launch_bounds__(kThreads) k_level1(const uint64_t* __restrict_
   uint32_t* scratch = start + nb + 1;                       // kWaves
   for (uint32_t i = threadIdx.x; i < nb; i += kThreads) cnt[i] = 0;
   __syncthreads();
-  const uint64_t w = (uint64_t)blockIdx.x * kTileWords + (threadIdx.x >> 1);
-  uint64_t key[16];
-  uint32_t meta[16];
+  // kPP consecutive positions per thread, kTPW threads per packed word
+  constexpr int kPP = kTilePos / kThreads;
+  constexpr int kTPW = 32 / kPP;
+  static_assert(kPP * kThreads == kTilePos && kTPW * kPP == 32, "level-1 tile shape");
+  const uint64_t w = (uint64_t)blockIdx.x * kTileWords + (threadIdx.x / kTPW);
+  uint64_t key[kPP];
+  uint32_t meta[kPP];
   uint32_t valid = 0;
   if (w < nwords) {
     const WordCtx c = load_word(packed, flags, w);
-    const int j0 = (threadIdx.x & 1) * 16;
+    const int j0 = (threadIdx.x % kTPW) * kPP;
 #pragma unroll
-    for (int jj = 0; jj < 16; ++jj) {
+    for (int jj = 0; jj < kPP; ++jj) {
       uint64_t x;
       if (window_key(c, k, j0 + jj, &x)) {
         const uint32_t b = (uint32_t)(mix64(x ^ s0) >> (64 - a1));
@@ -325,10 +331,9 @@ __global__ void __launch_bounds__(kThreads) k_level1(const uint64_t* __restrict_
   __syncthreads();
   block_exclusive_scan(cnt, start, nb, scratch);
   for (uint32_t i = threadIdx.x; i < nb; i += kThreads) hist[(uint64_t)i * ntiles + blockIdx.x] = cnt[i];
-  for (uint32_t i = threadIdx.x; i <= nb; i += kThreads)
-    lstart[(uint64_t)blockIdx.x * (nb + 1) + i] = start[i];
+  for (uint32_t i = threadIdx.x; i < nb; i += kThreads) lstart[(uint64_t)i * ntiles + blockIdx.x] = start[i];
 #pragma unroll
-  for (int jj = 0; jj < 16; ++jj)
+  for (int jj = 0; jj < kPP; ++jj)
     if (valid & (1u << jj)) stage[start[meta[jj] >> 16] + (meta[jj] & 0xFFFF)] = key[jj];
   __syncthreads();
   const uint32_t total = start[nb];
@@ -506,7 +511,7 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
     if (t < ntiles1) {
       const uint32_t rel = (uint32_t)(offc[t] - bo);
       wrel[threadIdx.x] = rel;
-      wsb[threadIdx.x] = t * kTilePos + lstart[t * (nb1 + 1) + c] - rel;
+      wsb[threadIdx.x] = t * kTilePos + lstart[(uint64_t)c * ntiles1 + t] - rel;
     } else {
       wrel[threadIdx.x] = 0xFFFFFFFFu;
     }
