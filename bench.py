@@ -47,16 +47,17 @@ def src_hash() -> str:
 
 
 def stage_alu_ops(stage: str, w, st: dict) -> float:
-    """Algorithmic integer ops of one launch: k_bloom evaluates h hashes per
-    occurrence; k_tally one slot hash per occurrence and h hashes per screened
-    key (occurrences of failing keys plus the first arrival of each passing
-    key); the shuffle levels one hash per occurrence."""
+    """Algorithmic integer ops of one launch: k_bloom evaluates one hash per
+    occurrence (the h bit positions follow from it by double hashing, 2 ops
+    each); k_tally one slot hash per occurrence and one hash per screened key
+    (occurrences of failing keys plus the first arrival of each passing key);
+    the shuffle levels one hash per occurrence."""
     n = st["n_valid"]
     if stage == "bloom":
-        return MIX64_OPS * w.bloom_hashes * n
+        return (MIX64_OPS + 2 * w.bloom_hashes) * n
     if stage == "tally":
         screened = (n - st["n_pass"]) + st["passed_distinct"]
-        return MIX64_OPS * w.bloom_hashes * screened + SLOT_HASH_OPS * n
+        return (MIX64_OPS + 2 * w.bloom_hashes) * screened + SLOT_HASH_OPS * n
     if stage in ("level1", "level2"):
         return MIX64_OPS * n
     return 0.0

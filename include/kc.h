@@ -62,11 +62,13 @@ typedef enum kc_status {
  *   code A=0 C=1 G=2 T=3; enc(w) = sum_j code(w_j) 4^(k-1-j); only the bytes
  *   A, C, G, T are bases, any other byte breaks the windows covering it;
  *   x = min(enc(w), enc(revcomp(w))); mix64 = SplitMix64 output function;
- *   s_i = mix64(seed + (i+1) * 0x9E3779B97F4A7C15) for i = 0..h;
+ *   s_i = mix64(seed + (i+1) * 0x9E3779B97F4A7C15) for i = 0, 1;
  *   g = mix64(x ^ s_0); block(x) = top (bloom_bits_log2 - bloom_block_log2)
- *   bits of g; S(x) = { block * 2^bloom_block_log2 + top bloom_block_log2
- *   bits of mix64(x ^ s_i) : i = 1..h };  hits(b) = number of occurrences of
- *   keys with b in S(x);  B1[b] = hits(b) >= 1, B2[b] = hits(b) >= 2;
+ *   bits of g; with B = 2^bloom_block_log2 and u = mix64(x ^ s_1), a = the
+ *   top bloom_block_log2 bits of u and b = the next bloom_block_log2 bits,
+ *   S(x) = { block * B + ((a + i*b) mod B) : i = 0..h-1 } (double hashing);
+ *   hits(b) = number of occurrences of keys with b in S(x);
+ *   B1[b] = hits(b) >= 1, B2[b] = hits(b) >= 2;
  *   a key passes the screen iff S(x) is a subset of B2.
  */
 typedef struct kc_config {

@@ -64,12 +64,18 @@ def salts(seed: int, h: int):
 
 
 def bloom_set(x: int, m_log2: int, h: int, block_log2: int, seed: int) -> set:
+    """S(x): h positions a + i*b (mod the block size) in x's block, where a
+    and b are the first two block_log2-bit fields of mix64(x ^ s_1), read off
+    its binary digits (double hashing)."""
     s = salts(seed, h)
     sb = m_log2 - block_log2
     g = mix64(x ^ s[0])
     block = (g >> (64 - sb)) if sb > 0 else 0
-    return {block * (1 << block_log2) + (mix64(x ^ s[i]) >> (64 - block_log2))
-            for i in range(1, h + 1)}
+    digits = format(mix64(x ^ s[1]), "064b")
+    a = int(digits[:block_log2], 2)
+    b = int(digits[block_log2:2 * block_log2], 2)
+    size = 1 << block_log2
+    return {block * size + (a + i * b) % size for i in range(h)}
 
 
 def count(reads, k, m_log2, h, block_log2, seed, min_count=2, tags=None, n_counters=1):

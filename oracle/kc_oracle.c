@@ -24,10 +24,13 @@
  *     (Sec. III, Count unit uses the second filter); keys seen once that pass
  *     are the false-positive singletons F that Unify removes (Sec. III,
  *     Unify unit);
- *   - bit positions: s_i = mix64(seed + (i+1)*0x9E3779B97F4A7C15), i=0..h;
- *     g = mix64(x ^ s_0); block = top (m_log2 - block_log2) bits of g;
- *     bit_i = block * 2^block_log2 + top block_log2 bits of mix64(x ^ s_i),
- *     i = 1..h, where mix64 is the SplitMix64 output function.
+ *   - bit positions (the paper names no hash functions): s_i = mix64(seed +
+ *     (i+1)*0x9E3779B97F4A7C15), i = 0, 1; g = mix64(x ^ s_0); block = top
+ *     (m_log2 - block_log2) bits of g; with u = mix64(x ^ s_1), a = its top
+ *     block_log2 bits and b = the next block_log2 bits, bit_i = block *
+ *     2^block_log2 + ((a + i*b) mod 2^block_log2), i = 0..h-1 (double hashing,
+ *     Kirsch and Mitzenmacher, "Less hashing, same performance", 2006); mix64
+ *     is the SplitMix64 output function.
  *
  * Algorithm: enumerate every valid window, push its canonical key, sort
  * (libc qsort), run-length encode into (x, counts), then derive B1/B2 from
@@ -120,12 +123,16 @@ static uint32_t or_bloom_positions(const or_params* p, const uint64_t* salt, uin
   uint32_t sb = p->m_log2 - p->block_log2;
   uint64_t g = or_mix64(x ^ salt[0]);
   uint64_t block = sb ? (g >> (64 - sb)) : 0;
+  uint64_t mask = (1ull << p->block_log2) - 1;
+  uint64_t u = or_mix64(x ^ salt[1]);
+  uint64_t a = u >> (64 - p->block_log2);
+  uint64_t b = (u >> (64 - 2 * p->block_log2)) & mask;
   uint32_t n = 0;
-  for (uint32_t i = 1; i <= p->h; ++i) {
-    uint64_t b = (block << p->block_log2) | (or_mix64(x ^ salt[i]) >> (64 - p->block_log2));
+  for (uint32_t i = 0; i < p->h; ++i) {
+    uint64_t q = (block << p->block_log2) | ((a + (uint64_t)i * b) & mask);
     int dup = 0;
-    for (uint32_t j = 0; j < n; ++j) dup |= (pos[j] == b);
-    if (!dup) pos[n++] = b;
+    for (uint32_t j = 0; j < n; ++j) dup |= (pos[j] == q);
+    if (!dup) pos[n++] = q;
   }
   return n;
 }

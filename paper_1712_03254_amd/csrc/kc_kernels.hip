@@ -730,14 +730,20 @@ __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint
   }
 }
 
-// In-block bit positions of S(x), i = 1..H; dup[i] marks a position equal to
-// an earlier one (S(x) is a set: one hit per occurrence per distinct bit).
+// In-block bit positions of S(x): a + i*b mod 2^bl for i < H, with a and b
+// the top two bl-bit fields of mix64(x ^ s_1) (double hashing: one hash for
+// all H positions).  dup[i] marks a position equal to an earlier one (S(x) is
+// a set: one hit per occurrence per distinct bit).
 template <int H>
 __device__ __forceinline__ void bloom_positions(const HashCfg& hc, uint64_t x, uint32_t pos[H],
                                                 bool dup[H]) {
+  const uint64_t u = mix64(x ^ hc.salt[1]);
+  const uint32_t mask = (1u << hc.bl) - 1u;
+  const uint32_t a = (uint32_t)(u >> (64 - hc.bl));
+  const uint32_t b = (uint32_t)(u >> (64 - 2 * hc.bl)) & mask;
 #pragma unroll
   for (int i = 0; i < H; ++i) {
-    pos[i] = (uint32_t)(mix64(x ^ hc.salt[i + 1]) >> (64 - hc.bl));
+    pos[i] = (a + (uint32_t)i * b) & mask;
     bool d = false;
 #pragma unroll
     for (int j = 0; j < i; ++j) d |= pos[j] == pos[i];
@@ -940,9 +946,13 @@ k_tally(const CountArgs A) {
     bool pass = false;
     if (fresh) {
       uint32_t w[H], p[H];
+      const uint64_t u = mix64(x ^ hc.salt[1]);
+      const uint32_t mask = (1u << hc.bl) - 1u;
+      const uint32_t a = (uint32_t)(u >> (64 - hc.bl));
+      const uint32_t b = (uint32_t)(u >> (64 - 2 * hc.bl)) & mask;
 #pragma unroll
       for (int i = 0; i < H; ++i) {
-        const uint64_t g = bit0 + (mix64(x ^ hc.salt[i + 1]) >> (64 - hc.bl));
+        const uint64_t g = bit0 + ((a + (uint32_t)i * b) & mask);
         p[i] = (uint32_t)(g & 31);
         w[i] = b2[g >> 5];
       }
