@@ -590,8 +590,9 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
 // FLAT = false walks run by run in chunks of 64 keys (a run's last chunk is
 // partly empty), with wave-uniform bookkeeping: right for long runs.
 // FLAT = true walks the concatenation of the wave's runs in full chunks of
-// 64: the wave prefix-sums the run lengths, and each lane finds the run that
-// holds its position by binary search over the sums (cross-lane reads):
+// 64: the wave prefix-sums the run lengths; two ballots bound the runs that
+// touch a chunk, and each lane steps through the few run starts inside it
+// (scalar reads), or binary-searches the sums when a chunk holds many runs:
 // right for short runs, where partly empty chunks would dominate.
 // s_waitcnt immediate (gfx9 encoding): vmcnt 0, expcnt and lgkmcnt unbounded.
 constexpr int kWaitVm0 = 0x0F70;
@@ -661,17 +662,41 @@ __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint
           r.n = v0 < total ? min((uint32_t)B, (total - v0 + 63) >> 6) : 0u;
 #pragma unroll
           for (int b = 0; b < B; ++b) {
-            const uint32_t v = v0 + 64 * b + lane_id();
+            const uint32_t vb = v0 + 64 * b;  // chunk start (wave-uniform)
+            const uint32_t v = vb + lane_id();
             const bool ok = v < total;
-            const uint32_t vc = ok ? v : 0u;
-            // largest run index jj with excl[jj] <= vc (excl is non-decreasing)
-            uint32_t jj = 0;
+            const uint32_t vc = ok ? v : vb;
+            // Runs touching the chunk: lanes jlo..jhi (excl is non-decreasing
+            // over lanes, so each ballot is a prefix of the lanes).
+            const uint64_t le_lo = __ballot(excl <= vb);
+            const uint64_t le_hi = __ballot(excl <= vb + 63);
+            const uint32_t jlo = le_lo ? 63 - (uint32_t)__builtin_clzll(le_lo) : 0u;
+            const uint32_t jhi = le_hi ? 63 - (uint32_t)__builtin_clzll(le_hi) : 0u;
+            uint32_t jj, start, ex;
+            if (jhi - jlo <= 8) {
+              // few run starts inside the chunk: step through them (scalar reads)
+              jj = jlo;
+              start = __builtin_amdgcn_readlane(mm0, jlo);
+              ex = __builtin_amdgcn_readlane(excl, jlo);
+              for (uint32_t t = jlo + 1; t <= jhi; ++t) {
+                const uint32_t et = __builtin_amdgcn_readlane(excl, t);
+                const uint32_t st = __builtin_amdgcn_readlane(mm0, t);
+                const bool in = vc >= et;
+                jj = in ? t : jj;
+                start = in ? st : start;
+                ex = in ? et : ex;
+              }
+            } else {
+              // many short runs: binary search over the lanes' run starts
+              jj = 0;
 #pragma unroll
-            for (int st = 32; st >= 1; st >>= 1) {
-              const uint32_t ex = __shfl(excl, jj + st, 64);
-              jj = ex <= vc ? jj + st : jj;
+              for (int sp = 32; sp >= 1; sp >>= 1) {
+                const uint32_t e = __shfl(excl, jj + sp, 64);
+                jj = e <= vc ? jj + sp : jj;
+              }
+              start = __shfl(mm0, jj, 64);
+              ex = __shfl(excl, jj, 64);
             }
-            const uint32_t start = __shfl(mm0, jj, 64), ex = __shfl(excl, jj, 64);
             off[b] = ok ? (tw + NW * jj) * kT2 + start + (vc - ex) : 0u;
             r.vmask |= (uint32_t)ok << b;
           }
