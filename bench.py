@@ -355,8 +355,8 @@ def main():
         trace_summary(args.trace_summary, args.command)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the counting path of this build runs on a single "
-              "MI355X (multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        print("bench.py measures one GPU only: the counting path runs on a single MI355X "
+              "(sharding by partition prefix across GPUs is designed, not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
