@@ -27,6 +27,14 @@ constexpr int kLdsSlack = 2048;                 // LDS left unused per k_tally w
 constexpr int kNst = 8;                         // statistics slots
 constexpr int kTallyWaves = 8;                  // waves per k_tally workgroup
 constexpr int kQueueBytes = kTallyWaves * 64 * 12;  // per-wave miss queues of k_tally
+constexpr uint32_t kXcds = 8;                   // XCDs; workgroup b is dispatched to XCD b mod 8
+
+// Second-level launch with an upper bound of `tiles2` tiles: the grid, a
+// multiple of kXcds.
+inline uint64_t level2_grid(uint64_t tiles2) { return (tiles2 + kXcds - 1) / kXcds * kXcds; }
+// u32 words of the tile_run buffer: one 64-bit descriptor per workgroup of
+// the second-level grid.
+inline uint64_t tile_run_words(uint64_t tiles2) { return 2 * level2_grid(tiles2); }
 
 enum Stat { ST_NPASS = 0, ST_ENTRIES, ST_SUM, ST_FP, ST_B1POP, ST_B2POP, ST_PASSED, ST_OVF };
 enum Err : uint32_t { ERR_OFFSETS = 1, ERR_OVF_FULL = 2, ERR_OVF_LOAD = 4, ERR_QUERY_RANGE = 8 };

@@ -299,6 +299,11 @@ __global__ void __launch_bounds__(kThreads) k_level1(const uint64_t* __restrict_
                                                      uint64_t ntiles,
                                                      uint64_t* __restrict__ out) {
   extern __shared__ uint64_t lds64[];
+  // XCD x takes tiles [x * per, (x + 1) * per): the histogram and run-start
+  // columns of neighbouring tiles share cache lines, which then fill in one L2
+  const uint64_t per = (ntiles + kXcds - 1) / kXcds;
+  const uint64_t tile = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+  if (tile >= ntiles) return;
   const uint32_t nb = 1u << a1;
   uint64_t* stage = lds64;                                  // kTilePos keys
   uint32_t* cnt = reinterpret_cast<uint32_t*>(stage + kTilePos);
@@ -310,7 +315,7 @@ __global__ void __launch_bounds__(kThreads) k_level1(const uint64_t* __restrict_
   constexpr int kPP = kTilePos / kThreads;
   constexpr int kTPW = 32 / kPP;
   static_assert(kPP * kThreads == kTilePos && kTPW * kPP == 32, "level-1 tile shape");
-  const uint64_t w = (uint64_t)blockIdx.x * kTileWords + (threadIdx.x / kTPW);
+  const uint64_t w = tile * kTileWords + (threadIdx.x / kTPW);
   uint64_t key[kPP];
   uint32_t meta[kPP];
   uint32_t valid = 0;
@@ -330,14 +335,14 @@ __global__ void __launch_bounds__(kThreads) k_level1(const uint64_t* __restrict_
   }
   __syncthreads();
   block_exclusive_scan(cnt, start, nb, scratch);
-  for (uint32_t i = threadIdx.x; i < nb; i += kThreads) hist[(uint64_t)i * ntiles + blockIdx.x] = cnt[i];
-  for (uint32_t i = threadIdx.x; i < nb; i += kThreads) lstart[(uint64_t)i * ntiles + blockIdx.x] = start[i];
+  for (uint32_t i = threadIdx.x; i < nb; i += kThreads) hist[(uint64_t)i * ntiles + tile] = cnt[i];
+  for (uint32_t i = threadIdx.x; i < nb; i += kThreads) lstart[(uint64_t)i * ntiles + tile] = start[i];
 #pragma unroll
   for (int jj = 0; jj < kPP; ++jj)
     if (valid & (1u << jj)) stage[start[meta[jj] >> 16] + (meta[jj] & 0xFFFF)] = key[jj];
   __syncthreads();
   const uint32_t total = start[nb];
-  uint64_t* dst = out + (uint64_t)blockIdx.x * kTilePos;
+  uint64_t* dst = out + tile * kTilePos;
   for (uint32_t i = threadIdx.x; i < total; i += kThreads) dst[i] = stage[i];
 }
 
@@ -442,29 +447,63 @@ __global__ void __launch_bounds__(kThreads) k_tiles2(const uint64_t* __restrict_
   block_exclusive_scan(cnt, tile_first, nb1, scratch);
 }
 
-// For every second-level tile: the first-level tile whose run of the tile's
-// bucket holds the tile's first key (largest t with off1[c][t] <= start).
+// For every second-level tile tt, a descriptor for the workgroup of the
+// second-level grid (grid8 workgroups) that takes it: tt, its first-level
+// bucket c and the first-level tile whose run of c holds the tile's first key
+// (largest t with off1[c][t] <= start), packed as tt | c << 20 | t << 30, so
+// the workgroup starts from one load instead of searches.  ~0 marks a
+// workgroup with no tile.
+//
+// Order: bucket c's tile j reads the runs of c in a stretch of first-level
+// tiles; bucket c + 1's tile j reads the neighbouring runs of nearly the same
+// stretch, and the two share a cache line at every run boundary.  The
+// buckets are split into min(8, nb1) groups of consecutive buckets, group g
+// goes to XCD g, and inside a group tiles are taken j-major (all buckets'
+// tile 0, then all tile 1, ...), so the workgroups an XCD runs at once read
+// adjacent runs through the same L2.  When a group holds more tiles than its
+// XCD has workgroups (skewed buckets) the grid takes tiles in plain order.
 __global__ void __launch_bounds__(256) k_tile_runs(const uint64_t* __restrict__ off1,
                                                    uint64_t ntiles1,
                                                    const uint64_t* __restrict__ bucket_off,
                                                    const uint32_t* __restrict__ tile_first,
-                                                   uint32_t nb1, uint32_t* __restrict__ tile_run) {
+                                                   uint32_t nb1, uint32_t grid8,
+                                                   uint64_t* __restrict__ order) {
+  __shared__ uint32_t tf[(1u << kMaxA1) + 1];
+  for (uint32_t i = threadIdx.x; i <= nb1; i += blockDim.x) tf[i] = tile_first[i];
+  __syncthreads();
   const uint32_t tt = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tt >= tile_first[nb1]) return;
+  if (tt >= tf[nb1]) return;
   uint32_t lo = 0, hi = nb1;
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
-    if (tile_first[mid] <= tt) lo = mid; else hi = mid;
+    if (tf[mid] <= tt) lo = mid; else hi = mid;
   }
   const uint32_t c = lo;
-  const uint64_t want = bucket_off[c] + (uint64_t)(tt - tile_first[c]) * kT2;
+  const uint64_t want = bucket_off[c] + (uint64_t)(tt - tf[c]) * kT2;
   const uint64_t* offc = off1 + (uint64_t)c * ntiles1;
   uint64_t a = 0, b = ntiles1;  // largest t in [0, ntiles1) with offc[t] <= want
   while (b - a > 1) {
     const uint64_t mid = (a + b) >> 1;
     if (offc[mid] <= want) a = mid; else b = mid;
   }
-  tile_run[tt] = (uint32_t)a;
+  const uint64_t desc = (uint64_t)tt | (uint64_t)c << 20 | a << 30;
+  {
+    const uint32_t ng = nb1 < kXcds ? nb1 : kXcds, gs = nb1 / ng, per = grid8 / kXcds;
+    bool fits = true;
+    for (uint32_t g = 0; g < ng; ++g) fits = fits && tf[(g + 1) * gs] - tf[g * gs] <= per;
+    if (fits) {
+      const uint32_t g = c / gs, j = tt - tf[c];
+      uint32_t pos = 0;
+      for (uint32_t d = g * gs; d < (g + 1) * gs; ++d) {
+        const uint32_t nd = tf[d + 1] - tf[d];
+        pos += nd < j ? nd : j;
+        if (d < c && nd > j) ++pos;
+      }
+      order[pos * kXcds + g] = desc;
+    } else {
+      order[tt] = desc;
+    }
+  }
 }
 
 // Second level: each workgroup takes kT2 consecutive keys of one first-level
@@ -477,20 +516,16 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
                                                      uint64_t ntiles1,
                                                      const uint64_t* __restrict__ bucket_off,
                                                      const uint32_t* __restrict__ tile_first,
-                                                     const uint32_t* __restrict__ tile_run,
+                                                     const uint64_t* __restrict__ order,
                                                      uint32_t a1, uint32_t a2, uint64_t s0,
                                                      uint64_t* __restrict__ keys2,
                                                      uint32_t* __restrict__ meta2) {
   extern __shared__ uint64_t lds64[];
-  const uint32_t nb1 = 1u << a1, nb2 = 1u << a2;
-  const uint32_t tt = blockIdx.x;
-  if (tt >= tile_first[nb1]) return;
-  uint32_t lo = 0, hi = nb1;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (tile_first[mid] <= tt) lo = mid; else hi = mid;
-  }
-  const uint32_t c = lo;
+  const uint32_t nb2 = 1u << a2;
+  const uint64_t desc = order[blockIdx.x];
+  if (desc == kEmpty) return;
+  const uint32_t tt = (uint32_t)desc & 0xFFFFF;
+  const uint32_t c = (uint32_t)(desc >> 20) & 0x3FF;
   const uint64_t bo = bucket_off[c];
   const uint32_t p0 = (tt - tile_first[c]) * (uint32_t)kT2;  // bucket-relative start
   const uint32_t n = (uint32_t)min((uint64_t)kT2, bucket_off[c + 1] - bo - p0);
@@ -504,7 +539,7 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
   const uint64_t* offc = off1 + (uint64_t)c * ntiles1;
 
   // gather: windows of kThreads first-level runs, binary search per key
-  uint64_t tw = tile_run[tt];
+  uint64_t tw = desc >> 30;
   uint32_t got = 0;
   while (got < n) {
     const uint64_t t = tw + threadIdx.x;
@@ -1359,7 +1394,8 @@ hipError_t launch_level1(const uint64_t* packed, const uint64_t* flags, uint64_t
   const size_t lds = level1_lds(a1);
   hipError_t e = allow_lds(reinterpret_cast<const void*>(k_level1));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_level1, dim3((uint32_t)ntiles), dim3(kThreads), lds, s, packed, flags,
+  const uint64_t grid = (ntiles + kXcds - 1) / kXcds * kXcds;
+  hipLaunchKernelGGL(k_level1, dim3((uint32_t)grid), dim3(kThreads), lds, s, packed, flags,
                      nwords, k, s0, a1, tag, hist, lstart, ntiles, out);
   return hipGetLastError();
 }
@@ -1375,13 +1411,20 @@ hipError_t launch_level2(const uint64_t* keys1, const uint64_t* off1, const uint
                          uint32_t* tile_run, uint32_t a1, uint32_t a2, uint64_t s0,
                          uint64_t* keys2, uint32_t* meta2, uint64_t grid, hipStream_t s) {
   if (!grid) return hipSuccess;
-  hipLaunchKernelGGL(k_tile_runs, dim3(div_up(grid, 256)), dim3(256), 0, s, off1, ntiles1,
-                     bucket_off, tile_first, 1u << a1, tile_run);
-  const size_t lds = level2_lds(a2);
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(k_level2));
+  // one descriptor per workgroup; tiles, buckets and first-level tiles must
+  // fit their fields (20, 10 and 34 bits; never all ones)
+  const uint64_t grid8 = level2_grid(grid);
+  if (grid8 > (1u << 20) || a1 > 10 || ntiles1 >= (1ull << 33)) return hipErrorInvalidValue;
+  uint64_t* order = reinterpret_cast<uint64_t*>(tile_run);
+  hipError_t e = launch_fill64(order, grid8, kEmpty, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_level2, dim3((uint32_t)grid), dim3(kThreads), lds, s, keys1, off1, lstart,
-                     ntiles1, bucket_off, tile_first, tile_run, a1, a2, s0, keys2, meta2);
+  hipLaunchKernelGGL(k_tile_runs, dim3(div_up(grid, 256)), dim3(256), 0, s, off1, ntiles1,
+                     bucket_off, tile_first, 1u << a1, (uint32_t)grid8, order);
+  const size_t lds = level2_lds(a2);
+  e = allow_lds(reinterpret_cast<const void*>(k_level2));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_level2, dim3((uint32_t)grid8), dim3(kThreads), lds, s, keys1, off1, lstart,
+                     ntiles1, bucket_off, tile_first, order, a1, a2, s0, keys2, meta2);
   return hipGetLastError();
 }
 

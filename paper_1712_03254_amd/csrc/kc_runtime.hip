@@ -576,7 +576,7 @@ uint64_t bytes_after(const kc_ctx* c, const kc_config* cfg, const uint64_t* part
     off = std::max(off, (nhist + 1) * 8);
     parts = std::max<uint64_t>(parts, scan_parts(nhist) * 8);
     keys1 = std::max<uint64_t>(keys1, ntiles * kTilePos * 8);
-    runs = std::max(runs, tiles2 * 4);
+    runs = std::max(runs, tile_run_words(tiles2) * 4);
     if (kmax) seg.push_back({kmax * 8, (nb1 + 1) * 12 + tiles2 * (nb2 + 1) * 4});
     keys += kmax;
   }
@@ -823,7 +823,7 @@ kc_status kc_insert_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offse
     seg.release();
     return hip_fail(c, e, "segment allocation");
   }
-  KC_HIP(c, c->tile_run.ensure(tiles2 * 4), "tile run buffer");
+  KC_HIP(c, c->tile_run.ensure(tile_run_words(tiles2) * 4), "tile run buffer");
   {
     StageTimer t(c, s, KC_T_LEVEL2);
     KC_HIP(c, launch_bucket_off(c->off1.as<uint64_t>(), ntiles, nb1, seg.bucket_off.as<uint64_t>(), s),
@@ -1385,7 +1385,7 @@ kc_status build_batch(kc_ctx* c, const kc_chunk* ch, uint32_t n, uint32_t counte
   KC_HIP(c, c->off1.ensure((max_hist + 1) * 8), "offset buffer");
   KC_HIP(c, c->parts.ensure(scan_parts(max_hist) * 8), "scan buffer");
   KC_HIP(c, c->keys1.ensure(max_tiles * kTilePos * 8), "first-level key buffer");
-  KC_HIP(c, c->tile_run.ensure(max_tiles2 * 4), "tile run buffer");
+  KC_HIP(c, c->tile_run.ensure(tile_run_words(max_tiles2) * 4), "tile run buffer");
   KC_HIP(c, b.counts.ensure(std::max<size_t>(1, b.groups.size()) * 8), "segment counts");
   std::vector<SegDesc> hd;
   for (size_t gi = 0; gi < b.groups.size(); ++gi) {
