@@ -295,7 +295,9 @@ def served_main(args, w):
 
     budget = w.serve_budget
     res = {}
-    with kc.Server(budget, workers=1) as plain, kc.Server(budget, workers=args.serve_workers) as srv:
+    overlap = int(args.serve_overlap)
+    with kc.Server(budget, workers=1) as plain, \
+            kc.Server(budget, workers=args.serve_workers, overlap_bases=overlap) as srv:
         run(plain, warm)
         run(srv, warm)
         closed_plain = run(plain, timed)
@@ -318,6 +320,7 @@ def served_main(args, w):
                    "read_len": L, "requests": len(timed), "request_reads": [w.req_lo, w.req_hi],
                    "k": w.k, "bloom_hashes": w.bloom_hashes, "n_counters": 2,
                    "hbm_budget_bytes": budget, "workers": args.serve_workers,
+                   "overlap_bases": overlap,
                    "mean_request_kmers": mean_kmers},
         "served_closed_loop": closed,
         "plain_closed_loop": closed_plain,
@@ -345,6 +348,9 @@ def main():
     ap.add_argument("--command", default="", help="command line recorded in the offline summaries")
     ap.add_argument("--serve-workers", type=int, default=4,
                     help="served workload: concurrent jobs (server worker threads)")
+    ap.add_argument("--serve-overlap", type=float, default=float(1 << 28),
+                    help="served workload: admission cap on the bases of requests running at "
+                         "once (0: none)")
     ap.add_argument("--loads", type=float, nargs="*", default=[0.3, 0.5, 0.7, 0.9],
                     help="served workload: offered loads as fractions of the plain capacity")
     args = ap.parse_args()
@@ -455,6 +461,28 @@ def main():
     e2e = n_valid / (time.perf_counter() - t1)
     del fresh
 
+    plain_same = None
+    if batched:
+        # the same resident chunks and configuration through the plain path
+        # (one kc_insert_reads per chunk, then kc_finalize); after this the
+        # context holds no graph, so it runs last
+        def plain_step():
+            counter.reset()
+            for b, o in chunks:
+                counter.insert_reads(b, o, stream=stream)
+            return counter.finalize(stream=stream)
+        plain_step()
+        torch.cuda.synchronize()
+        reps = max(1, min(3, args.steps))
+        t2 = time.perf_counter()
+        for _ in range(reps):
+            pst = plain_step()
+        torch.cuda.synchronize()
+        pdt = (time.perf_counter() - t2) / reps
+        assert pst["n_valid"] == n_valid and pst["entries"] == last["entries"]
+        plain_same = {"value": n_valid / pdt, "ms_per_step": round(pdt * 1e3, 2), "steps": reps,
+                      "batched_over_plain": round(value / (n_valid / pdt), 3)}
+
     cfg_eff = {"partitions_log2": last["partitions_log2"], "table_slots": last["table_slots"],
                "total_bases": total_bases, "n_reads": n_reads}
     stages = {}
@@ -511,6 +539,8 @@ def main():
     }
     if tune is not None:
         out["autotune"] = tune
+    if plain_same is not None:
+        out["plain_same_workload"] = plain_same
     if args.copy_probe:
         src = torch.empty(COPY_BYTES, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

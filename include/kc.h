@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define KC_ABI_VERSION 2u
+#define KC_ABI_VERSION 3u
 
 typedef struct kc_ctx kc_ctx;
 
@@ -310,6 +310,13 @@ typedef struct kc_response {
  * within hbm_budget_bytes of device memory (> 0). */
 kc_status kc_server_create(int device, uint64_t hbm_budget_bytes, uint32_t workers,
                            kc_server** out);
+
+/* Caps the work on the device at once: a request is admitted only while no
+ * request runs, or the total bases of the running requests and its own stay
+ * within max_inflight_bases.  A large request then runs alone and small ones
+ * overlap.  0 (the default) sets no cap: requests are admitted as memory
+ * allows.  Takes effect for admissions after the call. */
+kc_status kc_server_set_overlap(kc_server* srv, uint64_t max_inflight_bases);
 
 /* Queues a request (copied; its read buffers must stay valid until the
  * request is done) and returns at once with its ticket.  A request whose

@@ -34,7 +34,7 @@ EXPORTED = ["kc_abi_version", "kc_status_str", "kc_create", "kc_insert_reads", "
             "kc_query", "kc_spill", "kc_export", "kc_export_bloom", "kc_debug_keys",
             "kc_get_stats", "kc_reset", "kc_destroy", "kc_last_error", "kc_count_batch",
             "kc_autotune_batch", "kc_server_create", "kc_server_submit", "kc_server_wait",
-            "kc_server_release", "kc_server_usage", "kc_server_destroy"]
+            "kc_server_release", "kc_server_usage", "kc_server_destroy", "kc_server_set_overlap"]
 
 
 class KcError(RuntimeError):
@@ -143,6 +143,7 @@ def load():
         "kc_server_release": ([V, U64], st),
         "kc_server_usage": ([V, P(KcServerStats)], st),
         "kc_server_destroy": ([V], None),
+        "kc_server_set_overlap": ([V, U64], st),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -394,15 +395,23 @@ class KmerCounter:
 
 class Server:
     """Request server (kc_server_*): jobs of their own configuration, admitted
-    under an HBM budget, run concurrently by `workers` threads."""
+    under an HBM budget, run concurrently by `workers` threads.  With
+    overlap_bases > 0, a request starts only when none runs or the running
+    ones and it hold at most that many bases (kc_server_set_overlap)."""
 
-    def __init__(self, budget_bytes: int, workers: int = 4, device: int = 0):
+    def __init__(self, budget_bytes: int, workers: int = 4, device: int = 0,
+                 overlap_bases: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Server needs a HIP device")
         h = ctypes.c_void_p()
         _check(None, load().kc_server_create(device, budget_bytes, workers, ctypes.byref(h)))
         self.h = h
+        if overlap_bases:
+            self.set_overlap(overlap_bases)
+
+    def set_overlap(self, max_inflight_bases: int):
+        _check(None, load().kc_server_set_overlap(self.h, max_inflight_bases))
 
     def submit(self, cfg: Config, parts) -> int:
         """parts: list of up to two (bases, offsets) device tensor pairs (part c

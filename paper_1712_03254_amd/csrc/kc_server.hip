@@ -62,6 +62,8 @@ struct kc_server {
   std::vector<Pooled> pool;
   uint64_t pooled = 0;  // bytes of pooled contexts
   uint32_t running = 0;
+  uint64_t inflight = 0;      // bases of the requests on workers now
+  uint64_t max_inflight = 0;  // admission cap on inflight (0: none)
   uint64_t created = 0, reused = 0, grown = 0, evicted = 0;
   bool stop = false;
   std::vector<std::thread> threads;
@@ -119,10 +121,15 @@ struct kc_server {
     }
     return -2;
   }
+  // The head of the queue may start: its memory fits, and (with a cap) no
+  // request is running or the running ones and it stay within the cap, so a
+  // large request runs alone while small ones overlap.
   bool admissible() const {
     if (queue.empty()) return false;
+    const Job& j = jobs.at(queue.front());
+    if (max_inflight && running && inflight + j.bases[0] + j.bases[1] > max_inflight) return false;
     uint64_t r = 0;
-    return choose(jobs.at(queue.front()), &r) != -2;
+    return choose(j, &r) != -2;
   }
 };
 
@@ -180,6 +187,7 @@ void worker_main(kc_server* S, uint32_t w) {
       ++S->evicted;
     }
     ++S->running;
+    S->inflight += j.bases[0] + j.bases[1];
     j.resp.admit_ms = S->now();
     j.resp.worker = w;
     const kc_request req = j.req;
@@ -202,6 +210,7 @@ void worker_main(kc_server* S, uint32_t w) {
     }
     lk.lock();
     --S->running;
+    S->inflight -= j.bases[0] + j.bases[1];
     j.resp.status = r;
     j.resp.stats = st;
     j.resp.ctx = ctx;
@@ -245,6 +254,14 @@ kc_status kc_server_create(int device, uint64_t hbm_budget_bytes, uint32_t worke
   }
   for (uint32_t w = 0; w < workers; ++w) S->threads.emplace_back(worker_main, S, w);
   *out = S;
+  return KC_OK;
+}
+
+kc_status kc_server_set_overlap(kc_server* S, uint64_t max_inflight_bases) {
+  if (!S) return KC_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->max_inflight = max_inflight_bases;
+  S->cv_work.notify_all();
   return KC_OK;
 }
 

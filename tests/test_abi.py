@@ -86,3 +86,5 @@ def test_null_context_calls_are_rejected():
     assert lib.kc_finalize(None, None, None) == kc.KC_ERR_INVALID_ARG
     assert lib.kc_reset(None) == kc.KC_ERR_INVALID_ARG
     lib.kc_destroy(None)
+    assert lib.kc_server_set_overlap(None, 1) == kc.KC_ERR_INVALID_ARG
+    assert lib.kc_server_release(None, 1) == kc.KC_ERR_INVALID_ARG

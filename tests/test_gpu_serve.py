@@ -151,3 +151,31 @@ def test_server_admission_errors_and_resident_tables():
         r2 = srv.wait(t2)
         assert r2.status == kc.KC_OK and r2.stats.entries == resp.stats.entries
         srv.release(t2)
+
+
+def test_overlap_cap_bounds_work_in_flight():
+    """kc_server_set_overlap: a request starts only when none runs or the
+    running ones and it hold at most the cap in bases; results stay equal to
+    the same jobs run alone."""
+    note("case: 16 joint jobs, 4 workers, overlap cap of twice the median job, seed 73")
+    jobs = make_jobs(73, 16)
+    dev = [(cfg, [to_device(b, o) for b, o in parts]) for cfg, parts in jobs]
+    ref = [alone(cfg, parts) for cfg, parts in dev]
+    sizes = [sum(int(o[-1]) for _, o in parts) for _, parts in jobs]
+    cap = 2 * int(np.median(sizes))
+    with kc.Server(256 << 20, workers=4, overlap_bases=cap) as srv:
+        tickets = [srv.submit(cfg, parts) for cfg, parts in dev]
+        spans = []
+        for t, (cfg, _), r, n in zip(tickets, dev, ref, sizes):
+            resp = srv.wait(t)
+            assert resp.status == kc.KC_OK, resp.status
+            same(served(resp, cfg), r)
+            spans.append((resp.admit_ms, resp.done_ms, n))
+            srv.release(t)
+    overlapped = 0
+    for a, d, n in spans:
+        running = [m for a2, d2, m in spans if a2 < a < d2]
+        assert not running or sum(running) + n <= cap, (running, n, cap)
+        overlapped += bool(running)
+    assert overlapped > 0  # small jobs still ran side by side
+    note("cap %d bases; %d of %d jobs started beside others" % (cap, overlapped, len(spans)))
