@@ -532,10 +532,14 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
   uint64_t* stage = lds64;                                            // kT2
   uint64_t* wsb = stage + kT2;                                        // kThreads
   uint32_t* wrel = reinterpret_cast<uint32_t*>(wsb + kThreads);       // kThreads
-  uint32_t* cnt = wrel + kThreads;                                    // nb2
+  // once the gather is done the window arrays are free: the sort's counts,
+  // starts and scan scratch take their place (this keeps two workgroups per
+  // CU up to 2^10 sub-buckets)
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(wsb);                   // nb2
   uint32_t* start = cnt + nb2;                                        // nb2 + 1
   uint32_t* scratch = start + nb2 + 1;                                // kWaves + 1
-  for (uint32_t i = threadIdx.x; i < nb2; i += kThreads) cnt[i] = 0;
+  uint32_t* wend = reinterpret_cast<uint32_t*>(wsb) +
+                   max((uint32_t)kThreads * 3, 2 * nb2 + 2 + kWaves); // 1
   const uint64_t* offc = off1 + (uint64_t)c * ntiles1;
 
   // gather: windows of kThreads first-level runs, binary search per key
@@ -552,10 +556,10 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
     }
     if (threadIdx.x == 0) {
       const uint64_t tn = tw + kThreads;
-      scratch[kWaves] = tn < ntiles1 ? (uint32_t)(offc[tn] - bo) : (uint32_t)(bucket_off[c + 1] - bo);
+      *wend = tn < ntiles1 ? (uint32_t)(offc[tn] - bo) : (uint32_t)(bucket_off[c + 1] - bo);
     }
     __syncthreads();
-    const uint32_t upto = min(n, scratch[kWaves] - p0);
+    const uint32_t upto = min(n, *wend - p0);
     // each thread's kT2/kThreads positions: all run searches, then all loads,
     // then the LDS stores, so the loads are in flight together
     constexpr int kPer = kT2 / kThreads;
@@ -585,6 +589,8 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
   }
 
   // sort by sub-bucket
+  for (uint32_t i = threadIdx.x; i < nb2; i += kThreads) cnt[i] = 0;
+  __syncthreads();
   uint64_t kv[kT2 / kThreads];
   uint32_t meta[kT2 / kThreads];
 #pragma unroll
@@ -1382,9 +1388,8 @@ size_t level1_lds(uint32_t a1) {
 }
 
 size_t level2_lds(uint32_t a2) {
-  const uint32_t nb = 1u << a2;
-  return (size_t)kT2 * 8 + (size_t)kThreads * 12 + (size_t)nb * 4 + (size_t)(nb + 1) * 4 +
-         (kWaves + 1) * 4;
+  const size_t nb = (size_t)1 << a2;
+  return (size_t)kT2 * 8 + 4 * std::max<size_t>((size_t)kThreads * 3, 2 * nb + 2 + kWaves) + 4;
 }
 
 hipError_t launch_level1(const uint64_t* packed, const uint64_t* flags, uint64_t nwords,
