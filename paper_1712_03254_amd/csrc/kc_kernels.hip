@@ -848,9 +848,12 @@ __device__ void overflow_add(const CountArgs& A, uint64_t x, uint32_t tag, uint6
 // Pass 1 (Prune), one workgroup per Bloom block: the block's two levels are
 // built in LDS from every occurrence of its partitions (every occurrence hits
 // each distinct bit of S(x) once; level 1 records a first hit of a bit, level
-// 2 a second one) and written out with their popcounts.
+// 2 a second one) and written out with their popcounts.  Eight waves per
+// SIMD (at most 64 VGPRs): with blocks of up to 2^18 bits two workgroups then
+// share a CU.
 template <int H>
-__global__ void __launch_bounds__(kThreads) k_bloom(const CountArgs A) {
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8)))
+k_bloom(const CountArgs A) {
   extern __shared__ uint32_t lds[];
   const HashCfg& hc = A.hc;
   const uint32_t blk = blockIdx.x;
