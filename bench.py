@@ -103,6 +103,31 @@ def cpu_baseline(w, genome, n_reads=300_000):
                       % (n_reads, WORKLOAD, r.stats["n_valid"], dt)}
 
 
+def atomic_summary(w, st: dict, stages: dict) -> dict:
+    """LDS atomic throughput of the Bloom and count kernels against the
+    microbenchmark peak (libkc_probe.so) under their access pattern: random
+    words of a block-sized array.  k_bloom issues h ORs with return per
+    occurrence (the second-level ORs for bits already set are not counted);
+    k_tally one add per passing occurrence and one CAS per inserted key."""
+    from paper_1712_03254_amd import probe
+    bloom_words_log2 = max(6, min(15, w.bloom_block_log2 - 5))
+    table_words_log2 = 12  # the count words of a ~3840-slot table
+    peak_or = probe.lds_atomic_peak(probe.KCP_OR_RTN, bloom_words_log2)
+    peak_add = probe.lds_atomic_peak(probe.KCP_ADD, table_words_log2)
+    out = {"probe": {"or_rtn_per_s": peak_or, "or_words_log2": bloom_words_log2,
+                     "add_per_s": peak_add, "add_words_log2": table_words_log2}}
+    n = st["n_valid"]
+    if "bloom" in stages:
+        ops = w.bloom_hashes * n
+        rate = ops / (stages["bloom"]["avg_ms"] * 1e-3)
+        out["k_bloom"] = {"ops": ops, "per_s": rate, "frac": round(rate / peak_or, 4)}
+    if "tally" in stages:
+        ops = st["n_pass"] + st["passed_distinct"]
+        rate = ops / (stages["tally"]["avg_ms"] * 1e-3)
+        out["k_tally"] = {"ops": ops, "per_s": rate, "frac": round(rate / peak_add, 4)}
+    return out
+
+
 def load_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
     None when it is missing or was taken on different kernel source."""
@@ -541,6 +566,8 @@ def main():
         out["autotune"] = tune
     if plain_same is not None:
         out["plain_same_workload"] = plain_same
+    if not batched:
+        out["atomics"] = atomic_summary(w, last, stages)
     if args.copy_probe:
         src = torch.empty(COPY_BYTES, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

@@ -10,6 +10,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkc.so")
 SOURCES = ["kc_kernels.hip", "kc_runtime.hip", "kc_server.hip"]
+# LDS atomic microbenchmark (measurement support, include/kc_probe.h)
+PROBE_LIB = os.path.join(HERE, "libkc_probe.so")
+PROBE_SOURCES = ["kc_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -20,10 +23,9 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compiles the HIP sources into libkc.so; always rebuilds."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp%d" % os.getpid()
+def _compile(sources, lib, verbose):
+    srcs = [os.path.join(CSRC, s) for s in sources]
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [HIPCC] + FLAGS + ["-o", tmp] + srcs
     res = subprocess.run(cmd, capture_output=True, text=True)
     out = "\n".join(l for l in (res.stdout + res.stderr).splitlines()
@@ -32,7 +34,14 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed:\n" + out)
     if verbose and out.strip():
         print(out, file=sys.stderr)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    """Compiles the HIP sources into libkc.so and the LDS atomic
+    microbenchmark into libkc_probe.so; always rebuilds."""
+    _compile(SOURCES, LIB, verbose)
+    _compile(PROBE_SOURCES, PROBE_LIB, verbose)
     return LIB
 
 

@@ -88,3 +88,20 @@ def test_null_context_calls_are_rejected():
     lib.kc_destroy(None)
     assert lib.kc_server_set_overlap(None, 1) == kc.KC_ERR_INVALID_ARG
     assert lib.kc_server_release(None, 1) == kc.KC_ERR_INVALID_ARG
+
+
+def test_probe_library_exports_and_checks_arguments():
+    from paper_1712_03254_amd import probe
+    text = open(os.path.join(ROOT, "include", "kc_probe.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"\b(kcp_[a-z_0-9]+)\s*\(", text)))
+    assert names == sorted(probe.EXPORTED)
+    lib = probe.load()
+    for n in names:
+        assert hasattr(lib, n), n
+    ms, chk = ctypes.c_float(), ctypes.c_uint64()
+    # argument checks run before any device call
+    assert lib.kcp_lds_atomics(7, 13, 1, 1, ctypes.byref(ms), ctypes.byref(chk)) == -1
+    assert lib.kcp_lds_atomics(0, 16, 1, 1, ctypes.byref(ms), ctypes.byref(chk)) == -1
+    assert lib.kcp_lds_atomics(0, 13, 0, 1, ctypes.byref(ms), ctypes.byref(chk)) == -1
+    assert lib.kcp_lds_atomics(0, 13, 1, 0, ctypes.byref(ms), ctypes.byref(chk)) == -1
