@@ -371,7 +371,7 @@ def main():
     ap.add_argument("--trace-summary", metavar="TRACE_DIR",
                     help="offline: turn a rocprofv3 --kernel-trace --stats run into a profiles/ file")
     ap.add_argument("--command", default="", help="command line recorded in the offline summaries")
-    ap.add_argument("--serve-workers", type=int, default=4,
+    ap.add_argument("--serve-workers", type=int, default=8,
                     help="served workload: concurrent jobs (server worker threads)")
     ap.add_argument("--serve-overlap", type=float, default=float(1 << 28),
                     help="served workload: admission cap on the bases of requests running at "
