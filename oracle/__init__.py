@@ -78,6 +78,11 @@ def _load():
         lib.or_sample_hits.argtypes = [P, U8P, U64P, ctypes.c_uint64, U64P, ctypes.c_uint64,
                                        U32P, ctypes.c_int]
         lib.or_sample_hits.restype = ctypes.c_int
+        U16PP = ctypes.POINTER(ctypes.POINTER(ctypes.c_uint16))
+        lib.or_stem_items.argtypes = [ctypes.c_uint32, ctypes.c_uint32, U64P, U32P, ctypes.c_uint64,
+                                      ctypes.POINTER(U64P), U16PP, U64P]
+        lib.or_stem_items.restype = ctypes.c_int
+        lib.or_free_ptr.argtypes = [ctypes.c_void_p]
         _lib = lib
     return _lib
 
@@ -165,6 +170,33 @@ def bloom_bits(params: Params, x: int) -> list[int]:
     out = np.zeros(8, dtype=np.uint64)
     n = _load().or_bloom_bits(ctypes.byref(p), x, _ptr(out, U64P))
     return [int(v) for v in out[:n]]
+
+
+def stem_items(k: int, n_counters: int, keys, counts):
+    """Stem items of a final table (kc_oracle.c, or_stem_items; paper Sec.
+    II-A stems, Sec. III-D items of 16 normal and 16 tumour counts): returns
+    (stems uint64[n] ascending, items uint16[n, 2, 16]) where items[i, t, 4a+b]
+    is counter t of the k-mer a + stem + b (stem in canonical orientation)."""
+    lib = _load()
+    keys = np.ascontiguousarray(keys, dtype=np.uint64).reshape(-1)
+    counts = np.ascontiguousarray(counts, dtype=np.uint32).reshape(-1)
+    if counts.size != keys.size * n_counters:
+        raise ValueError("counts must hold n_counters per key")
+    sp = U64P()
+    ip = ctypes.POINTER(ctypes.c_uint16)()
+    n = ctypes.c_uint64(0)
+    rc = lib.or_stem_items(k, n_counters, _ptr(keys, U64P), _ptr(counts, U32P), keys.size,
+                           ctypes.byref(sp), ctypes.byref(ip), ctypes.byref(n))
+    if rc != 0:
+        raise ValueError("or_stem_items failed (k must be 3..31)")
+    try:
+        m = int(n.value)
+        stems = np.ctypeslib.as_array(sp, shape=(max(m, 1),))[:m].copy()
+        items = np.ctypeslib.as_array(ip, shape=(max(m, 1) * 32,))[:m * 32].copy()
+    finally:
+        lib.or_free_ptr(ctypes.cast(sp, ctypes.c_void_p))
+        lib.or_free_ptr(ctypes.cast(ip, ctypes.c_void_p))
+    return stems, items.reshape(m, 2, 16)
 
 
 def sample_counts(params: Params, bases, offsets, sample_keys, tags=None, threads: int = 0):

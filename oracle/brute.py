@@ -10,6 +10,10 @@ C oracle implements, written on strings rather than integers:
   A=0 C=1 G=2 T=3, first base most significant);
 * count(x) = number of occurrences; the table keeps count >= min_count
   (Sec. II-B, Count unit);
+* stems (Sec. II-A): a k-mer without its first and last base; stem items
+  (Sec. III-D): per canonical stem (lexicographically smaller of the stem and
+  its reverse complement), the counts of the k-mers read as a + stem + b in
+  that orientation, at slot 4*rank(a) + rank(b), saturated to 65535;
 * Bloom levels (Sec. III, Prune unit) from explicit per-bit hit counters:
   hits(b) = sum over occurrences of x of [b in S(x)], B1 = hits >= 1,
   B2 = hits >= 2; a key passes iff every bit of S(x) is in B2; F = keys seen
@@ -108,3 +112,23 @@ def count(reads, k, m_log2, h, block_log2, seed, min_count=2, tags=None, n_count
                  sum_counts=sum(sum(v) for v in table.values()), fp_singletons=fp,
                  b1_pop=len(b1), b2_pop=len(b2))
     return table, b1, b2, stats
+
+
+def stem_items(table: dict, k: int, n_counters: int = 1) -> dict:
+    """table: canonical k-mer string -> counts tuple (the final table).
+    Returns canonical stem string -> [[16 counts] per counter]."""
+    rank = {c: i for i, c in enumerate("ACGT")}
+    out = {}
+    for kmer, cs in table.items():
+        assert len(kmer) == k
+        stem = kmer[1:-1]
+        rstem = revcomp(stem)
+        if stem <= rstem:
+            canon, a, b = stem, kmer[0], kmer[-1]
+        else:
+            r = revcomp(kmer)
+            canon, a, b = rstem, r[0], r[-1]
+        item = out.setdefault(canon, [[0] * 16 for _ in range(n_counters)])
+        for t in range(n_counters):
+            item[t][4 * rank[a] + rank[b]] = min(cs[t], 65535)
+    return out

@@ -32,6 +32,15 @@
  *     Kirsch and Mitzenmacher, "Less hashing, same performance", 2006); mix64
  *     is the SplitMix64 output function.
  *
+ *   - stem items (Sec. II-A: the stem of a k-mer is its middle k-2 bases;
+ *     Sec. III-D, Unify: counts grouped per stem into items of 16 normal and
+ *     16 tumour counts of 2 bytes): for each key x of the final table, S =
+ *     its middle k-2 bases; the canonical stem is min(S, rc(S)); if S is the
+ *     canonical one the k-mer is read as a S b with a, b its first and last
+ *     bases, otherwise as rc(x) = a rc(S) b (a = comp(last), b = comp(first));
+ *     its counts go to slot 4a + b of the stem's item, counter 0 in the
+ *     first 16 slots and counter 1 in the last 16, each saturated to 65535.
+ *
  * Algorithm: enumerate every valid window, push its canonical key, sort
  * (libc qsort), run-length encode into (x, counts), then derive B1/B2 from
  * the run-length list with the saturating update, then the screen, F and the
@@ -289,6 +298,91 @@ uint32_t or_bloom_bits(const or_params* p, uint64_t x, uint64_t* out) {
   or_salts(p, salt);
   return or_bloom_positions(p, salt, x, out);
 }
+
+/* ------------------------------------------------------------ stem items */
+typedef struct {
+  uint64_t stem;
+  uint32_t slot;
+  uint32_t c[2];
+} or_stem_rec;
+
+static int or_cmp_stem(const void* a, const void* b) {
+  const or_stem_rec* x = (const or_stem_rec*)a;
+  const or_stem_rec* y = (const or_stem_rec*)b;
+  if (x->stem != y->stem) return x->stem < y->stem ? -1 : 1;
+  return x->slot < y->slot ? -1 : (x->slot > y->slot);
+}
+
+/* Reverse complement of the n-base code v (first base most significant). */
+static uint64_t or_revcomp(uint64_t v, uint32_t n) {
+  uint64_t r = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    r = (r << 2) | (3u - (v & 3u));
+    v >>= 2;
+  }
+  return r;
+}
+
+/* Stem items of a final table (keys[n], counts[n * n_counters]), sorted by
+ * stem; *stems_out[*n_out] and *items_out[*n_out * 32] are malloc'd (the
+ * caller frees them with or_free_ptr).  Returns 0, or -1 for k < 3 or a
+ * failed allocation. */
+int or_stem_items(uint32_t k, uint32_t n_counters, const uint64_t* keys, const uint32_t* counts,
+                  uint64_t n, uint64_t** stems_out, uint16_t** items_out, uint64_t* n_out) {
+  *stems_out = NULL;
+  *items_out = NULL;
+  *n_out = 0;
+  if (k < 3 || k > 31 || n_counters < 1 || n_counters > 2) return -1;
+  const uint32_t m = k - 2;
+  const uint64_t mmask = (1ULL << (2 * m)) - 1;
+  or_stem_rec* rec = (or_stem_rec*)malloc((n ? n : 1) * sizeof(or_stem_rec));
+  if (!rec) return -1;
+  for (uint64_t i = 0; i < n; ++i) {
+    const uint64_t x = keys[i];
+    const uint32_t first = (uint32_t)(x >> (2 * (k - 1))) & 3u, last = (uint32_t)(x & 3u);
+    const uint64_t s = (x >> 2) & mmask;
+    const uint64_t rs = or_revcomp(s, m);
+    uint32_t a = first, b = last;
+    uint64_t stem = s;
+    if (rs < s) {
+      stem = rs;
+      a = 3u - last;
+      b = 3u - first;
+    }
+    rec[i].stem = stem;
+    rec[i].slot = 4u * a + b;
+    for (uint32_t t = 0; t < 2; ++t) {
+      const uint32_t c = t < n_counters ? counts[i * n_counters + t] : 0u;
+      rec[i].c[t] = c > 65535u ? 65535u : c;
+    }
+  }
+  qsort(rec, n, sizeof(or_stem_rec), or_cmp_stem);
+  uint64_t items = 0;
+  for (uint64_t i = 0; i < n; ++i)
+    if (i == 0 || rec[i].stem != rec[i - 1].stem) ++items;
+  uint64_t* stems = (uint64_t*)malloc((items ? items : 1) * 8);
+  uint16_t* it = (uint16_t*)calloc((items ? items : 1) * 32, 2);
+  if (!stems || !it) {
+    free(rec);
+    free(stems);
+    free(it);
+    return -1;
+  }
+  uint64_t j = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    if (i == 0 || rec[i].stem != rec[i - 1].stem) stems[j++] = rec[i].stem;
+    uint16_t* row = it + (j - 1) * 32;
+    row[rec[i].slot] = (uint16_t)rec[i].c[0];
+    row[16 + rec[i].slot] = (uint16_t)rec[i].c[1];
+  }
+  free(rec);
+  *stems_out = stems;
+  *items_out = it;
+  *n_out = items;
+  return 0;
+}
+
+void or_free_ptr(void* p) { free(p); }
 
 /* ------------------------------------------------------ sampled checking */
 /* For workloads too large to sort on the host: exact counts of a sorted list
