@@ -128,6 +128,29 @@ def atomic_summary(w, st: dict, stages: dict) -> dict:
     return out
 
 
+def stem_relayout(counter, reps: int = 3) -> dict:
+    """kc_export_stems on the finalized table (Unify's stem items), outside the
+    timed steps: HIP-event time of the call (three passes over the table
+    slots, a prefix sum over the stem table), items written, and the output
+    rate (72 B per item: 8 B stem, 32 two-byte counts)."""
+    import torch
+    counter.export_stems()
+    torch.cuda.synchronize()
+    before = counter.stats()["kernel_ms"]["stems"]
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        stems, _ = counter.export_stems()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    ms = (counter.stats()["kernel_ms"]["stems"] - before) / reps
+    n = int(stems.numel())
+    del stems
+    torch.cuda.empty_cache()
+    return {"items": n, "entries": counter.stats()["entries"], "ms": round(ms, 3),
+            "wall_ms": round(wall * 1e3, 3), "items_per_s": n / (ms * 1e-3),
+            "out_gbs": round(n * 72 / (ms * 1e-3) / 1e9, 1)}
+
+
 def load_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
     None when it is missing or was taken on different kernel source."""
@@ -568,6 +591,7 @@ def main():
         out["plain_same_workload"] = plain_same
     if not batched:
         out["atomics"] = atomic_summary(w, last, stages)
+        out["stem_relayout"] = stem_relayout(counter)
     if args.copy_probe:
         src = torch.empty(COPY_BYTES, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define KC_ABI_VERSION 3u
+#define KC_ABI_VERSION 4u
 
 typedef struct kc_ctx kc_ctx;
 
@@ -103,6 +103,7 @@ enum {
   KC_T_QUERY = 7,
   KC_T_SPILL = 8,  /* device -> pinned host copies of spilled partitions */
   KC_T_GRAPH = 9,  /* kc_count_batch: the whole batch as one graph launch */
+  KC_T_STEMS = 10, /* kc_export_stems: the stem layout of the final table */
   KC_T_COUNT_OF = 16
 };
 
@@ -198,6 +199,26 @@ kc_status kc_export(kc_ctx* ctx, uint64_t* keys_host, uint32_t* counts_host, uin
  * little-endian: bit b in word b >> 6 at position b & 63).  Either pointer
  * may be NULL. */
 kc_status kc_export_bloom(kc_ctx* ctx, uint64_t* b1_host, uint64_t* b2_host, uint64_t words);
+
+/* Unify's stem layout of the final table (Sec. II-A: the stem of a k-mer is
+ * its middle k-2 bases; Sec. III-D: counts grouped per stem, the 16 normal
+ * and 16 tumour k-mers of a stem in one item of 2-byte counts).  After
+ * kc_finalize; needs k >= 3.  Each k-mer of the table (what kc_export
+ * returns) is read in the orientation of its canonical stem S, the smaller
+ * code of its middle k-2 bases and their reverse complement: as a S b (a, b
+ * its first and last bases) when its own middle is S, else as its reverse
+ * complement (and as written when S is its own reverse complement).  Item i
+ * is stems_dev[i] (the (k-2)-base code of S) and counts_dev[32 i .. 32 i + 31]:
+ * entry 4a+b holds counter 0's count and 16+4a+b counter 1's, each saturated
+ * to 65535; entries of k-mers not in the table are 0.  Items are in no
+ * particular order.  *n_out receives the item count, at most stats.entries
+ * (so a capacity of stats.entries always suffices); with a smaller capacity
+ * the call fails with KC_ERR_INVALID_ARG after setting *n_out.  counts_dev
+ * must be 4-byte aligned.  Spilled tables are staged back to HBM.  Scratch:
+ * about 20 bytes of device memory per slot of a stem table of the next power
+ * of two above 2 x entries, allocated and freed inside.  Synchronises. */
+kc_status kc_export_stems(kc_ctx* ctx, uint64_t* stems_dev, uint16_t* counts_dev, uint64_t capacity,
+                          uint64_t* n_out, void* hip_stream);
 
 /*
  * Debug view of pass 1: every stored key occurrence (x | counter << 62) and the

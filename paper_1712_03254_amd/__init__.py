@@ -28,13 +28,15 @@ KC_ERR_BAD_STATE = -3
 KC_ERR_DEVICE = -4
 KC_ERR_OVER_BUDGET = -5
 
-STAGES = ["pack", "level1", "scan", "level2", "bloom", "tally", "unify", "query", "spill", "graph"]
+STAGES = ["pack", "level1", "scan", "level2", "bloom", "tally", "unify", "query", "spill", "graph",
+          "stems"]
 
 EXPORTED = ["kc_abi_version", "kc_status_str", "kc_create", "kc_insert_reads", "kc_finalize",
             "kc_query", "kc_spill", "kc_export", "kc_export_bloom", "kc_debug_keys",
             "kc_get_stats", "kc_reset", "kc_destroy", "kc_last_error", "kc_count_batch",
             "kc_autotune_batch", "kc_server_create", "kc_server_submit", "kc_server_wait",
-            "kc_server_release", "kc_server_usage", "kc_server_destroy", "kc_server_set_overlap"]
+            "kc_server_release", "kc_server_usage", "kc_server_destroy", "kc_server_set_overlap",
+            "kc_export_stems"]
 
 
 class KcError(RuntimeError):
@@ -129,6 +131,7 @@ def load():
         "kc_spill": ([V, I64, P(U64)], st),
         "kc_export": ([V, V, V, U64, P(U64)], st),
         "kc_export_bloom": ([V, V, V, U64], st),
+        "kc_export_stems": ([V, V, V, U64, P(U64), V], st),
         "kc_debug_keys": ([V, V, V, U64, P(U64)], st),
         "kc_get_stats": ([V, P(KcStats)], st),
         "kc_reset": ([V], st),
@@ -202,6 +205,13 @@ def kc_export(ctx, n_counters: int):
     counts = np.empty(max(e * n_counters, 1), dtype=np.uint32)
     _check(ctx, lib.kc_export(ctx, keys.ctypes.data, counts.ctypes.data, e, ctypes.byref(n)))
     return keys[:e], counts[:e * n_counters].reshape(e, n_counters)
+
+
+def kc_export_stems(ctx, stems_ptr: int, counts_ptr: int, capacity: int, stream: int = 0) -> int:
+    """Writes the stem items into device buffers; returns their number."""
+    n = ctypes.c_uint64(0)
+    _check(ctx, load().kc_export_stems(ctx, stems_ptr, counts_ptr, capacity, ctypes.byref(n), stream))
+    return int(n.value)
 
 
 def kc_export_bloom(ctx, words: int):
@@ -380,6 +390,17 @@ class KmerCounter:
     def export_bloom(self):
         words = max(1, (1 << self.cfg.bloom_bits_log2) // 64)
         return kc_export_bloom(self.ctx, words)
+
+    def export_stems(self, stream=None):
+        """Stem items of the final table (kc_export_stems), as device tensors:
+        stems int64[n] (codes of k-2 bases) and counts int16[n, 2, 16]
+        (counter, 4a+b), 16-bit counts read as unsigned."""
+        import torch
+        cap = max(1, self.stats()["entries"])
+        stems = torch.empty(cap, dtype=torch.int64, device="cuda")
+        counts = torch.empty((cap, 2, 16), dtype=torch.int16, device="cuda")
+        n = kc_export_stems(self.ctx, stems.data_ptr(), counts.data_ptr(), cap, _stream_ptr(stream))
+        return stems[:n], counts[:n]
 
     def debug_keys(self):
         return kc_debug_keys(self.ctx)

@@ -139,6 +139,13 @@ int tally_threads();
 hipError_t launch_ovf_emit(const CountArgs& a, uint64_t* pstats_ovf, uint32_t blocks,
                            hipStream_t s);
 hipError_t launch_reduce(const uint64_t* rows, uint64_t nrows, uint64_t* out, hipStream_t s);
+hipError_t launch_stems(bool claim, const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,
+                        const uint32_t* live, uint32_t cap, uint32_t nc, uint32_t k,
+                        uint64_t* skeys, uint32_t s_log2, const uint64_t* off, uint16_t* items,
+                        uint32_t* err, hipStream_t s);
+hipError_t launch_stem_flags(const uint64_t* skeys, uint64_t n, uint32_t* flags, hipStream_t s);
+hipError_t launch_stem_emit(const uint64_t* skeys, const uint64_t* off, uint64_t n,
+                            uint64_t* stems, hipStream_t s);
 hipError_t launch_query(const QueryArgs& a, const uint64_t* kmers, uint64_t n, uint32_t* out,
                         hipStream_t s);
 hipError_t launch_export(const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,

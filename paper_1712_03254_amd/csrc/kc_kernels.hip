@@ -1334,6 +1334,103 @@ __global__ void __launch_bounds__(256) k_scatter_rows(const uint32_t* __restrict
   for (uint32_t t = 0; t < nc; ++t) out[(uint64_t)rows[i] * nc + t] = vals[(uint64_t)i * nc + t];
 }
 
+// ------------------------------------------------------------ stem items
+
+// Canonical stem of the table k-mer x (k >= 3, first base most significant):
+// the middle k-2 bases S, or their reverse complement when that is smaller;
+// *slot = 4a + b for the k-mer read as a S' b in the stem's orientation (for
+// a palindromic stem, as x is written).
+__device__ __forceinline__ uint64_t stem_of(uint64_t x, uint32_t k, uint32_t* slot) {
+  const uint32_t m = k - 2;
+  const uint64_t s = (x >> 2) & ((1ull << (2 * m)) - 1);
+  // complement every base, reverse the 32 two-bit groups, keep the top m
+  uint64_t u = ~s;
+  u = ((u >> 2) & 0x3333333333333333ull) | ((u & 0x3333333333333333ull) << 2);
+  u = ((u >> 4) & 0x0F0F0F0F0F0F0F0Full) | ((u & 0x0F0F0F0F0F0F0F0Full) << 4);
+  u = __builtin_bswap64(u);
+  const uint64_t rs = u >> (64 - 2 * m);
+  const uint32_t first = (uint32_t)(x >> (2 * (k - 1))) & 3u, last = (uint32_t)x & 3u;
+  if (rs < s) {
+    *slot = 4u * (3u - last) + (3u - first);
+    return rs;
+  }
+  *slot = 4u * first + last;
+  return s;
+}
+
+constexpr uint64_t kStemSalt = 0x2545F4914F6CDD1Dull;  // stem-table hash salt
+
+// One pass over table slots [0, nslots) (live[i / cap] gates the slots of
+// resident tables; nullptr for the overflow table and staged spilled
+// tables).  CLAIM: each k-mer's canonical stem takes a slot of the stem table
+// (open addressing, linear probing, CAS).  Otherwise: each k-mer finds its
+// stem's slot h and stores its counts, saturated to 16 bits, at 4a+b
+// (counter 0) and 16+4a+b (counter 1) of item off[h].  A stem not found
+// within the table sets err.
+template <bool CLAIM>
+__global__ void __launch_bounds__(256) k_stems(const uint64_t* __restrict__ tkeys,
+                                               const uint32_t* __restrict__ tcounts,
+                                               uint64_t nslots, const uint32_t* __restrict__ live,
+                                               uint32_t cap, uint32_t nc, uint32_t k,
+                                               uint64_t* __restrict__ skeys, uint32_t s_log2,
+                                               const uint64_t* __restrict__ off,
+                                               uint16_t* __restrict__ items,
+                                               uint32_t* __restrict__ err) {
+  const uint64_t mask = (1ull << s_log2) - 1;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    if (live && !live[i / cap]) continue;
+    const uint64_t key = tkeys[i];
+    const uint32_t c0 = tcounts[i * nc], c1 = nc > 1 ? tcounts[i * nc + 1] : 0u;
+    if (key == kEmpty || (c0 | c1) == 0) continue;
+    uint32_t slot;
+    const uint64_t stem = stem_of(key, k, &slot);
+    uint64_t h = mix64(stem ^ kStemSalt) & mask;
+    bool found = false;
+    for (uint64_t probe = 0; probe <= mask; ++probe) {
+      uint64_t cur = __hip_atomic_load(&skeys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (CLAIM && cur == kEmpty) {
+        cur = atomicCAS(reinterpret_cast<unsigned long long*>(&skeys[h]),
+                        (unsigned long long)kEmpty, (unsigned long long)stem);
+        if (cur == kEmpty) cur = stem;
+      }
+      if (cur == stem) {
+        found = true;
+        break;
+      }
+      if (!CLAIM && cur == kEmpty) break;
+      h = (h + 1) & mask;
+    }
+    if (!found) {
+      atomicOr(err, 1u);
+      continue;
+    }
+    if (!CLAIM) {
+      uint16_t* row = items + off[h] * 32;
+      row[slot] = (uint16_t)min(c0, 65535u);
+      row[16 + slot] = (uint16_t)min(c1, 65535u);
+    }
+  }
+}
+
+// flags[i] = slot i of the stem table holds a stem
+__global__ void k_stem_flags(const uint64_t* __restrict__ skeys, uint64_t n,
+                             uint32_t* __restrict__ flags) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    flags[i] = skeys[i] != kEmpty;
+}
+
+// stems[off[i]] = the stem in slot i
+__global__ void k_stem_emit(const uint64_t* __restrict__ skeys, const uint64_t* __restrict__ off,
+                            uint64_t n, uint64_t* __restrict__ stems) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t v = skeys[i];
+    if (v != kEmpty) stems[off[i]] = v;
+  }
+}
+
 inline uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 }  // namespace
@@ -1512,6 +1609,31 @@ hipError_t launch_debug_part(const SegDesc& sd, uint64_t n, uint32_t* part, hipS
 // grid-stride launches: enough workgroups to fill the chip, at most one per 256 items
 static uint32_t stride_grid(uint64_t n) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(n, 256), 8192));
+}
+
+hipError_t launch_stems(bool claim, const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,
+                        const uint32_t* live, uint32_t cap, uint32_t nc, uint32_t k,
+                        uint64_t* skeys, uint32_t s_log2, const uint64_t* off, uint16_t* items,
+                        uint32_t* err, hipStream_t s) {
+  if (!nslots) return hipSuccess;
+  if (claim)
+    hipLaunchKernelGGL(k_stems<true>, dim3(stride_grid(nslots)), dim3(256), 0, s, tkeys, tcounts,
+                       nslots, live, cap, nc, k, skeys, s_log2, off, items, err);
+  else
+    hipLaunchKernelGGL(k_stems<false>, dim3(stride_grid(nslots)), dim3(256), 0, s, tkeys, tcounts,
+                       nslots, live, cap, nc, k, skeys, s_log2, off, items, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_stem_flags(const uint64_t* skeys, uint64_t n, uint32_t* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_stem_flags, dim3(stride_grid(n)), dim3(256), 0, s, skeys, n, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_stem_emit(const uint64_t* skeys, const uint64_t* off, uint64_t n,
+                            uint64_t* stems, hipStream_t s) {
+  hipLaunchKernelGGL(k_stem_emit, dim3(stride_grid(n)), dim3(256), 0, s, skeys, off, n, stems);
+  return hipGetLastError();
 }
 
 hipError_t launch_pack_batch(const ChunkDesc* cd, uint32_t nchunks, uint64_t nwords,

@@ -110,6 +110,16 @@ struct DevBuf {
   }
 };
 
+// Releases call-local device buffers when the call returns (DevBuf itself has
+// no destructor: contexts and segments hold theirs by value and copy them).
+struct ReleaseOnExit {
+  std::vector<DevBuf*> bufs;
+  ReleaseOnExit(std::initializer_list<DevBuf*> l) : bufs(l) {}
+  ~ReleaseOnExit() {
+    for (DevBuf* b : bufs) b->release();
+  }
+};
+
 struct Segment {
   DevBuf keys, bucket_off, tile_first, meta2;
   uint64_t n = 0;
@@ -1114,6 +1124,7 @@ kc_status kc_query(kc_ctx* c, const uint64_t* kmers, uint64_t n, uint32_t* count
       if (d >= 0) host_probe(c, c->spill_dir[d], x, &res[(size_t)i * nc]);
     }
     DevBuf vals;
+    ReleaseOnExit free_vals{&vals};
     KC_HIP(c, vals.ensure(res.size() * 4), "query results");
     KC_HIP(c, hipMemcpyAsync(vals.p, res.data(), res.size() * 4, hipMemcpyHostToDevice, s), "results");
     KC_HIP(c, launch_scatter_rows(c->qrows.as<uint32_t>(), vals.as<uint32_t>(), nhost, nc, counts, s),
@@ -1160,6 +1171,7 @@ kc_status kc_export(kc_ctx* c, uint64_t* keys, uint32_t* counts, uint64_t cap, u
   const uint32_t nc = c->cfg.n_counters;
   const uint64_t E = c->st.entries;
   DevBuf ok, oc, cur;
+  ReleaseOnExit free_bufs{&ok, &oc, &cur};
   KC_HIP(c, ok.ensure(E * 8), "export buffer");
   KC_HIP(c, oc.ensure(E * 4 * nc), "export buffer");
   KC_HIP(c, cur.ensure(8), "export cursor");
@@ -1201,6 +1213,91 @@ kc_status kc_export(kc_ctx* c, uint64_t* keys, uint32_t* counts, uint64_t cap, u
   return KC_OK;
 }
 
+// Stem items of the final table in three passes over its live slots (resident
+// tables, the overflow table, and spilled tables staged back in batches):
+// claim each k-mer's canonical stem in a device hash table, number the
+// claimed slots by a prefix sum (writing the stems out), then store every
+// k-mer's counts in its stem's item.
+kc_status kc_export_stems(kc_ctx* c, uint64_t* stems, uint16_t* items, uint64_t capacity,
+                          uint64_t* n_out, void* hip_stream) {
+  if (!c) return KC_ERR_INVALID_ARG;
+  if (c->state != FINALIZED) return fail(c, KC_ERR_BAD_STATE, "stem export before finalize");
+  if (!n_out) return fail(c, KC_ERR_INVALID_ARG, "n_out is NULL");
+  if (c->cfg.k < 3) return fail(c, KC_ERR_INVALID_ARG, "stems need k >= 3");
+  if (reinterpret_cast<uintptr_t>(items) & 3u)
+    return fail(c, KC_ERR_INVALID_ARG, "counts_dev must be 4-byte aligned");
+  KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  AllocStream alloc_on(s);
+  StageTimer tm(c, s, KC_T_STEMS);
+  const uint32_t nc = c->cfg.n_counters, k = c->cfg.k;
+  const uint64_t E = c->st.entries;
+  const uint32_t s_log2 = std::max<uint32_t>(10, ceil_log2(2 * E + 1));  // load <= 1/2
+  const uint64_t S = 1ull << s_log2;
+  DevBuf skeys, flags, off, parts, err, stage_k, stage_c;
+  ReleaseOnExit free_bufs{&skeys, &flags, &off, &parts, &err, &stage_k, &stage_c};
+  KC_HIP(c, skeys.ensure(S * 8), "stem table");
+  KC_HIP(c, flags.ensure(S * 4), "stem flags");
+  KC_HIP(c, off.ensure((S + 1) * 8), "stem offsets");
+  KC_HIP(c, parts.ensure(scan_parts(S) * 8), "scan buffer");
+  KC_HIP(c, err.ensure(4), "error flag");
+  KC_HIP(c, launch_fill64(skeys.as<uint64_t>(), S, kEmpty, s), "fill");
+  KC_HIP(c, launch_fill32(err.as<uint32_t>(), 1, 0, s), "fill");
+  // spilled tables come back to HBM in batches of up to kStage tables
+  const uint64_t cap = c->cap;
+  const uint64_t kStage = std::max<uint64_t>(1, std::min<uint64_t>(c->spill_used, 2048));
+  if (c->spill_used) {
+    KC_HIP(c, stage_k.ensure(kStage * cap * 8), "staging buffer");
+    KC_HIP(c, stage_c.ensure(kStage * cap * 4 * nc), "staging buffer");
+  }
+  auto pass = [&](bool claim) -> kc_status {
+    KC_HIP(c, launch_stems(claim, c->tkeys.as<uint64_t>(), c->tcounts.as<uint32_t>(),
+                           (uint64_t)c->pool_slots * cap, c->slot_live.as<uint32_t>(), c->cap, nc,
+                           k, skeys.as<uint64_t>(), s_log2, off.as<uint64_t>(), items,
+                           err.as<uint32_t>(), s),
+           "stem pass");
+    KC_HIP(c, launch_stems(claim, c->okeys.as<uint64_t>(), c->ocounts.as<uint32_t>(),
+                           1ull << c->ovf_log2, nullptr, 0, nc, k, skeys.as<uint64_t>(), s_log2,
+                           off.as<uint64_t>(), items, err.as<uint32_t>(), s),
+           "stem pass");
+    for (uint64_t t0 = 0; t0 < c->spill_used; t0 += kStage) {
+      const uint64_t nt = std::min<uint64_t>(kStage, c->spill_used - t0);
+      KC_HIP(c, hipMemcpyAsync(stage_k.p, c->spill_keys + t0 * cap, nt * cap * 8,
+                               hipMemcpyHostToDevice, s),
+             "stage copy");
+      KC_HIP(c, hipMemcpyAsync(stage_c.p, c->spill_counts + t0 * cap * nc, nt * cap * 4 * nc,
+                               hipMemcpyHostToDevice, s),
+             "stage copy");
+      KC_HIP(c, launch_stems(claim, stage_k.as<uint64_t>(), stage_c.as<uint32_t>(), nt * cap,
+                             nullptr, 0, nc, k, skeys.as<uint64_t>(), s_log2, off.as<uint64_t>(),
+                             items, err.as<uint32_t>(), s),
+             "stem pass");
+    }
+    return KC_OK;
+  };
+  kc_status r = pass(true);
+  if (r != KC_OK) return r;
+  KC_HIP(c, launch_stem_flags(skeys.as<uint64_t>(), S, flags.as<uint32_t>(), s), "stem flags");
+  KC_HIP(c, launch_scan(flags.as<uint32_t>(), S, off.as<uint64_t>(), parts.as<uint64_t>(), s),
+         "stem scan");
+  uint64_t n = 0;
+  if ((r = sync_read(c, s, off.as<uint64_t>() + S, 8, &n)) != KC_OK) return r;
+  *n_out = n;
+  if (n > E) return fail(c, KC_ERR_DEVICE, "more stems than table entries");
+  if (n > capacity) return fail(c, KC_ERR_INVALID_ARG, "capacity smaller than the stem count");
+  if (n && (!stems || !items)) return fail(c, KC_ERR_INVALID_ARG, "stems_dev or counts_dev is NULL");
+  if (n) {
+    KC_HIP(c, launch_stem_emit(skeys.as<uint64_t>(), off.as<uint64_t>(), S, stems, s), "stem emit");
+    KC_HIP(c, launch_fill32(reinterpret_cast<uint32_t*>(items), n * 16, 0, s), "fill");
+    if ((r = pass(false)) != KC_OK) return r;
+  }
+  uint32_t e = 0;
+  if ((r = sync_read(c, s, err.p, 4, &e)) != KC_OK) return r;
+  tm.stop();
+  if (e) return fail(c, KC_ERR_DEVICE, "stem table overflow");
+  return KC_OK;
+}
+
 kc_status kc_export_bloom(kc_ctx* c, uint64_t* b1, uint64_t* b2, uint64_t words) {
   if (!c) return KC_ERR_INVALID_ARG;
   if (c->state != FINALIZED) return fail(c, KC_ERR_BAD_STATE, "Bloom export before finalize");
@@ -1225,6 +1322,7 @@ kc_status kc_debug_keys(kc_ctx* c, uint64_t* keys, uint32_t* part, uint64_t cap,
     KC_HIP(c, hipMemcpy(keys + at, g.keys.p, g.n * 8, hipMemcpyDeviceToHost), "key copy");
     if (part) {
       DevBuf pb;
+      ReleaseOnExit free_pb{&pb};
       KC_HIP(c, pb.ensure(g.n * 4), "partition buffer");
       SegDesc sd{g.keys.as<uint64_t>(), g.bucket_off.as<uint64_t>(), g.tile_first.as<uint32_t>(),
                  g.meta2.as<uint32_t>(), c->a1, c->a2};
