@@ -83,6 +83,10 @@ def _load():
                                       ctypes.POINTER(U64P), U16PP, U64P]
         lib.or_stem_items.restype = ctypes.c_int
         lib.or_free_ptr.argtypes = [ctypes.c_void_p]
+        lib.or_filter_reads.argtypes = [ctypes.c_uint32, ctypes.c_uint32, U64P, U32P, ctypes.c_uint64,
+                                        U8P, U64P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                        U32P]
+        lib.or_filter_reads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -197,6 +201,26 @@ def stem_items(k: int, n_counters: int, keys, counts):
         lib.or_free_ptr(ctypes.cast(sp, ctypes.c_void_p))
         lib.or_free_ptr(ctypes.cast(ip, ctypes.c_void_p))
     return stems, items.reshape(m, 2, 16)
+
+
+def filter_reads(k: int, n_counters: int, keys, counts, bases, offsets, tumour_min: int,
+                 normal_max: int) -> np.ndarray:
+    """Filter-unit lookup (kc_oracle.c, or_filter_reads; paper Sec. II-B):
+    per read, the number of windows whose k-mer has tumour count >=
+    tumour_min and normal count <= normal_max in the final table (keys
+    ascending, counts [n, n_counters])."""
+    lib = _load()
+    keys = np.ascontiguousarray(keys, dtype=np.uint64).reshape(-1)
+    counts = np.ascontiguousarray(counts, dtype=np.uint32).reshape(-1)
+    bases, offsets, _ = _arrays(bases, offsets, None)
+    n_reads = offsets.size - 1
+    out = np.zeros(max(n_reads, 1), np.uint32)
+    rc = lib.or_filter_reads(k, n_counters, _ptr(keys, U64P), _ptr(counts, U32P), keys.size,
+                             _ptr(bases, U8P), _ptr(offsets, U64P), n_reads, tumour_min, normal_max,
+                             _ptr(out, U32P))
+    if rc != 0:
+        raise ValueError("or_filter_reads failed")
+    return out[:n_reads]
 
 
 def sample_counts(params: Params, bases, offsets, sample_keys, tags=None, threads: int = 0):

@@ -14,6 +14,9 @@ C oracle implements, written on strings rather than integers:
   (Sec. III-D): per canonical stem (lexicographically smaller of the stem and
   its reverse complement), the counts of the k-mers read as a + stem + b in
   that orientation, at slot 4*rank(a) + rank(b), saturated to 65535;
+* Filter-unit lookup (Sec. II-B): per read, the windows whose canonical
+  k-mer has tumour count >= tumour_min and normal count <= normal_max in the
+  final table (absent: 0 and 0; one counter: normal 0, tumour = the count);
 * Bloom levels (Sec. III, Prune unit) from explicit per-bit hit counters:
   hits(b) = sum over occurrences of x of [b in S(x)], B1 = hits >= 1,
   B2 = hits >= 2; a key passes iff every bit of S(x) is in B2; F = keys seen
@@ -131,4 +134,18 @@ def stem_items(table: dict, k: int, n_counters: int = 1) -> dict:
         item = out.setdefault(canon, [[0] * 16 for _ in range(n_counters)])
         for t in range(n_counters):
             item[t][4 * rank[a] + rank[b]] = min(cs[t], 65535)
+    return out
+
+
+def filter_reads(table: dict, reads, k: int, tumour_min: int, normal_max: int,
+                 n_counters: int = 2) -> list:
+    """table: canonical k-mer code -> counts tuple (the final table)."""
+    out = []
+    for read in reads:
+        sel = 0
+        for w in windows(read, k):
+            cs = table.get(encode(canonical(w)), (0,) * n_counters)
+            normal, tumour = (cs[0], cs[1]) if n_counters == 2 else (0, cs[0])
+            sel += tumour >= tumour_min and normal <= normal_max
+        out.append(sel)
     return out

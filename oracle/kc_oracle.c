@@ -41,6 +41,15 @@
  *     its counts go to slot 4a + b of the stem's item, counter 0 in the
  *     first 16 slots and counter 1 in the last 16, each saturated to 65535.
  *
+ *   - Filter-unit lookup (Sec. II-B, Filter unit: the input sequences are
+ *     read again and their k-mers looked up in the frequency table to select
+ *     k-mers with imbalanced frequencies; the imbalance test itself is not
+ *     given): with (normal, tumour) = the final table's counters 0 and 1 of
+ *     the window's canonical k-mer ((0, 0) for a k-mer not in the table; a
+ *     one-counter table reads as normal 0, tumour = its count), a window is
+ *     selected iff tumour >= tumour_min and normal <= normal_max; the result
+ *     per read is its number of selected windows.
+ *
  * Algorithm: enumerate every valid window, push its canonical key, sort
  * (libc qsort), run-length encode into (x, counts), then derive B1/B2 from
  * the run-length list with the saturating update, then the screen, F and the
@@ -383,6 +392,40 @@ int or_stem_items(uint32_t k, uint32_t n_counters, const uint64_t* keys, const u
 }
 
 void or_free_ptr(void* p) { free(p); }
+
+/* -------------------------------------------------------- filter lookup */
+static int64_t or_find(const uint64_t* a, uint64_t n, uint64_t v);
+/* out[r] = selected windows of read r (see the header); keys[n_keys] is the
+ * final table in ascending order with counts[n_keys * n_counters].  Windows
+ * are those the count enumerates (valid bases only, inside one read).
+ * Returns 0, or -1 for bad arguments. */
+int or_filter_reads(uint32_t k, uint32_t n_counters, const uint64_t* keys, const uint32_t* counts,
+                    uint64_t n_keys, const uint8_t* bases, const uint64_t* offsets, uint64_t n_reads,
+                    uint32_t tumour_min, uint32_t normal_max, uint32_t* out) {
+  if (k < 1 || k > 31 || n_counters < 1 || n_counters > 2) return -1;
+  for (uint64_t r = 0; r < n_reads; ++r) {
+    uint32_t sel = 0;
+    const uint64_t lo = offsets[r], hi = offsets[r + 1];
+    for (uint64_t j = lo; j + k <= hi; ++j) {
+      int ok = 0;
+      const uint64_t x = or_canonical(bases + j, k, &ok);
+      if (!ok) continue;
+      uint32_t normal = 0, tumour = 0;
+      const int64_t at = or_find(keys, n_keys, x);
+      if (at >= 0) {
+        if (n_counters == 2) {
+          normal = counts[(uint64_t)at * 2];
+          tumour = counts[(uint64_t)at * 2 + 1];
+        } else {
+          tumour = counts[at];
+        }
+      }
+      if (tumour >= tumour_min && normal <= normal_max) ++sel;
+    }
+    out[r] = sel;
+  }
+  return 0;
+}
 
 /* ------------------------------------------------------ sampled checking */
 /* For workloads too large to sort on the host: exact counts of a sorted list
