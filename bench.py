@@ -151,6 +151,25 @@ def stem_relayout(counter, reps: int = 3) -> dict:
             "out_gbs": round(n * 72 / (ms * 1e-3) / 1e9, 1)}
 
 
+def filter_lookup(counter, chunks, n_valid: int, reps: int = 3) -> dict:
+    """kc_filter_reads on the finalized table, re-reading the same resident
+    reads (the Filter unit's second pass over the input), outside the timed
+    steps: HIP-event time, window lookups per second and the selected
+    windows (threshold: count >= 2, no normal counter)."""
+    import torch
+    b, o = chunks[0]
+    counter.filter_reads(b, o, 2, 0)
+    torch.cuda.synchronize()
+    before = counter.stats()["kernel_ms"]["filter"]
+    for _ in range(reps):
+        sel = counter.filter_reads(b, o, 2, 0)
+    torch.cuda.synchronize()
+    ms = (counter.stats()["kernel_ms"]["filter"] - before) / reps
+    picked = int(sel.to(torch.int64).sum().item())
+    return {"windows": n_valid, "selected": picked, "ms": round(ms, 3),
+            "lookups_per_s": n_valid / (ms * 1e-3)}
+
+
 def load_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
     None when it is missing or was taken on different kernel source."""
@@ -592,6 +611,7 @@ def main():
     if not batched:
         out["atomics"] = atomic_summary(w, last, stages)
         out["stem_relayout"] = stem_relayout(counter)
+        out["filter_lookup"] = filter_lookup(counter, chunks, n_valid)
     if args.copy_probe:
         src = torch.empty(COPY_BYTES, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define KC_ABI_VERSION 4u
+#define KC_ABI_VERSION 5u
 
 typedef struct kc_ctx kc_ctx;
 
@@ -104,6 +104,7 @@ enum {
   KC_T_SPILL = 8,  /* device -> pinned host copies of spilled partitions */
   KC_T_GRAPH = 9,  /* kc_count_batch: the whole batch as one graph launch */
   KC_T_STEMS = 10, /* kc_export_stems: the stem layout of the final table */
+  KC_T_FILTER = 11, /* kc_filter_reads: lookups of every window of a read batch */
   KC_T_COUNT_OF = 16
 };
 
@@ -219,6 +220,23 @@ kc_status kc_export_bloom(kc_ctx* ctx, uint64_t* b1_host, uint64_t* b2_host, uin
  * of two above 2 x entries, allocated and freed inside.  Synchronises. */
 kc_status kc_export_stems(kc_ctx* ctx, uint64_t* stems_dev, uint16_t* counts_dev, uint64_t capacity,
                           uint64_t* n_out, void* hip_stream);
+
+/* Filter-unit lookup (Sec. II-B: the Filter unit reads the input sequences
+ * again and looks their k-mers up in the frequency table to select k-mers
+ * with imbalanced frequencies; the imbalance test is a parameter here).
+ * After kc_finalize.  The reads come in the layout of kc_insert_reads
+ * (bases_dev, offsets_dev[n_reads + 1], at most 2^32 - 1 bases).  Every
+ * window the count enumerates is looked up: with (normal, tumour) = its
+ * k-mer's counters 0 and 1 in the final table (0 and 0 when the k-mer is not
+ * in it; for a one-counter table normal is 0 and tumour is the count), the
+ * window is selected when tumour >= tumour_min and normal <= normal_max.
+ * out_dev[r] (uint32, device) receives read r's number of selected windows.
+ * Needs every partition table in HBM: after a spill it returns
+ * KC_ERR_BAD_STATE (kc_query answers such tables from the host).  Scratch of
+ * 2.5 bits per base, allocated and freed inside.  Synchronises. */
+kc_status kc_filter_reads(kc_ctx* ctx, const uint8_t* bases_dev, const uint64_t* offsets_dev,
+                          uint64_t n_reads, uint64_t total_bases, uint32_t tumour_min,
+                          uint32_t normal_max, uint32_t* out_dev, void* hip_stream);
 
 /*
  * Debug view of pass 1: every stored key occurrence (x | counter << 62) and the

@@ -29,14 +29,14 @@ KC_ERR_DEVICE = -4
 KC_ERR_OVER_BUDGET = -5
 
 STAGES = ["pack", "level1", "scan", "level2", "bloom", "tally", "unify", "query", "spill", "graph",
-          "stems"]
+          "stems", "filter"]
 
 EXPORTED = ["kc_abi_version", "kc_status_str", "kc_create", "kc_insert_reads", "kc_finalize",
             "kc_query", "kc_spill", "kc_export", "kc_export_bloom", "kc_debug_keys",
             "kc_get_stats", "kc_reset", "kc_destroy", "kc_last_error", "kc_count_batch",
             "kc_autotune_batch", "kc_server_create", "kc_server_submit", "kc_server_wait",
             "kc_server_release", "kc_server_usage", "kc_server_destroy", "kc_server_set_overlap",
-            "kc_export_stems"]
+            "kc_export_stems", "kc_filter_reads"]
 
 
 class KcError(RuntimeError):
@@ -132,6 +132,7 @@ def load():
         "kc_export": ([V, V, V, U64, P(U64)], st),
         "kc_export_bloom": ([V, V, V, U64], st),
         "kc_export_stems": ([V, V, V, U64, P(U64), V], st),
+        "kc_filter_reads": ([V, V, V, U64, U64, U32, U32, V, V], st),
         "kc_debug_keys": ([V, V, V, U64, P(U64)], st),
         "kc_get_stats": ([V, P(KcStats)], st),
         "kc_reset": ([V], st),
@@ -390,6 +391,19 @@ class KmerCounter:
     def export_bloom(self):
         words = max(1, (1 << self.cfg.bloom_bits_log2) // 64)
         return kc_export_bloom(self.ctx, words)
+
+    def filter_reads(self, bases, offsets, tumour_min: int, normal_max: int, stream=None):
+        """Filter-unit lookup (kc_filter_reads): per read of the batch, its
+        windows whose k-mer has tumour count >= tumour_min and normal count
+        <= normal_max.  bases uint8 / offsets int64 device tensors; returns an
+        int32 device tensor (counts, read as unsigned)."""
+        import torch
+        n = offsets.numel() - 1
+        out = torch.empty(max(n, 1), dtype=torch.int32, device=offsets.device)
+        _check(self.ctx, load().kc_filter_reads(self.ctx, bases.data_ptr(), offsets.data_ptr(), n,
+                                                 bases.numel(), tumour_min, normal_max,
+                                                 out.data_ptr(), _stream_ptr(stream)))
+        return out[:n]
 
     def export_stems(self, stream=None):
         """Stem items of the final table (kc_export_stems), as device tensors:

@@ -146,6 +146,9 @@ hipError_t launch_stems(bool claim, const uint64_t* tkeys, const uint32_t* tcoun
 hipError_t launch_stem_flags(const uint64_t* skeys, uint64_t n, uint32_t* flags, hipStream_t s);
 hipError_t launch_stem_emit(const uint64_t* skeys, const uint64_t* off, uint64_t n,
                             uint64_t* stems, hipStream_t s);
+hipError_t launch_filter(const QueryArgs& a, const uint64_t* packed, const uint64_t* flags,
+                         uint64_t nwords, const uint64_t* offsets, uint64_t n_reads, uint64_t total,
+                         uint32_t tmin, uint32_t nmax, uint32_t* hit, uint32_t* out, hipStream_t s);
 hipError_t launch_query(const QueryArgs& a, const uint64_t* kmers, uint64_t n, uint32_t* out,
                         hipStream_t s);
 hipError_t launch_export(const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,

@@ -1216,6 +1216,33 @@ __device__ __forceinline__ bool probe_table(const uint64_t* keys, uint64_t base,
   return false;
 }
 
+// Counts of the canonical key x in the final tables: its partition's table in
+// HBM, else the overflow table (a key lives in one of the two, never both).
+// Returns 1 when found, 0 when absent, -1 when its partition's table is not
+// in HBM (spilled) and the key is not in the overflow table: then it is
+// unknown here.
+__device__ __forceinline__ int table_counts(const QueryArgs& A, uint64_t x, uint32_t* c0,
+                                            uint32_t* c1) {
+  const uint32_t nc = A.hc.nc;
+  const uint64_t u = top_bits(mix64(x ^ A.hc.salt[0]), A.hc.p_log2);
+  const uint64_t th = (x ^ A.hc.salt[0]) * kTableMul;
+  const uint32_t slot = A.slot_of[u];
+  uint64_t at;
+  if (slot != kNoSlot &&
+      probe_table(A.tkeys, (uint64_t)slot * A.cap, A.cap, home_slot(th, A.cap), x, &at)) {
+    *c0 = A.tcounts[at * nc];
+    if (nc > 1) *c1 = A.tcounts[at * nc + 1];
+    return 1;
+  }
+  if (*A.ovf_used &&
+      probe_table(A.okeys, 0, 1ull << A.ovf_log2, mix64(th) >> (64 - A.ovf_log2), x, &at)) {
+    *c0 = A.ocounts[at * nc];
+    if (nc > 1) *c1 = A.ocounts[at * nc + 1];
+    return 1;
+  }
+  return slot == kNoSlot ? -1 : 0;
+}
+
 __global__ void __launch_bounds__(256) k_query(const QueryArgs A, const uint64_t* __restrict__ kmers,
                                                uint64_t n, uint32_t* __restrict__ out) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1229,27 +1256,68 @@ __global__ void __launch_bounds__(256) k_query(const QueryArgs A, const uint64_t
   } else {
     const uint64_t r = rc_word(q) >> (64 - 2 * hc.k);
     const uint64_t x = q < r ? q : r;
-    const uint64_t u = top_bits(mix64(x ^ hc.salt[0]), hc.p_log2);
-    const uint64_t th = (x ^ hc.salt[0]) * kTableMul;
-    const uint32_t slot = A.slot_of[u];
-    uint64_t at;
-    // A key lives in its partition table or in the overflow table, never both.
-    if (slot != kNoSlot &&
-        probe_table(A.tkeys, (uint64_t)slot * A.cap, A.cap, home_slot(th, A.cap), x, &at)) {
-      c0 = A.tcounts[at * nc];
-      if (nc > 1) c1 = A.tcounts[at * nc + 1];
-    } else if (*A.ovf_used && probe_table(A.okeys, 0, 1ull << A.ovf_log2,
-                                          mix64(th) >> (64 - A.ovf_log2), x, &at)) {
-      c0 = A.ocounts[at * nc];
-      if (nc > 1) c1 = A.ocounts[at * nc + 1];
-    } else if (slot == kNoSlot) {
-      const uint32_t r = atomicAdd(A.host_count, 1u);  // answered from the host copy
-      A.host_rows[r] = (uint32_t)i;
-      A.host_keys[r] = x;
+    if (table_counts(A, x, &c0, &c1) < 0) {
+      const uint32_t h = atomicAdd(A.host_count, 1u);  // answered from the host copy
+      A.host_rows[h] = (uint32_t)i;
+      A.host_keys[h] = x;
     }
   }
   out[i * nc] = c0;
   if (nc > 1) out[i * nc + 1] = c1;
+}
+
+// Filter-unit lookup, first pass: bit j of hit[w] marks the window ending at
+// base j of packed word w when its canonical k-mer is selected: tumour count
+// >= tmin and normal count <= nmax (counters 1 and 0 of a two-counter table;
+// normal 0 and tumour = the count for one counter; 0 and 0 when absent).
+// Four consecutive threads share a word, eight windows each; every table is
+// in HBM (the caller checks).
+__global__ void __launch_bounds__(256) k_filter_windows(const QueryArgs A,
+                                                        const uint64_t* __restrict__ packed,
+                                                        const uint64_t* __restrict__ flags,
+                                                        uint64_t nwords, uint32_t tmin,
+                                                        uint32_t nmax, uint32_t* __restrict__ hit) {
+  constexpr int kPP = 8, kTPW = 4;
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t w = t / kTPW;
+  uint32_t bits = 0;
+  if (w < nwords) {
+    const WordCtx c = load_word(packed, flags, w);
+    const int j0 = (int)(t % kTPW) * kPP;
+    for (int jj = 0; jj < kPP; ++jj) {
+      uint64_t x;
+      if (!window_key(c, A.hc.k, j0 + jj, &x)) continue;
+      uint32_t c0 = 0, c1 = 0;
+      table_counts(A, x & kKeyMask, &c0, &c1);
+      const uint32_t tumour = A.hc.nc > 1 ? c1 : c0, normal = A.hc.nc > 1 ? c0 : 0u;
+      if (tumour >= tmin && normal <= nmax) bits |= 1u << (j0 + jj);
+    }
+  }
+  bits |= __shfl_xor(bits, 1, 64);
+  bits |= __shfl_xor(bits, 2, 64);
+  if (w < nwords && t % kTPW == 0) hit[w] = bits;
+}
+
+// Filter-unit lookup, second pass: out[r] = set bits of hit over read r's
+// positions [offsets[r], offsets[r+1]) (a window belongs to the read its
+// last base is in).  The range is clamped to [0, total): offsets are checked
+// on the host only after this pass has run.
+__global__ void __launch_bounds__(256) k_filter_reads(const uint64_t* __restrict__ offsets,
+                                                      uint64_t n_reads, uint64_t total,
+                                                      const uint32_t* __restrict__ hit,
+                                                      uint32_t* __restrict__ out) {
+  const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_reads) return;
+  const uint64_t hi = min(offsets[r + 1], total), lo = min(offsets[r], hi);
+  uint32_t n = 0;
+  for (uint64_t p = lo; p < hi;) {
+    const uint32_t b = (uint32_t)(p & 31);
+    const uint64_t take = min((uint64_t)(32 - b), hi - p);
+    const uint32_t m = (take == 32 ? 0xFFFFFFFFu : ((1u << take) - 1u)) << b;
+    n += __popc(hit[p >> 5] & m);
+    p += take;
+  }
+  out[r] = n;
 }
 
 // Entries with a nonzero count, wave-aggregated append (no particular order).
@@ -1633,6 +1701,18 @@ hipError_t launch_stem_flags(const uint64_t* skeys, uint64_t n, uint32_t* flags,
 hipError_t launch_stem_emit(const uint64_t* skeys, const uint64_t* off, uint64_t n,
                             uint64_t* stems, hipStream_t s) {
   hipLaunchKernelGGL(k_stem_emit, dim3(stride_grid(n)), dim3(256), 0, s, skeys, off, n, stems);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter(const QueryArgs& a, const uint64_t* packed, const uint64_t* flags,
+                         uint64_t nwords, const uint64_t* offsets, uint64_t n_reads, uint64_t total,
+                         uint32_t tmin, uint32_t nmax, uint32_t* hit, uint32_t* out, hipStream_t s) {
+  if (nwords)
+    hipLaunchKernelGGL(k_filter_windows, dim3(div_up(nwords * 4, 256)), dim3(256), 0, s, a, packed,
+                       flags, nwords, tmin, nmax, hit);
+  if (n_reads)
+    hipLaunchKernelGGL(k_filter_reads, dim3(div_up(n_reads, 256)), dim3(256), 0, s, offsets,
+                       n_reads, total, hit, out);
   return hipGetLastError();
 }
 

@@ -1135,6 +1135,62 @@ kc_status kc_query(kc_ctx* c, const uint64_t* kmers, uint64_t n, uint32_t* count
   return KC_OK;
 }
 
+// Filter-unit lookup: the reads are packed and their read starts marked as
+// for an insert, then every window is looked up in the final tables (bitmap
+// of selected windows) and each read's selected windows are counted.
+kc_status kc_filter_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offsets,
+                          uint64_t n_reads, uint64_t total_bases, uint32_t tumour_min,
+                          uint32_t normal_max, uint32_t* out, void* hip_stream) {
+  if (!c) return KC_ERR_INVALID_ARG;
+  if (c->state != FINALIZED) return fail(c, KC_ERR_BAD_STATE, "filter before finalize");
+  if (!c->spill_dir.empty())
+    return fail(c, KC_ERR_BAD_STATE, "filter needs every partition table in HBM (tables were spilled)");
+  if (n_reads == 0) return KC_OK;
+  if (!offsets || !out || (total_bases && !bases))
+    return fail(c, KC_ERR_INVALID_ARG, "NULL read or output buffer");
+  if (total_bases > 0xFFFFFFFFull) return fail(c, KC_ERR_INVALID_ARG, "more than 2^32 - 1 bases in one call");
+  hipStream_t s = as_stream(hip_stream);
+  kc::AllocStream alloc_on(s);
+  KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
+  const uint64_t nwords = (total_bases + 31) / 32;
+  DevBuf packed, flags, hit;
+  ReleaseOnExit free_bufs{&packed, &flags, &hit};
+  KC_HIP(c, packed.ensure(nwords * 8), "packed buffer");
+  KC_HIP(c, flags.ensure(nwords * 8), "flag buffer");
+  KC_HIP(c, hit.ensure(nwords * 4), "window bitmap");
+  KC_HIP(c, launch_fill32(c->derr.as<uint32_t>(), 1, 0, s), "fill");
+  QueryArgs a{};
+  a.hc = c->hc;
+  a.cap = c->cap;
+  a.tkeys = c->tkeys.as<uint64_t>();
+  a.tcounts = c->tcounts.as<uint32_t>();
+  a.slot_of = c->slot_of.as<uint32_t>();
+  a.okeys = c->okeys.as<uint64_t>();
+  a.ocounts = c->ocounts.as<uint32_t>();
+  a.ovf_used = c->ovf_used.as<uint32_t>();
+  a.ovf_log2 = c->ovf_log2;
+  a.err = c->derr.as<uint32_t>();
+  {
+    StageTimer t(c, s, KC_T_FILTER);
+    KC_HIP(c, launch_pack(bases, total_bases, nwords, packed.as<uint64_t>(), flags.as<uint64_t>(), s),
+           "pack");
+    KC_HIP(c, launch_rstart(offsets, n_reads, total_bases, flags.as<uint64_t>(), c->derr.as<uint32_t>(),
+                            s),
+           "read starts");
+    KC_HIP(c, launch_filter(a, packed.as<uint64_t>(), flags.as<uint64_t>(), nwords, offsets, n_reads,
+                            total_bases, tumour_min, normal_max, hit.as<uint32_t>(), out, s),
+           "filter");
+    t.stop();
+  }
+  uint32_t errf = 0;
+  kc_status r = sync_read(c, s, c->derr.p, 4, &errf);
+  if (r != KC_OK) return r;
+  if (errf & ERR_OFFSETS)
+    return fail(c, KC_ERR_INVALID_ARG,
+                "offsets must start at 0, be non-decreasing and end at total_bases");
+  return KC_OK;
+}
+
 kc_status kc_spill(kc_ctx* c, int64_t partition, uint64_t* bytes_out) {
   if (!c) return KC_ERR_INVALID_ARG;
   if (bytes_out) *bytes_out = 0;

@@ -48,6 +48,19 @@ def test_plain_100mbp_sampled_parity():
         sample = np.unique(np.concatenate([from_table, np.array(wins, np.uint64), rand]))
         q = torch.from_numpy(sample.view(np.int64)).cuda()
         got = c.query(q).cpu().numpy().astype(np.uint32)[:, 0]
+        # Filter lookup over all windows: with count >= min_count selected, the
+        # selected windows are exactly the occurrences of table k-mers
+        sel = c.filter_reads(db, do, cfg.min_count, 0).to(torch.int64)
+        assert int(sel.sum().item()) == st["sum_counts"]
+        # ... and with no threshold every window is selected
+        every = c.filter_reads(db, do, 0, 0xFFFFFFFF).to(torch.int64)
+        assert int(every.sum().item()) == st["n_valid"]
+        # stem items hold every table k-mer once (counts stay below 2^16 here)
+        stems, items = c.export_stems()
+        it = items.to(torch.int32) & 0xFFFF
+        assert int((it > 0).sum().item()) == st["entries"]
+        assert int(it.sum().item()) == st["sum_counts"]
+        del stems, items, it
     note("sample keys: %d; oracle scan over all windows" % sample.size)
     p = oracle_params(cfg)
     ks, cs, nv = oracle.sample_counts(p, b, o, sample, threads=16)
