@@ -418,6 +418,8 @@ def main():
     ap.add_argument("--serve-overlap", type=float, default=float(1 << 28),
                     help="served workload: admission cap on the bases of requests running at "
                          "once (0: none)")
+    ap.add_argument("--checkpoint", default="",
+                    help="plain workloads: also time kc_checkpoint to this path and kc_restore from it")
     ap.add_argument("--loads", type=float, nargs="*", default=[0.3, 0.5, 0.7, 0.9],
                     help="served workload: offered loads as fractions of the plain capacity")
     args = ap.parse_args()
@@ -612,6 +614,22 @@ def main():
         out["atomics"] = atomic_summary(w, last, stages)
         out["stem_relayout"] = stem_relayout(counter)
         out["filter_lookup"] = filter_lookup(counter, chunks, n_valid)
+        if args.checkpoint:
+            t_a = time.perf_counter()
+            counter.checkpoint(args.checkpoint)
+            t_b = time.perf_counter()
+            with kc.KmerCounter.restore(args.checkpoint) as back:
+                torch.cuda.synchronize()
+                t_c = time.perf_counter()
+                same = all(back.stats()[k] == last[k] for k in ("entries", "sum_counts", "n_valid",
+                                                                  "fp_singletons", "b2_popcount"))
+            size = os.path.getsize(args.checkpoint)
+            os.remove(args.checkpoint)
+            out["checkpoint"] = {"bytes": size, "write_s": round(t_b - t_a, 3),
+                                 "restore_s": round(t_c - t_b, 3),
+                                 "write_gbs": round(size / (t_b - t_a) / 1e9, 2),
+                                 "restore_gbs": round(size / (t_c - t_b) / 1e9, 2),
+                                 "restored_stats_equal": same}
     if args.copy_probe:
         src = torch.empty(COPY_BYTES, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define KC_ABI_VERSION 5u
+#define KC_ABI_VERSION 6u
 
 typedef struct kc_ctx kc_ctx;
 
@@ -220,6 +220,29 @@ kc_status kc_export_bloom(kc_ctx* ctx, uint64_t* b1_host, uint64_t* b2_host, uin
  * of two above 2 x entries, allocated and freed inside.  Synchronises. */
 kc_status kc_export_stems(kc_ctx* ctx, uint64_t* stems_dev, uint16_t* counts_dev, uint64_t capacity,
                           uint64_t* n_out, void* hip_stream);
+
+/* Checkpoint of a finalized context (Sec. II-B: the application's units are
+ * checkpointable, dumping Bloom filters and k-mer tables at their end;
+ * Sec. III-D: swapped tables are identified by metadata records - partition,
+ * stale flag, byte offset, item count - kept in a reserved area at the start
+ * of the device).  Writes `path` (through path + ".tmp", renamed when
+ * complete): a reserved area with a header (ABI version, configuration,
+ * table geometry, statistics) and one record per partition table, then
+ * every partition table in partition order (resident ones copied from HBM,
+ * spilled ones from the pinned pool), both Bloom levels and the overflow
+ * table.  Synchronises the device. */
+kc_status kc_checkpoint(kc_ctx* ctx, const char* path);
+
+/* Creates a finalized context on `device` from a checkpoint file: the
+ * configuration, tables, Bloom levels and statistics it holds.  Tables are
+ * laid out as kc_finalize lays them out under the saved table budget (the
+ * lowest partitions in pinned host memory when the budget is smaller than
+ * all tables), so queries, exports, the stem layout and the filter answer as
+ * before the checkpoint; the statistics' timers start at zero and the spill
+ * counts describe the restored layout.  A file from another ABI version, or
+ * truncated or inconsistent, is rejected with KC_ERR_INVALID_ARG (text in
+ * kc_last_error(NULL)). */
+kc_status kc_restore(const char* path, int device, kc_ctx** out);
 
 /* Filter-unit lookup (Sec. II-B: the Filter unit reads the input sequences
  * again and looks their k-mers up in the frequency table to select k-mers

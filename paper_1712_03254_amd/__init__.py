@@ -36,7 +36,7 @@ EXPORTED = ["kc_abi_version", "kc_status_str", "kc_create", "kc_insert_reads", "
             "kc_get_stats", "kc_reset", "kc_destroy", "kc_last_error", "kc_count_batch",
             "kc_autotune_batch", "kc_server_create", "kc_server_submit", "kc_server_wait",
             "kc_server_release", "kc_server_usage", "kc_server_destroy", "kc_server_set_overlap",
-            "kc_export_stems", "kc_filter_reads"]
+            "kc_export_stems", "kc_filter_reads", "kc_checkpoint", "kc_restore"]
 
 
 class KcError(RuntimeError):
@@ -133,6 +133,8 @@ def load():
         "kc_export_bloom": ([V, V, V, U64], st),
         "kc_export_stems": ([V, V, V, U64, P(U64), V], st),
         "kc_filter_reads": ([V, V, V, U64, U64, U32, U32, V, V], st),
+        "kc_checkpoint": ([V, ctypes.c_char_p], st),
+        "kc_restore": ([ctypes.c_char_p, ctypes.c_int, P(V)], st),
         "kc_debug_keys": ([V, V, V, U64, P(U64)], st),
         "kc_get_stats": ([V, P(KcStats)], st),
         "kc_reset": ([V], st),
@@ -173,6 +175,26 @@ def kc_create(cfg: KcConfig, device: int = 0):
     h = ctypes.c_void_p()
     _check(None, load().kc_create(ctypes.byref(cfg), device, ctypes.byref(h)))
     return h
+
+
+def kc_checkpoint(ctx, path: str):
+    _check(ctx, load().kc_checkpoint(ctx, os.fsencode(path)))
+
+
+def kc_restore(path: str, device: int = 0):
+    h = ctypes.c_void_p()
+    _check(None, load().kc_restore(os.fsencode(path), device, ctypes.byref(h)))
+    return h
+
+
+def checkpoint_config(path: str) -> "Config":
+    """The configuration stored in a checkpoint's header (it follows an
+    8-byte magic, the ABI version, a reserved word and the header size)."""
+    with open(path, "rb") as f:
+        raw = f.read(24 + ctypes.sizeof(KcConfig))
+    if len(raw) < 24 + ctypes.sizeof(KcConfig):
+        raise ValueError("%s is too short to be a checkpoint" % path)
+    return Config.from_c(KcConfig.from_buffer_copy(raw, 24))
 
 
 def kc_insert_reads(ctx, bases_ptr: int, offsets_ptr: int, n_reads: int, total_bases: int,
@@ -360,6 +382,22 @@ class KmerCounter:
 
     def __exit__(self, *exc):
         self.close()
+
+    def checkpoint(self, path: str):
+        """Writes the finalized context to `path` (kc_checkpoint)."""
+        kc_checkpoint(self.ctx, path)
+
+    @classmethod
+    def restore(cls, path: str, device: int = 0) -> "KmerCounter":
+        """A finalized counter read back from a checkpoint (kc_restore)."""
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("KmerCounter needs a HIP device")
+        obj = cls.__new__(cls)
+        obj.cfg = checkpoint_config(path)
+        obj.device = device
+        obj.ctx = kc_restore(path, device)
+        return obj
 
     def insert_reads(self, bases, offsets, counter: int = 0, stream=None):
         """bases: uint8 device tensor; offsets: int64/uint64 device tensor of n_reads+1."""

@@ -1191,6 +1191,265 @@ kc_status kc_filter_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offse
   return KC_OK;
 }
 
+// ------------------------------------------------------------ checkpoints
+//
+// File layout (little endian): a reserved area at the start holding the
+// header and one record per partition table {partition, stale, byte offset,
+// entries}, then every partition table in partition order (cap keys, then
+// cap * n_counters counts), the two Bloom levels and the overflow table.
+
+namespace {
+
+constexpr char kCkptMagic[8] = {'K', 'C', 'C', 'K', 'P', 'T', 0, 1};
+
+struct CkptHeader {
+  char magic[8];
+  uint32_t abi_version;
+  uint32_t reserved_;
+  uint64_t header_bytes;  // the reserved area: this header and the records
+  kc_config cfg;
+  uint32_t p_log2, cap, n_counters, ovf_log2;
+  uint64_t n_parts, bloom_words64;
+  uint64_t records_offset, b1_offset, b2_offset, ovf_keys_offset, ovf_counts_offset, file_bytes;
+  kc_stats stats;
+};
+
+struct CkptRecord {
+  uint32_t partition;
+  uint32_t stale;
+  uint64_t offset;   // bytes from the start of the file
+  uint64_t entries;  // keys with a count at or above min_count
+};
+
+struct FileCloser {
+  FILE* f = nullptr;
+  ~FileCloser() {
+    if (f) fclose(f);
+  }
+};
+
+bool write_all(FILE* f, const void* p, size_t n) { return n == 0 || fwrite(p, 1, n, f) == n; }
+bool read_all(FILE* f, void* p, size_t n) { return n == 0 || fread(p, 1, n, f) == n; }
+
+}  // namespace
+
+kc_status kc_checkpoint(kc_ctx* c, const char* path) {
+  if (!c) return KC_ERR_INVALID_ARG;
+  if (c->state != FINALIZED) return fail(c, KC_ERR_BAD_STATE, "checkpoint before finalize");
+  if (!path || !*path) return fail(c, KC_ERR_INVALID_ARG, "path is empty");
+  KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
+  KC_HIP(c, hipDeviceSynchronize(), "synchronise");
+  const uint32_t nc = c->cfg.n_counters;
+  const uint64_t cap = c->cap, P = 1ull << c->p_log2, R = c->pool_slots;
+  const uint64_t on = 1ull << c->ovf_log2, words = c->bloom_words64;
+  // HBM copies: the resident tables, the overflow table, both Bloom levels
+  std::vector<uint64_t> tk(R * cap), ok(on), b1(words), b2(words);
+  std::vector<uint32_t> tc(R * cap * nc), oc(on * nc);
+  KC_HIP(c, hipMemcpy(tk.data(), c->tkeys.p, tk.size() * 8, hipMemcpyDeviceToHost), "checkpoint copy");
+  KC_HIP(c, hipMemcpy(tc.data(), c->tcounts.p, tc.size() * 4, hipMemcpyDeviceToHost), "checkpoint copy");
+  KC_HIP(c, hipMemcpy(ok.data(), c->okeys.p, on * 8, hipMemcpyDeviceToHost), "checkpoint copy");
+  KC_HIP(c, hipMemcpy(oc.data(), c->ocounts.p, on * 4 * nc, hipMemcpyDeviceToHost), "checkpoint copy");
+  KC_HIP(c, hipMemcpy(b1.data(), c->b1.p, words * 8, hipMemcpyDeviceToHost), "checkpoint copy");
+  KC_HIP(c, hipMemcpy(b2.data(), c->b2.p, words * 8, hipMemcpyDeviceToHost), "checkpoint copy");
+  resolve_timers(c);
+  CkptHeader h{};
+  memcpy(h.magic, kCkptMagic, 8);
+  h.abi_version = KC_ABI_VERSION;
+  h.cfg = c->cfg;
+  h.p_log2 = c->p_log2;
+  h.cap = (uint32_t)cap;
+  h.n_counters = nc;
+  h.ovf_log2 = c->ovf_log2;
+  h.n_parts = P;
+  h.bloom_words64 = words;
+  h.records_offset = sizeof(CkptHeader);
+  h.header_bytes = (sizeof(CkptHeader) + P * sizeof(CkptRecord) + 4095) / 4096 * 4096;
+  h.stats = c->st;
+  const uint64_t table_bytes = cap * 8 + cap * 4 * nc;
+  h.b1_offset = h.header_bytes + P * table_bytes;
+  h.b2_offset = h.b1_offset + words * 8;
+  h.ovf_keys_offset = h.b2_offset + words * 8;
+  h.ovf_counts_offset = h.ovf_keys_offset + on * 8;
+  h.file_bytes = h.ovf_counts_offset + on * 4 * nc;
+  const std::string tmp = std::string(path) + ".tmp";
+  FileCloser fc;
+  fc.f = fopen(tmp.c_str(), "wb");
+  if (!fc.f) return fail(c, KC_ERR_INVALID_ARG, "cannot open " + tmp + " for writing");
+  std::vector<CkptRecord> recs(P);
+  std::vector<char> pad(h.header_bytes, 0);
+  bool ok_io = write_all(fc.f, pad.data(), pad.size());
+  for (uint64_t u = 0; u < P && ok_io; ++u) {
+    const uint64_t* keys;
+    const uint32_t* counts;
+    if (c->slot_of_h[u] != kNoSlot) {
+      keys = tk.data() + (uint64_t)c->slot_of_h[u] * cap;
+      counts = tc.data() + (uint64_t)c->slot_of_h[u] * cap * nc;
+    } else {
+      const SpillRec& rec = c->spill_dir[c->spill_of[u]];
+      keys = c->spill_keys + rec.host_offset;
+      counts = c->spill_counts + rec.host_offset * nc;
+    }
+    uint64_t entries = 0;
+    for (uint64_t i = 0; i < cap; ++i) {
+      uint32_t any = 0;
+      for (uint32_t t = 0; t < nc; ++t) any |= counts[i * nc + t];
+      entries += keys[i] != kEmpty && any;
+    }
+    recs[u] = CkptRecord{(uint32_t)u, 0u, h.header_bytes + u * table_bytes, entries};
+    ok_io = write_all(fc.f, keys, cap * 8) && write_all(fc.f, counts, cap * 4 * nc);
+  }
+  ok_io = ok_io && write_all(fc.f, b1.data(), words * 8) && write_all(fc.f, b2.data(), words * 8) &&
+          write_all(fc.f, ok.data(), on * 8) && write_all(fc.f, oc.data(), on * 4 * nc) &&
+          fseek(fc.f, 0, SEEK_SET) == 0 && write_all(fc.f, &h, sizeof(h)) &&
+          write_all(fc.f, recs.data(), P * sizeof(CkptRecord)) && fflush(fc.f) == 0;
+  const bool closed = fclose(fc.f) == 0;
+  fc.f = nullptr;
+  if (!ok_io || !closed || rename(tmp.c_str(), path) != 0) {
+    (void)remove(tmp.c_str());
+    return fail(c, KC_ERR_INVALID_ARG, std::string("writing the checkpoint ") + path + " failed");
+  }
+  return KC_OK;
+}
+
+kc_status kc_restore(const char* path, int device, kc_ctx** out) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return KC_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  if (!path) {
+    g_create_error = "path is NULL";
+    return KC_ERR_INVALID_ARG;
+  }
+  FileCloser fc;
+  fc.f = fopen(path, "rb");
+  if (!fc.f) {
+    g_create_error = std::string("cannot open ") + path;
+    return KC_ERR_INVALID_ARG;
+  }
+  CkptHeader h{};
+  auto bad = [](const std::string& why) {
+    g_create_error = "not a usable checkpoint: " + why;
+    return KC_ERR_INVALID_ARG;
+  };
+  if (!read_all(fc.f, &h, sizeof(h))) return bad("short header");
+  if (memcmp(h.magic, kCkptMagic, 8) != 0) return bad("bad magic");
+  if (h.abi_version != KC_ABI_VERSION) return bad("written by another ABI version");
+  if (h.n_counters < 1 || h.n_counters > 2 || h.p_log2 > (uint32_t)kMaxPartLog2 ||
+      h.n_parts != (1ull << h.p_log2) || h.cap < 64 || h.ovf_log2 < 12 || h.ovf_log2 > 34)
+    return bad("inconsistent sizes");
+  const uint32_t nc = h.n_counters;
+  const uint64_t cap = h.cap, P = h.n_parts, on = 1ull << h.ovf_log2;
+  const uint64_t table_bytes = cap * 8 + cap * 4 * nc;
+  if (h.records_offset != sizeof(CkptHeader) ||
+      h.header_bytes < sizeof(CkptHeader) + P * sizeof(CkptRecord) ||
+      h.b1_offset != h.header_bytes + P * table_bytes ||
+      h.file_bytes != h.b1_offset + 2 * h.bloom_words64 * 8 + on * 8 + on * 4 * nc)
+    return bad("inconsistent offsets");
+  std::vector<CkptRecord> recs(P);
+  if (!read_all(fc.f, recs.data(), P * sizeof(CkptRecord))) return bad("short record area");
+  for (uint64_t u = 0; u < P; ++u)
+    if (recs[u].partition != u || recs[u].stale || recs[u].offset != h.header_bytes + u * table_bytes)
+      return bad("inconsistent record");
+  // the tables start after the reserved area
+  if (fseek(fc.f, (long)h.header_bytes, SEEK_SET) != 0) return bad("short reserved area");
+  kc_config cfg = h.cfg;
+  cfg.partitions_log2 = h.p_log2;
+  cfg.table_slots = h.cap;
+  kc_ctx* c = nullptr;
+  kc_status r = kc_create(&cfg, device, &c);
+  if (r != KC_OK) return r;
+  auto give_up = [&](kc_status st, const std::string& why) {
+    g_create_error = why;
+    kc_destroy(c);
+    return st;
+  };
+  if (c->p_log2 != h.p_log2 || c->cap != cap || c->bloom_words64 != h.bloom_words64)
+    return give_up(KC_ERR_INVALID_ARG, "not a usable checkpoint: layout differs from its configuration");
+  const uint64_t budget = c->cfg.hbm_table_budget_bytes, per_table = cap * c->slot_bytes;
+  const uint64_t R = budget ? std::min<uint64_t>(P, budget / per_table) : P;
+  const uint64_t n_spill = P - R;
+  if (R == 0) return give_up(KC_ERR_OVER_BUDGET, "table budget smaller than one partition table");
+  hipError_t e;
+  auto hip_ok = [&](hipError_t x) { return (e = x) == hipSuccess; };
+  c->pool_slots = (uint32_t)R;
+  c->ovf_log2 = h.ovf_log2;
+  if (!hip_ok(c->tkeys.ensure(R * cap * 8)) || !hip_ok(c->tcounts.ensure(R * cap * 4 * nc)) ||
+      !hip_ok(c->slot_of.ensure(P * 4)) || !hip_ok(c->slot_live.ensure(R * 4)) ||
+      !hip_ok(c->okeys.ensure(on * 8)) || !hip_ok(c->ocounts.ensure(on * 4 * nc)))
+    return give_up(KC_ERR_OUT_OF_MEMORY, "restore allocation failed");
+  free_spill(c);
+  if (n_spill && ensure_spill_pool(c, n_spill) != KC_OK)
+    return give_up(KC_ERR_OUT_OF_MEMORY, "pinned spill pool allocation failed");
+  // tables: the lowest n_spill partitions into the pinned pool, the others to
+  // HBM slots u - n_spill, as finalize lays them out under the same budget
+  std::vector<char> buf;
+  std::vector<uint64_t> hk;
+  std::vector<uint32_t> hc;
+  const uint64_t batch = std::max<uint64_t>(1, std::min<uint64_t>(R, (256ull << 20) / table_bytes));
+  for (uint64_t u = 0; u < P;) {
+    if (u < n_spill) {
+      if (!read_all(fc.f, c->spill_keys + u * cap, cap * 8) ||
+          !read_all(fc.f, c->spill_counts + u * cap * nc, cap * 4 * nc))
+        return give_up(KC_ERR_INVALID_ARG, "not a usable checkpoint: short table area");
+      add_spill_record(c, (uint32_t)u, u, recs[u].entries);
+      ++u;
+      continue;
+    }
+    const uint64_t n = std::min<uint64_t>(batch, P - u);
+    buf.resize(n * table_bytes);
+    if (!read_all(fc.f, buf.data(), buf.size()))
+      return give_up(KC_ERR_INVALID_ARG, "not a usable checkpoint: short table area");
+    // slots u - n_spill .. are consecutive: keys and counts of the batch go
+    // to HBM in one copy each
+    hk.resize(n * cap);
+    hc.resize(n * cap * nc);
+    for (uint64_t i = 0; i < n; ++i) {
+      const char* t = buf.data() + i * table_bytes;
+      memcpy(hk.data() + i * cap, t, cap * 8);
+      memcpy(hc.data() + i * cap * nc, t + cap * 8, cap * 4 * nc);
+    }
+    const uint64_t slot = u - n_spill;
+    if (!hip_ok(hipMemcpy(c->tkeys.as<uint64_t>() + slot * cap, hk.data(), n * cap * 8,
+                          hipMemcpyHostToDevice)) ||
+        !hip_ok(hipMemcpy(c->tcounts.as<uint32_t>() + slot * cap * nc, hc.data(), n * cap * 4 * nc,
+                          hipMemcpyHostToDevice)))
+      return give_up(KC_ERR_DEVICE, "restore copy failed");
+    u += n;
+  }
+  c->spill_used = n_spill;
+  std::vector<uint64_t> w(std::max<uint64_t>(h.bloom_words64, on));
+  std::vector<uint32_t> oc(on * nc);
+  bool ok_io = read_all(fc.f, w.data(), h.bloom_words64 * 8) &&
+               hip_ok(hipMemcpy(c->b1.p, w.data(), h.bloom_words64 * 8, hipMemcpyHostToDevice)) &&
+               read_all(fc.f, w.data(), h.bloom_words64 * 8) &&
+               hip_ok(hipMemcpy(c->b2.p, w.data(), h.bloom_words64 * 8, hipMemcpyHostToDevice)) &&
+               read_all(fc.f, w.data(), on * 8) &&
+               hip_ok(hipMemcpy(c->okeys.p, w.data(), on * 8, hipMemcpyHostToDevice)) &&
+               read_all(fc.f, oc.data(), on * 4 * nc) &&
+               hip_ok(hipMemcpy(c->ocounts.p, oc.data(), on * 4 * nc, hipMemcpyHostToDevice));
+  if (!ok_io) return give_up(KC_ERR_INVALID_ARG, "not a usable checkpoint: short Bloom or overflow area");
+  const uint32_t used = (uint32_t)h.stats.overflow_keys;
+  if (!hip_ok(hipMemcpy(c->ovf_used.p, &used, 4, hipMemcpyHostToDevice)) ||
+      !hip_ok(launch_slot_map(c->slot_of.as<uint32_t>(), (uint32_t)P, (uint32_t)n_spill, nullptr)) ||
+      !hip_ok(launch_fill32(c->slot_live.as<uint32_t>(), R, 1, nullptr)) ||
+      !hip_ok(hipDeviceSynchronize()))
+    return give_up(KC_ERR_DEVICE, "restore setup failed");
+  c->slot_of_h.resize(P);
+  for (uint64_t u = 0; u < P; ++u) c->slot_of_h[u] = u < n_spill ? kNoSlot : (uint32_t)(u - n_spill);
+  const uint64_t sp = c->st.spilled_partitions, sb = c->st.spilled_bytes;
+  c->st = h.stats;
+  c->st.spilled_partitions = sp;
+  c->st.spilled_bytes = sb;
+  for (int i = 0; i < KC_T_COUNT_OF; ++i) {
+    c->st.kernel_ms[i] = 0;
+    c->st.kernel_launches[i] = 0;
+  }
+  c->state = FINALIZED;
+  *out = c;
+  return KC_OK;
+}
+
 kc_status kc_spill(kc_ctx* c, int64_t partition, uint64_t* bytes_out) {
   if (!c) return KC_ERR_INVALID_ARG;
   if (bytes_out) *bytes_out = 0;

@@ -105,3 +105,24 @@ def test_probe_library_exports_and_checks_arguments():
     assert lib.kcp_lds_atomics(0, 16, 1, 1, ctypes.byref(ms), ctypes.byref(chk)) == -1
     assert lib.kcp_lds_atomics(0, 13, 0, 1, ctypes.byref(ms), ctypes.byref(chk)) == -1
     assert lib.kcp_lds_atomics(0, 13, 1, 0, ctypes.byref(ms), ctypes.byref(chk)) == -1
+
+
+def test_restore_rejects_bad_files_without_a_device(tmp_path):
+    lib = kc.load()
+    h = ctypes.c_void_p()
+    missing = str(tmp_path / "none.kcckpt").encode()
+    assert lib.kc_restore(missing, 0, ctypes.byref(h)) == kc.KC_ERR_INVALID_ARG
+    junk = tmp_path / "junk.kcckpt"
+    junk.write_bytes(bytes(range(256)) * 64)
+    assert lib.kc_restore(str(junk).encode(), 0, ctypes.byref(h)) == kc.KC_ERR_INVALID_ARG
+    assert b"magic" in lib.kc_last_error(None)
+    # right magic, another ABI version
+    other = tmp_path / "other.kcckpt"
+    other.write_bytes(b"KCCKPT\x00\x01" + (999).to_bytes(4, "little") + bytes(4096))
+    assert lib.kc_restore(str(other).encode(), 0, ctypes.byref(h)) == kc.KC_ERR_INVALID_ARG
+    assert b"ABI" in lib.kc_last_error(None)
+    # right magic and version, truncated
+    short = tmp_path / "short.kcckpt"
+    short.write_bytes(b"KCCKPT\x00\x01" + kc.kc_abi_version().to_bytes(4, "little") + bytes(16))
+    assert lib.kc_restore(str(short).encode(), 0, ctypes.byref(h)) == kc.KC_ERR_INVALID_ARG
+    assert not h.value
