@@ -365,8 +365,11 @@ def served_main(args, w):
     overlap = int(args.serve_overlap)
     with kc.Server(budget, workers=1) as plain, \
             kc.Server(budget, workers=args.serve_workers, overlap_bases=overlap) as srv:
-        run(plain, warm)
-        run(srv, warm)
+        # warm-up: the warm requests, then one untimed pass of the timed set, so
+        # both servers' context pools hold contexts for every request size
+        for server in (plain, srv):
+            run(server, warm)
+            run(server, timed)
         closed_plain = run(plain, timed)
         closed = run(srv, timed)
         cap = closed_plain["kmers_per_s"]
