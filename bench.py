@@ -88,7 +88,7 @@ def stage_bytes(stage: str, w, st: dict, cfg_eff: dict) -> float:
     return 0.0
 
 
-def cpu_baseline(w, genome, n_reads=300_000):
+def cpu_baseline(w, genome, n_reads=450_000):
     import oracle
     b, o = w.make_reads(genome, first=0, n=n_reads, threads=16)
     p = oracle.Params(k=w.k, n_counters=w.n_counters, min_count=w.min_count,
