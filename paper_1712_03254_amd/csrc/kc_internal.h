@@ -32,9 +32,9 @@ constexpr uint32_t kXcds = 8;                   // XCDs; workgroup b is dispatch
 // Second-level launch with an upper bound of `tiles2` tiles: the grid, a
 // multiple of kXcds.
 inline uint64_t level2_grid(uint64_t tiles2) { return (tiles2 + kXcds - 1) / kXcds * kXcds; }
-// u32 words of the tile_run buffer: one 64-bit descriptor per workgroup of
-// the second-level grid.
-inline uint64_t tile_run_words(uint64_t tiles2) { return 2 * level2_grid(tiles2); }
+// Bytes of the second-level descriptor buffer: one 64-bit descriptor per
+// workgroup of the second-level grid.
+inline uint64_t tile_desc_bytes(uint64_t tiles2) { return 8 * level2_grid(tiles2); }
 
 enum Stat { ST_NPASS = 0, ST_ENTRIES, ST_SUM, ST_FP, ST_B1POP, ST_B2POP, ST_PASSED, ST_OVF };
 enum Err : uint32_t { ERR_OFFSETS = 1, ERR_OVF_FULL = 2, ERR_OVF_LOAD = 4, ERR_QUERY_RANGE = 8 };
@@ -131,7 +131,7 @@ hipError_t launch_tiles2(const uint64_t* bucket_off, uint32_t nb1, uint32_t* til
                          hipStream_t s);
 hipError_t launch_level2(const uint64_t* keys1, const uint64_t* off1, const uint32_t* lstart,
                          uint64_t ntiles1, const uint64_t* bucket_off, const uint32_t* tile_first,
-                         uint32_t* tile_run, uint32_t a1, uint32_t a2, uint64_t s0,
+                         uint64_t* tile_desc, uint32_t a1, uint32_t a2, uint64_t s0,
                          uint64_t* keys2, uint32_t* meta2, uint64_t grid, hipStream_t s);
 hipError_t launch_bloom(const CountArgs& a, uint32_t blocks, size_t lds, hipStream_t s);
 hipError_t launch_tally(const CountArgs& a, uint32_t parts, size_t lds, hipStream_t s);

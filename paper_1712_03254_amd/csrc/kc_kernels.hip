@@ -5,10 +5,14 @@
 // two counting-sort levels (histogram, exclusive prefix sum, broker scatter;
 // the paper's GPU shuffle, Sec. III-B).  Pass 2 (kc_finalize): one workgroup
 // per Bloom block builds that block's two Bloom levels in LDS from every
-// occurrence in the block (Prune, Sec. III), screens every occurrence against
-// level 2 and counts passing keys exactly in an LDS open-addressing table per
-// partition (Count, Sec. III), then writes the table to HBM with keys below
-// min_count zeroed (Unify, Sec. III).
+// occurrence in the block (Prune, Sec. III); then one workgroup per partition
+// counts the partition's keys in an LDS open-addressing table, screening each
+// new key against level 2 (Count, Sec. III), and writes the table to HBM with
+// keys below min_count zeroed (Unify, Sec. III).  After finalize: queries,
+// the Filter unit's lookup of every window of a read batch (Sec. II-B), the
+// stem layout of the table (Sec. II-A, III-D) and the table export.  The
+// batched form's pack and read-start kernels and the fill kernels that
+// replace memsets in captured graphs are here too.
 #include "kc_internal.h"
 
 namespace kc {
@@ -462,7 +466,7 @@ __global__ void __launch_bounds__(kThreads) k_tiles2(const uint64_t* __restrict_
 // tile 0, then all tile 1, ...), so the workgroups an XCD runs at once read
 // adjacent runs through the same L2.  When a group holds more tiles than its
 // XCD has workgroups (skewed buckets) the grid takes tiles in plain order.
-__global__ void __launch_bounds__(256) k_tile_runs(const uint64_t* __restrict__ off1,
+__global__ void __launch_bounds__(256) k_tile_desc(const uint64_t* __restrict__ off1,
                                                    uint64_t ntiles1,
                                                    const uint64_t* __restrict__ bucket_off,
                                                    const uint32_t* __restrict__ tile_first,
@@ -1581,17 +1585,18 @@ hipError_t launch_tiles2(const uint64_t* bucket_off, uint32_t nb1, uint32_t* til
 
 hipError_t launch_level2(const uint64_t* keys1, const uint64_t* off1, const uint32_t* lstart,
                          uint64_t ntiles1, const uint64_t* bucket_off, const uint32_t* tile_first,
-                         uint32_t* tile_run, uint32_t a1, uint32_t a2, uint64_t s0,
+                         uint64_t* tile_desc, uint32_t a1, uint32_t a2, uint64_t s0,
                          uint64_t* keys2, uint32_t* meta2, uint64_t grid, hipStream_t s) {
   if (!grid) return hipSuccess;
-  // one descriptor per workgroup; tiles, buckets and first-level tiles must
-  // fit their fields (20, 10 and 34 bits; never all ones)
+  // one descriptor per workgroup (tile_desc holds level2_grid(grid)); tiles,
+  // buckets and first-level tiles must fit their fields (20, 10 and 34 bits;
+  // never all ones)
   const uint64_t grid8 = level2_grid(grid);
   if (grid8 > (1u << 20) || a1 > 10 || ntiles1 >= (1ull << 33)) return hipErrorInvalidValue;
-  uint64_t* order = reinterpret_cast<uint64_t*>(tile_run);
+  uint64_t* order = tile_desc;
   hipError_t e = launch_fill64(order, grid8, kEmpty, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_tile_runs, dim3(div_up(grid, 256)), dim3(256), 0, s, off1, ntiles1,
+  hipLaunchKernelGGL(k_tile_desc, dim3(div_up(grid, 256)), dim3(256), 0, s, off1, ntiles1,
                      bucket_off, tile_first, 1u << a1, (uint32_t)grid8, order);
   const size_t lds = level2_lds(a2);
   e = allow_lds(reinterpret_cast<const void*>(k_level2));

@@ -197,7 +197,7 @@ struct kc_ctx {
   DevBuf b1, b2;
   DevBuf dstat;   // kNst u64 stats, then ovf stats scratch
   DevBuf derr;    // u32 error flags
-  DevBuf packed, flags, hist1, lstart1, off1, parts, keys1, tile_run;
+  DevBuf packed, flags, hist1, lstart1, off1, parts, keys1, tile_desc;
   DevBuf segdesc;
   DevBuf tkeys, tcounts, pstats, pstats2, pstats_ovf;
   DevBuf slot_of, slot_live;  // partition -> HBM table slot; slot -> holds a live table
@@ -543,7 +543,7 @@ namespace kc {
 
 uint64_t ctx_device_bytes(const kc_ctx* c) {
   const DevBuf* bufs[] = {&c->b1, &c->b2, &c->dstat, &c->derr, &c->packed, &c->flags, &c->hist1,
-                          &c->lstart1, &c->off1, &c->parts, &c->keys1, &c->tile_run, &c->segdesc,
+                          &c->lstart1, &c->off1, &c->parts, &c->keys1, &c->tile_desc, &c->segdesc,
                           &c->tkeys, &c->tcounts, &c->slot_of, &c->slot_live, &c->pstats,
                           &c->pstats2, &c->pstats_ovf, &c->okeys, &c->ocounts, &c->ovf_used,
                           &c->qrows, &c->qkeys, &c->qcount};
@@ -586,14 +586,14 @@ uint64_t bytes_after(const kc_ctx* c, const kc_config* cfg, const uint64_t* part
     off = std::max(off, (nhist + 1) * 8);
     parts = std::max<uint64_t>(parts, scan_parts(nhist) * 8);
     keys1 = std::max<uint64_t>(keys1, ntiles * kTilePos * 8);
-    runs = std::max(runs, tile_run_words(tiles2) * 4);
+    runs = std::max(runs, tile_desc_bytes(tiles2));
     if (kmax) seg.push_back({kmax * 8, (nb1 + 1) * 12 + tiles2 * (nb2 + 1) * 4});
     keys += kmax;
   }
   uint64_t n = mx(&kc_ctx::b1, d.bloom_words64 * 8) + mx(&kc_ctx::b2, d.bloom_words64 * 8) +
                mx(&kc_ctx::packed, packed) + mx(&kc_ctx::flags, packed) + mx(&kc_ctx::hist1, hist) +
                mx(&kc_ctx::lstart1, lstart) + mx(&kc_ctx::off1, off) + mx(&kc_ctx::parts, parts) +
-               mx(&kc_ctx::keys1, keys1) + mx(&kc_ctx::tile_run, runs);
+               mx(&kc_ctx::keys1, keys1) + mx(&kc_ctx::tile_desc, runs);
   const uint32_t ovf_log2 = std::max<uint32_t>(12, std::min<uint32_t>(30, ceil_log2(keys / 256 + 1)));
   const uint64_t on = 1ull << ovf_log2;
   const uint64_t oblocks = std::min<uint64_t>(1024, (on + 255) / 256);
@@ -833,7 +833,7 @@ kc_status kc_insert_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offse
     seg.release();
     return hip_fail(c, e, "segment allocation");
   }
-  KC_HIP(c, c->tile_run.ensure(tile_run_words(tiles2) * 4), "tile run buffer");
+  KC_HIP(c, c->tile_desc.ensure(tile_desc_bytes(tiles2)), "tile descriptor buffer");
   {
     StageTimer t(c, s, KC_T_LEVEL2);
     KC_HIP(c, launch_bucket_off(c->off1.as<uint64_t>(), ntiles, nb1, seg.bucket_off.as<uint64_t>(), s),
@@ -842,7 +842,7 @@ kc_status kc_insert_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offse
            "tiles");
     KC_HIP(c, launch_level2(c->keys1.as<uint64_t>(), c->off1.as<uint64_t>(),
                             c->lstart1.as<uint32_t>(), ntiles, seg.bucket_off.as<uint64_t>(),
-                            seg.tile_first.as<uint32_t>(), c->tile_run.as<uint32_t>(), c->a1,
+                            seg.tile_first.as<uint32_t>(), c->tile_desc.as<uint64_t>(), c->a1,
                             c->a2, s0, seg.keys.as<uint64_t>(), seg.meta2.as<uint32_t>(), tiles2,
                             s),
            "second-level shuffle");
@@ -1703,7 +1703,7 @@ void kc_destroy(kc_ctx* c) {
   c->batch.release();
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   DevBuf* bufs[] = {&c->b1, &c->b2, &c->dstat, &c->derr, &c->packed, &c->flags, &c->hist1,
-                    &c->lstart1, &c->off1, &c->parts, &c->keys1, &c->tile_run, &c->segdesc,
+                    &c->lstart1, &c->off1, &c->parts, &c->keys1, &c->tile_desc, &c->segdesc,
                     &c->tkeys, &c->tcounts, &c->slot_of, &c->slot_live, &c->pstats, &c->pstats2,
                     &c->pstats_ovf, &c->okeys, &c->ocounts, &c->ovf_used, &c->qrows, &c->qkeys,
                     &c->qcount};
@@ -1798,7 +1798,7 @@ kc_status build_batch(kc_ctx* c, const kc_chunk* ch, uint32_t n, uint32_t counte
   KC_HIP(c, c->off1.ensure((max_hist + 1) * 8), "offset buffer");
   KC_HIP(c, c->parts.ensure(scan_parts(max_hist) * 8), "scan buffer");
   KC_HIP(c, c->keys1.ensure(max_tiles * kTilePos * 8), "first-level key buffer");
-  KC_HIP(c, c->tile_run.ensure(tile_run_words(max_tiles2) * 4), "tile run buffer");
+  KC_HIP(c, c->tile_desc.ensure(tile_desc_bytes(max_tiles2)), "tile descriptor buffer");
   KC_HIP(c, b.counts.ensure(std::max<size_t>(1, b.groups.size()) * 8), "segment counts");
   std::vector<SegDesc> hd;
   for (size_t gi = 0; gi < b.groups.size(); ++gi) {
@@ -1875,7 +1875,7 @@ kc_status build_batch(kc_ctx* c, const kc_chunk* ch, uint32_t n, uint32_t counte
       KC_REC(launch_tiles2(g.seg.bucket_off.as<uint64_t>(), nb1, g.seg.tile_first.as<uint32_t>(), cs));
       KC_REC(launch_level2(c->keys1.as<uint64_t>(), c->off1.as<uint64_t>(), c->lstart1.as<uint32_t>(),
                            g.ntiles, g.seg.bucket_off.as<uint64_t>(), g.seg.tile_first.as<uint32_t>(),
-                           c->tile_run.as<uint32_t>(), c->a1, c->a2, s0, g.seg.keys.as<uint64_t>(),
+                           c->tile_desc.as<uint64_t>(), c->a1, c->a2, s0, g.seg.keys.as<uint64_t>(),
                            g.seg.meta2.as<uint32_t>(), g.tiles2, cs));
     }
     KC_REC(launch_fill64(c->okeys.as<uint64_t>(), on, kEmpty, cs));
