@@ -825,11 +825,20 @@ __device__ __forceinline__ uint32_t home_slot(uint64_t th, uint32_t cap) {
   return (uint32_t)(((th >> 32) * (uint64_t)cap) >> 32);
 }
 
+// Once more keys than ovf_limit have been placed the pass is void (the host
+// grows the table and runs it again), so an insert stops as soon as it sees
+// the limit passed, on entry and every 32 probes: a table filled far beyond
+// its limit would otherwise make each later key probe every slot.
 __device__ void overflow_add(const CountArgs& A, uint64_t x, uint32_t tag, uint64_t th) {
   const uint32_t nc = A.hc.nc;
   const uint64_t mask = (1ull << A.ovf_log2) - 1;
   uint64_t slot = th >> (64 - A.ovf_log2);
   for (uint64_t probe = 0; probe <= mask; ++probe) {
+    if ((probe & 31) == 0 &&
+        __hip_atomic_load(A.ovf_used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > A.ovf_limit) {
+      atomicOr(A.err, (uint32_t)ERR_OVF_LOAD);
+      return;
+    }
     uint64_t cur = __hip_atomic_load(&A.okeys[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (cur == kEmpty) {
       cur = atomicCAS(reinterpret_cast<unsigned long long*>(&A.okeys[slot]),

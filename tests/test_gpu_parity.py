@@ -91,6 +91,24 @@ def test_parameter_grid_parity(k, m, h, bl, pl, tl, nc, mc, seed):
         assert g["stats"]["overflow_keys"] > 0
 
 
+def test_overflow_table_far_past_its_limit():
+    """About 1.4·10^5 counted keys against 1024 table slots: the first overflow
+    table (sized from n_valid / 256, a few thousand slots) takes a small
+    fraction of them, so finalize grows it more than once; each void pass stops
+    inserting once the table's limit is passed, and the last one equals the
+    oracle."""
+    note("case: overflow table far past its limit, 15000 reads x 100 bp from a 3e5 bp genome, "
+         "16 partitions of 64 slots, seed 21")
+    reads = random_reads(21, 15000, 100, 100, genome_len=300000)
+    cfg = kc.Config(k=31, bloom_bits_log2=24, bloom_hashes=4, bloom_block_log2=16,
+                    partitions_log2=4, table_slots=64, seed=21)
+    g, ref = assert_parity(cfg, [pack_reads(reads)])
+    st = g["stats"]
+    note("overflow keys %d, retries %d" % (st["overflow_keys"], st["retries"]))
+    assert st["overflow_keys"] > 100_000
+    assert st["retries"] >= 2
+
+
 def test_chunking_and_order_invariance():
     note("case: chunking invariance, 7 calls vs 1, plus shuffled read order")
     reads = random_reads(11, 4000, 20, 150, genome_len=5000)
