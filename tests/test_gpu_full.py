@@ -97,3 +97,45 @@ def test_plain_100mbp_sampled_parity():
     assert int(keys.max()) < (1 << (2 * cfg.k))
     note("entries %d, F %d, overflow keys %d" % (st["entries"], st["fp_singletons"],
                                                 st["overflow_keys"]))
+
+
+def test_plain_100mbp_most_keys_in_the_overflow_table():
+    """The same workload with 2^14 partition tables of 1024 slots (1.7·10^7
+    slots in all): about 8·10^7 of the 9.8·10^7 counted keys do not fit and go
+    to the overflow table, which finalize grows more than once.  Partitioning
+    and table size change no result: statistics, exported table and queries
+    equal those of the configuration bench.py times."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    note("case: plain_100mbp full size, 2^14 partitions of 1024 slots (overflow-heavy) "
+         "against 2^16 partitions of 3840")
+    w, _, b, o = workload_chunks("plain_100mbp")
+    base = workload_config(w)
+    heavy = workload_config(w, partitions_log2=14, table_slots=1024)
+    db, do = to_device(b, o)
+    rng = np.random.default_rng(77)
+    out = []
+    for cfg in (base, heavy):
+        with kc.KmerCounter(cfg) as c:
+            c.insert_reads(db, do)
+            st = c.finalize()
+            keys, counts = c.export()
+            if not out:
+                sample = np.concatenate([keys[rng.integers(0, keys.size, 20000)],
+                                         rng.integers(0, 1 << (2 * w.k), 5000, dtype=np.uint64)])
+                q = torch.from_numpy(sample.view(np.int64)).cuda()
+            got = c.query(q).cpu().numpy()
+        note("partitions 2^%d: entries %d, overflow keys %d, retries %d"
+             % (st["partitions_log2"], st["entries"], st["overflow_keys"], st["retries"]))
+        out.append((st, keys, counts, got))
+    (s0, k0, c0, q0), (s1, k1, c1, q1) = out
+    assert s1["overflow_keys"] > s1["entries"] // 2
+    assert s1["retries"] >= 1
+    for key in ("n_valid", "n_pass", "entries", "sum_counts", "fp_singletons",
+                "passed_distinct", "b1_popcount", "b2_popcount"):
+        assert s1[key] == s0[key], key
+    o0, o1 = np.argsort(k0), np.argsort(k1)
+    assert np.array_equal(k0[o0], k1[o1])
+    assert np.array_equal(c0[o0], c1[o1])
+    assert np.array_equal(q0, q1)
