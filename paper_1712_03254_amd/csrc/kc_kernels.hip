@@ -315,17 +315,23 @@ __global__ void __launch_bounds__(kThreads) k_level1(const uint64_t* __restrict_
   uint32_t* scratch = start + nb + 1;                       // kWaves
   for (uint32_t i = threadIdx.x; i < nb; i += kThreads) cnt[i] = 0;
   __syncthreads();
-  // kPP consecutive positions per thread, kTPW threads per packed word
+  // Lane l of wave v takes packed word (v mod kWordGroups) * 64 + l and in it
+  // the kPP positions from kPP * (v / kWordGroups): the window offsets are the
+  // same on every lane, so every shift in the extraction is by a scalar and
+  // no branch on them diverges; a wave's word loads are contiguous.
   constexpr int kPP = kTilePos / kThreads;
-  constexpr int kTPW = 32 / kPP;
-  static_assert(kPP * kThreads == kTilePos && kTPW * kPP == 32, "level-1 tile shape");
-  const uint64_t w = tile * kTileWords + (threadIdx.x / kTPW);
+  constexpr int kWordGroups = kTileWords / 64;
+  static_assert(kPP * kThreads == kTilePos && kPP * (kThreads / 64 / kWordGroups) == 32 &&
+                    kWordGroups * 64 == kTileWords,
+                "level-1 tile shape");
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t w = tile * kTileWords + (wv % kWordGroups) * 64 + (threadIdx.x & 63);
   uint64_t key[kPP];
   uint32_t meta[kPP];
   uint32_t valid = 0;
   if (w < nwords) {
     const WordCtx c = load_word(packed, flags, w);
-    const int j0 = (threadIdx.x % kTPW) * kPP;
+    const int j0 = (int)(wv / kWordGroups) * kPP;
 #pragma unroll
     for (int jj = 0; jj < kPP; ++jj) {
       uint64_t x;
