@@ -285,6 +285,41 @@ __device__ __forceinline__ bool window_key(const WordCtx& c, uint32_t k, int j, 
   return true;
 }
 
+// OR of z << i over i < w (w < 32): every set bit spread over the w - 1
+// indices above it.  w is the same on every lane, so the branches are scalar.
+__device__ __forceinline__ uint64_t smear(uint64_t z, uint32_t w) {
+  uint64_t acc = 0, cur = z;  // cur: OR of z << i over i < 2^b
+  uint32_t sh = 0;
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    if (w & (1u << b)) {
+      acc |= cur << sh;
+      sh += 1u << b;
+    }
+    cur |= cur << (1u << b);
+  }
+  return acc;
+}
+
+// Bit j set when the window ending at base j of word w is one window_key
+// accepts: the window [33+j-k, 32+j] of the (w-1, w) frame holds no invalid
+// base, and no read starts in [34+j-k, 32+j].
+__device__ __forceinline__ uint32_t window_mask(const WordCtx& c, uint32_t k) {
+  const uint64_t bad = smear(c.inv, k) | smear(c.rst, k - 1);
+  return ~(uint32_t)(bad >> 32);
+}
+
+// Canonical key of the window ending at base j of word w, whether or not the
+// window is valid (window_mask says which are).
+__device__ __forceinline__ uint64_t window_code(const WordCtx& c, uint32_t k, int j) {
+  const uint64_t kmask = (1ull << (2 * k)) - 1;
+  const int s = 62 - 2 * j;
+  const uint64_t f = (s ? ((c.pc >> s) | (c.pp << (64 - s))) : c.pc) & kmask;
+  const int s2 = 66 + 2 * j - 2 * (int)k;  // in [4, 126]
+  const uint64_t r = (s2 >= 64 ? (c.qc >> (s2 - 64)) : ((c.qp >> s2) | (c.qc << (64 - s2)))) & kmask;
+  return f < r ? f : r;
+}
+
 // --------------------------------------------------- first-level shuffle
 
 // One pass per tile of kTilePos window positions: extract the canonical keys,
@@ -332,15 +367,15 @@ __global__ void __launch_bounds__(kThreads) k_level1(const uint64_t* __restrict_
   if (w < nwords) {
     const WordCtx c = load_word(packed, flags, w);
     const int j0 = (int)(wv / kWordGroups) * kPP;
+    valid = (window_mask(c, k) >> j0) & ((1u << kPP) - 1);
+    // keys and hashes of all kPP windows, branch-free; only the count of a
+    // valid one is taken
 #pragma unroll
     for (int jj = 0; jj < kPP; ++jj) {
-      uint64_t x;
-      if (window_key(c, k, j0 + jj, &x)) {
-        const uint32_t b = (uint32_t)(mix64(x ^ s0) >> (64 - a1));
-        meta[jj] = (b << 16) | atomicAdd(&cnt[b], 1u);
-        key[jj] = x | tag;
-        valid |= 1u << jj;
-      }
+      const uint64_t x = window_code(c, k, j0 + jj);
+      const uint32_t b = (uint32_t)(mix64(x ^ s0) >> (64 - a1));
+      if ((valid >> jj) & 1u) meta[jj] = (b << 16) | atomicAdd(&cnt[b], 1u);
+      key[jj] = x | tag;
     }
   }
   __syncthreads();
