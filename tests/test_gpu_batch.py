@@ -91,6 +91,30 @@ def test_batch_parity(group_log2):
         assert np.array_equal(out, ref.counts)
 
 
+def test_batch_overflow_table_fill_falls_back_to_the_eager_path():
+    """Tables of 64 slots against ~1.1·10^5 passing keys: the overflow table the
+    graph was built with fills, so the call counts again on the eager path,
+    which grows the table; the result equals the oracle's, and a second batch
+    on the same context does the same."""
+    note("case: batch of 8 chunks x 2000 reads x 100 bp from a 2e5 bp genome, 256 tables of "
+         "64 slots (overflow fill in the graph), seed 67")
+    chunks = [pack_reads(random_reads(6700 + i, 2000, 100, 100, genome_len=200000))
+              for i in range(8)]
+    cfg = kc.Config(k=31, bloom_bits_log2=22, bloom_hashes=4, bloom_block_log2=14,
+                    partitions_log2=8, table_slots=64, seed=67)
+    ref = oracle_of(cfg, chunks)
+    dev = [to_device(b, o) for b, o in chunks]
+    with kc.KmerCounter(cfg) as c:
+        for rep in range(2):
+            g = run_batch(c, dev)
+            st = g["stats"]
+            note("rep %d: overflow keys %d, retries %d" % (rep, st["overflow_keys"], st["retries"]))
+            assert st["overflow_keys"] > 50_000
+            assert st["retries"] >= 1
+            assert_matches_oracle(g, ref)
+            c.reset()
+
+
 def test_batch_graph_replays_with_eager_work_between():
     """The captured graph is replayed after kc_reset; between replays the
     program runs its own eager work (another context's plain count, torch
