@@ -14,6 +14,12 @@ constexpr uint64_t kKeyMask = (1ull << 62) - 1; // key bits; bit 62 carries the 
 constexpr uint64_t kTableMul = 0xD6E8FEB86659FD93ull; // odd multiplier of the table slot hash
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;          // partition table not in HBM (spilled)
 constexpr uint32_t kProbeLimit = 128;              // probes before a key goes to the overflow table
+// A key is stored less than this many slots past its home slot in a table of
+// cap slots (further along it goes to the overflow table), so a lookup stops
+// after as many probes.
+inline __host__ __device__ uint32_t probe_limit_of(uint64_t cap) {
+  return cap < kProbeLimit ? (uint32_t)cap : kProbeLimit;
+}
 constexpr int kThreads = 1024;                  // block size of the tile kernels
 constexpr int kWaves = kThreads / 64;
 constexpr int kTileWords = 256;                 // first-level tile: 256 packed words
@@ -99,6 +105,7 @@ struct CountArgs {
 struct QueryArgs {
   HashCfg hc;
   uint64_t cap;            // slots per partition table
+  uint32_t probe_limit;    // probes of a partition-table lookup (probe_limit_of(cap))
   const uint64_t* tkeys;
   const uint32_t* tcounts;
   const uint32_t* slot_of;  // partition -> its table slot in HBM, or kNoSlot if spilled

@@ -1254,11 +1254,12 @@ __global__ void __launch_bounds__(kThreads) k_reduce(const uint64_t* __restrict_
 
 // ----------------------------------------------------------------- query
 
-// Linear probing in a table of n slots starting at `slot`; true with the
-// slot index when x is present.
+// Linear probing in a table of n slots starting at `slot`, at most `limit`
+// probes; true with the slot index when x is present.
 __device__ __forceinline__ bool probe_table(const uint64_t* keys, uint64_t base, uint64_t n,
-                                            uint64_t slot, uint64_t x, uint64_t* at) {
-  for (uint64_t p = 0; p < n; ++p) {
+                                            uint64_t limit, uint64_t slot, uint64_t x,
+                                            uint64_t* at) {
+  for (uint64_t p = 0; p < limit; ++p) {
     const uint64_t cur = keys[base + slot];
     if (cur == x) {
       *at = base + slot;
@@ -1283,13 +1284,15 @@ __device__ __forceinline__ int table_counts(const QueryArgs& A, uint64_t x, uint
   const uint32_t slot = A.slot_of[u];
   uint64_t at;
   if (slot != kNoSlot &&
-      probe_table(A.tkeys, (uint64_t)slot * A.cap, A.cap, home_slot(th, A.cap), x, &at)) {
+      probe_table(A.tkeys, (uint64_t)slot * A.cap, A.cap, A.probe_limit, home_slot(th, A.cap), x,
+                  &at)) {
     *c0 = A.tcounts[at * nc];
     if (nc > 1) *c1 = A.tcounts[at * nc + 1];
     return 1;
   }
   if (*A.ovf_used &&
-      probe_table(A.okeys, 0, 1ull << A.ovf_log2, mix64(th) >> (64 - A.ovf_log2), x, &at)) {
+      probe_table(A.okeys, 0, 1ull << A.ovf_log2, 1ull << A.ovf_log2,
+                  mix64(th) >> (64 - A.ovf_log2), x, &at)) {
     *c0 = A.ocounts[at * nc];
     if (nc > 1) *c1 = A.ocounts[at * nc + 1];
     return 1;

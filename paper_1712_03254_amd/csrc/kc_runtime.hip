@@ -502,7 +502,7 @@ CountArgs count_args(kc_ctx* c, uint32_t nsegs) {
   a.nbw = c->nbw;
   a.l2w = c->l2w;
   a.cap = c->cap;
-  a.probe_limit = std::min<uint32_t>(c->cap, kProbeLimit);
+  a.probe_limit = probe_limit_of(c->cap);
   a.ovf_log2 = c->ovf_log2;
   a.ovf_limit = (uint32_t)std::min<uint64_t>(on / 2, 0xFFFFFFFFull);
   a.b1 = c->b1.as<uint32_t>();
@@ -1054,7 +1054,7 @@ void host_probe(const kc_ctx* c, const SpillRec& rec, uint64_t x, uint32_t* out)
   uint64_t slot = ((th >> 32) * cap) >> 32;
   const uint64_t* keys = c->spill_keys + rec.host_offset;
   const uint32_t* counts = c->spill_counts + rec.host_offset * nc;
-  for (uint64_t n = 0; n < cap; ++n) {
+  for (uint64_t n = 0, limit = probe_limit_of(cap); n < limit; ++n) {
     const uint64_t k = keys[slot];
     if (k == x) {
       for (uint32_t t = 0; t < nc; ++t) out[t] = counts[slot * nc + t];
@@ -1084,6 +1084,7 @@ kc_status kc_query(kc_ctx* c, const uint64_t* kmers, uint64_t n, uint32_t* count
   QueryArgs a{};
   a.hc = c->hc;
   a.cap = c->cap;
+  a.probe_limit = probe_limit_of(c->cap);
   a.tkeys = c->tkeys.as<uint64_t>();
   a.tcounts = c->tcounts.as<uint32_t>();
   a.slot_of = c->slot_of.as<uint32_t>();
@@ -1162,6 +1163,7 @@ kc_status kc_filter_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offse
   QueryArgs a{};
   a.hc = c->hc;
   a.cap = c->cap;
+  a.probe_limit = probe_limit_of(c->cap);
   a.tkeys = c->tkeys.as<uint64_t>();
   a.tcounts = c->tcounts.as<uint32_t>();
   a.slot_of = c->slot_of.as<uint32_t>();
