@@ -844,21 +844,25 @@ __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint
 // In-block bit positions of S(x): a + i*b mod 2^bl for i < H, with a and b
 // the top two bl-bit fields of mix64(x ^ s_1) (double hashing: one hash for
 // all H positions).  dup[i] marks a position equal to an earlier one (S(x) is
-// a set: one hit per occurrence per distinct bit).
+// a set: one hit per occurrence per distinct bit).  Position i equals
+// position j < i exactly when 2^bl divides (i - j) * b; the largest power of
+// two among 1..i is 2^floor(log2 i), so position i repeats an earlier one
+// exactly when b has at least bl - floor(log2 i) trailing zero bits (all of
+// them when b = 0).
 template <int H>
 __device__ __forceinline__ void bloom_positions(const HashCfg& hc, uint64_t x, uint32_t pos[H],
                                                 bool dup[H]) {
+  static_assert(H >= 1 && H <= 8, "bloom_positions: 1..8 hashes");
   const uint64_t u = mix64(x ^ hc.salt[1]);
   const uint32_t mask = (1u << hc.bl) - 1u;
   const uint32_t a = (uint32_t)(u >> (64 - hc.bl));
   const uint32_t b = (uint32_t)(u >> (64 - 2 * hc.bl)) & mask;
+  const uint32_t tz = b ? (uint32_t)__builtin_ctz(b) : 32u;
 #pragma unroll
   for (int i = 0; i < H; ++i) {
     pos[i] = (a + (uint32_t)i * b) & mask;
-    bool d = false;
-#pragma unroll
-    for (int j = 0; j < i; ++j) d |= pos[j] == pos[i];
-    dup[i] = d;
+    const uint32_t lg = i >= 4 ? 2u : i >= 2 ? 1u : 0u;  // floor(log2 i) for 1 <= i < 8
+    dup[i] = i > 0 && tz + lg >= hc.bl;
   }
 }
 
