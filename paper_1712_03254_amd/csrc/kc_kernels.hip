@@ -908,8 +908,10 @@ __device__ void overflow_add(const CountArgs& A, uint64_t x, uint32_t tag, uint6
 // each distinct bit of S(x) once; level 1 records a first hit of a bit, level
 // 2 a second one) and written out with their popcounts.  Eight waves per
 // SIMD (at most 64 VGPRs): with blocks of up to 2^18 bits two workgroups then
-// share a CU.
-template <int H>
+// share a CU.  FLAT picks the walk over the block's runs: the flattened one
+// when a block holds one or two partitions, whose runs in a second-level tile
+// are short; run by run otherwise.
+template <int H, bool FLAT>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8)))
 k_bloom(const CountArgs A) {
   extern __shared__ uint32_t lds[];
@@ -921,10 +923,12 @@ k_bloom(const CountArgs A) {
   uint32_t* L1 = lds + A.l2w;
   for (uint32_t i = threadIdx.x; i < A.l2w + nbw; i += kThreads) lds[i] = 0;
   __syncthreads();
-  for_runs<kWaves, 8, false>(A, u0, u0 + nu, [&](const uint64_t (&kv)[8], uint32_t vmask, uint32_t nbat) {
+  constexpr int NB = FLAT ? 4 : 8;  // chunks per batch (the flattened walk needs more registers)
+  for_runs<kWaves, NB, FLAT>(A, u0, u0 + nu, [&](const uint64_t (&kv)[NB], uint32_t vmask,
+                                                 uint32_t nbat) {
     constexpr int G = 2;  // keys whose level-1 updates are in flight together
 #pragma unroll
-    for (int g = 0; g < 8 / G; ++g) {
+    for (int g = 0; g < NB / G; ++g) {
       if (g * G >= (int)nbat) break;
       uint32_t pos[G][H], old[G][H];
       bool dup[G][H];
@@ -1665,9 +1669,16 @@ hipError_t launch_level2(const uint64_t* keys1, const uint64_t* off1, const uint
 
 template <int H>
 hipError_t launch_bloom_h(const CountArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(k_bloom<H>));
+  // a block holding at most two partitions has short runs: flattened walk
+  const bool flat = a.upb_log2 <= 1;
+  const void* fn = flat ? reinterpret_cast<const void*>(k_bloom<H, true>)
+                        : reinterpret_cast<const void*>(k_bloom<H, false>);
+  hipError_t e = allow_lds(fn);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bloom<H>, dim3(blocks), dim3(kThreads), lds, s, a);
+  if (flat)
+    hipLaunchKernelGGL((k_bloom<H, true>), dim3(blocks), dim3(kThreads), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_bloom<H, false>), dim3(blocks), dim3(kThreads), lds, s, a);
   return hipGetLastError();
 }
 
