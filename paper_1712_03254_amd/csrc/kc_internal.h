@@ -81,6 +81,7 @@ struct CountArgs {
   const SegDesc* segs;
   uint32_t nsegs;
   uint32_t upb_log2;     // partitions per Bloom block (log2)
+  uint32_t bsub_log2;    // Bloom blocks per k_bloom workgroup (log2)
   uint32_t part_base;    // k_tally: first partition of this launch
   uint32_t part_n;       // k_tally: partitions in this launch (= grid size)
   uint32_t slot_base;    // k_tally: table slot of partition part_base

@@ -687,6 +687,7 @@ template <int B>
 struct RunBatch {
   uint64_t kv[B];
   uint32_t vmask;  // bit b: kv[b] holds a key for this lane
+  uint32_t sub;    // bits 2b..2b+1: sub-range of kv[b] (SUBL > 0)
   uint32_t n;      // chunks in the batch (wave-uniform)
 };
 
@@ -700,9 +701,18 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
   return v;
 }
 
-template <int NW, int B, bool FLAT, typename F>
+//
+// SUBL > 0 (run-by-run walk only): the range is 2^SUBL sub-ranges of
+// sub_span partitions each, all in one first-level bucket, and fn receives
+// with each key the sub-range it belongs to (bits 2b..2b+1 of `sub` for
+// kv[b]), found from the sub-bucket starts of the key's tile.
+template <int NW, int B, bool FLAT, int SUBL = 0, typename F>
 __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint32_t u_hi,
-                                         F&& fn) {
+                                         uint32_t sub_span, F&& fn) {
+  static_assert(!(FLAT && SUBL), "sub-ranges need the run-by-run walk");
+  static_assert(SUBL >= 0 && SUBL <= 2 && 2 * B <= 32, "sub-range bits");
+  constexpr int NQ = (1 << SUBL) - 1;  // sub-range starts inside the range
+  constexpr int NQA = NQ > 0 ? NQ : 1;
   const auto segs = cview(A.segs);
   for (uint32_t s = 0; s < A.nsegs; ++s) {
     const uint32_t a2 = segs[s].a2;
@@ -723,10 +733,15 @@ __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint
         const uint32_t nj = min(64u, (nt - tw + NW - 1) / NW);
         const uint32_t ti = tw + NW * lane_id();
         uint32_t mm0 = 0, mm1 = 0;
+        uint32_t mq[NQA];  // lane j: tile-relative starts of sub-ranges 1..NQ
+#pragma unroll
+        for (int q = 0; q < NQA; ++q) mq[q] = 0;
         if (lane_id() < nj) {
           const auto m = meta2 + (uint64_t)(t0 + ti) * (nb2 + 1);
           mm0 = m[s_lo];
           mm1 = m[s_hi];
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) mq[q] = m[s_lo + (q + 1) * sub_span];
         }
         // Next B chunks of the walk, their loads issued.  The B loads are
         // issued unconditionally, after the bookkeeping, so that the compiler
@@ -735,6 +750,9 @@ __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint
         // it has a tile) and are masked off in vmask.
         uint32_t j = 0;
         uint32_t i = __builtin_amdgcn_readlane(mm0, 0), e = __builtin_amdgcn_readlane(mm1, 0);
+        uint32_t bq[NQA];  // sub-range starts of tile j (wave-uniform)
+#pragma unroll
+        for (int q = 0; q < NQA; ++q) bq[q] = NQ ? __builtin_amdgcn_readlane(mq[q], 0) : 0u;
         // FLAT: lane j's run starts at position excl of the concatenation
         // (lanes past nj hold the total, which no position reaches)
         const uint32_t len = mm1 - mm0;
@@ -745,6 +763,7 @@ __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint
         auto next_flat = [&](RunBatch<B>& r) {
           uint32_t off[B];
           r.vmask = 0;
+          r.sub = 0;
           r.n = v0 < total ? min((uint32_t)B, (total - v0 + 63) >> 6) : 0u;
 #pragma unroll
           for (int b = 0; b < B; ++b) {
@@ -794,6 +813,7 @@ __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint
           uint32_t off[B];
           r.n = 0;
           r.vmask = 0;
+          r.sub = 0;
 #pragma unroll
           for (int b = 0; b < B; ++b) {
             while (j < nj && i >= e) {
@@ -801,6 +821,8 @@ __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint
               if (j < nj) {
                 i = __builtin_amdgcn_readlane(mm0, j);
                 e = __builtin_amdgcn_readlane(mm1, j);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) bq[q] = __builtin_amdgcn_readlane(mq[q], j);
               }
             }
             off[b] = 0;
@@ -809,6 +831,10 @@ __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint
               const bool ok = idx < e;
               off[b] = ok ? (tw + NW * j) * kT2 + idx : 0u;
               r.vmask |= (uint32_t)ok << b;
+              uint32_t sb = 0;
+#pragma unroll
+              for (int q = 0; q < NQ; ++q) sb += idx >= bq[q] ? 1u : 0u;
+              r.sub |= sb << (2 * b);
               i += 64;
               r.n = b + 1;
             }
@@ -828,10 +854,10 @@ __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint
         next(x);
         while (x.n) {
           next(y);
-          fn(x.kv, x.vmask, x.n);
+          fn(x.kv, x.vmask, x.n, x.sub);
           if (!y.n) break;
           next(x);
-          fn(y.kv, y.vmask, y.n);
+          fn(y.kv, y.vmask, y.n, y.sub);
         }
         // The last batch's (masked) loads land here, once per group of
         // tiles, instead of at the loop head on every pass.
@@ -908,33 +934,40 @@ __device__ void overflow_add(const CountArgs& A, uint64_t x, uint32_t tag, uint6
 // each distinct bit of S(x) once; level 1 records a first hit of a bit, level
 // 2 a second one) and written out with their popcounts.  Eight waves per
 // SIMD (at most 64 VGPRs): with blocks of up to 2^18 bits two workgroups then
-// share a CU.  FLAT picks the walk over the block's runs: the flattened one
-// when a block holds one or two partitions, whose runs in a second-level tile
-// are short; run by run otherwise.
-template <int H, bool FLAT>
+// share a CU.  A workgroup takes 2^SUBL consecutive blocks (blocks smaller
+// than 2^18 bits, so that its LDS and its runs are those of one larger
+// block); each key's block is its sub-range in the walk.  FLAT picks the walk
+// over the runs: the flattened one when the workgroup's blocks hold one or two
+// partitions, whose runs in a second-level tile are short; run by run
+// otherwise.
+template <int H, bool FLAT, int SUBL>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8)))
 k_bloom(const CountArgs A) {
   extern __shared__ uint32_t lds[];
   const HashCfg& hc = A.hc;
-  const uint32_t blk = blockIdx.x;
-  const uint32_t nbw = A.nbw;
-  const uint32_t u0 = blk << A.upb_log2, nu = 1u << A.upb_log2;
+  const uint32_t blk = blockIdx.x << SUBL;  // first block of the workgroup
+  const uint32_t nbw = A.nbw << SUBL;      // words per level, all its blocks
+  const uint32_t span = 1u << A.upb_log2;  // partitions per block
+  const uint32_t u0 = blk << A.upb_log2, nu = span << SUBL;
   uint32_t* L2 = lds;
   uint32_t* L1 = lds + A.l2w;
   for (uint32_t i = threadIdx.x; i < A.l2w + nbw; i += kThreads) lds[i] = 0;
   __syncthreads();
-  constexpr int NB = FLAT ? 4 : 8;  // chunks per batch (the flattened walk needs more registers)
-  for_runs<kWaves, NB, FLAT>(A, u0, u0 + nu, [&](const uint64_t (&kv)[NB], uint32_t vmask,
-                                                 uint32_t nbat) {
+  const uint32_t sub_sh = SUBL ? hc.bl - 5 : 0u;  // words per block (log2)
+  constexpr int NB = FLAT || SUBL ? 4 : 8;  // chunks per batch (within 64 VGPRs)
+  for_runs<kWaves, NB, FLAT, SUBL>(A, u0, u0 + nu, span, [&](const uint64_t (&kv)[NB],
+                                                               uint32_t vmask, uint32_t nbat,
+                                                               uint32_t sub) {
     constexpr int G = 2;  // keys whose level-1 updates are in flight together
 #pragma unroll
     for (int g = 0; g < NB / G; ++g) {
       if (g * G >= (int)nbat) break;
-      uint32_t pos[G][H], old[G][H];
+      uint32_t pos[G][H], old[G][H], w0[G];
       bool dup[G][H];
 #pragma unroll
       for (int q = 0; q < G; ++q) {
         bloom_positions<H>(hc, kv[g * G + q] & kKeyMask, pos[q], dup[q]);
+        w0[q] = SUBL ? ((sub >> (2 * (g * G + q))) & 3u) << sub_sh : 0u;  // the key's block
 #pragma unroll
         for (int i = 0; i < H; ++i) dup[q][i] |= !((vmask >> (g * G + q)) & 1u);
       }
@@ -942,13 +975,14 @@ k_bloom(const CountArgs A) {
       for (int q = 0; q < G; ++q)
 #pragma unroll
         for (int i = 0; i < H; ++i)
-          old[q][i] = dup[q][i] ? 0u : atomicOr(&L1[pos[q][i] >> 5], 1u << (pos[q][i] & 31));
+          old[q][i] = dup[q][i] ? 0u
+                                : atomicOr(&L1[w0[q] + (pos[q][i] >> 5)], 1u << (pos[q][i] & 31));
 #pragma unroll
       for (int q = 0; q < G; ++q)
 #pragma unroll
         for (int i = 0; i < H; ++i) {
           const uint32_t bit = 1u << (pos[q][i] & 31);
-          if (old[q][i] & bit) atomicOr(&L2[pos[q][i] >> 5], bit);
+          if (old[q][i] & bit) atomicOr(&L2[w0[q] + (pos[q][i] >> 5)], bit);
         }
     }
   });
@@ -957,8 +991,8 @@ k_bloom(const CountArgs A) {
   if (hc.bl >= 5) {
     for (uint32_t i = threadIdx.x; i < nbw; i += kThreads) {
       const uint32_t a = L1[i], b = L2[i];
-      A.b1[(uint64_t)blk * nbw + i] = a;
-      A.b2[(uint64_t)blk * nbw + i] = b;
+      A.b1[(uint64_t)blk * A.nbw + i] = a;
+      A.b2[(uint64_t)blk * A.nbw + i] = b;
       p1 += __popc(a);
       p2 += __popc(b);
     }
@@ -980,11 +1014,12 @@ k_bloom(const CountArgs A) {
     red[wave_id() * 2 + 1] = p2;
   }
   __syncthreads();
+  // one statistics row per workgroup
   if (threadIdx.x < kNst) {
     uint64_t v = 0;
     if (threadIdx.x == ST_B1POP || threadIdx.x == ST_B2POP)
       for (int w = 0; w < kWaves; ++w) v += red[w * 2 + (threadIdx.x == ST_B2POP)];
-    A.pstats[(uint64_t)blk * kNst + threadIdx.x] = v;
+    A.pstats[(uint64_t)blockIdx.x * kNst + threadIdx.x] = v;
   }
 }
 
@@ -1118,8 +1153,8 @@ k_tally(const CountArgs A) {
 
   uint32_t qn = 0;  // wave-uniform queue length
   constexpr int B2 = 2;
-  for_runs<kTallyWaves, B2, true>(A, u, u + 1, [&](const uint64_t (&kv)[B2], uint32_t vmask,
-                                                  uint32_t nbat) {
+  for_runs<kTallyWaves, B2, true>(A, u, u + 1, 1, [&](const uint64_t (&kv)[B2], uint32_t vmask,
+                                                     uint32_t nbat, uint32_t /*sub*/) {
     // One probe at the home slot per occurrence: a hit counts at once; any
     // other outcome (a new key, or a key further along its chain) is queued.
     uint64_t cur[B2];
@@ -1667,19 +1702,26 @@ hipError_t launch_level2(const uint64_t* keys1, const uint64_t* off1, const uint
   return hipGetLastError();
 }
 
+template <int H, bool FLAT, int SUBL>
+hipError_t launch_bloom_v(const CountArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(k_bloom<H, FLAT, SUBL>));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_bloom<H, FLAT, SUBL>), dim3(blocks >> SUBL), dim3(kThreads), lds, s, a);
+  return hipGetLastError();
+}
+
 template <int H>
 hipError_t launch_bloom_h(const CountArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
-  // a block holding at most two partitions has short runs: flattened walk
-  const bool flat = a.upb_log2 <= 1;
-  const void* fn = flat ? reinterpret_cast<const void*>(k_bloom<H, true>)
-                        : reinterpret_cast<const void*>(k_bloom<H, false>);
-  hipError_t e = allow_lds(fn);
-  if (e != hipSuccess) return e;
-  if (flat)
-    hipLaunchKernelGGL((k_bloom<H, true>), dim3(blocks), dim3(kThreads), lds, s, a);
-  else
-    hipLaunchKernelGGL((k_bloom<H, false>), dim3(blocks), dim3(kThreads), lds, s, a);
-  return hipGetLastError();
+  // 2^bsub_log2 blocks per workgroup (their partitions lie in one first-level
+  // bucket); the flattened walk when a workgroup's blocks hold at most two
+  // partitions
+  switch (a.bsub_log2) {
+    case 1: return launch_bloom_v<H, false, 1>(a, blocks, lds, s);
+    case 2: return launch_bloom_v<H, false, 2>(a, blocks, lds, s);
+    default:
+      return a.upb_log2 <= 1 ? launch_bloom_v<H, true, 0>(a, blocks, lds, s)
+                             : launch_bloom_v<H, false, 0>(a, blocks, lds, s);
+  }
 }
 
 template <int H>

@@ -189,7 +189,7 @@ struct kc_ctx {
 
   // derived layout
   HashCfg hc{};
-  uint32_t s_log2 = 0, p_log2 = 0, cap = 0, a1 = 0, a2 = 0, upb_log2 = 0;
+  uint32_t s_log2 = 0, p_log2 = 0, cap = 0, a1 = 0, a2 = 0, upb_log2 = 0, bsub_log2 = 0;
   uint32_t nbw = 1, l2w = 2, slot_bytes = 12;
   size_t count_lds = 0, tally_lds = 0;
   uint64_t bloom_words64 = 1;
@@ -356,7 +356,6 @@ kc_status derive(kc_ctx* c) {
   hc.s_log2 = c->s_log2;
   hc.p_log2 = c->p_log2;
   c->nbw = f.bloom_block_log2 >= 5 ? (1u << (f.bloom_block_log2 - 5)) : 1u;
-  c->l2w = (c->nbw + 1) & ~1u;
   c->slot_bytes = 8 + 4 * f.n_counters;
   // k_bloom: the block's two levels in LDS.  k_tally: a partition table (cap
   // slots) plus per-wave miss queues; by default three workgroups fit a CU,
@@ -374,17 +373,29 @@ kc_status derive(kc_ctx* c) {
   } else {
     c->cap = cap_def;
   }
-  c->count_lds = std::max((size_t)4 * (c->l2w + c->nbw), (size_t)kWaves * 2 * 8);
-  c->tally_lds = std::max((size_t)c->cap * c->slot_bytes + kQueueBytes,
-                          (size_t)kTallyWaves * kNst * 8);
-  if (c->count_lds > (size_t)kLdsMax || c->tally_lds > (size_t)kLdsMax)
-    return fail(c, KC_ERR_INVALID_ARG, "LDS layout too large");
   // two shuffle levels: a1 bits in the first, the rest in the second
   c->a1 = f.scatter_bits ? std::min<uint32_t>(f.scatter_bits, c->p_log2 - 1)
                          : std::min<uint32_t>(c->p_log2 / 2, kMaxA1);
   c->a2 = c->p_log2 - c->a1;
   if (c->a1 < 1 || c->a1 > (uint32_t)kMaxA1 || c->a2 < 1 || c->a2 > (uint32_t)kMaxA2)
     return fail(c, KC_ERR_INVALID_ARG, "partition count needs a wider shuffle (set scatter_bits)");
+  // k_bloom takes up to four Bloom blocks smaller than 2^18 bits per
+  // workgroup (the LDS and run lengths of one 2^18-bit block), as long as
+  // their partitions lie in one first-level bucket
+  c->bsub_log2 = 0;
+  if (f.bloom_block_log2 >= 5 && f.bloom_block_log2 < 18) {
+    uint32_t bs = std::min<uint32_t>(2, 18 - f.bloom_block_log2);
+    bs = std::min<uint32_t>(bs, c->s_log2);
+    bs = c->a2 >= c->upb_log2 ? std::min<uint32_t>(bs, c->a2 - c->upb_log2) : 0u;
+    c->bsub_log2 = bs;
+  }
+  const uint32_t wg_words = c->nbw << c->bsub_log2;  // words per level in one k_bloom workgroup
+  c->l2w = (wg_words + 1) & ~1u;
+  c->count_lds = std::max((size_t)4 * (c->l2w + wg_words), (size_t)kWaves * 2 * 8);
+  c->tally_lds = std::max((size_t)c->cap * c->slot_bytes + kQueueBytes,
+                          (size_t)kTallyWaves * kNst * 8);
+  if (c->count_lds > (size_t)kLdsMax || c->tally_lds > (size_t)kLdsMax)
+    return fail(c, KC_ERR_INVALID_ARG, "LDS layout too large");
   c->bloom_words64 = f.bloom_bits_log2 >= 6 ? (1ull << (f.bloom_bits_log2 - 6)) : 1ull;
   return KC_OK;
 }
@@ -501,6 +512,7 @@ CountArgs count_args(kc_ctx* c, uint32_t nsegs) {
   a.upb_log2 = c->upb_log2;
   a.nbw = c->nbw;
   a.l2w = c->l2w;
+  a.bsub_log2 = c->bsub_log2;
   a.cap = c->cap;
   a.probe_limit = probe_limit_of(c->cap);
   a.ovf_log2 = c->ovf_log2;
@@ -992,7 +1004,8 @@ kc_status kc_finalize(kc_ctx* c, void* hip_stream, kc_stats* out) {
     {
       StageTimer t(c, s, KC_T_UNIFY);
       KC_HIP(c, launch_ovf_emit(a, c->pstats_ovf.as<uint64_t>(), oblocks, s), "overflow pass");
-      KC_HIP(c, launch_reduce(c->pstats.as<uint64_t>(), 1ull << c->s_log2, c->dstat.as<uint64_t>(), s),
+      KC_HIP(c, launch_reduce(c->pstats.as<uint64_t>(), (1ull << c->s_log2) >> c->bsub_log2,
+                              c->dstat.as<uint64_t>(), s),
              "reduce");
       KC_HIP(c, launch_reduce(c->pstats_ovf.as<uint64_t>(), oblocks, c->dstat.as<uint64_t>() + kNst, s),
              "reduce");
@@ -1894,7 +1907,8 @@ kc_status build_batch(kc_ctx* c, const kc_chunk* ch, uint32_t n, uint32_t counte
     KC_REC(launch_bloom(a, 1u << c->s_log2, c->count_lds, cs));
     KC_REC(launch_tally(a, (uint32_t)nparts, c->tally_lds, cs));
     KC_REC(launch_ovf_emit(a, c->pstats_ovf.as<uint64_t>(), oblocks, cs));
-    KC_REC(launch_reduce(c->pstats.as<uint64_t>(), 1ull << c->s_log2, c->dstat.as<uint64_t>(), cs));
+    KC_REC(launch_reduce(c->pstats.as<uint64_t>(), (1ull << c->s_log2) >> c->bsub_log2,
+                         c->dstat.as<uint64_t>(), cs));
     KC_REC(launch_reduce(c->pstats_ovf.as<uint64_t>(), oblocks, c->dstat.as<uint64_t>() + kNst, cs));
     KC_REC(launch_reduce(c->pstats2.as<uint64_t>(), nparts, c->dstat.as<uint64_t>() + 2 * kNst, cs));
     KC_REC(launch_slot_map(c->slot_of.as<uint32_t>(), (uint32_t)nparts, 0, cs));
