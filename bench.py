@@ -110,7 +110,10 @@ def atomic_summary(w, st: dict, stages: dict) -> dict:
     occurrence (the second-level ORs for bits already set are not counted);
     k_tally one add per passing occurrence and one CAS per inserted key."""
     from paper_1712_03254_amd import probe
-    bloom_words_log2 = max(6, min(15, w.bloom_block_log2 - 5))
+    # one Bloom workgroup's level: up to four blocks smaller than 2^18 bits
+    bl = w.bloom_block_log2
+    bsub = min(2, 18 - bl) if 5 <= bl < 18 else 0
+    bloom_words_log2 = max(6, min(15, bl - 5 + bsub))
     table_words_log2 = 12  # the count words of a ~3840-slot table
     peak_or = probe.lds_atomic_peak(probe.KCP_OR_RTN, bloom_words_log2)
     peak_add = probe.lds_atomic_peak(probe.KCP_ADD, table_words_log2)
@@ -388,7 +391,8 @@ def served_main(args, w):
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": w.name, "genome_bp": w.genome_len, "reads_per_sample": w.n_reads,
                    "read_len": L, "requests": len(timed), "request_reads": [w.req_lo, w.req_hi],
-                   "k": w.k, "bloom_hashes": w.bloom_hashes, "n_counters": 2,
+                   "k": w.k, "bloom_hashes": w.bloom_hashes,
+                   "bloom_block_log2": w.bloom_block_log2, "n_counters": 2,
                    "hbm_budget_bytes": budget, "workers": args.serve_workers,
                    "overlap_bases": overlap,
                    "mean_request_kmers": mean_kmers},

@@ -205,19 +205,22 @@ class Workload:
 # The five workloads.  Partition counts are result-neutral; the value here is
 # the one the GPU path runs with (each partition's table lives in LDS, so the
 # count is set from the expected distinct k-mers per Bloom block).  Bloom
-# blocks are 2^18 bits: two levels of one block (64 KiB) let two Bloom
-# workgroups share a CU.
+# blocks are 2^16 bits where the partitions allow it: a Bloom workgroup takes
+# four such blocks (64 KiB of LDS for both levels, two workgroups per CU), and
+# the count kernel screens against an 8 KiB level that stays in the CU's cache.
+# The batched workload keeps 2^18-bit blocks: at 2^35 bits, 2^16-bit blocks
+# would force 2^19 partitions, past the autotuner's choice.
 WORKLOADS = {
     "plain_1mbp": Workload("plain_1mbp", 1, 1_000_000, 20_000, 100, 100, 0.01, 0.0,
-                           31, 24, 3, 18, 8),
+                           31, 24, 3, 16, 8),
     "plain_100mbp": Workload("plain_100mbp", 2, 100_000_000, 10_000_000, 100, 100, 0.005, 0.001,
-                             31, 32, 4, 18, 16),
+                             31, 32, 4, 16, 16),
     "batched_200mbp": Workload("batched_200mbp", 3, 200_000_000, 0, 100, 250, 0.005, 0.0,
                                31, 35, 4, 18, 19, batch_chunks=256, chunk_lo=1e3, chunk_hi=2e6),
     "served_300mbp": Workload("served_300mbp", 4, 300_000_000, 30_000_000, 100, 100, 0.005, 0.0,
-                              31, 32, 4, 18, 16, n_counters=2, requests=512, warmup_requests=32,
+                              31, 32, 4, 16, 16, n_counters=2, requests=512, warmup_requests=32,
                               req_lo=1e4, req_hi=5e6, snv_rate=0.001, n_inv=200, inv_lo=1000,
                               inv_hi=10000, serve_budget=32 << 30),
     "spill_3gbp": Workload("spill_3gbp", 5, 3_000_000_000, 200_000_000, 100, 100, 0.01, 0.0,
-                           31, 36, 4, 18, 20, table_budget=64 << 30),
+                           31, 36, 4, 16, 20, table_budget=64 << 30),
 }
