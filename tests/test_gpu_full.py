@@ -100,7 +100,7 @@ def test_plain_100mbp_sampled_parity():
 
 
 def test_plain_100mbp_most_keys_in_the_overflow_table():
-    """The same workload with 2^14 partition tables of 1024 slots (1.7·10^7
+    """The same workload with 2^17 partition tables of 128 slots (1.7·10^7
     slots in all): about 8·10^7 of the 9.8·10^7 counted keys do not fit and go
     to the overflow table, which finalize grows more than once.  Partitioning
     and table size change no result: statistics, exported table and queries
@@ -108,11 +108,11 @@ def test_plain_100mbp_most_keys_in_the_overflow_table():
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    note("case: plain_100mbp full size, 2^14 partitions of 1024 slots (overflow-heavy) "
+    note("case: plain_100mbp full size, 2^17 partitions of 128 slots (overflow-heavy) "
          "against 2^16 partitions of 3840")
     w, _, b, o = workload_chunks("plain_100mbp")
     base = workload_config(w)
-    heavy = workload_config(w, partitions_log2=14, table_slots=1024)
+    heavy = workload_config(w, partitions_log2=17, table_slots=128)
     db, do = to_device(b, o)
     rng = np.random.default_rng(77)
     out = []
