@@ -1275,11 +1275,15 @@ __global__ void __launch_bounds__(256) k_ovf_emit(const CountArgs A, uint64_t* p
   }
 }
 
+// Column sums of nrows statistics rows into out[kNst] (zeroed before): each
+// workgroup sums a grid-stride share of the rows and adds its sums to out
+// with integer atomics, so the result does not depend on the order.
 __global__ void __launch_bounds__(kThreads) k_reduce(const uint64_t* __restrict__ rows,
                                                      uint64_t nrows, uint64_t* __restrict__ out) {
   __shared__ uint64_t red[kWaves * kNst];
   uint64_t st[kNst] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (uint64_t r = threadIdx.x; r < nrows; r += kThreads)
+  for (uint64_t r = (uint64_t)blockIdx.x * kThreads + threadIdx.x; r < nrows;
+       r += (uint64_t)gridDim.x * kThreads)
 #pragma unroll
     for (int i = 0; i < kNst; ++i) st[i] += rows[r * kNst + i];
 #pragma unroll
@@ -1291,7 +1295,7 @@ __global__ void __launch_bounds__(kThreads) k_reduce(const uint64_t* __restrict_
   if (threadIdx.x < kNst) {
     uint64_t s = 0;
     for (int w = 0; w < kWaves; ++w) s += red[w * kNst + threadIdx.x];
-    out[threadIdx.x] = s;
+    if (s) atomicAdd(reinterpret_cast<unsigned long long*>(&out[threadIdx.x]), (unsigned long long)s);
   }
 }
 
@@ -1762,7 +1766,9 @@ hipError_t launch_ovf_emit(const CountArgs& a, uint64_t* pstats_ovf, uint32_t bl
 }
 
 hipError_t launch_reduce(const uint64_t* rows, uint64_t nrows, uint64_t* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, s, rows, nrows, out);
+  hipLaunchKernelGGL(k_fill64, dim3(1), dim3(256), 0, s, out, (uint64_t)kNst, (uint64_t)0);
+  const uint64_t grid = std::min<uint64_t>(256, std::max<uint64_t>(1, div_up(nrows, (uint64_t)kThreads * 4)));
+  hipLaunchKernelGGL(k_reduce, dim3((uint32_t)grid), dim3(kThreads), 0, s, rows, nrows, out);
   return hipGetLastError();
 }
 
