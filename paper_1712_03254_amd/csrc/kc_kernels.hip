@@ -664,7 +664,7 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
 
 // ----------------------------------------- per-block Bloom + exact count
 
-// Calls fn(kv, vmask, nbat) for the stored occurrences of partitions
+// Calls fn(kv, vmask, nbat, sub) for the stored occurrences of partitions
 // [u_lo, u_hi), across segments: kv[b] holds one key per lane for b < nbat,
 // valid where bit b of the lane's vmask is set.  Every lane of a wave reaches
 // every call.  The whole block must call it.  The range's run inside a
@@ -680,6 +680,11 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
 // touch a chunk, and each lane steps through the few run starts inside it
 // (scalar reads), or binary-searches the sums when a chunk holds many runs:
 // right for short runs, where partly empty chunks would dominate.
+//
+// SUBL > 0 (run-by-run walk only): the range is 2^SUBL sub-ranges of
+// sub_span partitions each, all in one first-level bucket, and bits
+// 2b..2b+1 of `sub` give the sub-range of kv[b], found from the sub-bucket
+// starts of the key's tile.  With SUBL = 0, sub is 0.
 // s_waitcnt immediate (gfx9 encoding): vmcnt 0, expcnt and lgkmcnt unbounded.
 constexpr int kWaitVm0 = 0x0F70;
 
@@ -701,11 +706,6 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
   return v;
 }
 
-//
-// SUBL > 0 (run-by-run walk only): the range is 2^SUBL sub-ranges of
-// sub_span partitions each, all in one first-level bucket, and fn receives
-// with each key the sub-range it belongs to (bits 2b..2b+1 of `sub` for
-// kv[b]), found from the sub-bucket starts of the key's tile.
 template <int NW, int B, bool FLAT, int SUBL = 0, typename F>
 __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint32_t u_hi,
                                          uint32_t sub_span, F&& fn) {
