@@ -1424,39 +1424,58 @@ __global__ void __launch_bounds__(256) k_filter_reads(const uint64_t* __restrict
   out[r] = n;
 }
 
-// Entries with a nonzero count, wave-aggregated append (no particular order).
-__global__ void __launch_bounds__(256) k_export(const uint64_t* __restrict__ tkeys,
-                                                const uint32_t* __restrict__ tcounts,
-                                                uint64_t nslots,
-                                                const uint32_t* __restrict__ live,
-                                                uint32_t cap, uint32_t nc,
-                                                uint64_t* __restrict__ out_keys,
-                                                uint32_t* __restrict__ out_counts,
-                                                uint64_t out_cap,
-                                                uint64_t* __restrict__ cursor) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool take = false;
-  uint64_t key = 0;
-  uint32_t c0 = 0, c1 = 0;
-  if (i < nslots && (live == nullptr || live[i / cap])) {
-    key = tkeys[i];
-    c0 = tcounts[i * nc];
-    c1 = nc > 1 ? tcounts[i * nc + 1] : 0;
-    take = key != kEmpty && (c0 | c1) != 0;
-  }
-  const uint64_t bal = __ballot(take);
-  if (!bal) return;
-  uint64_t base = 0;
-  if (lane_id() == (uint32_t)(__ffsll((unsigned long long)bal) - 1))
-    base = atomicAdd(reinterpret_cast<unsigned long long*>(cursor),
-                     (unsigned long long)__popcll(bal));
-  base = __shfl(base, __ffsll((unsigned long long)bal) - 1, 64);
-  if (take) {
-    const uint64_t at = base + __popcll(bal & ((1ull << lane_id()) - 1));
-    if (at >= out_cap) return;  // the cursor still counts it: the host sees the mismatch
-    out_keys[at] = key;
-    out_counts[at * nc] = c0;
-    if (nc > 1) out_counts[at * nc + 1] = c1;
+// Entries with a nonzero count, appended in no particular order.  Each
+// workgroup walks chunks of kThreads slots (grid-stride) and reserves room for
+// a chunk's entries with one atomic on the shared cursor: one atomic per
+// kThreads slots, not per wave, keeps the cursor from serialising the pass.
+__global__ void __launch_bounds__(kThreads) k_export(const uint64_t* __restrict__ tkeys,
+                                                     const uint32_t* __restrict__ tcounts,
+                                                     uint64_t nslots,
+                                                     const uint32_t* __restrict__ live,
+                                                     uint32_t cap, uint32_t nc,
+                                                     uint64_t* __restrict__ out_keys,
+                                                     uint32_t* __restrict__ out_counts,
+                                                     uint64_t out_cap,
+                                                     uint64_t* __restrict__ cursor) {
+  __shared__ uint32_t wcnt[kWaves];
+  __shared__ uint64_t wgbase;
+  for (uint64_t c0i = (uint64_t)blockIdx.x * kThreads; c0i < nslots;
+       c0i += (uint64_t)gridDim.x * kThreads) {
+    const uint64_t i = c0i + threadIdx.x;
+    bool take = false;
+    uint64_t key = 0;
+    uint32_t c0 = 0, c1 = 0;
+    if (i < nslots && (live == nullptr || live[i / cap])) {
+      key = tkeys[i];
+      c0 = tcounts[i * nc];
+      c1 = nc > 1 ? tcounts[i * nc + 1] : 0;
+      take = key != kEmpty && (c0 | c1) != 0;
+    }
+    const uint64_t bal = __ballot(take);
+    if (lane_id() == 0) wcnt[wave_id()] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t tot = 0;
+      for (int w = 0; w < kWaves; ++w) {
+        const uint32_t c = wcnt[w];
+        wcnt[w] = tot;  // exclusive prefix over the waves
+        tot += c;
+      }
+      wgbase = tot ? atomicAdd(reinterpret_cast<unsigned long long*>(cursor),
+                               (unsigned long long)tot)
+                   : 0;
+    }
+    __syncthreads();
+    if (take) {
+      const uint64_t at =
+          wgbase + wcnt[wave_id()] + __popcll(bal & ((1ull << lane_id()) - 1));
+      if (at < out_cap) {  // past it the cursor still counts: the host sees the mismatch
+        out_keys[at] = key;
+        out_counts[at * nc] = c0;
+        if (nc > 1) out_counts[at * nc + 1] = c1;
+      }
+    }
+    __syncthreads();  // wcnt and wgbase are reused by the next chunk
   }
 }
 
@@ -1784,7 +1803,8 @@ hipError_t launch_export(const uint64_t* tkeys, const uint32_t* tcounts, uint64_
                          uint64_t* out_keys, uint32_t* out_counts, uint64_t out_cap,
                          uint64_t* cursor, hipStream_t s) {
   if (!nslots) return hipSuccess;
-  hipLaunchKernelGGL(k_export, dim3(div_up(nslots, 256)), dim3(256), 0, s, tkeys, tcounts, nslots,
+  const uint64_t grid = std::min<uint64_t>(4096, div_up(nslots, kThreads));
+  hipLaunchKernelGGL(k_export, dim3((uint32_t)grid), dim3(kThreads), 0, s, tkeys, tcounts, nslots,
                      live, cap, nc, out_keys, out_counts, out_cap, cursor);
   return hipGetLastError();
 }
