@@ -310,14 +310,20 @@ __device__ __forceinline__ uint32_t window_mask(const WordCtx& c, uint32_t k) {
 }
 
 // Canonical key of the window ending at base j of word w, whether or not the
-// window is valid (window_mask says which are).
+// window is valid (window_mask says which are).  Both orientations are taken
+// left-aligned, the window in the top 2k bits and the bases after it below:
+// where the two codes differ their top bits decide the comparison, and where
+// they are equal either choice gives the same key, so the smaller 64-bit
+// value shifted down by 64 - 2k is min(enc(w), enc(revcomp(w))).
 __device__ __forceinline__ uint64_t window_code(const WordCtx& c, uint32_t k, int j) {
-  const uint64_t kmask = (1ull << (2 * k)) - 1;
-  const int s = 62 - 2 * j;
-  const uint64_t f = (s ? ((c.pc >> s) | (c.pp << (64 - s))) : c.pc) & kmask;
-  const int s2 = 66 + 2 * j - 2 * (int)k;  // in [4, 126]
-  const uint64_t r = (s2 >= 64 ? (c.qc >> (s2 - 64)) : ((c.qp >> s2) | (c.qc << (64 - s2)))) & kmask;
-  return f < r ? f : r;
+  // forward: bases 33+j-k.. of the (w-1, w) frame at the top
+  const int sh = 66 + 2 * j - 2 * (int)k;  // in [4, 126]
+  const uint64_t f = sh >= 64 ? c.pc << (sh - 64) : (c.pp << sh) | (c.pc >> (64 - sh));
+  // reverse complement: the (w, w-1) frame of reversed, complemented words
+  // from the complement of base 32+j on
+  const int sr = 62 - 2 * j;  // in [0, 62]
+  const uint64_t r = (c.qc << sr) | (sr == 0 ? 0ull : c.qp >> (64 - sr));
+  return (f < r ? f : r) >> (64 - 2 * k);
 }
 
 // --------------------------------------------------- first-level shuffle
