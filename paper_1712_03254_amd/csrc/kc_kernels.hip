@@ -400,15 +400,34 @@ __global__ void __launch_bounds__(kThreads) k_level1(const uint64_t* __restrict_
 // Exclusive scan u32 -> u64 in three phases over chunks of 8192 elements.
 constexpr int kScanChunk = kThreads * 8;
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+
+// A thread's 8 consecutive counts (32-byte aligned: the arrays start on
+// allocation boundaries): two 16-byte loads, or element loads at a ragged end.
+__device__ __forceinline__ void load8(const uint32_t* __restrict__ in, uint64_t base, uint64_t n,
+                                      uint32_t v[8]) {
+  if (base + 8 <= n) {
+    const u32x4 a = *reinterpret_cast<const u32x4*>(in + base);
+    const u32x4 b = *reinterpret_cast<const u32x4*>(in + base + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = base + q < n ? in[base + q] : 0u;
+  }
+}
+
 __global__ void __launch_bounds__(kThreads) k_scan_reduce(const uint32_t* __restrict__ in,
                                                           uint64_t n,
                                                           uint64_t* __restrict__ parts) {
   __shared__ uint64_t red[kWaves];
   const uint64_t base = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * 8;
+  uint32_t v[8];
+  load8(in, base, n, v);
   uint64_t s = 0;
 #pragma unroll
-  for (int q = 0; q < 8; ++q)
-    if (base + q < n) s += in[base + q];
+  for (int q = 0; q < 8; ++q) s += v[q];
   s = wave_sum(s);
   if (lane_id() == 0) red[wave_id()] = s;
   __syncthreads();
@@ -454,12 +473,10 @@ __global__ void __launch_bounds__(kThreads) k_scan_down(const uint32_t* __restri
   __shared__ uint64_t red[kWaves];
   const uint64_t base = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * 8;
   uint32_t v[8];
+  load8(in, base, n, v);
   uint64_t s = 0;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    v[q] = base + q < n ? in[base + q] : 0;
-    s += v[q];
-  }
+  for (int q = 0; q < 8; ++q) s += v[q];
   uint64_t inc = s;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -471,10 +488,20 @@ __global__ void __launch_bounds__(kThreads) k_scan_down(const uint32_t* __restri
   uint64_t run = parts[blockIdx.x];
   for (uint32_t w = 0; w < wave_id(); ++w) run += red[w];
   run += inc - s;
+  uint64_t o[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    if (base + q < n) out[base + q] = run;
+    o[q] = run;
     run += v[q];
+  }
+  if (base + 8 <= n) {  // 64-byte aligned: four 16-byte stores
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+      *reinterpret_cast<u64x2*>(out + base + 2 * h) = u64x2{o[2 * h], o[2 * h + 1]};
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (base + q < n) out[base + q] = o[q];
   }
 }
 
