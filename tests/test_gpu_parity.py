@@ -69,6 +69,8 @@ PARAMS = [
     (31, 24, 4, 10, 18, 64, 1, 2, 10),  # 2^18 partitions: runs of 0-1 keys per tile
     (31, 26, 4, 6, 20, 64, 1, 2, 12),   # 2^20 partitions: widest first level (2^10)
     (31, 27, 3, 6, 21, 64, 2, 2, 13),   # 2^21 partitions: widest second level (2^11)
+    (31, 21, 4, 17, 0, 0, 1, 2, 14),    # 2^17-bit blocks: two per Bloom workgroup
+    (25, 22, 3, 18, 5, 0, 1, 2, 15),    # blocks of two partitions, one per workgroup: flattened walk
 ]
 
 
