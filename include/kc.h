@@ -84,7 +84,9 @@ typedef struct kc_config {
   uint32_t partitions_log2;  /* hash partitions = top bits of g; raised to
                                 bloom_bits_log2 - bloom_block_log2 when lower; <= 21 */
   uint32_t table_slots;      /* slots per partition table, rounded down to a multiple of
-                                64 (>= 64); 0 = the largest that fits LDS */
+                                64 (>= 64, at most what one count workgroup's LDS holds);
+                                0 = the largest with which three count workgroups share a
+                                CU (3840 with one counter, 2880 with two) */
   uint32_t scatter_bits;     /* first-level shuffle fan-out bits; 0 = automatic */
   uint32_t group_bases_log2; /* kc_count_batch: at most 2^this bases (with padding) per key
                                 segment; 0 = 2^32 - 64, else 10..32 */
