@@ -71,6 +71,7 @@ PARAMS = [
     (31, 27, 3, 6, 21, 64, 2, 2, 13),   # 2^21 partitions: widest second level (2^11)
     (31, 21, 4, 17, 0, 0, 1, 2, 14),    # 2^17-bit blocks: two per Bloom workgroup
     (25, 22, 3, 18, 5, 0, 1, 2, 15),    # blocks of two partitions, one per workgroup: flattened walk
+    (9, 8, 3, 5, 0, 0, 1, 2, 16),       # one-word blocks, four per Bloom workgroup
 ]
 
 
@@ -135,7 +136,8 @@ def test_result_neutral_parameters():
     base = dict(k=19, bloom_bits_log2=20, bloom_hashes=3, bloom_block_log2=14, seed=12)
     runs = [run_gpu(kc.Config(**base, partitions_log2=p, table_slots=t, scatter_bits=sb),
                     [pack_reads(reads)])
-            for p, t, sb in [(0, 0, 0), (9, 0, 0), (12, 64, 0), (12, 0, 4), (6, 128, 3)]]
+            for p, t, sb in [(0, 0, 0), (9, 0, 0), (12, 64, 0), (12, 0, 4), (6, 128, 3),
+                             (9, 0, 5)]]  # last: two Bloom blocks per workgroup (bucket-limited)
     for r in runs[1:]:
         assert_same_table(r["keys"], r["counts"], runs[0]["keys"], runs[0]["counts"])
         assert np.array_equal(r["b1"], runs[0]["b1"]) and np.array_equal(r["b2"], runs[0]["b2"])
