@@ -265,8 +265,11 @@ hipEvent_t take_event(kc_ctx* c) {
     c->event_pool.pop_back();
     return e;
   }
+  // Timer events only time the stream (completion queries, elapsed times);
+  // results reach the host through copies and stream synchronisation, so the
+  // system-scope fence a default event record carries is not needed.
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
