@@ -172,7 +172,9 @@ def enumerate_keys(params: Params, bases, offsets, tags=None) -> np.ndarray:
 def bloom_bits(params: Params, x: int) -> list[int]:
     p = params.c()
     out = np.zeros(8, dtype=np.uint64)
-    n = _load().or_bloom_bits(ctypes.byref(p), x, _ptr(out, U64P))
+    n = _load().or_bloom_bits(ctypes.byref(p), x & ((1 << 64) - 1), _ptr(out, U64P))
+    if n == 0:
+        raise ValueError("oracle rejected the Bloom parameters")
     return [int(v) for v in out[:n]]
 
 

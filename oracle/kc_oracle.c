@@ -108,7 +108,10 @@ static int or_params_ok(const or_params* p) {
   if (p->n_counters < 1 || p->n_counters > 2) return 0;
   if (p->min_count < 2) return 0;
   if (p->h < 1 || p->h > 8) return 0;
-  if (p->block_log2 < 1 || p->block_log2 > p->m_log2 || p->m_log2 > 40) return 0;
+  /* a and b are the top two block_log2-bit fields of one 64-bit hash, so a
+   * block holds at most 2^32 bits */
+  if (p->block_log2 < 1 || p->block_log2 > 32 || p->block_log2 > p->m_log2 || p->m_log2 > 40)
+    return 0;
   return 1;
 }
 
@@ -301,8 +304,10 @@ or_result* or_count(const or_params* p, const uint8_t* bases, const uint64_t* of
   return res;
 }
 
-/* Bloom bit positions of one key (distinct, in hash order); returns count. */
+/* Bloom bit positions of one key (distinct, in hash order); returns count,
+ * or 0 when the parameters are out of range. */
 uint32_t or_bloom_bits(const or_params* p, uint64_t x, uint64_t* out) {
+  if (!or_params_ok(p)) return 0;
   uint64_t salt[9];
   or_salts(p, salt);
   return or_bloom_positions(p, salt, x, out);

@@ -204,6 +204,40 @@ def test_bloom_bits_match_brute():
             assert set(oracle.bloom_bits(p, x)) == brute.bloom_set(x, m_log2, h, bl, seed)
 
 
+def test_bloom_positions_hand_worked(golden):
+    """S(x) against positions worked by hand from the published SplitMix64
+    outputs (tests/golden/bloom_positions.txt): a wrong field of the hash (a
+    or b), a wrong step, a missed reduction modulo the block or a wrong block
+    prefix changes one of them."""
+    rows = golden("bloom_positions.txt")
+    assert len(rows) == 7
+    for kind, seed, key, m, bl, h, want in rows:
+        p = oracle.Params(k=31, m_log2=int(m), h=int(h), block_log2=int(bl), seed=int(seed, 16))
+        x = int(key, 16)
+        got = oracle.bloom_bits(p, x)
+        ref = brute.bloom_set(x, int(m), int(h), int(bl), int(seed, 16))
+        assert set(got) == ref
+        if kind == "positions":
+            vals = [int(v) for v in want.split(",")]
+            # distinct positions in hash order (S(x) is a set)
+            assert got == list(dict.fromkeys(vals))
+        else:
+            assert {q >> int(bl) for q in got} == {int(want)}
+
+
+def test_oracle_rejects_blocks_wider_than_half_a_hash():
+    """a and b are two block-sized fields of one 64-bit hash, so a Bloom block
+    of more than 2^32 bits has no defined positions: the oracle refuses it."""
+    import numpy as np
+    p = oracle.Params(k=5, m_log2=36, h=4, block_log2=33, seed=1)
+    with pytest.raises(ValueError):
+        oracle.bloom_bits(p, 12345)
+    with pytest.raises(ValueError):
+        oracle.count(p, np.frombuffer(b"ACGTACGTAC", np.uint8), np.array([0, 10], np.uint64))
+    ok = oracle.Params(k=5, m_log2=36, h=4, block_log2=32, seed=1)
+    assert set(oracle.bloom_bits(ok, 12345)) == brute.bloom_set(12345, 36, 4, 32, 1)
+
+
 # ---------------------------------------------------------------- invariants
 
 def _sim_reads(seed, n, L, err=0.01):
