@@ -203,6 +203,15 @@ kc_status kc_export(kc_ctx* ctx, uint64_t* keys_host, uint32_t* counts_host, uin
  * may be NULL. */
 kc_status kc_export_bloom(kc_ctx* ctx, uint64_t* b1_host, uint64_t* b2_host, uint64_t words);
 
+/* Copies chosen words of the two Bloom levels (Sec. III, Prune: the first and
+ * second filter), for filters too large to copy whole: b1_host[i] and
+ * b2_host[i] receive word word_idx_host[i] of each level (same word layout as
+ * kc_export_bloom).  Host arrays of n entries, owned by the caller.  After
+ * kc_finalize; an index at or past 2^bloom_bits_log2 / 64 returns
+ * KC_ERR_INVALID_ARG (the outputs are then unspecified). */
+kc_status kc_export_bloom_words(kc_ctx* ctx, const uint64_t* word_idx_host, uint64_t n,
+                                uint64_t* b1_host, uint64_t* b2_host);
+
 /* Unify's stem layout of the final table (Sec. II-A: the stem of a k-mer is
  * its middle k-2 bases; Sec. III-D: counts grouped per stem, the 16 normal
  * and 16 tumour k-mers of a stem in one item of 2-byte counts).  After

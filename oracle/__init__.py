@@ -43,7 +43,8 @@ class OrStats(ctypes.Structure):
 
 class OrResult(ctypes.Structure):
     _fields_ = [("st", OrStats), ("n_entries", ctypes.c_uint64), ("keys", U64P),
-                ("counts", U32P), ("m_words", ctypes.c_uint64), ("b1", U64P), ("b2", U64P)]
+                ("counts", U32P), ("m_words", ctypes.c_uint64), ("b1", U64P), ("b2", U64P),
+                ("n_touched", ctypes.c_uint64), ("touched", U64P), ("t1", U64P), ("t2", U64P)]
 
 
 def build(force: bool = True) -> str:
@@ -68,6 +69,9 @@ def _load():
         lib.or_count.argtypes = [P, U8P, U64P, ctypes.c_uint64, U8P, ctypes.c_int]
         lib.or_count.restype = ctypes.POINTER(OrResult)
         lib.or_free.argtypes = [ctypes.POINTER(OrResult)]
+        lib.or_count_ranges.argtypes = [P, U8P, U64P, ctypes.c_uint64, U8P, ctypes.c_int,
+                                        ctypes.c_uint32, ctypes.c_int, ctypes.c_int]
+        lib.or_count_ranges.restype = ctypes.POINTER(OrResult)
         lib.or_enumerate.argtypes = [P, U8P, U64P, ctypes.c_uint64, U8P, U64P, ctypes.c_uint64]
         lib.or_enumerate.restype = ctypes.c_uint64
         lib.or_bloom_bits.argtypes = [P, ctypes.c_uint64, U64P]
@@ -113,6 +117,10 @@ class Result:
     b1: np.ndarray | None  # uint64 [m/64]
     b2: np.ndarray | None
     stats: dict
+    # bloom="sparse": the nonzero words of B1 (indices ascending) and both levels there
+    touched: np.ndarray | None = None
+    t1: np.ndarray | None = None
+    t2: np.ndarray | None = None
 
 
 def _arrays(bases, offsets, tags):
@@ -131,13 +139,42 @@ def mix64(z: int) -> int:
     return int(_load().or_mix64(z & ((1 << 64) - 1)))
 
 
-def count(params: Params, bases, offsets, tags=None, want_bloom: bool = True) -> Result:
-    """Full count: final table, Bloom levels and statistics."""
+def _bloom_mode(want_bloom) -> int:
+    return 2 if want_bloom == "sparse" else (1 if want_bloom else 0)
+
+
+def count(params: Params, bases, offsets, tags=None, want_bloom=True) -> Result:
+    """Full count: final table, Bloom levels and statistics.  want_bloom =
+    "sparse" returns the levels as their nonzero words (Result.touched, t1,
+    t2) instead of whole arrays."""
     bases, offsets, tags = _arrays(bases, offsets, tags)
     n_reads = offsets.size - 1
     p = params.c()
     r = _load().or_count(ctypes.byref(p), _ptr(bases, U8P), _ptr(offsets, U64P), n_reads,
-                         _ptr(tags, U8P), 1 if want_bloom else 0)
+                         _ptr(tags, U8P), _bloom_mode(want_bloom))
+    return _result(r, params, want_bloom)
+
+
+def count_ranges(params: Params, bases, offsets, tags=None, want_bloom=True,
+                 qbits: int = 0, threads: int = 0, keep_singles: bool = True) -> Result:
+    """The same result as ``count``, by value-range passes (kc_oracle.c,
+    or_count_ranges): 2^qbits ranges of the k-mer space by their top bits,
+    ``threads`` of them per pass; qbits = 0 picks the smallest power of two
+    that gives every thread a range.  keep_singles = False screens in a second
+    round of passes instead of keeping the keys seen once."""
+    bases, offsets, tags = _arrays(bases, offsets, tags)
+    n_reads = offsets.size - 1
+    threads = threads or _threads()
+    if not qbits:
+        qbits = min(2 * params.k, max(0, (threads - 1).bit_length()))
+    p = params.c()
+    r = _load().or_count_ranges(ctypes.byref(p), _ptr(bases, U8P), _ptr(offsets, U64P), n_reads,
+                                _ptr(tags, U8P), _bloom_mode(want_bloom), qbits, threads,
+                                1 if keep_singles else 0)
+    return _result(r, params, want_bloom)
+
+
+def _result(r, params: Params, want_bloom) -> Result:
     if not r:
         raise ValueError("oracle rejected the parameters or input")
     try:
@@ -146,14 +183,19 @@ def count(params: Params, bases, offsets, tags=None, want_bloom: bool = True) ->
         nc = params.n_counters
         keys = np.ctypeslib.as_array(res.keys, shape=(max(ne, 1),))[:ne].copy()
         counts = np.ctypeslib.as_array(res.counts, shape=(max(ne * nc, 1),))[:ne * nc].copy()
-        b1 = b2 = None
-        if want_bloom:
+        b1 = b2 = touched = t1 = t2 = None
+        if want_bloom == "sparse":
+            n = res.n_touched
+            touched = np.ctypeslib.as_array(res.touched, shape=(max(n, 1),))[:n].copy()
+            t1 = np.ctypeslib.as_array(res.t1, shape=(max(n, 1),))[:n].copy()
+            t2 = np.ctypeslib.as_array(res.t2, shape=(max(n, 1),))[:n].copy()
+        elif want_bloom:
             b1 = np.ctypeslib.as_array(res.b1, shape=(res.m_words,)).copy()
             b2 = np.ctypeslib.as_array(res.b2, shape=(res.m_words,)).copy()
         st = {name: int(getattr(res.st, name)) for name, _ in OrStats._fields_}
     finally:
         _load().or_free(r)
-    return Result(keys, counts.reshape(ne, nc), b1, b2, st)
+    return Result(keys, counts.reshape(ne, nc), b1, b2, st, touched, t1, t2)
 
 
 def enumerate_keys(params: Params, bases, offsets, tags=None) -> np.ndarray:

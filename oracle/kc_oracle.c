@@ -53,7 +53,9 @@
  * Algorithm: enumerate every valid window, push its canonical key, sort
  * (libc qsort), run-length encode into (x, counts), then derive B1/B2 from
  * the run-length list with the saturating update, then the screen, F and the
- * table.  All integer arithmetic, no floating point.
+ * table.  All integer arithmetic, no floating point.  Inputs too large to
+ * sort at once go through or_count_ranges: the same steps one value range of
+ * the k-mer space at a time (see the comment above it).
  */
 #include <pthread.h>
 #include <stdint.h>
@@ -84,6 +86,12 @@ typedef struct {
   uint64_t m_words;
   uint64_t* b1;     /* [m_words] little-endian bit order: bit b in word b>>6, bit b&63 */
   uint64_t* b2;
+  /* want_bloom = 2: the levels' nonzero words only (level 2 is zero where
+   * level 1 is): their indices, ascending, and both levels' words there */
+  uint64_t n_touched;
+  uint64_t* touched;
+  uint64_t* t1;
+  uint64_t* t2;
 } or_result;
 
 /* SplitMix64 output function (Steele, Lea, Flood, OOPSLA 2014). */
@@ -133,7 +141,7 @@ static int or_window(const uint8_t* s, uint32_t k, uint64_t* fwd, uint64_t* rev)
 
 /* Canonical key of the window starting at s (assumed valid). */
 static uint64_t or_canonical(const uint8_t* s, uint32_t k, int* ok) {
-  uint64_t f, r;
+  uint64_t f = 0, r = 0;
   *ok = or_window(s, k, &f, &r);
   return f < r ? f : r;
 }
@@ -199,10 +207,50 @@ void or_free(or_result* r) {
   free(r->counts);
   free(r->b1);
   free(r->b2);
+  free(r->touched);
+  free(r->t1);
+  free(r->t2);
   free(r);
 }
 
-/* Full count.  want_bloom = 0 skips returning B1/B2 (they are still used). */
+/* Hands the levels to the result: whole (want_bloom = 1), as their nonzero
+ * words (2), or not at all (0).  Returns 0, or -1 when out of memory. */
+static int or_give_bloom(or_result* res, uint64_t* b1, uint64_t* b2, uint64_t m_words,
+                         int want_bloom) {
+  res->m_words = m_words;
+  if (want_bloom == 1) {
+    res->b1 = b1;
+    res->b2 = b2;
+    return 0;
+  }
+  int rc = 0;
+  if (want_bloom == 2) {
+    uint64_t n = 0;
+    for (uint64_t w = 0; w < m_words; ++w) n += b1[w] != 0;
+    res->touched = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
+    res->t1 = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
+    res->t2 = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
+    if (res->touched && res->t1 && res->t2) {
+      uint64_t j = 0;
+      for (uint64_t w = 0; w < m_words; ++w)
+        if (b1[w]) {
+          res->touched[j] = w;
+          res->t1[j] = b1[w];
+          res->t2[j] = b2[w];
+          ++j;
+        }
+      res->n_touched = n;
+    } else {
+      rc = -1;
+    }
+  }
+  free(b1);
+  free(b2);
+  return rc;
+}
+
+/* Full count.  want_bloom = 0 skips returning B1/B2 (they are still used);
+ * 2 returns their nonzero words only. */
 or_result* or_count(const or_params* p, const uint8_t* bases, const uint64_t* offsets,
                     uint64_t n_reads, const uint8_t* tags, int want_bloom) {
   if (!or_params_ok(p)) return NULL;
@@ -293,13 +341,9 @@ or_result* or_count(const or_params* p, const uint8_t* bases, const uint64_t* of
   res->st.entries = ne;
   free(rk);
   free(rc);
-  res->m_words = m_words;
-  if (want_bloom) {
-    res->b1 = b1;
-    res->b2 = b2;
-  } else {
-    free(b1);
-    free(b2);
+  if (or_give_bloom(res, b1, b2, m_words, want_bloom)) {
+    or_free(res);
+    return NULL;
   }
   return res;
 }
@@ -551,4 +595,373 @@ int or_sample_hits(const or_params* p, const uint8_t* bases, const uint64_t* off
                    uint64_t n_reads, const uint64_t* sample, uint64_t n_sample, uint32_t* out,
                    int threads) {
   return or_scan(p, bases, offsets, n_reads, NULL, sample, n_sample, out, NULL, threads, 1);
+}
+
+/* --------------------------------------------------- value-range passes */
+/* The same result as or_count, for inputs whose keys do not fit in memory
+ * at once.  The k-mer space is cut into Q = 2^qbits value ranges by the top
+ * qbits of the 2k-bit code (SMUFIN splits its work into partitions of the
+ * k-mer space and re-reads the input once per partition, Sec. II-B).  A pass
+ * takes `threads` consecutive ranges, one per thread: the threads split the
+ * reads, enumerate every valid window and keep the keys of the pass's ranges
+ * in one bucket per (thread, range); then each thread gathers one range's
+ * buckets, sorts them (libc qsort) and run-length encodes them.  The ranges
+ * are value ranges, so their tables concatenated in range order are the
+ * sorted table.  B1/B2 take every range's run-length list with the
+ * saturating update of or_count, made with atomic OR so that the order in
+ * which ranges finish does not matter: a bit is set in level 2 by a key seen
+ * at least twice, or by the second of two keys that hit it (the atomic OR
+ * returns the level-1 word as it was).  The screen needs the final level 2,
+ * so it runs after the last pass: either over the keys seen once, kept from
+ * the passes (a key seen at least twice always passes: each bit of S(x) has
+ * at least c(x) >= 2 hits, so N_pass = sum of c over keys with c >= 2, plus
+ * F), or, with keep_singles = 0, by a second round of passes that screens
+ * every distinct key. */
+
+typedef struct {
+  uint64_t* v;
+  uint64_t n, cap;
+} or_vec64;
+
+typedef struct {
+  uint32_t* v;
+  uint64_t n, cap;
+} or_vec32;
+
+static int or_push64(or_vec64* a, uint64_t x) {
+  if (a->n == a->cap) {
+    uint64_t c = a->cap ? a->cap + a->cap / 2 : 4096;
+    uint64_t* v = (uint64_t*)realloc(a->v, c * sizeof(uint64_t));
+    if (!v) return -1;
+    a->v = v;
+    a->cap = c;
+  }
+  a->v[a->n++] = x;
+  return 0;
+}
+
+static int or_push32(or_vec32* a, uint32_t x) {
+  if (a->n == a->cap) {
+    uint64_t c = a->cap ? a->cap + a->cap / 2 : 4096;
+    uint32_t* v = (uint32_t*)realloc(a->v, c * sizeof(uint32_t));
+    if (!v) return -1;
+    a->v = v;
+    a->cap = c;
+  }
+  a->v[a->n++] = x;
+  return 0;
+}
+
+static void or_vfree64(or_vec64* a) {
+  free(a->v);
+  a->v = NULL;
+  a->n = a->cap = 0;
+}
+
+static void or_vfree32(or_vec32* a) {
+  free(a->v);
+  a->v = NULL;
+  a->n = a->cap = 0;
+}
+
+typedef struct {
+  uint64_t n_distinct, sum_ge2, entries, sum_counts, n_pass, fp;
+} or_range_stats;
+
+typedef struct {
+  const or_params* p;
+  const uint8_t* bases;
+  const uint64_t* offsets;
+  uint64_t n_reads;
+  const uint8_t* tags;
+  const uint64_t* salt;
+  uint32_t qbits, threads;
+  int keep_singles;
+  int sweep;             /* 1: counts, Bloom, table; 2: screen every key */
+  uint64_t q0;           /* first range of the pass */
+  uint64_t* b1;
+  uint64_t* b2;
+  or_vec64* bucket;      /* [threads * threads]: thread t, range q0 + j */
+  or_vec64* tkeys;       /* [Q] table keys per range */
+  or_vec32* tcounts;     /* [Q] their counts, n_counters each */
+  or_vec64* singles;     /* [Q] keys seen once (keep_singles) */
+  or_range_stats* rst;   /* [Q] */
+  uint64_t* nvalid;      /* [threads] */
+  int* fail;             /* [threads] */
+} or_rp;
+
+typedef struct {
+  or_rp* rp;
+  uint32_t t;
+} or_rp_job;
+
+static uint64_t or_range_of(const or_params* p, uint32_t qbits, uint64_t x) {
+  return qbits ? x >> (2 * p->k - qbits) : 0;
+}
+
+/* Enumeration: thread t takes its share of the reads and keeps the keys of
+ * the pass's ranges, tagged (x << 1 | counter) as or_enumerate does. */
+static void* or_rp_enum(void* arg) {
+  or_rp_job* j = (or_rp_job*)arg;
+  or_rp* rp = j->rp;
+  const or_params* p = rp->p;
+  const uint32_t T = rp->threads;
+  const uint64_t lo = rp->n_reads * (uint64_t)j->t / T, hi = rp->n_reads * (uint64_t)(j->t + 1) / T;
+  uint64_t nv = 0;
+  for (uint64_t r = lo; r < hi; ++r) {
+    const uint64_t a = rp->offsets[r], b = rp->offsets[r + 1];
+    if (b - a < p->k) continue;
+    for (uint64_t s = a; s + p->k <= b; ++s) {
+      int ok;
+      const uint64_t x = or_canonical(rp->bases + s, p->k, &ok);
+      if (!ok) continue;
+      ++nv;
+      const uint64_t q = or_range_of(p, rp->qbits, x);
+      if (q < rp->q0 || q - rp->q0 >= T) continue;
+      const uint64_t tagged = (x << 1) | (uint64_t)(rp->tags ? rp->tags[r] : 0);
+      if (or_push64(&rp->bucket[(uint64_t)j->t * T + (q - rp->q0)], tagged)) {
+        rp->fail[j->t] = 1;
+        return NULL;
+      }
+    }
+  }
+  rp->nvalid[j->t] = nv;
+  return NULL;
+}
+
+/* One range: gather its buckets, sort, run-length encode, then (sweep 1) the
+ * Bloom update, the table and the kept singletons, or (sweep 2) the screen. */
+static void* or_rp_range(void* arg) {
+  or_rp_job* j = (or_rp_job*)arg;
+  or_rp* rp = j->rp;
+  const or_params* p = rp->p;
+  const uint32_t T = rp->threads, nc = p->n_counters;
+  const uint64_t q = rp->q0 + j->t;
+  if (q >= (1ull << rp->qbits)) return NULL;
+  uint64_t n = 0;
+  for (uint32_t i = 0; i < T; ++i) n += rp->bucket[(uint64_t)i * T + j->t].n;
+  uint64_t* occ = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
+  if (!occ) {
+    rp->fail[j->t] = 1;
+    return NULL;
+  }
+  uint64_t at = 0;
+  for (uint32_t i = 0; i < T; ++i) {
+    or_vec64* b = &rp->bucket[(uint64_t)i * T + j->t];
+    if (b->n) memcpy(occ + at, b->v, b->n * sizeof(uint64_t));
+    at += b->n;
+    or_vfree64(b);
+  }
+  qsort(occ, n, sizeof(uint64_t), or_cmp_u64);
+  or_range_stats* st = &rp->rst[q];
+  uint64_t pos[8];
+  for (uint64_t i = 0; i < n;) {
+    const uint64_t x = occ[i] >> 1;
+    uint32_t c[2] = {0, 0};
+    uint64_t e = i;
+    for (; e < n && (occ[e] >> 1) == x; ++e) c[occ[e] & 1] += 1;
+    i = e;
+    const uint64_t tot = (uint64_t)c[0] + c[1];
+    const uint32_t np = or_bloom_positions(p, rp->salt, x, pos);
+    if (rp->sweep == 1) {
+      st->n_distinct += 1;
+      if (tot >= 2) st->sum_ge2 += tot;
+      for (uint32_t k = 0; k < np; ++k) {
+        const uint64_t bit = 1ULL << (pos[k] & 63);
+        if (tot >= 2) {
+          __atomic_fetch_or(&rp->b1[pos[k] >> 6], bit, __ATOMIC_RELAXED);
+          __atomic_fetch_or(&rp->b2[pos[k] >> 6], bit, __ATOMIC_RELAXED);
+        } else {
+          const uint64_t old = __atomic_fetch_or(&rp->b1[pos[k] >> 6], bit, __ATOMIC_RELAXED);
+          if (old & bit) __atomic_fetch_or(&rp->b2[pos[k] >> 6], bit, __ATOMIC_RELAXED);
+        }
+      }
+      int bad = 0;
+      if (tot >= p->min_count) {
+        st->entries += 1;
+        st->sum_counts += tot;
+        bad |= or_push64(&rp->tkeys[q], x);
+        for (uint32_t t = 0; t < nc; ++t) bad |= or_push32(&rp->tcounts[q], c[t]);
+      }
+      if (tot == 1 && rp->keep_singles) bad |= or_push64(&rp->singles[q], x);
+      if (bad) {
+        rp->fail[j->t] = 1;
+        break;
+      }
+    } else {
+      int pass = 1;
+      for (uint32_t k = 0; k < np; ++k) pass &= or_bit(rp->b2, pos[k]);
+      if (pass) {
+        st->n_pass += tot;
+        if (tot == 1) st->fp += 1;
+      }
+    }
+  }
+  free(occ);
+  return NULL;
+}
+
+/* Screen of the kept singletons of ranges j, j + threads, ... */
+static void* or_rp_screen_singles(void* arg) {
+  or_rp_job* j = (or_rp_job*)arg;
+  or_rp* rp = j->rp;
+  uint64_t pos[8];
+  for (uint64_t q = j->t; q < (1ull << rp->qbits); q += rp->threads) {
+    or_range_stats* st = &rp->rst[q];
+    for (uint64_t i = 0; i < rp->singles[q].n; ++i) {
+      const uint32_t np = or_bloom_positions(rp->p, rp->salt, rp->singles[q].v[i], pos);
+      int pass = 1;
+      for (uint32_t k = 0; k < np; ++k) pass &= or_bit(rp->b2, pos[k]);
+      st->fp += (uint64_t)pass;
+    }
+    or_vfree64(&rp->singles[q]);
+  }
+  return NULL;
+}
+
+static int or_rp_run(or_rp* rp, void* (*fn)(void*)) {
+  const uint32_t T = rp->threads;
+  pthread_t* tid = (pthread_t*)malloc(T * sizeof(pthread_t));
+  or_rp_job* jobs = (or_rp_job*)malloc(T * sizeof(or_rp_job));
+  if (!tid || !jobs) {
+    free(tid);
+    free(jobs);
+    return -1;
+  }
+  uint32_t started = 0;
+  int bad = 0;
+  for (uint32_t t = 0; t < T; ++t) {
+    jobs[t].rp = rp;
+    jobs[t].t = t;
+    if (pthread_create(&tid[t], NULL, fn, &jobs[t])) {
+      bad = 1;
+      break;
+    }
+    ++started;
+  }
+  for (uint32_t t = 0; t < started; ++t) pthread_join(tid[t], NULL);
+  for (uint32_t t = 0; t < T; ++t) bad |= rp->fail[t];
+  free(tid);
+  free(jobs);
+  return bad ? -1 : 0;
+}
+
+/* Passes over all ranges: enumeration, then one range per thread. */
+static int or_rp_sweep(or_rp* rp, int sweep, uint64_t* n_valid) {
+  const uint64_t Q = 1ull << rp->qbits;
+  rp->sweep = sweep;
+  for (uint64_t q0 = 0; q0 < Q; q0 += rp->threads) {
+    rp->q0 = q0;
+    if (or_rp_run(rp, or_rp_enum)) return -1;
+    if (n_valid && q0 == 0) {
+      *n_valid = 0;
+      for (uint32_t t = 0; t < rp->threads; ++t) *n_valid += rp->nvalid[t];
+    }
+    if (or_rp_run(rp, or_rp_range)) return -1;
+  }
+  return 0;
+}
+
+or_result* or_count_ranges(const or_params* p, const uint8_t* bases, const uint64_t* offsets,
+                           uint64_t n_reads, const uint8_t* tags, int want_bloom, uint32_t qbits,
+                           int threads, int keep_singles) {
+  if (!or_params_ok(p)) return NULL;
+  if (qbits > 2 * p->k || qbits > 20 || threads < 1 || threads > 256) return NULL;
+  if (offsets[0] != 0) return NULL;
+  for (uint64_t r = 0; r < n_reads; ++r)
+    if (offsets[r + 1] < offsets[r]) return NULL;
+  if (tags)
+    for (uint64_t r = 0; r < n_reads; ++r)
+      if (tags[r] >= p->n_counters) return NULL;
+  const uint32_t T = (uint32_t)threads, nc = p->n_counters;
+  const uint64_t Q = 1ull << qbits;
+  uint64_t salt[9];
+  or_salts(p, salt);
+  or_rp rp;
+  memset(&rp, 0, sizeof(rp));
+  rp.p = p;
+  rp.bases = bases;
+  rp.offsets = offsets;
+  rp.n_reads = n_reads;
+  rp.tags = tags;
+  rp.salt = salt;
+  rp.qbits = qbits;
+  rp.threads = T;
+  rp.keep_singles = keep_singles;
+  const uint64_t m_words = p->m_log2 >= 6 ? (1ULL << (p->m_log2 - 6)) : 1;
+  rp.b1 = (uint64_t*)calloc(m_words, sizeof(uint64_t));
+  rp.b2 = (uint64_t*)calloc(m_words, sizeof(uint64_t));
+  rp.bucket = (or_vec64*)calloc((uint64_t)T * T, sizeof(or_vec64));
+  rp.tkeys = (or_vec64*)calloc(Q, sizeof(or_vec64));
+  rp.tcounts = (or_vec32*)calloc(Q, sizeof(or_vec32));
+  rp.singles = (or_vec64*)calloc(Q, sizeof(or_vec64));
+  rp.rst = (or_range_stats*)calloc(Q, sizeof(or_range_stats));
+  rp.nvalid = (uint64_t*)calloc(T, sizeof(uint64_t));
+  rp.fail = (int*)calloc(T, sizeof(int));
+  or_result* res = (or_result*)calloc(1, sizeof(or_result));
+  int ok = rp.b1 && rp.b2 && rp.bucket && rp.tkeys && rp.tcounts && rp.singles && rp.rst &&
+           rp.nvalid && rp.fail && res;
+  uint64_t n_valid = 0;
+  if (ok) ok = or_rp_sweep(&rp, 1, &n_valid) == 0;
+  if (ok) {
+    if (keep_singles) {
+      ok = or_rp_run(&rp, or_rp_screen_singles) == 0;
+    } else {
+      ok = or_rp_sweep(&rp, 2, NULL) == 0;
+    }
+  }
+  if (ok) {
+    res->st.n_valid = n_valid;
+    uint64_t ne = 0;
+    for (uint64_t q = 0; q < Q; ++q) {
+      const or_range_stats* s = &rp.rst[q];
+      res->st.n_distinct += s->n_distinct;
+      res->st.entries += s->entries;
+      res->st.sum_counts += s->sum_counts;
+      res->st.fp_singletons += s->fp;
+      res->st.n_pass += keep_singles ? s->sum_ge2 + s->fp : s->n_pass;
+      ne += s->entries;
+    }
+    for (uint64_t w = 0; w < m_words; ++w) {
+      res->st.b1_pop += (uint64_t)__builtin_popcountll(rp.b1[w]);
+      res->st.b2_pop += (uint64_t)__builtin_popcountll(rp.b2[w]);
+    }
+    res->keys = (uint64_t*)malloc((ne ? ne : 1) * sizeof(uint64_t));
+    res->counts = (uint32_t*)malloc((ne ? ne : 1) * nc * sizeof(uint32_t));
+    ok = res->keys && res->counts;
+    if (ok) {
+      uint64_t e = 0;
+      for (uint64_t q = 0; q < Q; ++q) {
+        if (rp.tkeys[q].n) {
+          memcpy(res->keys + e, rp.tkeys[q].v, rp.tkeys[q].n * sizeof(uint64_t));
+          memcpy(res->counts + e * nc, rp.tcounts[q].v, rp.tkeys[q].n * nc * sizeof(uint32_t));
+        }
+        e += rp.tkeys[q].n;
+      }
+      res->n_entries = ne;
+    }
+  }
+  if (rp.bucket)
+    for (uint64_t i = 0; i < (uint64_t)T * T; ++i) or_vfree64(&rp.bucket[i]);
+  for (uint64_t q = 0; q < Q && rp.tkeys; ++q) or_vfree64(&rp.tkeys[q]);
+  for (uint64_t q = 0; q < Q && rp.tcounts; ++q) or_vfree32(&rp.tcounts[q]);
+  for (uint64_t q = 0; q < Q && rp.singles; ++q) or_vfree64(&rp.singles[q]);
+  free(rp.bucket);
+  free(rp.tkeys);
+  free(rp.tcounts);
+  free(rp.singles);
+  free(rp.rst);
+  free(rp.nvalid);
+  free(rp.fail);
+  if (!ok) {
+    free(rp.b1);
+    free(rp.b2);
+    or_free(res);
+    return NULL;
+  }
+  if (or_give_bloom(res, rp.b1, rp.b2, m_words, want_bloom)) {
+    or_free(res);
+    return NULL;
+  }
+  return res;
 }

@@ -32,7 +32,8 @@ STAGES = ["pack", "level1", "scan", "level2", "bloom", "tally", "unify", "query"
           "stems", "filter"]
 
 EXPORTED = ["kc_abi_version", "kc_status_str", "kc_create", "kc_insert_reads", "kc_finalize",
-            "kc_query", "kc_spill", "kc_export", "kc_export_bloom", "kc_debug_keys",
+            "kc_query", "kc_spill", "kc_export", "kc_export_bloom", "kc_export_bloom_words",
+            "kc_debug_keys",
             "kc_get_stats", "kc_reset", "kc_destroy", "kc_last_error", "kc_count_batch",
             "kc_autotune_batch", "kc_server_create", "kc_server_submit", "kc_server_wait",
             "kc_server_release", "kc_server_usage", "kc_server_destroy", "kc_server_set_overlap",
@@ -131,6 +132,7 @@ def load():
         "kc_spill": ([V, I64, P(U64)], st),
         "kc_export": ([V, V, V, U64, P(U64)], st),
         "kc_export_bloom": ([V, V, V, U64], st),
+        "kc_export_bloom_words": ([V, V, U64, V, V], st),
         "kc_export_stems": ([V, V, V, U64, P(U64), V], st),
         "kc_filter_reads": ([V, V, V, U64, U64, U32, U32, V, V], st),
         "kc_checkpoint": ([V, ctypes.c_char_p], st),
@@ -242,6 +244,15 @@ def kc_export_bloom(ctx, words: int):
     b2 = np.empty(words, dtype=np.uint64)
     _check(ctx, load().kc_export_bloom(ctx, b1.ctypes.data, b2.ctypes.data, words))
     return b1, b2
+
+
+def kc_export_bloom_words(ctx, word_idx):
+    idx = np.ascontiguousarray(word_idx, dtype=np.uint64)
+    b1 = np.empty(max(idx.size, 1), dtype=np.uint64)
+    b2 = np.empty(max(idx.size, 1), dtype=np.uint64)
+    _check(ctx, load().kc_export_bloom_words(ctx, idx.ctypes.data, idx.size, b1.ctypes.data,
+                                             b2.ctypes.data))
+    return b1[:idx.size], b2[:idx.size]
 
 
 def kc_debug_keys(ctx):
@@ -429,6 +440,10 @@ class KmerCounter:
     def export_bloom(self):
         words = max(1, (1 << self.cfg.bloom_bits_log2) // 64)
         return kc_export_bloom(self.ctx, words)
+
+    def export_bloom_words(self, word_idx):
+        """Words word_idx (uint64 indices) of both Bloom levels (kc_export_bloom_words)."""
+        return kc_export_bloom_words(self.ctx, word_idx)
 
     def filter_reads(self, bases, offsets, tumour_min: int, normal_max: int, stream=None):
         """Filter-unit lookup (kc_filter_reads): per read of the batch, its

@@ -171,6 +171,9 @@ hipError_t launch_rstart_batch(const ChunkDesc* cd, uint32_t nchunks, uint64_t n
 hipError_t launch_fill64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_fill32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_copy64(const uint64_t* src, uint64_t* dst, hipStream_t s);
+hipError_t launch_gather2(const uint64_t* a, const uint64_t* b, const uint64_t* idx, uint64_t n,
+                          uint64_t nwords, uint64_t* out_a, uint64_t* out_b, uint32_t* err,
+                          hipStream_t s);
 hipError_t launch_slot_map(uint32_t* slot_of, uint32_t n, uint32_t first, hipStream_t s);
 hipError_t launch_scatter_rows(const uint32_t* rows, const uint32_t* vals, uint32_t n,
                                uint32_t nc, uint32_t* out, hipStream_t s);

@@ -244,6 +244,24 @@ __global__ void k_copy64(const uint64_t* __restrict__ src, uint64_t* __restrict_
   if (threadIdx.x == 0) *dst = *src;
 }
 
+// Words idx[i] of two arrays of nwords 64-bit words; an index past the end
+// sets ERR_QUERY_RANGE and reads as 0.
+__global__ void __launch_bounds__(256) k_gather2(const uint64_t* __restrict__ a,
+                                                 const uint64_t* __restrict__ b,
+                                                 const uint64_t* __restrict__ idx, uint64_t n,
+                                                 uint64_t nwords, uint64_t* __restrict__ out_a,
+                                                 uint64_t* __restrict__ out_b,
+                                                 uint32_t* __restrict__ err) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t w = idx[i];
+    const bool ok = w < nwords;
+    if (!ok) atomicOr(err, (uint32_t)ERR_QUERY_RANGE);
+    out_a[i] = ok ? a[w] : 0;
+    out_b[i] = ok ? b[w] : 0;
+  }
+}
+
 // ----------------------------------------------------- window extraction
 
 struct WordCtx {
@@ -1915,6 +1933,16 @@ hipError_t launch_fill64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
 hipError_t launch_fill32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
   if (!n) return hipSuccess;
   hipLaunchKernelGGL(k_fill32, dim3(stride_grid(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather2(const uint64_t* a, const uint64_t* b, const uint64_t* idx, uint64_t n,
+                          uint64_t nwords, uint64_t* out_a, uint64_t* out_b, uint32_t* err,
+                          hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_gather2, dim3((uint32_t)blocks), dim3(256), 0, s, a, b, idx, n, nwords,
+                     out_a, out_b, err);
   return hipGetLastError();
 }
 

@@ -1641,6 +1641,31 @@ kc_status kc_export_bloom(kc_ctx* c, uint64_t* b1, uint64_t* b2, uint64_t words)
   return KC_OK;
 }
 
+kc_status kc_export_bloom_words(kc_ctx* c, const uint64_t* word_idx, uint64_t n, uint64_t* b1,
+                                uint64_t* b2) {
+  if (!c) return KC_ERR_INVALID_ARG;
+  if (c->state != FINALIZED) return fail(c, KC_ERR_BAD_STATE, "Bloom export before finalize");
+  if (n == 0) return KC_OK;
+  if (!word_idx || !b1 || !b2) return fail(c, KC_ERR_INVALID_ARG, "NULL index or output buffer");
+  KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
+  DevBuf idx, out;
+  ReleaseOnExit free_bufs{&idx, &out};
+  KC_HIP(c, idx.ensure(n * 8), "index buffer");
+  KC_HIP(c, out.ensure(n * 16), "gather buffer");
+  KC_HIP(c, hipMemcpy(idx.p, word_idx, n * 8, hipMemcpyHostToDevice), "index copy");
+  KC_HIP(c, hipMemset(c->derr.p, 0, 4), "memset");
+  KC_HIP(c, launch_gather2(c->b1.as<uint64_t>(), c->b2.as<uint64_t>(), idx.as<uint64_t>(), n,
+                           c->bloom_words64, out.as<uint64_t>(), out.as<uint64_t>() + n,
+                           c->derr.as<uint32_t>(), nullptr),
+         "gather");
+  uint32_t errf = 0;
+  KC_HIP(c, hipMemcpy(&errf, c->derr.p, 4, hipMemcpyDeviceToHost), "readback");
+  if (errf & ERR_QUERY_RANGE) return fail(c, KC_ERR_INVALID_ARG, "word index past the Bloom size");
+  KC_HIP(c, hipMemcpy(b1, out.p, n * 8, hipMemcpyDeviceToHost), "Bloom copy");
+  KC_HIP(c, hipMemcpy(b2, out.as<uint64_t>() + n, n * 8, hipMemcpyDeviceToHost), "Bloom copy");
+  return KC_OK;
+}
+
 kc_status kc_debug_keys(kc_ctx* c, uint64_t* keys, uint32_t* part, uint64_t cap, uint64_t* n_out) {
   if (!c) return KC_ERR_INVALID_ARG;
   uint64_t n = 0;

@@ -1,0 +1,91 @@
+"""Digests of whole outputs, for comparing results too large to store.
+
+Test infrastructure: a serialisation and SHA-256 of arrays, holding none of
+the counting arithmetic.  The committed digests under ``tests/golden/`` are
+written from the CPU oracle's output by ``tests/golden/make_digests.py``; the
+GPU tests digest the library's output the same way and compare.
+
+Byte stream of a table: its entries in ascending key order, each the key as
+a little-endian uint64 followed by its n_counters counts as little-endian
+uint32.  The stream is also cut by value range (the top RANGE_BITS bits of
+the 2k-bit code), so that a mismatch names the range it is in.  Bloom levels:
+their little-endian uint64 words in order.
+"""
+from __future__ import annotations
+
+import hashlib
+
+import numpy as np
+
+RANGE_BITS = 4
+
+
+def table_bytes(keys_sorted: np.ndarray, counts_sorted: np.ndarray) -> np.ndarray:
+    keys_sorted = np.asarray(keys_sorted, dtype=np.uint64).reshape(-1)
+    counts_sorted = np.asarray(counts_sorted, dtype=np.uint32).reshape(keys_sorted.size, -1)
+    nc = counts_sorted.shape[1]
+    rec = np.empty(keys_sorted.size, dtype=np.dtype([("k", "<u8"), ("c", "<u4", (nc,))]))
+    rec["k"] = keys_sorted
+    rec["c"] = counts_sorted
+    return rec
+
+
+def table_digests(keys_sorted: np.ndarray, counts_sorted: np.ndarray, k: int) -> dict:
+    """{'sha256': whole stream, 'ranges': [(entries, sum of counts, sha256)]}
+    of a table already sorted by key."""
+    keys_sorted = np.asarray(keys_sorted, dtype=np.uint64).reshape(-1)
+    counts_sorted = np.asarray(counts_sorted, dtype=np.uint32).reshape(keys_sorted.size, -1)
+    if keys_sorted.size > 1 and not bool(np.all(keys_sorted[1:] > keys_sorted[:-1])):
+        raise ValueError("table keys are not strictly ascending")
+    rb = min(RANGE_BITS, 2 * k)
+    edges = np.searchsorted(keys_sorted, np.arange((1 << rb) + 1, dtype=np.uint64)
+                            << np.uint64(2 * k - rb))
+    whole = hashlib.sha256()
+    ranges = []
+    for q in range(1 << rb):
+        lo, hi = int(edges[q]), int(edges[q + 1])
+        blob = table_bytes(keys_sorted[lo:hi], counts_sorted[lo:hi]).tobytes()
+        whole.update(blob)
+        ranges.append((hi - lo, int(counts_sorted[lo:hi].sum(dtype=np.uint64)),
+                       hashlib.sha256(blob).hexdigest()))
+    return {"sha256": whole.hexdigest(), "ranges": ranges}
+
+
+def words_digest(words: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(words, dtype="<u8").tobytes()).hexdigest()
+
+
+STAT_KEYS = ["n_valid", "n_pass", "entries", "sum_counts", "fp_singletons", "b1_popcount",
+             "b2_popcount"]
+
+
+def write_digest_file(path: str, header: list[str], stats: dict, table: dict, b1: str, b2: str):
+    with open(path, "w") as f:
+        for line in header:
+            f.write("# %s\n" % line)
+        for name in STAT_KEYS:
+            f.write("stat %s %d\n" % (name, stats[name]))
+        f.write("table %s\n" % table["sha256"])
+        for q, (n, s, h) in enumerate(table["ranges"]):
+            f.write("range %d %d %d %s\n" % (q, n, s, h))
+        f.write("b1 %s\n" % b1)
+        f.write("b2 %s\n" % b2)
+
+
+def read_digest_file(path: str) -> dict:
+    out = {"stats": {}, "ranges": []}
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            parts = line.split()
+            if parts[0] == "stat":
+                out["stats"][parts[1]] = int(parts[2])
+            elif parts[0] == "table":
+                out["sha256"] = parts[1]
+            elif parts[0] == "range":
+                out["ranges"].append((int(parts[2]), int(parts[3]), parts[4]))
+            elif parts[0] in ("b1", "b2"):
+                out[parts[0]] = parts[1]
+    return out

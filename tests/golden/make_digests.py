@@ -1,0 +1,74 @@
+"""Writes the whole-output digest of a workload from the CPU oracle.
+
+    python tests/golden/make_digests.py plain_100mbp [--threads N]
+
+Calls only the oracle (``oracle.count_ranges``: value-range passes over
+every window) and the seeded input generator (``synth``); nothing here runs
+the GPU library.  The result, ``tests/golden/digest_<workload>.txt``, holds
+every statistic, the SHA-256 of the sorted table (whole and per value range)
+and of both Bloom levels; ``tests/test_gpu_full.py`` digests the library's
+output at the same workload and compares.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+for p in (ROOT, os.path.dirname(HERE)):
+    if p not in sys.path:
+        sys.path.insert(0, p)
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+from digest import table_digests, words_digest, write_digest_file  # noqa: E402
+
+STATS = {"n_valid": "n_valid", "n_pass": "n_pass", "entries": "entries",
+         "sum_counts": "sum_counts", "fp_singletons": "fp_singletons",
+         "b1_popcount": "b1_pop", "b2_popcount": "b2_pop"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("workload")
+    ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--qbits", type=int, default=0)
+    args = ap.parse_args()
+    w = synth.WORKLOADS[args.workload]
+    if w.batch_chunks or w.requests:
+        raise SystemExit("only plain workloads have a single read stream")
+    t0 = time.time()
+    genome = w.make_genome()
+    bases, offsets = w.make_reads(genome)
+    del genome
+    p = oracle.Params(k=w.k, n_counters=w.n_counters, min_count=w.min_count,
+                      m_log2=w.bloom_bits_log2, h=w.bloom_hashes,
+                      block_log2=min(w.bloom_block_log2, w.bloom_bits_log2), seed=w.seed)
+    t1 = time.time()
+    res = oracle.count_ranges(p, bases, offsets, threads=args.threads, qbits=args.qbits)
+    t2 = time.time()
+    stats = {k: res.stats[v] for k, v in STATS.items()}
+    table = table_digests(res.keys, res.counts, w.k)
+    b1, b2 = words_digest(res.b1), words_digest(res.b2)
+    out = os.path.join(HERE, "digest_%s.txt" % w.name)
+    header = [
+        "Whole output of the CPU oracle (value-range passes) at workload %s:" % w.name,
+        "genome %d bp, %d reads of %d-%d bp, substitutions %g, N rate %g, seed %d;"
+        % (w.genome_len, w.n_reads, w.lmin, w.lmax, w.err, w.nrate, w.seed),
+        "k=%d, %d counter(s), min_count %d, Bloom 2^%d bits per level, %d hashes, blocks of 2^%d bits."
+        % (w.k, w.n_counters, w.min_count, w.bloom_bits_log2, w.bloom_hashes,
+           min(w.bloom_block_log2, w.bloom_bits_log2)),
+        "Written by: python tests/golden/make_digests.py %s (oracle %.0f s, input %.0f s)."
+        % (w.name, t2 - t1, t1 - t0),
+        "Table stream: entries ascending by key, key <u8 then counts <u4; ranges by the top 4",
+        "bits of the 2k-bit code: 'range q entries sum_of_counts sha256'.",
+    ]
+    write_digest_file(out, header, stats, table, b1, b2)
+    print("wrote %s in %.0f s" % (out, time.time() - t0))
+
+
+if __name__ == "__main__":
+    main()

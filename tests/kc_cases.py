@@ -143,3 +143,27 @@ def workload_config(w: synth.Workload, **over) -> kc.Config:
     for k_, v in over.items():
         setattr(cfg, k_, v)
     return cfg
+
+
+def gpu_table_sorted(keys, counts):
+    """The exported table sorted by key on the device (the table can hold 10^8
+    entries and more); returns host arrays."""
+    import torch
+    k = torch.from_numpy(np.ascontiguousarray(keys).view(np.int64)).cuda()
+    order = torch.argsort(k)  # keys < 2^62: signed order is unsigned order
+    ks = k[order].cpu().numpy().view(np.uint64)
+    c = torch.from_numpy(np.ascontiguousarray(counts).view(np.int32)).cuda()
+    cs = c[order].cpu().numpy().view(np.uint32)
+    return ks, cs
+
+
+def assert_bloom_sparse(counter_words, ref, stats):
+    """Both Bloom levels equal the oracle's, from its nonzero words: the
+    library's words at those indices are the oracle's and its popcounts are
+    the oracle's, so no bit is set anywhere else."""
+    g1, g2 = counter_words(ref.touched)
+    assert np.array_equal(g1, ref.t1)
+    assert np.array_equal(g2, ref.t2)
+    pop = lambda v: int(np.unpackbits(np.ascontiguousarray(v).view(np.uint8)).sum())
+    assert stats["b1_popcount"] == ref.stats["b1_pop"] == pop(ref.t1)
+    assert stats["b2_popcount"] == ref.stats["b2_pop"] == pop(ref.t2)

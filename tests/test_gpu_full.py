@@ -4,12 +4,17 @@ oracle computes sampled outputs exactly (threaded scans over every window):
 counts of sampled keys and saturating hits of sampled Bloom bits.  Properties
 that hold at any size are checked on the full outputs.
 """
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 import paper_1712_03254_amd as kc
-from kc_cases import note, oracle_params, to_device, workload_chunks, workload_config
+from conftest import GOLDEN
+from digest import STAT_KEYS, read_digest_file, table_digests, words_digest
+from kc_cases import (gpu_table_sorted, note, oracle_params, to_device, workload_chunks,
+                      workload_config)
 from oracle import brute
 
 pytestmark = pytest.mark.gpu
@@ -18,6 +23,37 @@ pytestmark = pytest.mark.gpu
 def _popcount(words):
     v = words.view(np.uint8)
     return int(np.unpackbits(v).sum())
+
+
+@pytest.mark.parametrize("name", ["plain_1mbp", "plain_100mbp"])
+def test_whole_output_digest(name):
+    """The whole output at full size, in the configuration bench.py times:
+    every statistic, the sorted table (SHA-256 as a whole and per value range)
+    and both Bloom levels (SHA-256 of every word) against the digest that
+    tests/golden/make_digests.py wrote from the CPU oracle's value-range
+    passes over every window."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    note("case: %s full size, whole-output digest" % name)
+    want = read_digest_file(os.path.join(GOLDEN, "digest_%s.txt" % name))
+    w, _, b, o = workload_chunks(name)
+    cfg = workload_config(w)
+    db, do = to_device(b, o)
+    with kc.KmerCounter(cfg) as c:
+        c.insert_reads(db, do)
+        st = c.finalize()
+        keys, counts = c.export()
+        b1, b2 = c.export_bloom()
+    for key in STAT_KEYS:
+        assert st[key] == want["stats"][key], (key, st[key], want["stats"][key])
+    ks, cs = gpu_table_sorted(keys, counts)
+    got = table_digests(ks, cs, w.k)
+    for q, (g, r) in enumerate(zip(got["ranges"], want["ranges"])):
+        assert tuple(g) == tuple(r), ("value range", q, g, r)
+    assert got["sha256"] == want["sha256"]
+    assert words_digest(b1) == want["b1"]
+    assert words_digest(b2) == want["b2"]
 
 
 def test_plain_100mbp_sampled_parity():

@@ -372,3 +372,94 @@ def test_sampled_counts_and_hits_match_full():
             assert (int(hcount) >= 1) == (int(bit) in b1)
             assert (int(hcount) >= 2) == (int(bit) in b2)
     del full
+
+
+# ------------------------------------------------------ value-range passes
+
+RANGE_CASES = [  # (k, m_log2, h, bl, nc, qbits, threads, keep_singles)
+    (31, 20, 4, 12, 1, 0, 1, True),
+    (31, 20, 4, 12, 1, 3, 4, True),
+    (21, 18, 3, 18, 2, 4, 3, False),
+    (13, 16, 2, 5, 1, 6, 8, True),
+    (5, 12, 4, 2, 2, 10, 8, False),   # qbits = 2k: one key per range
+    (3, 10, 3, 3, 1, 2, 8, True),     # more threads than ranges
+    (31, 24, 4, 16, 2, 5, 7, True),
+]
+
+
+@pytest.mark.parametrize("k,m_log2,h,bl,nc,qbits,threads,keep", RANGE_CASES)
+def test_value_range_passes_equal_the_full_count(k, m_log2, h, bl, nc, qbits, threads, keep):
+    """or_count_ranges (value-range passes, threads, atomic Bloom updates,
+    the screen after the last pass) gives the table, both levels and every
+    statistic of the single sort, also with fewer threads than ranges (several
+    passes) and with a second round of passes for the screen."""
+    import numpy as np
+    from kc_cases import pack_reads, random_reads
+    reads = random_reads(100 + k, 1500, 5, 160, genome_len=3000)
+    b, o = pack_reads(reads)
+    tags = np.array([i % 2 for i in range(len(reads))], np.uint8) if nc == 2 else None
+    p = oracle.Params(k=k, n_counters=nc, m_log2=m_log2, h=h, block_log2=bl, seed=k * 7 + 1)
+    ref = oracle.count(p, b, o, tags=tags)
+    got = oracle.count_ranges(p, b, o, tags=tags, qbits=qbits, threads=threads, keep_singles=keep)
+    assert np.array_equal(got.keys, ref.keys)
+    assert np.array_equal(got.counts, ref.counts)
+    assert np.array_equal(got.b1, ref.b1) and np.array_equal(got.b2, ref.b2)
+    assert got.stats == ref.stats
+
+
+def test_value_range_passes_match_brute_force():
+    """The range passes against the string-level brute force directly."""
+    import numpy as np
+    from kc_cases import pack_reads, random_reads
+    reads = random_reads(7, 300, 8, 60, genome_len=400)
+    b, o = pack_reads(reads)
+    p = oracle.Params(k=9, m_log2=10, h=3, block_log2=4, seed=5)
+    got = oracle.count_ranges(p, b, o, qbits=5, threads=4)
+    t, b1, b2, st = brute.count(reads, 9, 10, 3, 4, 5)
+    assert {int(x): (int(c),) for x, c in zip(got.keys, got.counts[:, 0])} == t
+    bits = lambda v: {w * 64 + j for w in range(v.size) for j in range(64) if (int(v[w]) >> j) & 1}
+    assert bits(got.b1) == b1 and bits(got.b2) == b2
+    assert got.stats == st
+
+
+def test_digest_file_reproduces_from_the_oracle():
+    """The committed whole-output digest of the 1 Mbp workload is what the
+    oracle gives now (the GPU tests compare against these files)."""
+    import os
+    import numpy as np
+    import synth
+    from digest import read_digest_file, table_digests, words_digest
+    from conftest import GOLDEN
+    w = synth.WORKLOADS["plain_1mbp"]
+    g = w.make_genome()
+    b, o = w.make_reads(g)
+    p = oracle.Params(k=w.k, m_log2=w.bloom_bits_log2, h=w.bloom_hashes,
+                      block_log2=w.bloom_block_log2, seed=w.seed)
+    res = oracle.count(p, b, o)
+    want = read_digest_file(os.path.join(GOLDEN, "digest_plain_1mbp.txt"))
+    got = table_digests(res.keys, res.counts, w.k)
+    assert got["sha256"] == want["sha256"]
+    assert [tuple(r) for r in got["ranges"]] == want["ranges"]
+    assert words_digest(res.b1) == want["b1"] and words_digest(res.b2) == want["b2"]
+    assert want["stats"]["fp_singletons"] == res.stats["fp_singletons"]
+    assert want["stats"]["n_pass"] == res.stats["n_pass"]
+    assert int(np.unpackbits(res.b1.view(np.uint8)).sum()) == want["stats"]["b1_popcount"]
+
+
+def test_sparse_bloom_output_is_the_nonzero_words():
+    """want_bloom="sparse" lists exactly the nonzero level-1 words and both
+    levels there (the GPU tests of filters of 2^33 bits and more compare
+    these words and the popcounts)."""
+    import numpy as np
+    from kc_cases import pack_reads, random_reads
+    reads = random_reads(9, 500, 20, 120, genome_len=1500)
+    b, o = pack_reads(reads)
+    p = oracle.Params(k=15, m_log2=22, h=4, block_log2=10, seed=4)
+    full = oracle.count(p, b, o)
+    for fn in (oracle.count, lambda *a, **kw: oracle.count_ranges(*a, threads=3, **kw)):
+        sp = fn(p, b, o, want_bloom="sparse")
+        nz = np.flatnonzero(full.b1)
+        assert np.array_equal(sp.touched, nz)
+        assert np.array_equal(sp.t1, full.b1[nz]) and np.array_equal(sp.t2, full.b2[nz])
+        assert not full.b2[full.b1 == 0].any()
+        assert sp.stats == full.stats
