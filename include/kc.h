@@ -272,6 +272,27 @@ kc_status kc_filter_reads(kc_ctx* ctx, const uint8_t* bases_dev, const uint64_t*
                           uint64_t n_reads, uint64_t total_bases, uint32_t tumour_min,
                           uint32_t normal_max, uint32_t* out_dev, void* hip_stream);
 
+/* Largest read batch (bases) of kc_filter_reads_noalloc. */
+#define KC_FILTER_NOALLOC_MAX_BASES (1ull << 25)
+
+/*
+ * kc_filter_reads for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, results and errors as kc_filter_reads, and the same
+ * kernels; it calls no device or host allocator.  Its scratch (packed words,
+ * flag words and the window bitmap of up to KC_FILTER_NOALLOC_MAX_BASES
+ * bases, 20 MiB) is one array per GPU, held by the library from the first
+ * kc_create on that GPU until the process ends; a batch of more bases
+ * returns KC_ERR_INVALID_ARG.  Every call on a GPU uses that GPU's one
+ * array, so calls that overlap in time on one GPU (from any context, stream
+ * or thread) race and give undefined results; calls that follow each other
+ * on one stream, or are synchronised, are safe.  Synchronises.
+ */
+kc_status kc_filter_reads_noalloc(kc_ctx* ctx, const uint8_t* bases_dev,
+                                  const uint64_t* offsets_dev, uint64_t n_reads,
+                                  uint64_t total_bases, uint32_t tumour_min, uint32_t normal_max,
+                                  uint32_t* out_dev, void* hip_stream);
+
 /*
  * Debug view of pass 1: every stored key occurrence (x | counter << 62) and the
  * partition it was shuffled to, segment by segment in storage order.  With

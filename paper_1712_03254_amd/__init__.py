@@ -37,7 +37,8 @@ EXPORTED = ["kc_abi_version", "kc_status_str", "kc_create", "kc_insert_reads", "
             "kc_get_stats", "kc_reset", "kc_destroy", "kc_last_error", "kc_count_batch",
             "kc_autotune_batch", "kc_server_create", "kc_server_submit", "kc_server_wait",
             "kc_server_release", "kc_server_usage", "kc_server_destroy", "kc_server_set_overlap",
-            "kc_export_stems", "kc_filter_reads", "kc_checkpoint", "kc_restore"]
+            "kc_export_stems", "kc_filter_reads", "kc_filter_reads_noalloc", "kc_checkpoint",
+            "kc_restore"]
 
 
 class KcError(RuntimeError):
@@ -135,6 +136,7 @@ def load():
         "kc_export_bloom_words": ([V, V, U64, V, V], st),
         "kc_export_stems": ([V, V, V, U64, P(U64), V], st),
         "kc_filter_reads": ([V, V, V, U64, U64, U32, U32, V, V], st),
+        "kc_filter_reads_noalloc": ([V, V, V, U64, U64, U32, U32, V, V], st),
         "kc_checkpoint": ([V, ctypes.c_char_p], st),
         "kc_restore": ([ctypes.c_char_p, ctypes.c_int, P(V)], st),
         "kc_debug_keys": ([V, V, V, U64, P(U64)], st),
@@ -456,6 +458,16 @@ class KmerCounter:
         _check(self.ctx, load().kc_filter_reads(self.ctx, bases.data_ptr(), offsets.data_ptr(), n,
                                                  bases.numel(), tumour_min, normal_max,
                                                  out.data_ptr(), _stream_ptr(stream)))
+        return out[:n]
+
+    def filter_reads_noalloc(self, bases, offsets, tumour_min: int, normal_max: int, out,
+                             stream=None):
+        """kc_filter_reads_noalloc: as filter_reads, into the caller's int32
+        device tensor `out` (n_reads entries), with no allocation inside."""
+        n = offsets.numel() - 1
+        _check(self.ctx, load().kc_filter_reads_noalloc(
+            self.ctx, bases.data_ptr(), offsets.data_ptr(), n, bases.numel(), tumour_min,
+            normal_max, out.data_ptr(), _stream_ptr(stream)))
         return out[:n]
 
     def export_stems(self, stream=None):

@@ -278,8 +278,8 @@ struct StageTimer {
   hipStream_t s;
   hipEvent_t a = nullptr;
   int id;
-  StageTimer(kc_ctx* c_, hipStream_t s_, int id_) : c(c_), s(s_), id(id_) {
-    a = take_event(c);
+  StageTimer(kc_ctx* c_, hipStream_t s_, int id_, bool on = true) : c(c_), s(s_), id(id_) {
+    a = on ? take_event(c) : nullptr;
     if (a) (void)hipEventRecord(a, s);
   }
   void stop() {
@@ -683,6 +683,103 @@ kc_status reconfigure(kc_ctx* c, const kc_config* cfg, hipStream_t s) {
 
 }  // namespace kc
 
+// Filter-unit lookup: the reads are packed and their read starts marked as
+// for an insert, then every window is looked up in the final tables (bitmap
+// of selected windows) and each read's selected windows are counted.  The
+// packed words, flag words and window bitmap are scratch: every word of them
+// that a kernel reads is written earlier in the same call.
+namespace {
+
+kc_status filter_checks(kc_ctx* c, const uint8_t* bases, const uint64_t* offsets, uint64_t n_reads,
+                        uint64_t total_bases, uint32_t* out) {
+  if (c->state != FINALIZED) return fail(c, KC_ERR_BAD_STATE, "filter before finalize");
+  if (!c->spill_dir.empty())
+    return fail(c, KC_ERR_BAD_STATE, "filter needs every partition table in HBM (tables were spilled)");
+  if (n_reads == 0) return KC_OK;
+  if (!offsets || !out || (total_bases && !bases))
+    return fail(c, KC_ERR_INVALID_ARG, "NULL read or output buffer");
+  if (total_bases > 0xFFFFFFFFull) return fail(c, KC_ERR_INVALID_ARG, "more than 2^32 - 1 bases in one call");
+  return KC_OK;
+}
+
+kc_status filter_run(kc_ctx* c, const uint8_t* bases, const uint64_t* offsets, uint64_t n_reads,
+                     uint64_t total_bases, uint32_t tumour_min, uint32_t normal_max, uint32_t* out,
+                     hipStream_t s, uint64_t* packed, uint64_t* flags, uint32_t* hit, bool timed) {
+  const uint64_t nwords = (total_bases + 31) / 32;
+  KC_HIP(c, launch_fill32(c->derr.as<uint32_t>(), 1, 0, s), "fill");
+  QueryArgs a{};
+  a.hc = c->hc;
+  a.cap = c->cap;
+  a.probe_limit = probe_limit_of(c->cap);
+  a.tkeys = c->tkeys.as<uint64_t>();
+  a.tcounts = c->tcounts.as<uint32_t>();
+  a.slot_of = c->slot_of.as<uint32_t>();
+  a.okeys = c->okeys.as<uint64_t>();
+  a.ocounts = c->ocounts.as<uint32_t>();
+  a.ovf_used = c->ovf_used.as<uint32_t>();
+  a.ovf_log2 = c->ovf_log2;
+  a.err = c->derr.as<uint32_t>();
+  {
+    StageTimer t(c, s, KC_T_FILTER, timed);
+    KC_HIP(c, launch_pack(bases, total_bases, nwords, packed, flags, s), "pack");
+    KC_HIP(c, launch_rstart(offsets, n_reads, total_bases, flags, c->derr.as<uint32_t>(), s),
+           "read starts");
+    KC_HIP(c, launch_filter(a, packed, flags, nwords, offsets, n_reads, total_bases, tumour_min,
+                            normal_max, hit, out, s),
+           "filter");
+    t.stop();
+  }
+  uint32_t errf = 0;
+  kc_status r = sync_read(c, s, c->derr.p, 4, &errf);
+  if (r != KC_OK) return r;
+  if (errf & ERR_OFFSETS)
+    return fail(c, KC_ERR_INVALID_ARG,
+                "offsets must start at 0, be non-decreasing and end at total_bases");
+  return KC_OK;
+}
+
+// Scratch of kc_filter_reads_noalloc: packed words, flag words and the
+// window bitmap of up to KC_FILTER_NOALLOC_MAX_BASES bases, one copy per
+// GPU for the life of the process.  Host code never uses the array's name
+// as an address: its device address comes from hipGetSymbolAddress, once per
+// device (noalloc_scratch), and that address is what the kernels receive.
+constexpr uint64_t kNaWords = KC_FILTER_NOALLOC_MAX_BASES / 32;
+constexpr size_t kNaPackedOff = 0;
+constexpr size_t kNaFlagsOff = kNaWords * 8;
+constexpr size_t kNaHitOff = kNaWords * 16;
+constexpr size_t kNaBytes = kNaWords * 20;
+static_assert(KC_FILTER_NOALLOC_MAX_BASES % 32 == 0 && kNaFlagsOff % 256 == 0 && kNaHitOff % 256 == 0,
+              "scratch layout");
+__device__ __align__(256) uint8_t scratch[kNaBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (which must be current),
+// looked up once per device.
+kc_status noalloc_scratch(int device, void** out, std::string* why) {
+  if (device < 0 || device >= kMaxDevices) {
+    *why = "device index too large for the scratch table";
+    return KC_ERR_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      *why = std::string("hipGetSymbolAddress of the filter scratch: ") + hipGetErrorString(e);
+      return KC_ERR_DEVICE;
+    }
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return KC_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 uint32_t kc_abi_version(void) { return KC_ABI_VERSION; }
@@ -740,6 +837,11 @@ kc_status kc_create(const kc_config* cfg, int device, kc_ctx** out) {
   };
   if (hipSetDevice(device) != hipSuccess) return bail(KC_ERR_DEVICE, "hipSetDevice failed");
   kc::keep_pool_memory(device);
+  {
+    void* scratch_ptr = nullptr;
+    std::string why;
+    if (noalloc_scratch(device, &scratch_ptr, &why) != KC_OK) return bail(KC_ERR_DEVICE, why);
+  }
   const size_t bloom_bytes = c->bloom_words64 * 8;
   if (c->b1.ensure(bloom_bytes) != hipSuccess || c->b2.ensure(bloom_bytes) != hipSuccess)
     return bail(KC_ERR_OUT_OF_MEMORY, "Bloom level allocation failed");
@@ -1152,20 +1254,13 @@ kc_status kc_query(kc_ctx* c, const uint64_t* kmers, uint64_t n, uint32_t* count
   return KC_OK;
 }
 
-// Filter-unit lookup: the reads are packed and their read starts marked as
-// for an insert, then every window is looked up in the final tables (bitmap
-// of selected windows) and each read's selected windows are counted.
+
 kc_status kc_filter_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offsets,
                           uint64_t n_reads, uint64_t total_bases, uint32_t tumour_min,
                           uint32_t normal_max, uint32_t* out, void* hip_stream) {
   if (!c) return KC_ERR_INVALID_ARG;
-  if (c->state != FINALIZED) return fail(c, KC_ERR_BAD_STATE, "filter before finalize");
-  if (!c->spill_dir.empty())
-    return fail(c, KC_ERR_BAD_STATE, "filter needs every partition table in HBM (tables were spilled)");
-  if (n_reads == 0) return KC_OK;
-  if (!offsets || !out || (total_bases && !bases))
-    return fail(c, KC_ERR_INVALID_ARG, "NULL read or output buffer");
-  if (total_bases > 0xFFFFFFFFull) return fail(c, KC_ERR_INVALID_ARG, "more than 2^32 - 1 bases in one call");
+  kc_status r = filter_checks(c, bases, offsets, n_reads, total_bases, out);
+  if (r != KC_OK || n_reads == 0) return r;
   hipStream_t s = as_stream(hip_stream);
   kc::AllocStream alloc_on(s);
   KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
@@ -1175,38 +1270,30 @@ kc_status kc_filter_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offse
   KC_HIP(c, packed.ensure(nwords * 8), "packed buffer");
   KC_HIP(c, flags.ensure(nwords * 8), "flag buffer");
   KC_HIP(c, hit.ensure(nwords * 4), "window bitmap");
-  KC_HIP(c, launch_fill32(c->derr.as<uint32_t>(), 1, 0, s), "fill");
-  QueryArgs a{};
-  a.hc = c->hc;
-  a.cap = c->cap;
-  a.probe_limit = probe_limit_of(c->cap);
-  a.tkeys = c->tkeys.as<uint64_t>();
-  a.tcounts = c->tcounts.as<uint32_t>();
-  a.slot_of = c->slot_of.as<uint32_t>();
-  a.okeys = c->okeys.as<uint64_t>();
-  a.ocounts = c->ocounts.as<uint32_t>();
-  a.ovf_used = c->ovf_used.as<uint32_t>();
-  a.ovf_log2 = c->ovf_log2;
-  a.err = c->derr.as<uint32_t>();
-  {
-    StageTimer t(c, s, KC_T_FILTER);
-    KC_HIP(c, launch_pack(bases, total_bases, nwords, packed.as<uint64_t>(), flags.as<uint64_t>(), s),
-           "pack");
-    KC_HIP(c, launch_rstart(offsets, n_reads, total_bases, flags.as<uint64_t>(), c->derr.as<uint32_t>(),
-                            s),
-           "read starts");
-    KC_HIP(c, launch_filter(a, packed.as<uint64_t>(), flags.as<uint64_t>(), nwords, offsets, n_reads,
-                            total_bases, tumour_min, normal_max, hit.as<uint32_t>(), out, s),
-           "filter");
-    t.stop();
-  }
-  uint32_t errf = 0;
-  kc_status r = sync_read(c, s, c->derr.p, 4, &errf);
-  if (r != KC_OK) return r;
-  if (errf & ERR_OFFSETS)
+  return filter_run(c, bases, offsets, n_reads, total_bases, tumour_min, normal_max, out, s,
+                    packed.as<uint64_t>(), flags.as<uint64_t>(), hit.as<uint32_t>(), true);
+}
+
+kc_status kc_filter_reads_noalloc(kc_ctx* c, const uint8_t* bases, const uint64_t* offsets,
+                                  uint64_t n_reads, uint64_t total_bases, uint32_t tumour_min,
+                                  uint32_t normal_max, uint32_t* out, void* hip_stream) {
+  if (!c) return KC_ERR_INVALID_ARG;
+  kc_status r = filter_checks(c, bases, offsets, n_reads, total_bases, out);
+  if (r != KC_OK || n_reads == 0) return r;
+  if (total_bases > KC_FILTER_NOALLOC_MAX_BASES)
     return fail(c, KC_ERR_INVALID_ARG,
-                "offsets must start at 0, be non-decreasing and end at total_bases");
-  return KC_OK;
+                "more bases than the allocation-free filter's scratch holds (" +
+                    std::to_string((unsigned long long)KC_FILTER_NOALLOC_MAX_BASES) + ")");
+  KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
+  void* base = nullptr;
+  std::string why;
+  r = noalloc_scratch(c->device, &base, &why);
+  if (r != KC_OK) return fail(c, r, why);
+  uint8_t* p = static_cast<uint8_t*>(base);
+  return filter_run(c, bases, offsets, n_reads, total_bases, tumour_min, normal_max, out,
+                    as_stream(hip_stream), reinterpret_cast<uint64_t*>(p + kNaPackedOff),
+                    reinterpret_cast<uint64_t*>(p + kNaFlagsOff),
+                    reinterpret_cast<uint32_t*>(p + kNaHitOff), false);
 }
 
 // ------------------------------------------------------------ checkpoints
