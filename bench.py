@@ -64,22 +64,34 @@ def stage_alu_ops(stage: str, w, st: dict) -> float:
 
 
 def stage_bytes(stage: str, w, st: dict, cfg_eff: dict) -> float:
-    """Algorithmic HBM bytes of one launch of a stage (what the algorithm must
-    move at least once), from the input's shape and the run's statistics."""
+    """Algorithmic HBM bytes of a stage over one step (the whole input): the
+    per-k-mer terms of the shuffle-once design (input, shuffle, Bloom, table,
+    output) that fall in that stage, times the units of the step.  N valid k-mers, B
+    bases, W = B/32 packed words, m Bloom bits per level, E table entries:
+      pack    ASCII read + packed and flag words written: B + 16 W
+      level1  packed and flag words read + keys written: 16 W + 8 N
+      level2  keys read and written (the second scatter level): 16 N
+      bloom   keys read + both levels written once, read once: 8 N + 4 m/8
+      tally   keys read + level 2 read + table initialised and read back at
+              load factor 1/2 + entries written: 8 N + m/8 + 2*S*E/0.5 + S*E
+              (S = 8 + 4 n_counters bytes per slot)
+    """
     total_bases, n_reads = cfg_eff["total_bases"], cfg_eff["n_reads"]
     nwords = (total_bases + 31) // 32
     n = st["n_valid"]
-    if stage == "pack":      # ASCII in, 2-bit words + flag words out, offsets in
+    m = 1 << w.bloom_bits_log2
+    slot = 8 + 4 * w.n_counters
+    if stage == "pack":
         return total_bases + nwords * 16 + (n_reads + 1) * 8
-    if stage == "level1":    # packed + flags in, 8 B keys out
+    if stage == "level1":
         return nwords * 16 + n * 8
-    if stage == "level2":    # keys in and out
+    if stage == "level2":
         return n * 16
-    if stage == "bloom":     # keys in, both Bloom levels out
-        return n * 8 + 2 * (1 << w.bloom_bits_log2) // 8
-    if stage == "tally":     # keys in, partition tables out
-        tables = (1 << cfg_eff["partitions_log2"]) * cfg_eff["table_slots"] * (8 + 4 * w.n_counters)
-        return n * 8 + tables
+    if stage == "bloom":
+        return n * 8 + 4 * m // 8
+    if stage == "tally":
+        e = st["entries"]
+        return n * 8 + m // 8 + 2 * slot * e / 0.5 + slot * e
     if stage == "query":
         return QUERY_BATCH * (8 + 4 * w.n_counters)
     if stage == "graph":     # every stage of the batch in one launch
@@ -88,19 +100,63 @@ def stage_bytes(stage: str, w, st: dict, cfg_eff: dict) -> float:
     return 0.0
 
 
-def cpu_baseline(w, genome, n_reads=450_000):
+def host_description() -> dict:
+    """The host the CPU baseline ran on: logical CPUs, CPUs this process may
+    use, CPU model and RAM."""
+    model, mem_kb = "", 0
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    mem_kb = int(line.split()[1])
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": model,
+            "ram_gib": round(mem_kb / 2**20, 1)}
+
+
+def cpu_baseline(w, genome, n_reads=3_000_000):
+    """The CPU oracle on the host's cores: value-range passes over the first
+    n_reads reads of the workload (threads split the reads, one value range of
+    the k-mer space per thread, Bloom levels, screen and table), timed from
+    reads in host memory to the final result.  Threads: the CPUs this process
+    may use, at most 16 (the host share of one GPU).  Beside it, one core on
+    the whole 1 Mbp workload."""
     import oracle
     b, o = w.make_reads(genome, first=0, n=n_reads, threads=16)
     p = oracle.Params(k=w.k, n_counters=w.n_counters, min_count=w.min_count,
                       m_log2=w.bloom_bits_log2, h=w.bloom_hashes, block_log2=w.bloom_block_log2,
                       seed=w.seed)
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
     t0 = time.perf_counter()
-    r = oracle.count(p, b, o, want_bloom=False)
+    r = oracle.count_ranges(p, b, o, want_bloom=False, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": r.stats["n_valid"] / dt, "unit": "k-mers/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d reads of %s (%d k-mers): sort + run-length count, Bloom levels, "
-                      "screen and table in %.1f s on one host core"
-                      % (n_reads, WORKLOAD, r.stats["n_valid"], dt)}
+    del b, o
+    import synth
+    w1 = synth.WORKLOADS["plain_1mbp"]
+    g1 = w1.make_genome()
+    b1, o1 = w1.make_reads(g1)
+    p1 = oracle.Params(k=w1.k, m_log2=w1.bloom_bits_log2, h=w1.bloom_hashes,
+                       block_log2=w1.bloom_block_log2, seed=w1.seed)
+    t1 = time.perf_counter()
+    r1 = oracle.count(p1, b1, o1, want_bloom=False)
+    dt1 = time.perf_counter() - t1
+    return {"value": r.stats["n_valid"] / dt, "unit": "k-mers/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "first %d reads of %s (%d k-mers, %.1f%% of the workload): value-range "
+                      "passes on %d threads, sort + run-length count, Bloom levels, screen and "
+                      "table in %.1f s"
+                      % (n_reads, w.name, r.stats["n_valid"], 100.0 * n_reads / w.n_reads,
+                         threads, dt),
+            "host": host_description(),
+            "single_core_1mbp": {"value": r1.stats["n_valid"] / dt1, "unit": "k-mers/s",
+                                 "seconds": round(dt1, 2), "kmers": r1.stats["n_valid"]}}
 
 
 def atomic_summary(w, st: dict, stages: dict) -> dict:
@@ -403,7 +459,7 @@ def served_main(args, w):
         "best_served_kmers_per_s": best["kmers_per_s"],
         "input_gen_s": round(gen_s, 2),
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -429,6 +485,15 @@ def main():
                     help="plain workloads: also time kc_checkpoint to this path and kc_restore from it")
     ap.add_argument("--loads", type=float, nargs="*", default=[0.3, 0.5, 0.7, 0.9],
                     help="served workload: offered loads as fractions of the plain capacity")
+    ap.add_argument("--legs", default="",
+                    help="comma-separated extra workloads run after the main one, each in a child "
+                         "process, their results added to the line (batched,served,large); default: "
+                         "all three with the default workload, none otherwise")
+    ap.add_argument("--lean", action="store_true",
+                    help="skip the stem, filter and atomics extras after the timed steps")
+    ap.add_argument("--spill-budget-gib", type=float, default=0.0,
+                    help="plain workloads: after the timed steps, count once more under this HBM "
+                         "table budget and report the spill")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.command)
@@ -443,15 +508,26 @@ def main():
 
     import torch
     import synth
-    import paper_1712_03254_amd as kc
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     w = synth.WORKLOADS[args.workload]
     if w.requests:
-        served_main(args, w)
-        return
+        out = served_main(args, w)
+    else:
+        out = count_main(args, w)
+    legs = args.legs if args.legs else ("batched,served,large" if args.workload == WORKLOAD
+                                        else "none")
+    for leg in [x for x in legs.split(",") if x and x != "none"]:
+        out[leg] = run_leg(leg, args)
+    print(json.dumps(out), flush=True)
+
+
+def count_main(args, w) -> dict:
+    """Plain and batched workloads: warm-up, then the timed steps."""
+    import torch
+    import paper_1712_03254_amd as kc
     kc.load()
     batched = w.batch_chunks > 0
     t0 = time.perf_counter()
@@ -464,9 +540,15 @@ def main():
         n_reads = int(sizes.sum())
         total_bases = int(sum(int(o[-1]) for _, o in host_chunks))
     else:
-        bases, offsets = w.make_reads(genome, threads=16)
-        host_chunks = [(bases, offsets)]
-        n_reads, total_bases = w.n_reads, int(offsets[-1])
+        # one insert takes fewer than 2^32 bases: larger inputs go in as
+        # consecutive slices of the read stream
+        per = w.n_reads
+        while per * w.lmax >= 1 << 32:
+            per = (per + 1) // 2
+        host_chunks = [w.make_reads(genome, first=f, n=min(per, w.n_reads - f), threads=16)
+                       for f in range(0, w.n_reads, per)]
+        n_reads = w.n_reads
+        total_bases = int(sum(int(o[-1]) for _, o in host_chunks))
     gen_s = time.perf_counter() - t0
     pinned = [(torch.from_numpy(b).pin_memory(), torch.from_numpy(o.view(np.int64)).pin_memory())
               for b, o in host_chunks]
@@ -502,14 +584,18 @@ def main():
             counter.query(q, stream=stream)
         return counter.stats() if q is not None else st
 
-    # query batch: half present (from the table), half random codes
-    step()
-    keys, _ = counter.export()
+    # query batch: half present (from the table), half random codes (all random
+    # when the table is too large to copy to the host in passing)
+    first = step()
     rng = np.random.default_rng(1)
-    half = QUERY_BATCH // 2
-    qk = np.concatenate([keys[rng.integers(0, keys.size, half)],
-                         rng.integers(0, 1 << (2 * w.k), QUERY_BATCH - half, dtype=np.uint64)])
-    del keys
+    half = QUERY_BATCH // 2 if first["entries"] <= 1 << 28 else 0
+    present = np.zeros(0, np.uint64)
+    if half:
+        keys, _ = counter.export()
+        present = keys[rng.integers(0, keys.size, half)]
+        del keys
+    qk = np.concatenate([present, rng.integers(0, 1 << (2 * w.k), QUERY_BATCH - half,
+                                               dtype=np.uint64)])
     q = torch.from_numpy(qk.view(np.int64)).to(dev)
     for _ in range(args.warmup):
         step(q)
@@ -565,7 +651,9 @@ def main():
     for s in per_stage_ms:
         if per_stage_n.get(s):
             avg = per_stage_ms[s] / per_stage_n[s]
-            b = stage_bytes(s, w, last, cfg_eff)
+            # stage_bytes covers the whole input; a stage launched once per insert
+            # (or per spill wave) moves its share of it per launch
+            b = stage_bytes(s, w, last, cfg_eff) / (per_stage_n[s] / args.steps)
             ops = stage_alu_ops(s, w, last)
             stages[s] = {"avg_ms": round(avg, 4), "launches_per_step": per_stage_n[s] / args.steps,
                          "alg_bytes": b,
@@ -575,7 +663,9 @@ def main():
     d = stages[dom]
     hbm_frac = d["gbs"] / HBM_PEAK_GBS if d["gbs"] else 0.0
     roofline = {"bound": "hbm", "kernel": STAGE_KERNEL.get(dom, dom), "achieved": d["gbs"],
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(hbm_frac, 4), "traffic": None}
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(hbm_frac, 4), "traffic": None,
+                "time_source": "HIP events on the launch stream, averaged over the timed steps",
+                "alg_bytes_per_launch": d["alg_bytes"], "avg_ms": d["avg_ms"]}
     ops = stage_alu_ops(dom, w, last)
     if ops:
         tops = ops / (d["avg_ms"] * 1e-3) / 1e12
@@ -617,26 +707,26 @@ def main():
         out["autotune"] = tune
     if plain_same is not None:
         out["plain_same_workload"] = plain_same
-    if not batched:
+    if not batched and not args.lean:
         out["atomics"] = atomic_summary(w, last, stages)
         out["stem_relayout"] = stem_relayout(counter)
         out["filter_lookup"] = filter_lookup(counter, chunks, n_valid)
-        if args.checkpoint:
-            t_a = time.perf_counter()
-            counter.checkpoint(args.checkpoint)
-            t_b = time.perf_counter()
-            with kc.KmerCounter.restore(args.checkpoint) as back:
-                torch.cuda.synchronize()
-                t_c = time.perf_counter()
-                same = all(back.stats()[k] == last[k] for k in ("entries", "sum_counts", "n_valid",
-                                                                  "fp_singletons", "b2_popcount"))
-            size = os.path.getsize(args.checkpoint)
-            os.remove(args.checkpoint)
-            out["checkpoint"] = {"bytes": size, "write_s": round(t_b - t_a, 3),
-                                 "restore_s": round(t_c - t_b, 3),
-                                 "write_gbs": round(size / (t_b - t_a) / 1e9, 2),
-                                 "restore_gbs": round(size / (t_c - t_b) / 1e9, 2),
-                                 "restored_stats_equal": same}
+    if not batched and args.checkpoint:
+        t_a = time.perf_counter()
+        counter.checkpoint(args.checkpoint)
+        t_b = time.perf_counter()
+        with kc.KmerCounter.restore(args.checkpoint) as back:
+            torch.cuda.synchronize()
+            t_c = time.perf_counter()
+            same = all(back.stats()[k] == last[k] for k in ("entries", "sum_counts", "n_valid",
+                                                              "fp_singletons", "b2_popcount"))
+        size = os.path.getsize(args.checkpoint)
+        os.remove(args.checkpoint)
+        out["checkpoint"] = {"bytes": size, "write_s": round(t_b - t_a, 3),
+                             "restore_s": round(t_c - t_b, 3),
+                             "write_gbs": round(size / (t_b - t_a) / 1e9, 2),
+                             "restore_gbs": round(size / (t_c - t_b) / 1e9, 2),
+                             "restored_stats_equal": same}
     if args.copy_probe:
         src = torch.empty(COPY_BYTES, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -644,10 +734,86 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    counter.close()
+    if not batched and args.spill_budget_gib:
+        # the same count under a table budget smaller than all tables: the
+        # partitions past the budget are counted in waves and spilled to
+        # pinned host memory
+        import dataclasses
+        scfg = dataclasses.replace(cfg, hbm_table_budget_bytes=int(args.spill_budget_gib * 2**30))
+        with kc.KmerCounter(scfg) as sc:
+            def spill_count():
+                sc.reset()
+                for b, o in chunks:
+                    sc.insert_reads(b, o, stream=stream)
+                return sc.finalize(stream=stream)
+            spill_count()
+            torch.cuda.synchronize()
+            t_s = time.perf_counter()
+            sst = spill_count()
+            torch.cuda.synchronize()
+            dt_s = time.perf_counter() - t_s
+        out["spill"] = {"budget_bytes": scfg.hbm_table_budget_bytes,
+                        "kmers_per_s": sst["n_valid"] / dt_s, "ms": round(dt_s * 1e3, 1),
+                        "spilled_partitions": sst["spilled_partitions"],
+                        "spilled_bytes": sst["spilled_bytes"],
+                        "kernel_ms": {k: round(v, 2) for k, v in sst["kernel_ms"].items() if v},
+                        "same_result": all(sst[k] == last[k] for k in (
+                            "n_valid", "n_pass", "entries", "sum_counts", "fp_singletons",
+                            "b1_popcount", "b2_popcount"))}
+    del chunks, pinned, q
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, genome)
-    counter.close()
-    print(json.dumps(out), flush=True)
+    return out
+
+
+LEG_WORKLOAD = {"batched": "batched_200mbp", "served": "served_300mbp", "large": "spill_3gbp"}
+
+
+def run_leg(leg: str, args) -> dict:
+    """One extra workload in a child process (its own device memory), reduced
+    to the figures that compare it with the plain path."""
+    import subprocess
+    wl = LEG_WORKLOAD[leg]
+    cmd = [sys.executable, os.path.abspath(__file__), "--workload", wl, "--legs", "none",
+           "--no-cpu-baseline"]
+    if leg == "batched":
+        cmd += ["--steps", "3", "--warmup", "1"]
+    elif leg == "large":
+        cmd += ["--steps", "2", "--warmup", "1", "--lean", "--spill-budget-gib", "24"]
+    print("leg %s: %s" % (leg, " ".join(cmd[1:])), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    res = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
+    wall = round(time.perf_counter() - t0, 1)
+    lines = [l for l in res.stdout.splitlines() if l.startswith("{")]
+    if res.returncode != 0 or not lines:
+        return {"workload": wl, "status": "failed", "rc": res.returncode, "wall_s": wall}
+    r = json.loads(lines[-1])
+    print("leg %s done in %.1f s" % (leg, wall), file=sys.stderr, flush=True)
+    if leg == "served":
+        return {"workload": wl, "wall_s": wall,
+                "served_kmers_per_s": r["served_closed_loop"]["kmers_per_s"],
+                "plain_kmers_per_s": r["plain_closed_loop"]["kmers_per_s"],
+                "served_vs_plain": r["served_vs_plain"],
+                "closed_loop_p99_ms": {"served": r["served_closed_loop"]["p99_ms"],
+                                       "plain": r["plain_closed_loop"]["p99_ms"]},
+                "latency_by_offered_load": {
+                    rho: {side: {k: v[side][k] for k in ("p50_ms", "p99_ms", "kmers_per_s")}
+                          for side in ("served", "plain")}
+                    for rho, v in r["latency_by_offered_load"].items()},
+                "config": r["config"]}
+    out = {"workload": wl, "wall_s": wall, "value": r["value"], "unit": r["unit"],
+           "ms_per_step": r["ms_per_step"], "roofline": r["roofline"],
+           "stages_ms": {k: v["avg_ms"] * v["launches_per_step"] for k, v in r["stages"].items()},
+           "step_alg_bytes_per_kmer": r["step_alg_bytes_per_kmer"],
+           "step_hbm_gbs": r["step_hbm_gbs"], "counts": r["counts"], "config": r["config"]}
+    for k in ("plain_same_workload", "autotune", "spill"):
+        if k in r:
+            out[k] = r[k]
+    if "plain_same_workload" in r:
+        out["batched_over_plain"] = r["plain_same_workload"]["batched_over_plain"]
+    return out
 
 
 if __name__ == "__main__":
