@@ -1121,62 +1121,43 @@ k_tally(const CountArgs A) {
   for (uint32_t i = threadIdx.x; i < cap * nc; i += kTallyThreads) tc[i] = 0;
   __syncthreads();
 
-  // Resolves the queued occurrences densely, 64 at a time.  Each walks its
-  // probe chain from the home slot: a key already in the table is counted
-  // there.  A key that reaches an empty slot (or the probe limit) is new: it
-  // is screened against level 2 and, if it passes, inserted from that slot on
-  // (CAS on the key, add on the count; a lost CAS continues the walk) or, at
-  // the probe limit, counted in the overflow table.  A failing key is
-  // dropped.
+  // Resolves the queued occurrences densely, 64 at a time.  Every queued key
+  // is screened against level 2 first: the words of its bit positions are
+  // loaded for all lanes at once.  Passing is a property of the key (S(x) in
+  // B2), so a key that fails is not in the table and is dropped, and a key
+  // that passes walks its probe chain with CAS from where the main loop left
+  // it (the home slot, or the slot after it when the home slot held another
+  // key): it is counted where it is found or inserted at the first empty
+  // slot (a CAS lost to another key walks on), or, past the probe limit,
+  // counted in the overflow table.
   auto drain = [&](uint32_t n) {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     const bool have = lane_id() < n;
     uint64_t key = 0;
-    uint32_t slot = 0;
+    uint32_t slot = 0, probes = 0;
     if (have) {
       key = qk[lane_id()];
       slot = qs[lane_id()];
+      // bit 31: the home slot held another key, so the walk starts after it
+      probes = slot >> 31;
+      slot &= 0x7FFFFFFFu;
+      if (probes) slot = slot + 1 == cap ? 0 : slot + 1;
     }
     const uint64_t x = key & kKeyMask;
     const uint32_t tag = (uint32_t)(key >> 62);
-    uint32_t probes = 0;
-    bool fresh = false;  // not in the table: needs the screen
-    if (have) {
-      for (;;) {
-        const uint64_t c =
-            __hip_atomic_load(&tk[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (c == x) {
-          atomicAdd(&tc[slot * nc + tag], 1u);
-          break;
-        }
-        if (c == kEmpty) {
-          fresh = true;
-          break;
-        }
-        slot = slot + 1 == cap ? 0 : slot + 1;
-        if (++probes >= limit) {
-          fresh = true;
-          break;
-        }
-      }
-    }
-    bool pass = false;
-    if (fresh) {
-      uint32_t w[H], p[H];
-      const uint64_t u = mix64(x ^ hc.salt[1]);
-      const uint32_t mask = (1u << hc.bl) - 1u;
-      const uint32_t a = (uint32_t)(u >> (64 - hc.bl));
-      const uint32_t b = (uint32_t)(u >> (64 - 2 * hc.bl)) & mask;
+    // positions a + i*b in the partition's Bloom block (in bounds for any x,
+    // so lanes without a key load too)
+    const uint64_t u = mix64(x ^ hc.salt[1]);
+    const uint32_t mask = (1u << hc.bl) - 1u;
+    const uint32_t a = (uint32_t)(u >> (64 - hc.bl));
+    const uint32_t b = (uint32_t)(u >> (64 - 2 * hc.bl)) & mask;
+    uint32_t w[H];
 #pragma unroll
-      for (int i = 0; i < H; ++i) {
-        const uint64_t g = bit0 + ((a + (uint32_t)i * b) & mask);
-        p[i] = (uint32_t)(g & 31);
-        w[i] = b2[g >> 5];
-      }
-      pass = true;
+    for (int i = 0; i < H; ++i) w[i] = b2[(bit0 + ((a + (uint32_t)i * b) & mask)) >> 5];
+    bool pass = have;
 #pragma unroll
-      for (int i = 0; i < H; ++i) pass &= ((w[i] >> p[i]) & 1u) != 0;
-    }
+    for (int i = 0; i < H; ++i)
+      pass &= ((w[i] >> ((uint32_t)(bit0 + ((a + (uint32_t)i * b) & mask)) & 31u)) & 1u) != 0;
     if (pass) {
       const uint64_t th = (x ^ hc.salt[0]) * kTableMul;
       for (;;) {
@@ -1185,12 +1166,9 @@ k_tally(const CountArgs A) {
           overflow_add(A, x, tag, mix64(th));
           break;
         }
-        uint64_t cur = __hip_atomic_load(&tk[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (cur == kEmpty) {
-          cur = atomicCAS(reinterpret_cast<unsigned long long*>(&tk[slot]),
-                          (unsigned long long)kEmpty, (unsigned long long)x);
-          if (cur == kEmpty) cur = x;
-        }
+        uint64_t cur = atomicCAS(reinterpret_cast<unsigned long long*>(&tk[slot]),
+                                 (unsigned long long)kEmpty, (unsigned long long)x);
+        if (cur == kEmpty) cur = x;
         if (cur == x) {
           atomicAdd(&tc[slot * nc + tag], 1u);
           break;
@@ -1233,15 +1211,16 @@ k_tally(const CountArgs A) {
       if (!nm) continue;
       const uint32_t rank = (uint32_t)__popcll(mb & ((1ull << lane_id()) - 1));
       const uint32_t room = 64 - qn;
+      const uint32_t qv = slot0[b] | (cur[b] != kEmpty ? 0x80000000u : 0u);
       if (miss && rank < room) {
         qk[qn + rank] = key;
-        qs[qn + rank] = slot0[b];
+        qs[qn + rank] = qv;
       }
       if (nm >= room) {
         drain(64);
         if (miss && rank >= room) {
           qk[rank - room] = key;
-          qs[rank - room] = slot0[b];
+          qs[rank - room] = qv;
         }
         qn = nm - room;
       } else {
