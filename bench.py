@@ -564,9 +564,11 @@ def count_main(args, w) -> dict:
         t_tune = time.perf_counter()
         cfg, trials = kc.autotune_batch(cfg, chunks, stream=stream)
         tune = {"chosen": {"partitions_log2": cfg.partitions_log2, "table_slots": cfg.table_slots,
-                           "scatter_bits": cfg.scatter_bits},
+                           "scatter_bits": cfg.scatter_bits,
+                           "shuffle_tile_log2": cfg.shuffle_tile_log2},
                 "trials": [[t["partitions_log2"], t["table_slots"], t["scatter_bits"],
-                            round(t["ms"], 3), t["status"]] for t in trials],
+                            t["shuffle_tile_log2"], round(t["ms"], 3), t["status"]]
+                           for t in trials],
                 "seconds": round(time.perf_counter() - t_tune, 1)}
     counter = kc.KmerCounter(cfg)
 

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define KC_ABI_VERSION 6u
+#define KC_ABI_VERSION 7u
 
 typedef struct kc_ctx kc_ctx;
 
@@ -91,6 +91,8 @@ typedef struct kc_config {
   uint32_t group_bases_log2; /* kc_count_batch: at most 2^this bases (with padding) per key
                                 segment; 0 = 2^32 - 64, else 10..32 */
   uint64_t hbm_table_budget_bytes; /* device bytes the partition tables may use; 0 = unlimited */
+  uint32_t shuffle_tile_log2; /* keys per second-level shuffle tile (log2), 10..13; 0 = 13 */
+  uint32_t reserved_;        /* 0 */
 } kc_config;
 
 /* Per-stage timers (kernel_ms indexes): sums of HIP-event durations. */
@@ -136,9 +138,16 @@ uint32_t kc_abi_version(void);
 /* Human-readable name of a status code (static string). */
 const char* kc_status_str(kc_status s);
 
-/* Creates a context on HIP device `device` and allocates its Bloom levels
- * (2 * 2^bloom_bits_log2 bits).  Validates cfg.  *out receives the context,
- * or NULL on failure (then kc_last_error(NULL) holds the reason). */
+/* Creates one counting unit on HIP device `device`: the state SMUFIN's
+ * counting unit holds across its pipeline cycles (Sec. II-B, Count unit;
+ * Sec. III: Prune's two chained Bloom filters and Count's frequency table),
+ * here a context that owns the two Bloom levels (allocated now, 2 *
+ * 2^bloom_bits_log2 bits, the configuration's k, counters, min_count, hash
+ * and partition parameters fixed for its life), the inserted keys and the
+ * partition tables.  Validates cfg and returns KC_ERR_INVALID_ARG for any
+ * field out of range, KC_ERR_OUT_OF_MEMORY when the levels do not fit.
+ * *out receives the context, which the caller frees with kc_destroy, or NULL
+ * on failure (then kc_last_error(NULL) holds the reason). */
 kc_status kc_create(const kc_config* cfg, int device, kc_ctx** out);
 
 /*
@@ -171,10 +180,16 @@ kc_status kc_insert_reads(kc_ctx* ctx, const uint8_t* bases_dev, const uint64_t*
 kc_status kc_finalize(kc_ctx* ctx, void* hip_stream, kc_stats* out_host);
 
 /*
- * Looks up n k-mers (2-bit codes < 4^k, either orientation): counts_dev[i *
- * n_counters + c] receives counter c of canonical(kmers_dev[i]) when its total
- * count is >= min_count, else 0.  Synchronises.  A code >= 4^k makes the call
- * return KC_ERR_INVALID_ARG (its output row is 0).
+ * Frequency-table lookups after Count and Unify (Sec. II-B: the Filter unit
+ * looks k-mers up in the final frequency table; Sec. III, Unify: the table
+ * holds the k-mers seen at least min_count times, false-positive singletons
+ * removed).  Looks up n k-mers given as 2-bit codes < 4^k in either
+ * orientation (kmers_dev[n], device, caller-owned): counts_dev[i * n_counters
+ * + c] (device, caller-owned, n * n_counters uint32) receives counter c of
+ * canonical(kmers_dev[i]) when its total count is >= min_count, else 0.
+ * Partitions spilled to pinned host memory are answered from their host
+ * copies.  After kc_finalize (else KC_ERR_BAD_STATE).  Synchronises.  A code
+ * >= 4^k makes the call return KC_ERR_INVALID_ARG (its output row is 0).
  */
 kc_status kc_query(kc_ctx* ctx, const uint64_t* kmers_dev, uint64_t n, uint32_t* counts_dev,
                    void* hip_stream);
@@ -344,15 +359,18 @@ typedef struct kc_tune_trial {
   int32_t status;          /* kc_status of the trial */
   double ms;               /* fastest of the timed kc_count_batch calls */
   uint64_t overflow_keys;
+  uint32_t shuffle_tile_log2;
+  uint32_t reserved_;
 } kc_tune_trial;
 
 /*
  * Chooses the result-neutral parameters of kc_count_batch for a batch by
- * measurement: partition count, table slots (load factor) and first-level
- * fan-out (the split of the shuffle between its two tile levels).  A
+ * measurement: partition count, table slots (load factor), first-level
+ * fan-out (the split of the shuffle between its two tile levels) and the
+ * second-level tile size (keys per shuffle workgroup, 2^13 down to 2^11).  A
  * coordinate search starts at about one partition per 2^13 key positions,
- * the default table and the automatic split, and steps along each dimension
- * while a neighbour is faster (at most 24 trials).  Each trial runs
+ * the default table, the automatic split and 2^13-key tiles, and steps along
+ * each dimension while a neighbour is faster (at most 28 trials).  Each trial runs
  * kc_count_batch on the batch itself, on a context of its own (the fastest
  * of two timed runs after one untimed).  The fastest configuration without
  * errors is written to *best_out (base's result-defining fields unchanged).

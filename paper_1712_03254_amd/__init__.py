@@ -54,7 +54,8 @@ class KcConfig(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("partitions_log2", ctypes.c_uint32),
                 ("table_slots", ctypes.c_uint32), ("scatter_bits", ctypes.c_uint32),
                 ("group_bases_log2", ctypes.c_uint32),
-                ("hbm_table_budget_bytes", ctypes.c_uint64)]
+                ("hbm_table_budget_bytes", ctypes.c_uint64),
+                ("shuffle_tile_log2", ctypes.c_uint32), ("reserved_", ctypes.c_uint32)]
 
 
 class KcStats(ctypes.Structure):
@@ -100,10 +101,11 @@ class KcServerStats(ctypes.Structure):
 class KcTuneTrial(ctypes.Structure):
     _fields_ = [("partitions_log2", ctypes.c_uint32), ("table_slots", ctypes.c_uint32),
                 ("scatter_bits", ctypes.c_uint32), ("status", ctypes.c_int32),
-                ("ms", ctypes.c_double), ("overflow_keys", ctypes.c_uint64)]
+                ("ms", ctypes.c_double), ("overflow_keys", ctypes.c_uint64),
+                ("shuffle_tile_log2", ctypes.c_uint32), ("reserved_", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
-        return {n: getattr(self, n) for n, _ in self._fields_}
+        return {n: getattr(self, n) for n, _ in self._fields_ if n != "reserved_"}
 
 
 def _status_name(s: int) -> str:
@@ -331,18 +333,21 @@ class Config:
     scatter_bits: int = 0
     hbm_table_budget_bytes: int = 0
     group_bases_log2: int = 0
+    shuffle_tile_log2: int = 0
 
     def c(self) -> KcConfig:
         return KcConfig(self.k, self.n_counters, self.min_count, self.bloom_bits_log2,
                         self.bloom_hashes, min(self.bloom_block_log2, self.bloom_bits_log2),
                         self.seed & ((1 << 64) - 1), self.partitions_log2, self.table_slots,
-                        self.scatter_bits, self.group_bases_log2, self.hbm_table_budget_bytes)
+                        self.scatter_bits, self.group_bases_log2, self.hbm_table_budget_bytes,
+                        self.shuffle_tile_log2, 0)
 
     @staticmethod
     def from_c(c: KcConfig) -> "Config":
         return Config(c.k, c.n_counters, c.min_count, c.bloom_bits_log2, c.bloom_hashes,
                       c.bloom_block_log2, c.seed, c.partitions_log2, c.table_slots,
-                      c.scatter_bits, c.hbm_table_budget_bytes, c.group_bases_log2)
+                      c.scatter_bits, c.hbm_table_budget_bytes, c.group_bases_log2,
+                      c.shuffle_tile_log2)
 
 
 def _stream_ptr(stream) -> int:

@@ -24,7 +24,8 @@ constexpr int kThreads = 1024;                  // block size of the tile kernel
 constexpr int kWaves = kThreads / 64;
 constexpr int kTileWords = 256;                 // first-level tile: 256 packed words
 constexpr int kTilePos = kTileWords * 32;       // = 8192 window positions
-constexpr int kT2 = 8192;                       // second-level tile: keys per workgroup
+constexpr int kT2 = 8192;                       // second-level tile: most keys per workgroup
+constexpr uint32_t kT2MinLog2 = 10;             // smallest second-level tile (log2 keys)
 constexpr int kMaxA1 = 10;                      // first-level fan-out limit (bits)
 constexpr int kMaxA2 = 11;                      // second-level fan-out limit (bits)
 constexpr int kMaxPartLog2 = kMaxA1 + kMaxA2;    // partitions (log2) two levels can reach
@@ -47,7 +48,7 @@ enum Err : uint32_t { ERR_OFFSETS = 1, ERR_OVF_FULL = 2, ERR_OVF_LOAD = 4, ERR_Q
 
 // One kc_insert_reads call: its keys grouped by partition.  Partition
 // u = c * 2^a2 + sub: first-level bucket c holds keys[bucket_off[c] ..
-// bucket_off[c+1]); with a2 > 0 that range is cut into tiles of kT2 keys
+// bucket_off[c+1]); with a2 > 0 that range is cut into tiles of 2^t2_log2 keys
 // (tile_first[c] .. tile_first[c+1]), and inside tile t the keys of sub-bucket
 // sub sit at [meta2[t*(2^a2+1)+sub], meta2[t*(2^a2+1)+sub+1]) of the tile.
 struct SegDesc {
@@ -56,6 +57,8 @@ struct SegDesc {
   const uint32_t* tile_first;
   const uint32_t* meta2;
   uint32_t a1, a2;
+  uint32_t t2_log2;  // keys per second-level tile (log2)
+  uint32_t pad_;
 };
 
 // One read chunk of a batch, placed in its group's position stream at
@@ -131,16 +134,17 @@ size_t scan_parts(uint64_t n);
 hipError_t launch_bucket_off(const uint64_t* off1, uint64_t ntiles, uint32_t nb1,
                              uint64_t* bucket_off, hipStream_t s);
 size_t level1_lds(uint32_t a1);
-size_t level2_lds(uint32_t a2);
+size_t level2_lds(uint32_t a2, uint32_t t2_log2);
 hipError_t launch_level1(const uint64_t* packed, const uint64_t* flags, uint64_t nwords,
                          uint32_t k, uint64_t s0, uint32_t a1, uint64_t tag, uint32_t* hist,
                          uint32_t* lstart, uint64_t ntiles, uint64_t* out, hipStream_t s);
-hipError_t launch_tiles2(const uint64_t* bucket_off, uint32_t nb1, uint32_t* tile_first,
-                         hipStream_t s);
+hipError_t launch_tiles2(const uint64_t* bucket_off, uint32_t nb1, uint32_t t2_log2,
+                         uint32_t* tile_first, hipStream_t s);
 hipError_t launch_level2(const uint64_t* keys1, const uint64_t* off1, const uint32_t* lstart,
                          uint64_t ntiles1, const uint64_t* bucket_off, const uint32_t* tile_first,
-                         uint64_t* tile_desc, uint32_t a1, uint32_t a2, uint64_t s0,
-                         uint64_t* keys2, uint32_t* meta2, uint64_t grid, hipStream_t s);
+                         uint64_t* tile_desc, uint32_t a1, uint32_t a2, uint32_t t2_log2,
+                         uint64_t s0, uint64_t* keys2, uint32_t* meta2, uint64_t grid,
+                         hipStream_t s);
 hipError_t launch_bloom(const CountArgs& a, uint32_t blocks, size_t lds, hipStream_t s);
 hipError_t launch_tally(const CountArgs& a, uint32_t parts, size_t lds, hipStream_t s);
 int tally_threads();

@@ -529,15 +529,15 @@ __global__ void k_bucket_off(const uint64_t* __restrict__ off1, uint64_t ntiles,
   if (c <= nb1) bucket_off[c] = off1[(uint64_t)c * ntiles];
 }
 
-// tile_first[c] = sum over c' < c of ceil(n_c' / kT2); tile_first[nb1] = total.
+// tile_first[c] = sum over c' < c of ceil(n_c' / 2^t2_log2); tile_first[nb1] = total.
 __global__ void __launch_bounds__(kThreads) k_tiles2(const uint64_t* __restrict__ bucket_off,
-                                                     uint32_t nb1,
+                                                     uint32_t nb1, uint32_t t2_log2,
                                                      uint32_t* __restrict__ tile_first) {
   __shared__ uint32_t cnt[kThreads];
   __shared__ uint32_t scratch[kWaves];
   for (uint32_t c = threadIdx.x; c < nb1; c += kThreads) {
     uint64_t n = bucket_off[c + 1] - bucket_off[c];
-    cnt[c] = (uint32_t)((n + kT2 - 1) / kT2);
+    cnt[c] = (uint32_t)((n + (1ull << t2_log2) - 1) >> t2_log2);
   }
   __syncthreads();
   block_exclusive_scan(cnt, tile_first, nb1, scratch);
@@ -562,7 +562,7 @@ __global__ void __launch_bounds__(256) k_tile_desc(const uint64_t* __restrict__ 
                                                    uint64_t ntiles1,
                                                    const uint64_t* __restrict__ bucket_off,
                                                    const uint32_t* __restrict__ tile_first,
-                                                   uint32_t nb1, uint32_t grid8,
+                                                   uint32_t nb1, uint32_t grid8, uint32_t t2_log2,
                                                    uint64_t* __restrict__ order) {
   __shared__ uint32_t tf[(1u << kMaxA1) + 1];
   for (uint32_t i = threadIdx.x; i <= nb1; i += blockDim.x) tf[i] = tile_first[i];
@@ -575,7 +575,7 @@ __global__ void __launch_bounds__(256) k_tile_desc(const uint64_t* __restrict__ 
     if (tf[mid] <= tt) lo = mid; else hi = mid;
   }
   const uint32_t c = lo;
-  const uint64_t want = bucket_off[c] + (uint64_t)(tt - tf[c]) * kT2;
+  const uint64_t want = bucket_off[c] + ((uint64_t)(tt - tf[c]) << t2_log2);
   const uint64_t* offc = off1 + (uint64_t)c * ntiles1;
   uint64_t a = 0, b = ntiles1;  // largest t in [0, ntiles1) with offc[t] <= want
   while (b - a > 1) {
@@ -602,7 +602,7 @@ __global__ void __launch_bounds__(256) k_tile_desc(const uint64_t* __restrict__ 
   }
 }
 
-// Second level: each workgroup takes kT2 consecutive keys of one first-level
+// Second level: each workgroup takes 2^t2_log2 (at most kT2) consecutive keys of one first-level
 // bucket, gathered from that bucket's run in every first-level tile, sorts them
 // by the next a2 bits of g in LDS and writes them contiguously into the
 // bucket's region; meta2 records where each sub-bucket starts in the tile.
@@ -613,8 +613,8 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
                                                      const uint64_t* __restrict__ bucket_off,
                                                      const uint32_t* __restrict__ tile_first,
                                                      const uint64_t* __restrict__ order,
-                                                     uint32_t a1, uint32_t a2, uint64_t s0,
-                                                     uint64_t* __restrict__ keys2,
+                                                     uint32_t a1, uint32_t a2, uint32_t t2_log2,
+                                                     uint64_t s0, uint64_t* __restrict__ keys2,
                                                      uint32_t* __restrict__ meta2) {
   extern __shared__ uint64_t lds64[];
   const uint32_t nb2 = 1u << a2;
@@ -623,10 +623,11 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
   const uint32_t tt = (uint32_t)desc & 0xFFFFF;
   const uint32_t c = (uint32_t)(desc >> 20) & 0x3FF;
   const uint64_t bo = bucket_off[c];
-  const uint32_t p0 = (tt - tile_first[c]) * (uint32_t)kT2;  // bucket-relative start
-  const uint32_t n = (uint32_t)min((uint64_t)kT2, bucket_off[c + 1] - bo - p0);
-  uint64_t* stage = lds64;                                            // kT2
-  uint64_t* wsb = stage + kT2;                                        // kThreads
+  const uint32_t t2 = 1u << t2_log2;
+  const uint32_t p0 = (tt - tile_first[c]) << t2_log2;  // bucket-relative start
+  const uint32_t n = (uint32_t)min((uint64_t)t2, bucket_off[c + 1] - bo - p0);
+  uint64_t* stage = lds64;                                            // t2
+  uint64_t* wsb = stage + t2;                                         // kThreads
   uint32_t* wrel = reinterpret_cast<uint32_t*>(wsb + kThreads);       // kThreads
   // once the gather is done the window arrays are free: the sort's counts,
   // starts and scan scratch take their place (this keeps two workgroups per
@@ -767,6 +768,7 @@ __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint
   const auto segs = cview(A.segs);
   for (uint32_t s = 0; s < A.nsegs; ++s) {
     const uint32_t a2 = segs[s].a2;
+    const uint32_t t2s = segs[s].t2_log2;  // keys per second-level tile (log2)
     const uint32_t nb2 = 1u << a2;
     const uint32_t c_lo = u_lo >> a2, c_hi = (u_hi - 1) >> a2;
     const auto tile_first = cview(segs[s].tile_first);
@@ -853,7 +855,7 @@ __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint
               start = __shfl(mm0, jj, 64);
               ex = __shfl(excl, jj, 64);
             }
-            off[b] = ok ? (tw + NW * jj) * kT2 + start + (vc - ex) : 0u;
+            off[b] = ok ? ((tw + NW * jj) << t2s) + start + (vc - ex) : 0u;
             r.vmask |= (uint32_t)ok << b;
           }
           v0 += 64 * B;
@@ -880,7 +882,7 @@ __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint
             if (j < nj) {
               const uint32_t idx = i + lane_id();
               const bool ok = idx < e;
-              off[b] = ok ? (tw + NW * j) * kT2 + idx : 0u;
+              off[b] = ok ? ((tw + NW * j) << t2s) + idx : 0u;
               r.vmask |= (uint32_t)ok << b;
               uint32_t sb = 0;
 #pragma unroll
@@ -1525,8 +1527,8 @@ __global__ void __launch_bounds__(256) k_debug_part(const SegDesc sd, uint64_t n
   if (sd.a2) {
     const uint32_t nb2 = 1u << sd.a2;
     const uint64_t rel = i - sd.bucket_off[c];
-    const uint32_t tt = sd.tile_first[c] + (uint32_t)(rel / kT2);
-    const uint32_t o = (uint32_t)(rel % kT2);
+    const uint32_t tt = sd.tile_first[c] + (uint32_t)(rel >> sd.t2_log2);
+    const uint32_t o = (uint32_t)(rel & ((1ull << sd.t2_log2) - 1));
     const uint32_t* m = sd.meta2 + (uint64_t)tt * (nb2 + 1);
     uint32_t l2 = 0, h2 = nb2;
     while (h2 - l2 > 1) {
@@ -1708,9 +1710,9 @@ size_t level1_lds(uint32_t a1) {
   return (size_t)kTilePos * 8 + (size_t)nb * 4 + (size_t)(nb + 1) * 4 + kWaves * 4;
 }
 
-size_t level2_lds(uint32_t a2) {
+size_t level2_lds(uint32_t a2, uint32_t t2_log2) {
   const size_t nb = (size_t)1 << a2;
-  return (size_t)kT2 * 8 + 4 * std::max<size_t>((size_t)kThreads * 3, 2 * nb + 2 + kWaves) + 4;
+  return ((size_t)8 << t2_log2) + 4 * std::max<size_t>((size_t)kThreads * 3, 2 * nb + 2 + kWaves) + 4;
 }
 
 hipError_t launch_level1(const uint64_t* packed, const uint64_t* flags, uint64_t nwords,
@@ -1726,17 +1728,21 @@ hipError_t launch_level1(const uint64_t* packed, const uint64_t* flags, uint64_t
   return hipGetLastError();
 }
 
-hipError_t launch_tiles2(const uint64_t* bucket_off, uint32_t nb1, uint32_t* tile_first,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_tiles2, dim3(1), dim3(kThreads), 0, s, bucket_off, nb1, tile_first);
+hipError_t launch_tiles2(const uint64_t* bucket_off, uint32_t nb1, uint32_t t2_log2,
+                         uint32_t* tile_first, hipStream_t s) {
+  if (t2_log2 < kT2MinLog2 || (1u << t2_log2) > (uint32_t)kT2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tiles2, dim3(1), dim3(kThreads), 0, s, bucket_off, nb1, t2_log2,
+                     tile_first);
   return hipGetLastError();
 }
 
 hipError_t launch_level2(const uint64_t* keys1, const uint64_t* off1, const uint32_t* lstart,
                          uint64_t ntiles1, const uint64_t* bucket_off, const uint32_t* tile_first,
-                         uint64_t* tile_desc, uint32_t a1, uint32_t a2, uint64_t s0,
-                         uint64_t* keys2, uint32_t* meta2, uint64_t grid, hipStream_t s) {
+                         uint64_t* tile_desc, uint32_t a1, uint32_t a2, uint32_t t2_log2,
+                         uint64_t s0, uint64_t* keys2, uint32_t* meta2, uint64_t grid,
+                         hipStream_t s) {
   if (!grid) return hipSuccess;
+  if (t2_log2 < kT2MinLog2 || (1u << t2_log2) > (uint32_t)kT2) return hipErrorInvalidValue;
   // one descriptor per workgroup (tile_desc holds level2_grid(grid)); tiles,
   // buckets and first-level tiles must fit their fields (20, 10 and 34 bits;
   // never all ones)
@@ -1746,12 +1752,12 @@ hipError_t launch_level2(const uint64_t* keys1, const uint64_t* off1, const uint
   hipError_t e = launch_fill64(order, grid8, kEmpty, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_tile_desc, dim3(div_up(grid, 256)), dim3(256), 0, s, off1, ntiles1,
-                     bucket_off, tile_first, 1u << a1, (uint32_t)grid8, order);
-  const size_t lds = level2_lds(a2);
+                     bucket_off, tile_first, 1u << a1, (uint32_t)grid8, t2_log2, order);
+  const size_t lds = level2_lds(a2, t2_log2);
   e = allow_lds(reinterpret_cast<const void*>(k_level2));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_level2, dim3((uint32_t)grid8), dim3(kThreads), lds, s, keys1, off1, lstart,
-                     ntiles1, bucket_off, tile_first, order, a1, a2, s0, keys2, meta2);
+                     ntiles1, bucket_off, tile_first, order, a1, a2, t2_log2, s0, keys2, meta2);
   return hipGetLastError();
 }
 

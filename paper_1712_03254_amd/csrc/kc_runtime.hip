@@ -190,6 +190,7 @@ struct kc_ctx {
   // derived layout
   HashCfg hc{};
   uint32_t s_log2 = 0, p_log2 = 0, cap = 0, a1 = 0, a2 = 0, upb_log2 = 0, bsub_log2 = 0;
+  uint32_t t2_log2 = 13;  // keys per second-level shuffle tile (log2)
   uint32_t nbw = 1, l2w = 2, slot_bytes = 12;
   size_t count_lds = 0, tally_lds = 0;
   uint64_t bloom_words64 = 1;
@@ -334,6 +335,10 @@ kc_status validate(const kc_config* cfg, std::string* why) {
   if (cfg->partitions_log2 > kMaxPartLog2) return bad("partitions_log2 must be <= 21");
   if (cfg->group_bases_log2 != 0 && (cfg->group_bases_log2 < 10 || cfg->group_bases_log2 > 32))
     return bad("group_bases_log2 must be 0 or in 10..32");
+  if (cfg->shuffle_tile_log2 != 0 &&
+      (cfg->shuffle_tile_log2 < kT2MinLog2 || (1u << cfg->shuffle_tile_log2) > (uint32_t)kT2))
+    return bad("shuffle_tile_log2 must be 0 or in 10..13");
+  if (cfg->reserved_ != 0) return bad("reserved_ must be 0");
   if (cfg->scatter_bits > kMaxA1) {
     snprintf(buf, sizeof buf, "scatter_bits must be <= %d", kMaxA1);
     *why = buf;
@@ -380,6 +385,7 @@ kc_status derive(kc_ctx* c) {
   c->a1 = f.scatter_bits ? std::min<uint32_t>(f.scatter_bits, c->p_log2 - 1)
                          : std::min<uint32_t>(c->p_log2 / 2, kMaxA1);
   c->a2 = c->p_log2 - c->a1;
+  c->t2_log2 = f.shuffle_tile_log2 ? f.shuffle_tile_log2 : 13u;
   if (c->a1 < 1 || c->a1 > (uint32_t)kMaxA1 || c->a2 < 1 || c->a2 > (uint32_t)kMaxA2)
     return fail(c, KC_ERR_INVALID_ARG, "partition count needs a wider shuffle (set scatter_bits)");
   // k_bloom takes up to four Bloom blocks smaller than 2^18 bits per
@@ -594,7 +600,7 @@ uint64_t bytes_after(const kc_ctx* c, const kc_config* cfg, const uint64_t* part
     const uint64_t ntiles = (nwords + kTileWords - 1) / kTileWords;
     const uint64_t nhist = nb1 * ntiles;
     const uint64_t kmax = nwords * 32;  // keys <= window positions
-    const uint64_t tiles2 = (kmax + kT2 - 1) / kT2 + nb1;
+    const uint64_t tiles2 = ((kmax + (1ull << d.t2_log2) - 1) >> d.t2_log2) + nb1;
     packed = std::max(packed, nwords * 8);
     hist = std::max(hist, nhist * 4);
     lstart = std::max(lstart, ntiles * (nb1 + 1) * 4);
@@ -942,7 +948,7 @@ kc_status kc_insert_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offse
   seg.n = n;
   seg.counter = counter;
   const uint32_t nb2 = 1u << c->a2;
-  const uint64_t tiles2 = (n + kT2 - 1) / kT2 + nb1;
+  const uint64_t tiles2 = ((n + (1ull << c->t2_log2) - 1) >> c->t2_log2) + nb1;
   hipError_t e;
   if ((e = seg.keys.ensure(n * 8)) != hipSuccess || (e = seg.bucket_off.ensure((nb1 + 1) * 8)) != hipSuccess ||
       (e = seg.tile_first.ensure((nb1 + 1) * 4)) != hipSuccess ||
@@ -955,12 +961,13 @@ kc_status kc_insert_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offse
     StageTimer t(c, s, KC_T_LEVEL2);
     KC_HIP(c, launch_bucket_off(c->off1.as<uint64_t>(), ntiles, nb1, seg.bucket_off.as<uint64_t>(), s),
            "bucket offsets");
-    KC_HIP(c, launch_tiles2(seg.bucket_off.as<uint64_t>(), nb1, seg.tile_first.as<uint32_t>(), s),
+    KC_HIP(c, launch_tiles2(seg.bucket_off.as<uint64_t>(), nb1, c->t2_log2,
+                            seg.tile_first.as<uint32_t>(), s),
            "tiles");
     KC_HIP(c, launch_level2(c->keys1.as<uint64_t>(), c->off1.as<uint64_t>(),
                             c->lstart1.as<uint32_t>(), ntiles, seg.bucket_off.as<uint64_t>(),
                             seg.tile_first.as<uint32_t>(), c->tile_desc.as<uint64_t>(), c->a1,
-                            c->a2, s0, seg.keys.as<uint64_t>(), seg.meta2.as<uint32_t>(), tiles2,
+                            c->a2, c->t2_log2, s0, seg.keys.as<uint64_t>(), seg.meta2.as<uint32_t>(), tiles2,
                             s),
            "second-level shuffle");
     t.stop();
@@ -1033,6 +1040,7 @@ kc_status kc_finalize(kc_ctx* c, void* hip_stream, kc_stats* out) {
     hd[i].meta2 = g.meta2.as<uint32_t>();
     hd[i].a1 = c->a1;
     hd[i].a2 = c->a2;
+    hd[i].t2_log2 = c->t2_log2;
   }
   KC_HIP(c, c->segdesc.ensure(std::max<size_t>(1, hd.size()) * sizeof(SegDesc)), "segment table");
   if (!hd.empty())
@@ -1770,7 +1778,7 @@ kc_status kc_debug_keys(kc_ctx* c, uint64_t* keys, uint32_t* part, uint64_t cap,
       ReleaseOnExit free_pb{&pb};
       KC_HIP(c, pb.ensure(g.n * 4), "partition buffer");
       SegDesc sd{g.keys.as<uint64_t>(), g.bucket_off.as<uint64_t>(), g.tile_first.as<uint32_t>(),
-                 g.meta2.as<uint32_t>(), c->a1, c->a2};
+                 g.meta2.as<uint32_t>(), c->a1, c->a2, c->t2_log2, 0};
       KC_HIP(c, launch_debug_part(sd, g.n, pb.as<uint32_t>(), nullptr), "partition view");
       KC_HIP(c, hipMemcpy(part + at, pb.p, g.n * 4, hipMemcpyDeviceToHost), "partition copy");
     }
@@ -1913,7 +1921,7 @@ kc_status build_batch(kc_ctx* c, const kc_chunk* ch, uint32_t n, uint32_t counte
     g.ntiles = (g.nwords + kTileWords - 1) / kTileWords;
     g.nhist = (uint64_t)nb1 * g.ntiles;
     const uint64_t bound = g.nwords * 32;  // keys <= positions
-    g.tiles2 = (bound + kT2 - 1) / kT2 + nb1;
+    g.tiles2 = ((bound + (1ull << c->t2_log2) - 1) >> c->t2_log2) + nb1;
     max_words = std::max(max_words, g.nwords);
     max_tiles = std::max(max_tiles, g.ntiles);
     max_hist = std::max(max_hist, g.nhist);
@@ -1952,6 +1960,7 @@ kc_status build_batch(kc_ctx* c, const kc_chunk* ch, uint32_t n, uint32_t counte
     sd.meta2 = g.seg.meta2.as<uint32_t>();
     sd.a1 = c->a1;
     sd.a2 = c->a2;
+    sd.t2_log2 = c->t2_log2;
     hd.push_back(sd);
   }
   KC_HIP(c, c->segdesc.ensure(std::max<size_t>(1, hd.size()) * sizeof(SegDesc)), "segment table");
@@ -2002,10 +2011,11 @@ kc_status build_batch(kc_ctx* c, const kc_chunk* ch, uint32_t n, uint32_t counte
                          c->parts.as<uint64_t>(), cs));
       KC_REC(launch_copy64(c->off1.as<uint64_t>() + g.nhist, b.counts.as<uint64_t>() + gi, cs));
       KC_REC(launch_bucket_off(c->off1.as<uint64_t>(), g.ntiles, nb1, g.seg.bucket_off.as<uint64_t>(), cs));
-      KC_REC(launch_tiles2(g.seg.bucket_off.as<uint64_t>(), nb1, g.seg.tile_first.as<uint32_t>(), cs));
+      KC_REC(launch_tiles2(g.seg.bucket_off.as<uint64_t>(), nb1, c->t2_log2,
+                           g.seg.tile_first.as<uint32_t>(), cs));
       KC_REC(launch_level2(c->keys1.as<uint64_t>(), c->off1.as<uint64_t>(), c->lstart1.as<uint32_t>(),
                            g.ntiles, g.seg.bucket_off.as<uint64_t>(), g.seg.tile_first.as<uint32_t>(),
-                           c->tile_desc.as<uint64_t>(), c->a1, c->a2, s0, g.seg.keys.as<uint64_t>(),
+                           c->tile_desc.as<uint64_t>(), c->a1, c->a2, c->t2_log2, s0, g.seg.keys.as<uint64_t>(),
                            g.seg.meta2.as<uint32_t>(), g.tiles2, cs));
     }
     KC_REC(launch_fill64(c->okeys.as<uint64_t>(), on, kEmpty, cs));
@@ -2162,9 +2172,13 @@ kc_status kc_autotune_batch(const kc_config* base, int device, const kc_chunk* c
   std::vector<uint32_t> slist;
   for (uint32_t f = 10; f >= 5; --f) slist.push_back(std::max<uint32_t>(64, cap_def * f / 10 / 64 * 64));
   std::vector<kc_tune_trial> got;
+  // second-level tile sizes (log2 keys), the largest first
+  const uint32_t tlist[] = {13, 12, 11};
   struct Key {
-    uint32_t p, si, a1;
-    bool operator==(const Key& o) const { return p == o.p && si == o.si && a1 == o.a1; }
+    uint32_t p, si, a1, ti;
+    bool operator==(const Key& o) const {
+      return p == o.p && si == o.si && a1 == o.a1 && ti == o.ti;
+    }
   };
   std::vector<std::pair<Key, double>> seen;
   kc_config best = *base;
@@ -2176,10 +2190,12 @@ kc_status kc_autotune_batch(const kc_config* base, int device, const kc_chunk* c
     cfg.partitions_log2 = key.p;
     cfg.table_slots = slist[key.si];
     cfg.scatter_bits = key.a1;
+    cfg.shuffle_tile_log2 = tlist[key.ti];
     kc_tune_trial t{};
     t.partitions_log2 = key.p;
     t.table_slots = slist[key.si];
     t.scatter_bits = key.a1;
+    t.shuffle_tile_log2 = tlist[key.ti];
     t.ms = -1.0;
     kc_ctx* c = nullptr;
     kc_status r = kc_create(&cfg, device, &c);
@@ -2211,17 +2227,17 @@ kc_status kc_autotune_batch(const kc_config* base, int device, const kc_chunk* c
   const uint32_t p0 = std::min<uint32_t>(kMaxPartLog2, (uint32_t)std::max<int64_t>(lo, pc));
   auto split = [&](uint32_t p) { return std::min<uint32_t>(p / 2, kMaxA1); };
   auto valid = [&](const Key& k) {
-    if (k.p < lo || k.p > (uint32_t)kMaxPartLog2 || k.si >= slist.size()) return false;
+    if (k.p < lo || k.p > (uint32_t)kMaxPartLog2 || k.si >= slist.size() || k.ti >= 3) return false;
     const int64_t a2 = (int64_t)k.p - k.a1;
     return k.a1 >= 1 && k.a1 <= (uint32_t)kMaxA1 && a2 >= 1 && a2 <= kMaxA2;
   };
-  Key cur{p0, 0, split(p0)};
+  Key cur{p0, 0, split(p0), 0};
   double cur_ms = run(cur);
-  const int kMaxTrials = 24;
+  const int kMaxTrials = 28;
   bool moved = true;
   while (moved && (int)got.size() < kMaxTrials) {
     moved = false;
-    for (int dim = 0; dim < 3 && (int)got.size() < kMaxTrials; ++dim) {
+    for (int dim = 0; dim < 4 && (int)got.size() < kMaxTrials; ++dim) {
       for (int dir : {-1, 1}) {
         for (;;) {
           Key nk = cur;
@@ -2230,8 +2246,10 @@ kc_status kc_autotune_batch(const kc_config* base, int device, const kc_chunk* c
             nk.a1 = split(nk.p);
           } else if (dim == 1) {
             nk.a1 = (uint32_t)((int64_t)cur.a1 + dir);
-          } else {
+          } else if (dim == 2) {
             nk.si = (uint32_t)((int64_t)cur.si + dir);
+          } else {
+            nk.ti = (uint32_t)((int64_t)cur.ti + dir);
           }
           if (!valid(nk) || (int)got.size() >= kMaxTrials) break;
           const double ms = run(nk);

@@ -53,6 +53,8 @@ int main(void) {
          offsetof(kc_chunk, total_bases), sizeof(kc_tune_trial), offsetof(kc_tune_trial, ms));
   printf("%zu %zu %zu %zu %zu\n", sizeof(kc_request), offsetof(kc_request, n_parts),
          sizeof(kc_response), offsetof(kc_response, ctx), offsetof(kc_response, footprint_bytes));
+  printf("%zu %zu\n", offsetof(kc_config, shuffle_tile_log2),
+         offsetof(kc_tune_trial, shuffle_tile_log2));
   return 0;
 }
 ''')
@@ -65,13 +67,15 @@ int main(void) {
             kc.KcStats.kernel_launches.offset, ctypes.sizeof(kc.KcChunk),
             kc.KcChunk.total_bases.offset, ctypes.sizeof(kc.KcTuneTrial), kc.KcTuneTrial.ms.offset,
             ctypes.sizeof(kc.KcRequest), kc.KcRequest.n_parts.offset, ctypes.sizeof(kc.KcResponse),
-            kc.KcResponse.ctx.offset, kc.KcResponse.footprint_bytes.offset]
+            kc.KcResponse.ctx.offset, kc.KcResponse.footprint_bytes.offset,
+            kc.KcConfig.shuffle_tile_log2.offset, kc.KcTuneTrial.shuffle_tile_log2.offset]
     assert got == want
 
 
 @pytest.mark.parametrize("field,value", [("k", 0), ("k", 32), ("n_counters", 3),
                                          ("min_count", 1), ("bloom_hashes", 9),
                                          ("bloom_block_log2", 20), ("bloom_bits_log2", 41),
+                                         ("shuffle_tile_log2", 9), ("shuffle_tile_log2", 14),
                                          ("group_bases_log2", 9), ("group_bases_log2", 33)])
 def test_config_validation_without_device(field, value):
     cfg = kc.Config(k=21, bloom_bits_log2=20, bloom_hashes=3, bloom_block_log2=12)

@@ -208,8 +208,9 @@ def test_autotune_choice_is_result_neutral():
     dev = [to_device(b, o) for b, o in chunks]
     best, trials = kc.autotune_batch(cfg, dev)
     note("trials: %s" % [(t["partitions_log2"], t["table_slots"], t["scatter_bits"],
-                          round(t["ms"], 3), t["status"]) for t in trials])
-    assert len(trials) >= 5  # the start and its neighbours along each dimension
+                          t["shuffle_tile_log2"], round(t["ms"], 3), t["status"]) for t in trials])
+    assert len(trials) >= 6  # the start and its neighbours along each dimension
+    assert {t["shuffle_tile_log2"] for t in trials} >= {12, 13}  # the tile size is searched
     assert all(t["status"] == 0 for t in trials)
     fastest = min(t["ms"] for t in trials)
     assert any(t["ms"] == fastest and t["partitions_log2"] == best.partitions_log2 and

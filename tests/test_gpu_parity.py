@@ -94,6 +94,20 @@ def test_parameter_grid_parity(k, m, h, bl, pl, tl, nc, mc, seed):
         assert g["stats"]["overflow_keys"] > 0
 
 
+@pytest.mark.parametrize("tile_log2", [10, 11, 12, 13])
+def test_second_level_tile_sizes(tile_log2):
+    """Second-level shuffle tiles of 2^10 to 2^13 keys (result-neutral): a
+    first-level bucket is cut into more, shorter tiles, so every partition has
+    more, shorter runs for the Bloom and count walks; the whole output equals
+    the oracle's."""
+    note("case: second-level tile 2^%d keys, 20000 reads of the 1 Mbp workload, 2^14 partitions"
+         % tile_log2)
+    w, _, b, o = workload_chunks("plain_1mbp", n_reads=20000)
+    cfg = workload_config(w, partitions_log2=14, shuffle_tile_log2=tile_log2)
+    g, ref = assert_parity(cfg, [(b, o)])
+    assert g["stats"]["partitions_log2"] == 14
+
+
 def test_overflow_table_far_past_its_limit():
     """About 1.4·10^5 counted keys against 1024 table slots: the first overflow
     table (sized from n_valid / 256, a few thousand slots) takes a small
