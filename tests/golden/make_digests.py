@@ -38,11 +38,14 @@ def main():
     ap.add_argument("--qbits", type=int, default=0)
     args = ap.parse_args()
     w = synth.WORKLOADS[args.workload]
-    if w.batch_chunks or w.requests:
-        raise SystemExit("only plain workloads have a single read stream")
+    if w.requests:
+        raise SystemExit("served workloads are checked per request, not as one stream")
     t0 = time.time()
     genome = w.make_genome()
-    bases, offsets = w.make_reads(genome)
+    # a batched workload's chunks are consecutive reads of one read stream
+    # (Workload.make_chunk), so all of them together are its first n reads
+    n_reads = int(w.chunk_plan().sum()) if w.batch_chunks else w.n_reads
+    bases, offsets = w.make_reads(genome, first=0, n=n_reads)
     del genome
     p = oracle.Params(k=w.k, n_counters=w.n_counters, min_count=w.min_count,
                       m_log2=w.bloom_bits_log2, h=w.bloom_hashes,
@@ -56,13 +59,16 @@ def main():
     out = os.path.join(HERE, "digest_%s.txt" % w.name)
     header = [
         "Whole output of the CPU oracle (value-range passes) at workload %s:" % w.name,
-        "genome %d bp, %d reads of %d-%d bp, substitutions %g, N rate %g, seed %d;"
-        % (w.genome_len, w.n_reads, w.lmin, w.lmax, w.err, w.nrate, w.seed),
+        "genome %d bp, %d reads of %d-%d bp%s, substitutions %g, N rate %g, seed %d;"
+        % (w.genome_len, n_reads, w.lmin, w.lmax,
+           " in %d chunks" % w.batch_chunks if w.batch_chunks else "", w.err, w.nrate, w.seed),
         "k=%d, %d counter(s), min_count %d, Bloom 2^%d bits per level, %d hashes, blocks of 2^%d bits."
         % (w.k, w.n_counters, w.min_count, w.bloom_bits_log2, w.bloom_hashes,
            min(w.bloom_block_log2, w.bloom_bits_log2)),
-        "Written by: python tests/golden/make_digests.py %s (oracle %.0f s, input %.0f s)."
-        % (w.name, t2 - t1, t1 - t0),
+        "Written by: python tests/golden/make_digests.py %s%s (oracle %.0f s, input %.0f s)."
+        % (w.name, "".join(" --%s %d" % (k, v) for k, v in (("threads", args.threads),
+                                                           ("qbits", args.qbits)) if v),
+           t2 - t1, t1 - t0),
         "Table stream: entries ascending by key, key <u8 then counts <u4; ranges by the top 4",
         "bits of the 2k-bit code: 'range q entries sum_of_counts sha256'.",
     ]

@@ -175,3 +175,45 @@ def test_plain_100mbp_most_keys_in_the_overflow_table():
     assert np.array_equal(k0[o0], k1[o1])
     assert np.array_equal(c0[o0], c1[o1])
     assert np.array_equal(q0, q1)
+
+
+def test_batched_200mbp_whole_output_digest():
+    """The batched workload at full size (256 chunks, 7.08·10^7 reads of
+    100-250 bp, 1.03·10^10 k-mers, 2^35-bit levels) as one kc_count_batch
+    graph launch with the configuration the autotuner picks there (2^18
+    partitions, first-level split 9; result-neutral): every statistic, the
+    sorted table (whole and per value range) and both levels against the
+    digest of the oracle's value-range passes over the same read stream."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    note("case: batched_200mbp full size (256 chunks), one graph launch, whole-output digest")
+    want = read_digest_file(os.path.join(GOLDEN, "digest_batched_200mbp.txt"))
+    import synth
+    w = synth.WORKLOADS["batched_200mbp"]
+    genome = w.make_genome(threads=16)
+    sizes = w.chunk_plan()
+    dev = []
+    for i in range(sizes.size):
+        b, o = w.make_chunk(genome, sizes, i, threads=16)
+        dev.append(to_device(b, o))
+    del genome
+    note("chunks on the device: %d reads, %d bases" % (int(sizes.sum()),
+                                                        sum(int(b.numel()) for b, _ in dev)))
+    cfg = workload_config(w, partitions_log2=18, scatter_bits=9)
+    with kc.KmerCounter(cfg) as c:
+        st = c.count_batch(dev)
+        torch.cuda.synchronize()
+        del dev
+        keys, counts = c.export()
+        b1, b2 = c.export_bloom()
+    for key in STAT_KEYS:
+        assert st[key] == want["stats"][key], (key, st[key], want["stats"][key])
+    ks, cs = gpu_table_sorted(keys, counts)
+    del keys, counts
+    got = table_digests(ks, cs, w.k)
+    for q, (g, r) in enumerate(zip(got["ranges"], want["ranges"])):
+        assert tuple(g) == tuple(r), ("value range", q, g, r)
+    assert got["sha256"] == want["sha256"]
+    assert words_digest(b1) == want["b1"]
+    assert words_digest(b2) == want["b2"]
