@@ -26,6 +26,7 @@ _lib = None
 U64P = ctypes.POINTER(ctypes.c_uint64)
 U32P = ctypes.POINTER(ctypes.c_uint32)
 U8P = ctypes.POINTER(ctypes.c_uint8)
+RANGE_CB = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint64, U64P, U32P, ctypes.c_uint64)
 
 
 class OrParams(ctypes.Structure):
@@ -70,7 +71,8 @@ def _load():
         lib.or_count.restype = ctypes.POINTER(OrResult)
         lib.or_free.argtypes = [ctypes.POINTER(OrResult)]
         lib.or_count_ranges.argtypes = [P, U8P, U64P, ctypes.c_uint64, U8P, ctypes.c_int,
-                                        ctypes.c_uint32, ctypes.c_int, ctypes.c_int]
+                                        ctypes.c_uint32, ctypes.c_int, ctypes.c_int, RANGE_CB,
+                                        ctypes.c_void_p]
         lib.or_count_ranges.restype = ctypes.POINTER(OrResult)
         lib.or_enumerate.argtypes = [P, U8P, U64P, ctypes.c_uint64, U8P, U64P, ctypes.c_uint64]
         lib.or_enumerate.restype = ctypes.c_uint64
@@ -156,21 +158,32 @@ def count(params: Params, bases, offsets, tags=None, want_bloom=True) -> Result:
 
 
 def count_ranges(params: Params, bases, offsets, tags=None, want_bloom=True,
-                 qbits: int = 0, threads: int = 0, keep_singles: bool = True) -> Result:
+                 qbits: int = 0, threads: int = 0, keep_singles: bool = True,
+                 on_range=None) -> Result:
     """The same result as ``count``, by value-range passes (kc_oracle.c,
     or_count_ranges): 2^qbits ranges of the k-mer space by their top bits,
     ``threads`` of them per pass; qbits = 0 picks the smallest power of two
     that gives every thread a range.  keep_singles = False screens in a second
-    round of passes instead of keeping the keys seen once."""
+    round of passes instead of keeping the keys seen once.  on_range(q, keys,
+    counts), when given, receives each range's final table (numpy views, valid
+    during the call) in ascending order instead of the result's table."""
     bases, offsets, tags = _arrays(bases, offsets, tags)
     n_reads = offsets.size - 1
     threads = threads or _threads()
     if not qbits:
         qbits = min(2 * params.k, max(0, (threads - 1).bit_length()))
     p = params.c()
+    nc = params.n_counters
+
+    def relay(_user, q, kp, cp, n):
+        keys = np.ctypeslib.as_array(kp, shape=(n,)) if n else np.zeros(0, np.uint64)
+        counts = np.ctypeslib.as_array(cp, shape=(n * nc,)) if n else np.zeros(0, np.uint32)
+        on_range(int(q), keys, counts.reshape(n, nc))
+
+    cb = RANGE_CB(relay) if on_range is not None else RANGE_CB()
     r = _load().or_count_ranges(ctypes.byref(p), _ptr(bases, U8P), _ptr(offsets, U64P), n_reads,
                                 _ptr(tags, U8P), _bloom_mode(want_bloom), qbits, threads,
-                                1 if keep_singles else 0)
+                                1 if keep_singles else 0, cb, None)
     return _result(r, params, want_bloom)
 
 

@@ -668,6 +668,13 @@ typedef struct {
   uint64_t n_distinct, sum_ge2, entries, sum_counts, n_pass, fp;
 } or_range_stats;
 
+/* Receives the final table of value range q (keys ascending, n_counters
+ * counts each) once the pass holding q is done; ranges arrive in ascending
+ * order.  With a callback the table is handed over range by range instead of
+ * being gathered into the result. */
+typedef void (*or_range_cb)(void* user, uint64_t q, const uint64_t* keys, const uint32_t* counts,
+                            uint64_t n);
+
 typedef struct {
   const or_params* p;
   const uint8_t* bases;
@@ -688,6 +695,8 @@ typedef struct {
   or_range_stats* rst;   /* [Q] */
   uint64_t* nvalid;      /* [threads] */
   int* fail;             /* [threads] */
+  or_range_cb cb;        /* NULL: gather the table into the result */
+  void* cb_user;
 } or_rp;
 
 typedef struct {
@@ -858,13 +867,19 @@ static int or_rp_sweep(or_rp* rp, int sweep, uint64_t* n_valid) {
       for (uint32_t t = 0; t < rp->threads; ++t) *n_valid += rp->nvalid[t];
     }
     if (or_rp_run(rp, or_rp_range)) return -1;
+    if (sweep == 1 && rp->cb)
+      for (uint64_t q = q0; q < q0 + rp->threads && q < Q; ++q) {
+        rp->cb(rp->cb_user, q, rp->tkeys[q].v, rp->tcounts[q].v, rp->tkeys[q].n);
+        or_vfree64(&rp->tkeys[q]);
+        or_vfree32(&rp->tcounts[q]);
+      }
   }
   return 0;
 }
 
 or_result* or_count_ranges(const or_params* p, const uint8_t* bases, const uint64_t* offsets,
                            uint64_t n_reads, const uint8_t* tags, int want_bloom, uint32_t qbits,
-                           int threads, int keep_singles) {
+                           int threads, int keep_singles, or_range_cb cb, void* cb_user) {
   if (!or_params_ok(p)) return NULL;
   if (qbits > 2 * p->k || qbits > 20 || threads < 1 || threads > 256) return NULL;
   if (offsets[0] != 0) return NULL;
@@ -888,6 +903,8 @@ or_result* or_count_ranges(const or_params* p, const uint8_t* bases, const uint6
   rp.qbits = qbits;
   rp.threads = T;
   rp.keep_singles = keep_singles;
+  rp.cb = cb;
+  rp.cb_user = cb_user;
   const uint64_t m_words = p->m_log2 >= 6 ? (1ULL << (p->m_log2 - 6)) : 1;
   rp.b1 = (uint64_t*)calloc(m_words, sizeof(uint64_t));
   rp.b2 = (uint64_t*)calloc(m_words, sizeof(uint64_t));
@@ -920,7 +937,7 @@ or_result* or_count_ranges(const or_params* p, const uint8_t* bases, const uint6
       res->st.sum_counts += s->sum_counts;
       res->st.fp_singletons += s->fp;
       res->st.n_pass += keep_singles ? s->sum_ge2 + s->fp : s->n_pass;
-      ne += s->entries;
+      if (!cb) ne += s->entries;  /* with a callback the table went out range by range */
     }
     for (uint64_t w = 0; w < m_words; ++w) {
       res->st.b1_pop += (uint64_t)__builtin_popcountll(rp.b1[w]);

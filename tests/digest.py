@@ -51,6 +51,39 @@ def table_digests(keys_sorted: np.ndarray, counts_sorted: np.ndarray, k: int) ->
     return {"sha256": whole.hexdigest(), "ranges": ranges}
 
 
+class TableDigest:
+    """table_digests over a table handed over in ascending pieces (the
+    oracle's value ranges, each wholly inside one digest range when the
+    oracle uses at least RANGE_BITS range bits)."""
+
+    def __init__(self, k: int):
+        self.rb = min(RANGE_BITS, 2 * k)
+        self.shift = 2 * k - self.rb
+        self.whole = hashlib.sha256()
+        self.parts = [[0, 0, hashlib.sha256()] for _ in range(1 << self.rb)]
+        self.last = -1
+
+    def update(self, keys_sorted: np.ndarray, counts_sorted: np.ndarray):
+        keys_sorted = np.asarray(keys_sorted, dtype=np.uint64).reshape(-1)
+        if keys_sorted.size == 0:
+            return
+        counts_sorted = np.asarray(counts_sorted, dtype=np.uint32).reshape(keys_sorted.size, -1)
+        first = int(keys_sorted[0]) >> self.shift
+        if int(keys_sorted[-1]) >> self.shift != first or first < self.last:
+            raise ValueError("piece crosses a digest range or comes out of order")
+        self.last = first
+        blob = table_bytes(keys_sorted, counts_sorted).tobytes()
+        self.whole.update(blob)
+        part = self.parts[first]
+        part[0] += keys_sorted.size
+        part[1] += int(counts_sorted.sum(dtype=np.uint64))
+        part[2].update(blob)
+
+    def result(self) -> dict:
+        return {"sha256": self.whole.hexdigest(),
+                "ranges": [(n, s, h.hexdigest()) for n, s, h in self.parts]}
+
+
 def words_digest(words: np.ndarray) -> str:
     return hashlib.sha256(np.ascontiguousarray(words, dtype="<u8").tobytes()).hexdigest()
 

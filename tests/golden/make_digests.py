@@ -24,7 +24,7 @@ for p in (ROOT, os.path.dirname(HERE)):
 
 import oracle  # noqa: E402
 import synth  # noqa: E402
-from digest import table_digests, words_digest, write_digest_file  # noqa: E402
+from digest import TableDigest, table_digests, words_digest, write_digest_file  # noqa: E402
 
 STATS = {"n_valid": "n_valid", "n_pass": "n_pass", "entries": "entries",
          "sum_counts": "sum_counts", "fp_singletons": "fp_singletons",
@@ -36,6 +36,9 @@ def main():
     ap.add_argument("workload")
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--qbits", type=int, default=0)
+    ap.add_argument("--stream", action="store_true",
+                    help="digest each value range's table as its pass ends and screen in a second "
+                         "sweep (for workloads whose table and singletons do not fit in memory)")
     args = ap.parse_args()
     w = synth.WORKLOADS[args.workload]
     if w.requests:
@@ -51,10 +54,18 @@ def main():
                       m_log2=w.bloom_bits_log2, h=w.bloom_hashes,
                       block_log2=min(w.bloom_block_log2, w.bloom_bits_log2), seed=w.seed)
     t1 = time.time()
-    res = oracle.count_ranges(p, bases, offsets, threads=args.threads, qbits=args.qbits)
+    if args.stream:
+        if args.qbits < 4:
+            raise SystemExit("--stream needs --qbits 4 or more (each range inside one digest range)")
+        td = TableDigest(w.k)
+        res = oracle.count_ranges(p, bases, offsets, threads=args.threads, qbits=args.qbits,
+                                  keep_singles=False, on_range=lambda q, k, c: td.update(k, c))
+        table = td.result()
+    else:
+        res = oracle.count_ranges(p, bases, offsets, threads=args.threads, qbits=args.qbits)
+        table = table_digests(res.keys, res.counts, w.k)
     t2 = time.time()
     stats = {k: res.stats[v] for k, v in STATS.items()}
-    table = table_digests(res.keys, res.counts, w.k)
     b1, b2 = words_digest(res.b1), words_digest(res.b2)
     out = os.path.join(HERE, "digest_%s.txt" % w.name)
     header = [
@@ -65,10 +76,10 @@ def main():
         "k=%d, %d counter(s), min_count %d, Bloom 2^%d bits per level, %d hashes, blocks of 2^%d bits."
         % (w.k, w.n_counters, w.min_count, w.bloom_bits_log2, w.bloom_hashes,
            min(w.bloom_block_log2, w.bloom_bits_log2)),
-        "Written by: python tests/golden/make_digests.py %s%s (oracle %.0f s, input %.0f s)."
+        "Written by: python tests/golden/make_digests.py %s%s%s (oracle %.0f s, input %.0f s)."
         % (w.name, "".join(" --%s %d" % (k, v) for k, v in (("threads", args.threads),
                                                            ("qbits", args.qbits)) if v),
-           t2 - t1, t1 - t0),
+           " --stream" if args.stream else "", t2 - t1, t1 - t0),
         "Table stream: entries ascending by key, key <u8 then counts <u4; ranges by the top 4",
         "bits of the 2k-bit code: 'range q entries sum_of_counts sha256'.",
     ]

@@ -422,6 +422,30 @@ def test_value_range_passes_match_brute_force():
     assert got.stats == st
 
 
+def test_streamed_table_digest_equals_the_whole_table_digest():
+    """Value-range passes handing each range's table to a callback (and
+    screening in a second sweep) give the digest and statistics of the
+    gathered table."""
+    import numpy as np
+    import synth
+    from digest import TableDigest, table_digests
+    w = synth.WORKLOADS["plain_1mbp"]
+    g = w.make_genome()
+    b, o = w.make_reads(g, n=6000)
+    p = oracle.Params(k=w.k, m_log2=w.bloom_bits_log2, h=w.bloom_hashes,
+                      block_log2=w.bloom_block_log2, seed=w.seed)
+    full = oracle.count(p, b, o, want_bloom=True)
+    td = TableDigest(w.k)
+    seen = []
+    part = oracle.count_ranges(p, b, o, qbits=6, threads=3, keep_singles=False,
+                               on_range=lambda q, k, c: (seen.append(q), td.update(k, c)))
+    assert seen == sorted(seen) and len(seen) == 64
+    assert part.keys.size == 0
+    assert td.result() == table_digests(full.keys, full.counts, w.k)
+    assert part.stats == full.stats
+    assert np.array_equal(part.b1, full.b1) and np.array_equal(part.b2, full.b2)
+
+
 def test_digest_file_reproduces_from_the_oracle():
     """The committed whole-output digest of the 1 Mbp workload is what the
     oracle gives now (the GPU tests compare against these files)."""
