@@ -105,35 +105,66 @@ __device__ void block_exclusive_scan(const uint32_t* in, uint32_t* out, uint32_t
 
 // ------------------------------------------------------------------ pack
 
+// Codes and validity of the four bases of a 32-bit word (base i in byte i),
+// four at a time: each byte's code is bits 1-2 of its ASCII value (A0 C1 G2
+// T3), and the byte is a base exactly when it equals "ACGT"[code] (a byte
+// permute of the four letters); a nonzero byte of the difference is found
+// without carries between bytes.  Returns the 8-bit code of the four bases
+// (first base in the top two bits, invalid bases coded 0) in bits 0-7 and
+// their invalid bits (base i at bit i) in bits 8-11.
+__device__ __forceinline__ uint32_t pack4(uint32_t v) {
+  uint32_t c = ((v >> 1) ^ (v >> 2)) & 0x03030303u;
+  const uint32_t want = __builtin_amdgcn_perm(0u, 0x54474341u, c);  // 'A' 'C' 'G' 'T'
+  const uint32_t z = v ^ want;
+  const uint32_t inv = (((((z & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | z) & 0x80808080u) >> 7);
+  c &= ~(inv * 3u);
+  // bytes 0..3 of c to bits 30, 28, 26, 24; of inv to bits 24..27 (no other
+  // product term reaches bit 24)
+  return ((c * 0x40100401u) >> 24) | ((((inv * 0x01020408u) >> 24) & 0xFu) << 8);
+}
+
+// Two threads per packed word: thread t takes bases [16 t, 16 t + 16) (one
+// 16-byte load; a wave reads 1 KB contiguous), thread 2w the first half of
+// word w and 2w + 1 the second; the pair exchange halves, then the even
+// thread writes the packed word and the odd one the flag word.
 __global__ void __launch_bounds__(256) k_pack(const uint8_t* __restrict__ bases, uint64_t total,
                                               uint64_t nwords, uint64_t* __restrict__ packed,
                                               uint64_t* __restrict__ flags, int aligned) {
-  uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= nwords) return;
-  uint64_t p0 = w * 32;
-  uint8_t b[32];
-  if (aligned && p0 + 32 <= total) {
-    const uint4* src = reinterpret_cast<const uint4*>(bases + p0);
-    uint4 lo = src[0], hi = src[1];
-    const uint32_t words[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t w = t >> 1;
+  const uint64_t p0 = t * 16;
+  uint32_t code = 0, inv = 0;  // 16 bases: code (first base on top), invalid bits
+  if (w < nwords) {
+    uint32_t v[4];
+    if (aligned && p0 + 16 <= total) {
+      const uint4 q = *reinterpret_cast<const uint4*>(bases + p0);
+      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
 #pragma unroll
-    for (int i = 0; i < 32; ++i) b[i] = (uint8_t)(words[i >> 2] >> (8 * (i & 3)));
-  } else {
+      for (int g = 0; g < 4; ++g) {
+        uint32_t x = 0;
 #pragma unroll
-    for (int i = 0; i < 32; ++i) b[i] = (p0 + i < total) ? bases[p0 + i] : (uint8_t)'N';
+        for (int i = 0; i < 4; ++i) {
+          const uint64_t p = p0 + 4 * g + i;
+          x |= (uint32_t)(p < total ? bases[p] : (uint8_t)'N') << (8 * i);
+        }
+        v[g] = x;
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const uint32_t r = pack4(v[g]);
+      code |= (r & 0xFFu) << (24 - 8 * g);
+      inv |= (r >> 8) << (4 * g);
+    }
   }
-  uint64_t code = 0;
-  uint32_t inv = 0;
-#pragma unroll
-  for (int i = 0; i < 32; ++i) {
-    uint32_t c = b[i];
-    bool ok = (c == 'A') | (c == 'C') | (c == 'G') | (c == 'T');
-    uint32_t cd = ((c >> 1) ^ (c >> 2)) & 3u;  // A->0 C->1 G->2 T->3
-    code = (code << 2) | (ok ? cd : 0u);
-    inv |= (ok ? 0u : 1u) << i;
+  const uint32_t ocode = __shfl_xor(code, 1, 64), oinv = __shfl_xor(inv, 1, 64);
+  if (w < nwords) {
+    if ((t & 1) == 0)
+      packed[w] = ((uint64_t)code << 32) | ocode;
+    else
+      flags[w] = inv << 16 | oinv;  // read-start bits (high half) are or-ed in by k_rstart
   }
-  packed[w] = code;
-  flags[w] = inv;  // read-start bits (high half) are or-ed in by k_rstart
 }
 
 // One thread per offset entry: marks the first base of every non-empty read
@@ -1671,7 +1702,7 @@ hipError_t launch_pack(const uint8_t* bases, uint64_t total, uint64_t nwords, ui
                        uint64_t* flags, hipStream_t s) {
   if (!nwords) return hipSuccess;
   const int aligned = ((uintptr_t)bases & 15) == 0;
-  hipLaunchKernelGGL(k_pack, dim3(div_up(nwords, 256)), dim3(256), 0, s, bases, total, nwords,
+  hipLaunchKernelGGL(k_pack, dim3(div_up(2 * nwords, 256)), dim3(256), 0, s, bases, total, nwords,
                      packed, flags, aligned);
   return hipGetLastError();
 }
