@@ -25,6 +25,18 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
+// The top 31 bits of mix64(z), in bits 31..1 (bit 0 is not part of them).
+// mix64's last step, z ^ (z >> 31), leaves bits 63..33 as they are, and the
+// high half of the second product needs three 32-bit multiplies: the
+// shuffle levels use only the top log2(partitions) <= 21 bits of g.
+__device__ __forceinline__ uint32_t mix64_top31(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  const uint64_t y = z ^ (z >> 27);
+  const uint32_t ylo = (uint32_t)y, yhi = (uint32_t)(y >> 32);
+  constexpr uint32_t clo = 0x133111EBu, chi = 0x94D049BBu;  // 0x94D049BB133111EB
+  return ylo * chi + yhi * clo + __umulhi(ylo, clo);
+}
+
 // Reverse complement of the 32 bases of a packed word (first base in the top
 // two bits): complement every 2-bit code (c -> 3-c = ~c) and reverse their order.
 __device__ __forceinline__ uint64_t rc_word(uint64_t v) {
@@ -428,7 +440,7 @@ __global__ void __launch_bounds__(kThreads) k_level1(const uint64_t* __restrict_
 #pragma unroll
     for (int jj = 0; jj < kPP; ++jj) {
       const uint64_t x = window_code(c, k, j0 + jj);
-      const uint32_t b = (uint32_t)(mix64(x ^ s0) >> (64 - a1));
+      const uint32_t b = mix64_top31(x ^ s0) >> (32 - a1);
       if ((valid >> jj) & 1u) meta[jj] = (b << 16) | atomicAdd(&cnt[b], 1u);
       key[jj] = x | tag;
     }
@@ -726,8 +738,7 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
     const uint32_t i = threadIdx.x + r * kThreads;
     if (i < n) {
       kv[r] = stage[i];
-      const uint64_t g = mix64((kv[r] & kKeyMask) ^ s0);
-      const uint32_t sub = (uint32_t)((g >> (64 - a1 - a2)) & (nb2 - 1));
+      const uint32_t sub = (mix64_top31((kv[r] & kKeyMask) ^ s0) >> (32 - a1 - a2)) & (nb2 - 1);
       meta[r] = (sub << 16) | atomicAdd(&cnt[sub], 1u);
     }
   }
