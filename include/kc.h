@@ -460,6 +460,50 @@ typedef struct kc_server_stats {
 
 kc_status kc_server_usage(kc_server* srv, kc_server_stats* out);
 
+/*
+ * The server's admission rule on plain numbers (the served form's memory
+ * budget, Sec. III-D; exposed so that the policy can be checked without a
+ * device).  A pooled context is described by its device bytes now, the bytes
+ * it would hold after the request (0: it cannot take it) and its last use.
+ */
+typedef struct kc_admit_pooled {
+  uint64_t bytes;
+  uint64_t after;
+  uint64_t stamp;  /* larger = used more recently */
+} kc_admit_pooled;
+
+typedef struct kc_admit_state {
+  uint64_t budget;        /* device bytes the server may use */
+  uint64_t in_use;        /* bytes reserved by admitted, unreleased requests */
+  uint64_t pooled;        /* bytes of the pooled contexts (the sum of their bytes) */
+  uint64_t max_inflight;  /* cap on the bases of requests running at once; 0 = none */
+  uint64_t inflight;      /* bases of the requests running now */
+  uint32_t running;       /* requests running now */
+  uint32_t reserved_;     /* 0 */
+} kc_admit_state;
+
+/*
+ * Plans the admission of the request at the head of the queue: job_bases
+ * bases, estimate device bytes as a new context.  *admit = 1 when it may
+ * start now: its memory fits, and with a cap no request runs or the running
+ * ones and it stay within max_inflight.  Then *choice is the pooled context
+ * it takes (index into pool) or -1 for a new one, chosen as the smallest
+ * pooled context that needs no new memory; else a new context if it fits
+ * beside the reservations and every pooled context; else the pooled context
+ * that grows least, if it grows by no more than a new context would take;
+ * else a new context that fits once pooled contexts are freed; else the
+ * least-growing pooled context.  *reserve is the bytes reserved for it, and
+ * evict[0 .. *n_evict) the pooled contexts (indices into pool, least recently
+ * used first; never the chosen one) to free so that reservations plus pooled
+ * bytes stay within the budget.  evict has room for n_pool entries.  Pure
+ * host computation; KC_ERR_INVALID_ARG for NULL outputs or a pooled sum that
+ * disagrees with state->pooled.
+ */
+kc_status kc_server_plan_admission(const kc_admit_state* state, const kc_admit_pooled* pool,
+                                   uint32_t n_pool, uint64_t job_bases, uint64_t estimate,
+                                   uint32_t* admit, int32_t* choice, uint64_t* reserve,
+                                   uint32_t* evict, uint32_t* n_evict);
+
 /* Waits for running requests, drops queued ones, frees every context.  NULL
  * is ignored. */
 void kc_server_destroy(kc_server* srv);

@@ -37,6 +37,7 @@ EXPORTED = ["kc_abi_version", "kc_status_str", "kc_create", "kc_insert_reads", "
             "kc_get_stats", "kc_reset", "kc_destroy", "kc_last_error", "kc_count_batch",
             "kc_autotune_batch", "kc_server_create", "kc_server_submit", "kc_server_wait",
             "kc_server_release", "kc_server_usage", "kc_server_destroy", "kc_server_set_overlap",
+            "kc_server_plan_admission",
             "kc_export_stems", "kc_filter_reads", "kc_filter_reads_noalloc", "kc_checkpoint",
             "kc_restore"]
 
@@ -98,6 +99,17 @@ class KcServerStats(ctypes.Structure):
                 ("grown", ctypes.c_uint64), ("evicted", ctypes.c_uint64)]
 
 
+class KcAdmitPooled(ctypes.Structure):
+    _fields_ = [("bytes", ctypes.c_uint64), ("after", ctypes.c_uint64), ("stamp", ctypes.c_uint64)]
+
+
+class KcAdmitState(ctypes.Structure):
+    _fields_ = [("budget", ctypes.c_uint64), ("in_use", ctypes.c_uint64),
+                ("pooled", ctypes.c_uint64), ("max_inflight", ctypes.c_uint64),
+                ("inflight", ctypes.c_uint64), ("running", ctypes.c_uint32),
+                ("reserved_", ctypes.c_uint32)]
+
+
 class KcTuneTrial(ctypes.Structure):
     _fields_ = [("partitions_log2", ctypes.c_uint32), ("table_slots", ctypes.c_uint32),
                 ("scatter_bits", ctypes.c_uint32), ("status", ctypes.c_int32),
@@ -156,6 +168,8 @@ def load():
         "kc_server_usage": ([V, P(KcServerStats)], st),
         "kc_server_destroy": ([V], None),
         "kc_server_set_overlap": ([V, U64], st),
+        "kc_server_plan_admission": ([P(KcAdmitState), P(KcAdmitPooled), U32, U64, U64, P(U32),
+                                      P(ctypes.c_int32), P(U64), P(U32), P(U32)], st),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -555,6 +569,29 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def plan_admission(budget: int, in_use: int, pool, job_bases: int, estimate: int,
+                   max_inflight: int = 0, inflight: int = 0, running: int = 0):
+    """kc_server_plan_admission on plain numbers (no device needed).  pool:
+    list of (bytes now, bytes after the job or 0, last-use stamp).  Returns
+    None when the request must wait, else (choice: pooled index or -1 for a
+    new context, reserved bytes, pooled indices to evict in order)."""
+    n = len(pool)
+    arr = (KcAdmitPooled * max(1, n))()
+    for i, (b, a, s) in enumerate(pool):
+        arr[i] = KcAdmitPooled(b, a, s)
+    state = KcAdmitState(budget, in_use, sum(p[0] for p in pool), max_inflight, inflight, running,
+                         0)
+    admit, nev = ctypes.c_uint32(0), ctypes.c_uint32(0)
+    choice, reserve = ctypes.c_int32(0), ctypes.c_uint64(0)
+    ev = (ctypes.c_uint32 * max(1, n))()
+    _check(None, load().kc_server_plan_admission(ctypes.byref(state), arr, n, job_bases, estimate,
+                                                 ctypes.byref(admit), ctypes.byref(choice),
+                                                 ctypes.byref(reserve), ev, ctypes.byref(nev)))
+    if not admit.value:
+        return None
+    return int(choice.value), int(reserve.value), [int(ev[i]) for i in range(nev.value)]
 
 
 def response_table(resp: KcResponse, n_counters: int):

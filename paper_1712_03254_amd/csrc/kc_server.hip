@@ -73,63 +73,39 @@ struct kc_server {
   double now() const {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
-  // Context for job j, *reserve receiving its size after the job: the
-  // smallest pooled context that needs no new memory (best fit); else a new
-  // one, if it fits beside the admitted jobs and the pooled contexts; else the
-  // pooled context that grows least, or a new one, if it fits once pooled
-  // contexts are freed.  Returns its pool index, -1 for a new context, -2
-  // when none fits yet.  (New memory and freed memory both cost: a growing
-  // buffer and an eviction free device memory, which waits for the device.)
-  int choose(const Job& j, uint64_t* reserve) const {
-    int fit = -2;
-    uint64_t fit_bytes = ~0ull;
-    int grow = -2;
-    uint64_t grow_by = ~0ull, grow_after = 0;
-    for (size_t i = 0; i < pool.size(); ++i) {
-      const uint64_t after = kc::bytes_after(pool[i].ctx, &j.req.cfg, j.bases, j.req.n_parts);
-      if (after == 0 || in_use + after > budget) continue;
-      if (after <= pool[i].bytes) {
-        if (pool[i].bytes < fit_bytes) {
-          fit = (int)i;
-          fit_bytes = pool[i].bytes;
-        }
-      } else if (after - pool[i].bytes < grow_by) {
-        grow = (int)i;
-        grow_by = after - pool[i].bytes;
-        grow_after = after;
-      }
-    }
-    if (fit >= 0) {
-      *reserve = fit_bytes;
-      return fit;
-    }
-    if (in_use + pooled + j.estimate <= budget) {
-      *reserve = j.estimate;
-      return -1;
-    }
-    if (grow >= 0 && grow_by <= j.estimate) {
-      *reserve = grow_after;
-      return grow;
-    }
-    if (in_use + j.estimate <= budget) {
-      *reserve = j.estimate;
-      return -1;
-    }
-    if (grow >= 0) {
-      *reserve = grow_after;
-      return grow;
-    }
-    return -2;
+  // Pool entries as the admission rule sees them: each pooled context's
+  // bytes now and after job j (0 when it cannot take it), and its last use.
+  std::vector<kc_admit_pooled> pool_view(const Job& j) const {
+    std::vector<kc_admit_pooled> v(pool.size());
+    for (size_t i = 0; i < pool.size(); ++i)
+      v[i] = {pool[i].bytes, kc::bytes_after(pool[i].ctx, &j.req.cfg, j.bases, j.req.n_parts),
+              pool[i].stamp};
+    return v;
   }
-  // The head of the queue may start: its memory fits, and (with a cap) no
-  // request is running or the running ones and it stay within the cap, so a
-  // large request runs alone while small ones overlap.
+  kc_admit_state admit_state() const {
+    kc_admit_state a{};
+    a.budget = budget;
+    a.in_use = in_use;
+    a.pooled = pooled;
+    a.max_inflight = max_inflight;
+    a.inflight = inflight;
+    a.running = running;
+    return a;
+  }
+  // The head of the queue may start now (kc_server_plan_admission).
   bool admissible() const {
     if (queue.empty()) return false;
     const Job& j = jobs.at(queue.front());
-    if (max_inflight && running && inflight + j.bases[0] + j.bases[1] > max_inflight) return false;
-    uint64_t r = 0;
-    return choose(j, &r) != -2;
+    const std::vector<kc_admit_pooled> v = pool_view(j);
+    const kc_admit_state a = admit_state();
+    std::vector<uint32_t> ev(v.size() + 1);
+    uint32_t admit = 0, nev = 0;
+    int32_t choice = -1;
+    uint64_t reserve = 0;
+    return kc_server_plan_admission(&a, v.data(), (uint32_t)v.size(), j.bases[0] + j.bases[1],
+                                    j.estimate, &admit, &choice, &reserve, ev.data(),
+                                    &nev) == KC_OK &&
+           admit;
   }
 };
 
@@ -163,29 +139,40 @@ void worker_main(kc_server* S, uint32_t w) {
     const uint64_t ticket = S->queue.front();
     S->queue.pop_front();
     Job& j = S->jobs.at(ticket);  // element references survive rehashing
-    kc_ctx* ctx = nullptr;
+    const std::vector<kc_admit_pooled> view = S->pool_view(j);
+    const kc_admit_state as = S->admit_state();
+    std::vector<uint32_t> ev(view.size() + 1);
+    uint32_t admit = 0, nev = 0;
+    int32_t m = -1;
     uint64_t reserve = 0;
-    const int m = S->choose(j, &reserve);
+    (void)kc_server_plan_admission(&as, view.data(), (uint32_t)view.size(),
+                                   j.bases[0] + j.bases[1], j.estimate, &admit, &m, &reserve,
+                                   ev.data(), &nev);
+    kc_ctx* ctx = nullptr;
+    std::vector<kc_ctx*> evict;
+    std::vector<char> gone(S->pool.size(), 0);
+    for (uint32_t e = 0; e < nev; ++e) {
+      evict.push_back(S->pool[ev[e]].ctx);
+      S->pooled -= S->pool[ev[e]].bytes;
+      gone[ev[e]] = 1;
+      ++S->evicted;
+    }
     if (m >= 0) {
       ctx = S->pool[m].ctx;
       ++(reserve > S->pool[m].bytes ? S->grown : S->reused);
       S->pooled -= S->pool[m].bytes;
-      S->pool.erase(S->pool.begin() + m);
+      gone[m] = 1;
     } else {
       ++S->created;
     }
+    {
+      std::vector<Pooled> keep;
+      for (size_t i = 0; i < S->pool.size(); ++i)
+        if (!gone[i]) keep.push_back(S->pool[i]);
+      S->pool.swap(keep);
+    }
     j.reserve = reserve;  // the context's size after the job
     S->in_use += j.reserve;
-    // free pooled contexts, least recently used first, until everything fits
-    std::vector<kc_ctx*> evict;
-    while (S->in_use + S->pooled > S->budget && !S->pool.empty()) {
-      auto lru = std::min_element(S->pool.begin(), S->pool.end(),
-                                  [](const Pooled& a, const Pooled& b) { return a.stamp < b.stamp; });
-      evict.push_back(lru->ctx);
-      S->pooled -= lru->bytes;
-      S->pool.erase(lru);
-      ++S->evicted;
-    }
     ++S->running;
     S->inflight += j.bases[0] + j.bases[1];
     j.resp.admit_ms = S->now();
@@ -254,6 +241,77 @@ kc_status kc_server_create(int device, uint64_t hbm_budget_bytes, uint32_t worke
   }
   for (uint32_t w = 0; w < workers; ++w) S->threads.emplace_back(worker_main, S, w);
   *out = S;
+  return KC_OK;
+}
+
+kc_status kc_server_plan_admission(const kc_admit_state* st, const kc_admit_pooled* pool,
+                                   uint32_t n_pool, uint64_t job_bases, uint64_t estimate,
+                                   uint32_t* admit, int32_t* choice, uint64_t* reserve,
+                                   uint32_t* evict, uint32_t* n_evict) {
+  if (!st || (n_pool && !pool) || !admit || !choice || !reserve || !n_evict || (n_pool && !evict))
+    return KC_ERR_INVALID_ARG;
+  uint64_t sum = 0;
+  for (uint32_t i = 0; i < n_pool; ++i) sum += pool[i].bytes;
+  if (sum != st->pooled) return KC_ERR_INVALID_ARG;
+  *admit = 0;
+  *choice = -1;
+  *reserve = 0;
+  *n_evict = 0;
+  // with a cap, a request starts only alone or within the cap beside the running ones
+  if (st->max_inflight && st->running && st->inflight + job_bases > st->max_inflight)
+    return KC_OK;
+  const uint64_t budget = st->budget, in_use = st->in_use;
+  int fit = -2, grow = -2;
+  uint64_t fit_bytes = ~0ull, grow_by = ~0ull, grow_after = 0;
+  for (uint32_t i = 0; i < n_pool; ++i) {
+    const uint64_t after = pool[i].after;
+    if (after == 0 || in_use + after > budget) continue;
+    if (after <= pool[i].bytes) {
+      if (pool[i].bytes < fit_bytes) {
+        fit = (int)i;
+        fit_bytes = pool[i].bytes;
+      }
+    } else if (after - pool[i].bytes < grow_by) {
+      grow = (int)i;
+      grow_by = after - pool[i].bytes;
+      grow_after = after;
+    }
+  }
+  int c = -2;
+  uint64_t r = 0;
+  if (fit >= 0) {
+    c = fit;
+    r = fit_bytes;
+  } else if (in_use + st->pooled + estimate <= budget) {
+    c = -1;
+    r = estimate;
+  } else if (grow >= 0 && grow_by <= estimate) {
+    c = grow;
+    r = grow_after;
+  } else if (in_use + estimate <= budget) {
+    c = -1;
+    r = estimate;
+  } else if (grow >= 0) {
+    c = grow;
+    r = grow_after;
+  }
+  if (c == -2) return KC_OK;  // nothing fits yet: wait for releases
+  *admit = 1;
+  *choice = c;
+  *reserve = r;
+  // free pooled contexts, least recently used first, until everything fits
+  uint64_t pooled = st->pooled - (c >= 0 ? pool[c].bytes : 0);
+  std::vector<char> taken(n_pool, 0);
+  if (c >= 0) taken[c] = 1;
+  while (in_use + r + pooled > budget) {
+    int lru = -1;
+    for (uint32_t i = 0; i < n_pool; ++i)
+      if (!taken[i] && (lru < 0 || pool[i].stamp < pool[lru].stamp)) lru = (int)i;
+    if (lru < 0) break;
+    taken[lru] = 1;
+    evict[(*n_evict)++] = (uint32_t)lru;
+    pooled -= pool[lru].bytes;
+  }
   return KC_OK;
 }
 
