@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define KC_ABI_VERSION 7u
+#define KC_ABI_VERSION 8u
 
 typedef struct kc_ctx kc_ctx;
 
@@ -404,6 +404,11 @@ typedef struct kc_request {
   kc_config cfg;        /* the job's configuration (its table budget is ignored) */
   kc_chunk parts[2];    /* parts[c] is counted into counter c */
   uint32_t n_parts;     /* 1 or 2, at most cfg.n_counters */
+  uint32_t reserved_;   /* 0 */
+  void* ready_event;    /* hipEvent_t recorded after the work that writes the read buffers
+                           (or NULL if they are ready at submission): the worker's stream
+                           waits for it before the first read is counted.  Owned by the
+                           caller; it must stay valid until the request is done. */
 } kc_request;
 
 typedef struct kc_response {
@@ -430,8 +435,8 @@ kc_status kc_server_create(int device, uint64_t hbm_budget_bytes, uint32_t worke
  * allows.  Takes effect for admissions after the call. */
 kc_status kc_server_set_overlap(kc_server* srv, uint64_t max_inflight_bases);
 
-/* Queues a request (copied; its read buffers must stay valid until the
- * request is done) and returns at once with its ticket.  A request whose
+/* Queues a request (copied; its read buffers and ready_event must stay valid
+ * until the request is done) and returns at once with its ticket.  A request whose
  * estimated footprint exceeds the whole budget finishes at once with status
  * KC_ERR_OVER_BUDGET. */
 kc_status kc_server_submit(kc_server* srv, const kc_request* req, uint64_t* ticket_out);

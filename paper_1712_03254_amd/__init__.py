@@ -81,7 +81,8 @@ class KcChunk(ctypes.Structure):
 
 
 class KcRequest(ctypes.Structure):
-    _fields_ = [("cfg", KcConfig), ("parts", KcChunk * 2), ("n_parts", ctypes.c_uint32)]
+    _fields_ = [("cfg", KcConfig), ("parts", KcChunk * 2), ("n_parts", ctypes.c_uint32),
+                ("reserved_", ctypes.c_uint32), ("ready_event", ctypes.c_void_p)]
 
 
 class KcResponse(ctypes.Structure):
@@ -526,6 +527,7 @@ class Server:
         h = ctypes.c_void_p()
         _check(None, load().kc_server_create(device, budget_bytes, workers, ctypes.byref(h)))
         self.h = h
+        self._held = {}  # ticket -> (event, part tensors) until the request is done
         if overlap_bases:
             self.set_overlap(overlap_bases)
 
@@ -534,23 +536,32 @@ class Server:
 
     def submit(self, cfg: Config, parts) -> int:
         """parts: list of up to two (bases, offsets) device tensor pairs (part c
-        counted into counter c).  Returns the ticket at once."""
+        counted into counter c).  Returns the ticket at once.  The worker waits
+        for the work queued so far on the current stream (which may still be
+        writing the reads), and the tensors are held until the request is done."""
+        import torch
         r = KcRequest()
         r.cfg = cfg.c()
         for i, (b, o, n, t) in enumerate(chunk_list(parts)):
             r.parts[i] = KcChunk(b, o, n, t)
         r.n_parts = len(parts)
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream())
+        r.ready_event = ev.cuda_event
         t = ctypes.c_uint64(0)
         _check(None, load().kc_server_submit(self.h, ctypes.byref(r), ctypes.byref(t)))
+        self._held[int(t.value)] = (ev, list(parts))
         return int(t.value)
 
     def wait(self, ticket: int) -> KcResponse:
         out = KcResponse()
         _check(None, load().kc_server_wait(self.h, ticket, ctypes.byref(out)))
+        self._held.pop(ticket, None)
         return out
 
     def release(self, ticket: int):
         _check(None, load().kc_server_release(self.h, ticket))
+        self._held.pop(ticket, None)
 
     def usage(self) -> dict:
         st = KcServerStats()
@@ -563,6 +574,7 @@ class Server:
         if self.h:
             load().kc_server_destroy(self.h)
             self.h = None
+            self._held.clear()
 
     def __enter__(self):
         return self

@@ -15,6 +15,8 @@
 #include <string>
 #include <vector>
 
+#include <sys/stat.h>
+
 #include "kc.h"
 #include "kc_internal.h"
 
@@ -1424,11 +1426,10 @@ kc_status kc_checkpoint(kc_ctx* c, const char* path) {
   return KC_OK;
 }
 
-kc_status kc_restore(const char* path, int device, kc_ctx** out) {
-  if (!out) {
-    g_create_error = "out is NULL";
-    return KC_ERR_INVALID_ARG;
-  }
+// kc_restore's body.  `made` tracks the context it created and has neither
+// destroyed nor handed out, so that kc_restore can free it when a host
+// allocation throws.
+static kc_status restore_file(const char* path, int device, kc_ctx** out, kc_ctx** made) {
   *out = nullptr;
   if (!path) {
     g_create_error = "path is NULL";
@@ -1459,6 +1460,10 @@ kc_status kc_restore(const char* path, int device, kc_ctx** out) {
       h.b1_offset != h.header_bytes + P * table_bytes ||
       h.file_bytes != h.b1_offset + 2 * h.bloom_words64 * 8 + on * 8 + on * 4 * nc)
     return bad("inconsistent offsets");
+  // every size below comes from the header: check it against the file first
+  struct stat fst;
+  if (fstat(fileno(fc.f), &fst) != 0 || (uint64_t)fst.st_size != h.file_bytes)
+    return bad("file size differs from its header");
   std::vector<CkptRecord> recs(P);
   if (!read_all(fc.f, recs.data(), P * sizeof(CkptRecord))) return bad("short record area");
   for (uint64_t u = 0; u < P; ++u)
@@ -1472,8 +1477,10 @@ kc_status kc_restore(const char* path, int device, kc_ctx** out) {
   kc_ctx* c = nullptr;
   kc_status r = kc_create(&cfg, device, &c);
   if (r != KC_OK) return r;
+  *made = c;
   auto give_up = [&](kc_status st, const std::string& why) {
     g_create_error = why;
+    *made = nullptr;
     kc_destroy(c);
     return st;
   };
@@ -1531,17 +1538,24 @@ kc_status kc_restore(const char* path, int device, kc_ctx** out) {
     u += n;
   }
   c->spill_used = n_spill;
-  std::vector<uint64_t> w(std::max<uint64_t>(h.bloom_words64, on));
-  std::vector<uint32_t> oc(on * nc);
-  bool ok_io = read_all(fc.f, w.data(), h.bloom_words64 * 8) &&
-               hip_ok(hipMemcpy(c->b1.p, w.data(), h.bloom_words64 * 8, hipMemcpyHostToDevice)) &&
-               read_all(fc.f, w.data(), h.bloom_words64 * 8) &&
-               hip_ok(hipMemcpy(c->b2.p, w.data(), h.bloom_words64 * 8, hipMemcpyHostToDevice)) &&
-               read_all(fc.f, w.data(), on * 8) &&
-               hip_ok(hipMemcpy(c->okeys.p, w.data(), on * 8, hipMemcpyHostToDevice)) &&
-               read_all(fc.f, oc.data(), on * 4 * nc) &&
-               hip_ok(hipMemcpy(c->ocounts.p, oc.data(), on * 4 * nc, hipMemcpyHostToDevice));
-  if (!ok_io) return give_up(KC_ERR_INVALID_ARG, "not a usable checkpoint: short Bloom or overflow area");
+  // B1, B2 and the overflow table pass through a host buffer of at most 64 MiB
+  std::vector<char> stage((size_t)std::min<uint64_t>(64ull << 20, std::max<uint64_t>(h.bloom_words64, on) * 8));
+  e = hipSuccess;
+  auto section = [&](void* dev, uint64_t bytes) {
+    for (uint64_t done = 0; done < bytes;) {
+      const uint64_t n = std::min<uint64_t>(bytes - done, stage.size());
+      if (!read_all(fc.f, stage.data(), n) ||
+          !hip_ok(hipMemcpy(static_cast<char*>(dev) + done, stage.data(), n, hipMemcpyHostToDevice)))
+        return false;
+      done += n;
+    }
+    return true;
+  };
+  const bool ok_io = section(c->b1.p, h.bloom_words64 * 8) && section(c->b2.p, h.bloom_words64 * 8) &&
+                     section(c->okeys.p, on * 8) && section(c->ocounts.p, on * 4 * nc);
+  if (!ok_io)
+    return e != hipSuccess ? give_up(KC_ERR_DEVICE, "restore copy failed")
+                           : give_up(KC_ERR_INVALID_ARG, "not a usable checkpoint: short Bloom or overflow area");
   const uint32_t used = (uint32_t)h.stats.overflow_keys;
   if (!hip_ok(hipMemcpy(c->ovf_used.p, &used, 4, hipMemcpyHostToDevice)) ||
       !hip_ok(launch_slot_map(c->slot_of.as<uint32_t>(), (uint32_t)P, (uint32_t)n_spill, nullptr)) ||
@@ -1559,8 +1573,28 @@ kc_status kc_restore(const char* path, int device, kc_ctx** out) {
     c->st.kernel_launches[i] = 0;
   }
   c->state = FINALIZED;
+  *made = nullptr;
   *out = c;
   return KC_OK;
+}
+
+kc_status kc_restore(const char* path, int device, kc_ctx** out) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return KC_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  kc_ctx* made = nullptr;
+  // host buffers are sized from the file: their failure is an error status,
+  // never an exception through the C boundary
+  try {
+    return restore_file(path, device, out, &made);
+  } catch (const std::bad_alloc&) {
+    if (made) kc_destroy(made);
+    *out = nullptr;
+    g_create_error = "host allocation failed while restoring";
+    return KC_ERR_OUT_OF_MEMORY;
+  }
 }
 
 kc_status kc_spill(kc_ctx* c, int64_t partition, uint64_t* bytes_out) {

@@ -122,6 +122,11 @@ kc_status run_job(kc_server* S, uint32_t w, const kc_request& req, kc_ctx** ctx,
     r = kc_create(&req.cfg, S->device, ctx);
   }
   if (r != KC_OK) return r;
+  // the reads may still be written on the caller's stream
+  if (req.ready_event && hipStreamWaitEvent(s, static_cast<hipEvent_t>(req.ready_event), 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return KC_ERR_DEVICE;
+  }
   for (uint32_t p = 0; p < req.n_parts; ++p) {
     const kc_chunk& c = req.parts[p];
     r = kc_insert_reads(*ctx, c.bases_dev, c.offsets_dev, c.n_reads, c.total_bases, p, s);
@@ -325,7 +330,8 @@ kc_status kc_server_set_overlap(kc_server* S, uint64_t max_inflight_bases) {
 
 kc_status kc_server_submit(kc_server* S, const kc_request* req, uint64_t* ticket_out) {
   if (!S || !req || !ticket_out) return KC_ERR_INVALID_ARG;
-  if (req->n_parts < 1 || req->n_parts > 2 || req->n_parts > req->cfg.n_counters)
+  if (req->n_parts < 1 || req->n_parts > 2 || req->n_parts > req->cfg.n_counters ||
+      req->reserved_ != 0)
     return KC_ERR_INVALID_ARG;
   Job j;
   j.req = *req;

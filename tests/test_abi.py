@@ -53,8 +53,8 @@ int main(void) {
          offsetof(kc_chunk, total_bases), sizeof(kc_tune_trial), offsetof(kc_tune_trial, ms));
   printf("%zu %zu %zu %zu %zu\n", sizeof(kc_request), offsetof(kc_request, n_parts),
          sizeof(kc_response), offsetof(kc_response, ctx), offsetof(kc_response, footprint_bytes));
-  printf("%zu %zu\n", offsetof(kc_config, shuffle_tile_log2),
-         offsetof(kc_tune_trial, shuffle_tile_log2));
+  printf("%zu %zu %zu\n", offsetof(kc_config, shuffle_tile_log2),
+         offsetof(kc_tune_trial, shuffle_tile_log2), offsetof(kc_request, ready_event));
   return 0;
 }
 ''')
@@ -68,7 +68,8 @@ int main(void) {
             kc.KcChunk.total_bases.offset, ctypes.sizeof(kc.KcTuneTrial), kc.KcTuneTrial.ms.offset,
             ctypes.sizeof(kc.KcRequest), kc.KcRequest.n_parts.offset, ctypes.sizeof(kc.KcResponse),
             kc.KcResponse.ctx.offset, kc.KcResponse.footprint_bytes.offset,
-            kc.KcConfig.shuffle_tile_log2.offset, kc.KcTuneTrial.shuffle_tile_log2.offset]
+            kc.KcConfig.shuffle_tile_log2.offset, kc.KcTuneTrial.shuffle_tile_log2.offset,
+            kc.KcRequest.ready_event.offset]
     assert got == want
 
 
@@ -129,4 +130,46 @@ def test_restore_rejects_bad_files_without_a_device(tmp_path):
     short = tmp_path / "short.kcckpt"
     short.write_bytes(b"KCCKPT\x00\x01" + kc.kc_abi_version().to_bytes(4, "little") + bytes(16))
     assert lib.kc_restore(str(short).encode(), 0, ctypes.byref(h)) == kc.KC_ERR_INVALID_ARG
+    assert not h.value
+
+
+class _CkptHeader(ctypes.Structure):
+    """The checkpoint header as the writer lays it out (a test-side copy)."""
+    _fields_ = [("magic", ctypes.c_uint8 * 8), ("abi_version", ctypes.c_uint32),
+                ("reserved_", ctypes.c_uint32), ("header_bytes", ctypes.c_uint64),
+                ("cfg", kc.KcConfig), ("p_log2", ctypes.c_uint32), ("cap", ctypes.c_uint32),
+                ("n_counters", ctypes.c_uint32), ("ovf_log2", ctypes.c_uint32),
+                ("n_parts", ctypes.c_uint64), ("bloom_words64", ctypes.c_uint64),
+                ("records_offset", ctypes.c_uint64), ("b1_offset", ctypes.c_uint64),
+                ("b2_offset", ctypes.c_uint64), ("ovf_keys_offset", ctypes.c_uint64),
+                ("ovf_counts_offset", ctypes.c_uint64), ("file_bytes", ctypes.c_uint64),
+                ("stats", kc.KcStats)]
+
+
+def test_restore_checks_the_file_size_before_allocating(tmp_path):
+    """A header whose sections are consistent but declare a 2^34-entry overflow
+    table and 2^36-bit Bloom levels (about 160 GiB), on a file of a few KiB:
+    refused from the file size, before any buffer is sized from the header."""
+    lib = kc.load()
+    hd = _CkptHeader()
+    hd.magic = (ctypes.c_uint8 * 8)(*b"KCCKPT\x00\x01")
+    hd.abi_version = kc.kc_abi_version()
+    hd.p_log2, hd.cap, hd.n_counters, hd.ovf_log2 = 4, 4096, 2, 34
+    hd.n_parts, hd.bloom_words64 = 16, 1 << 30
+    hd.records_offset = ctypes.sizeof(_CkptHeader)
+    hd.header_bytes = (hd.records_offset + 16 * 24 + 4095) // 4096 * 4096
+    table = hd.cap * 8 + hd.cap * 4 * hd.n_counters
+    hd.b1_offset = hd.header_bytes + hd.n_parts * table
+    hd.b2_offset = hd.b1_offset + hd.bloom_words64 * 8
+    hd.ovf_keys_offset = hd.b2_offset + hd.bloom_words64 * 8
+    hd.ovf_counts_offset = hd.ovf_keys_offset + (8 << 34)
+    hd.file_bytes = hd.ovf_counts_offset + (8 << 34)
+    recs = b"".join(u.to_bytes(4, "little") + bytes(4) +
+                    (hd.header_bytes + u * table).to_bytes(8, "little") + bytes(8)
+                    for u in range(16))
+    path = tmp_path / "huge.kcckpt"
+    path.write_bytes(bytes(hd) + recs + bytes(4096))
+    h = ctypes.c_void_p()
+    assert lib.kc_restore(str(path).encode(), 0, ctypes.byref(h)) == kc.KC_ERR_INVALID_ARG
+    assert b"file size" in lib.kc_last_error(None)
     assert not h.value

@@ -179,3 +179,35 @@ def test_overlap_cap_bounds_work_in_flight():
         overlapped += bool(running)
     assert overlapped > 0  # small jobs still ran side by side
     note("cap %d bases; %d of %d jobs started beside others" % (cap, overlapped, len(spans)))
+
+
+def test_submit_orders_after_the_producing_stream_and_holds_the_reads():
+    """Reads copied to the device on a side stream, behind a spinning kernel,
+    are submitted at once as temporaries: the worker waits for that stream
+    (the request's ready event) and the server binding keeps the tensors alive,
+    so the memory the caller drops is not reused under the running job."""
+    import torch
+    note("case: 6 joint jobs, reads copied behind a spin kernel on a side stream, seed 74")
+    jobs = make_jobs(74, 6)
+    ref = [alone(cfg, [to_device(b, o) for b, o in parts]) for cfg, parts in jobs]
+    side = torch.cuda.Stream()
+    with kc.Server(256 << 20, workers=3) as srv:
+        tickets = []
+        with torch.cuda.stream(side):
+            for cfg, parts in jobs:
+                torch.cuda._sleep(20_000_000)
+                dev = [(torch.from_numpy(b).pin_memory().to("cuda", non_blocking=True),
+                        torch.from_numpy(o.view(np.int64)).pin_memory().to("cuda", non_blocking=True))
+                       for b, o in parts]
+                tickets.append(srv.submit(cfg, dev))
+                del dev
+            # memory the caller has dropped, written over while the jobs run
+            junk = [torch.full((int(o[-1]) + 64,), 0xFF, dtype=torch.uint8, device="cuda")
+                    for _, parts in jobs for _, o in parts]
+        for t, (cfg, _), r in zip(tickets, jobs, ref):
+            resp = srv.wait(t)
+            assert resp.status == kc.KC_OK, resp.status
+            same(served(resp, cfg), r)
+            srv.release(t)
+        del junk
+    torch.cuda.synchronize()
