@@ -175,32 +175,81 @@ __global__ void __launch_bounds__(256) k_pack(const uint8_t* __restrict__ bases,
     if ((t & 1) == 0)
       packed[w] = ((uint64_t)code << 32) | ocode;
     else
-      flags[w] = inv << 16 | oinv;  // read-start bits (high half) are or-ed in by k_rstart
+      flags[w] = inv << 16 | oinv;  // read-start bits (high half) are set by k_rstart
   }
 }
 
-// One thread per offset entry: marks the first base of every non-empty read
-// and checks the offsets' contract.
+// Read-start bits (the high half of each flag word; the pack kernels leave it
+// zero), one thread per offset entry, without an atomic per read.  Reads tile
+// the bases, so every word's first base lies in exactly one non-empty read,
+// the word's leader, which writes the word's start bits with one 32-bit store:
+// a word wholly inside the read can hold only the read's own start, and the
+// last word the read leads also holds the starts of the reads after it that
+// begin in that word, found by scanning up to kStartScan offset entries.  A
+// start further than that from its word's leader (only runs of empty reads
+// make one) is or-ed in atomically, and a leader whose scan was cut short ors
+// its bits as well.  Offsets are chunk-relative; word0 is the chunk's first
+// word in the flag array (chunks start on a word boundary).  The offsets'
+// contract is checked on the way.
+constexpr uint32_t kStartScan = 64;
+
+__device__ __forceinline__ void put_starts(uint64_t* flags, uint64_t w, uint32_t bits, bool atomic) {
+  uint32_t* hi = reinterpret_cast<uint32_t*>(flags + w) + 1;
+  if (atomic)
+    atomicOr(hi, bits);
+  else
+    *hi = bits;
+}
+
+__device__ __forceinline__ void read_start(const uint64_t* __restrict__ offsets, uint64_t r,
+                                           uint64_t n_reads, uint64_t total, uint64_t word0,
+                                           uint64_t* __restrict__ flags, uint32_t* __restrict__ err) {
+  const uint64_t o = offsets[r];
+  if (r == 0 && o != 0) atomicOr(err, (uint32_t)ERR_OFFSETS);
+  if (r == n_reads) {
+    if (o != total) atomicOr(err, (uint32_t)ERR_OFFSETS);
+    return;
+  }
+  const uint64_t e = offsets[r + 1];
+  if (e < o || e > total) {
+    atomicOr(err, (uint32_t)ERR_OFFSETS);
+    return;
+  }
+  if (e == o) return;  // empty read
+  // this read's start, when its word's leader is out of scan range: the
+  // leader is the last entry at or before the word's first base
+  const uint64_t ws = o >> 5;
+  if ((o & 31) != 0 && r >= kStartScan && offsets[r - kStartScan] > (ws << 5))
+    put_starts(flags, word0 + ws, 1u << (o & 31), true);
+  // words whose first base this read holds: wf .. wl
+  const uint64_t wf = (o + 31) >> 5, wl = (e - 1) >> 5;
+  if (wf > wl) return;
+  if (wf < wl && (o & 31) == 0) put_starts(flags, word0 + wf, 1u, false);
+  const uint64_t lo = wl << 5;
+  uint32_t bits = o == lo ? 1u : 0u;
+  bool cut = true;
+  for (uint32_t d = 1; d <= kStartScan; ++d) {
+    const uint64_t j = r + d;
+    if (j >= n_reads) {
+      cut = false;
+      break;
+    }
+    const uint64_t v = offsets[j];
+    if (v < lo || v >= lo + 32) {
+      cut = false;
+      break;
+    }
+    if (offsets[j + 1] > v) bits |= 1u << (v - lo);
+  }
+  if (bits) put_starts(flags, word0 + wl, bits, cut);
+}
+
 __global__ void __launch_bounds__(256) k_rstart(const uint64_t* __restrict__ offsets,
                                                 uint64_t n_reads, uint64_t total,
                                                 uint64_t* __restrict__ flags,
                                                 uint32_t* __restrict__ err) {
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > n_reads) return;
-  uint64_t o = offsets[i];
-  if (i == 0 && o != 0) atomicOr(err, (uint32_t)ERR_OFFSETS);
-  if (i == n_reads) {
-    if (o != total) atomicOr(err, (uint32_t)ERR_OFFSETS);
-    return;
-  }
-  uint64_t o1 = offsets[i + 1];
-  if (o1 < o || o1 > total) {
-    atomicOr(err, (uint32_t)ERR_OFFSETS);
-    return;
-  }
-  if (o1 > o && o < total)
-    atomicOr(reinterpret_cast<unsigned long long*>(&flags[o >> 5]),
-             1ull << (32 + (o & 31)));
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= n_reads) read_start(offsets, i, n_reads, total, 0, flags, err);
 }
 
 // Largest j < n with key(j) <= v, for a non-decreasing key (chunks with no
@@ -251,23 +300,8 @@ __global__ void __launch_bounds__(256) k_rstart_batch(const ChunkDesc* __restric
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t j = chunk_of(cd, nchunks, i, [](const ChunkDesc& d) { return d.read0; });
-    const uint64_t r = i - cd[j].read0, n = cd[j].n_reads, total = cd[j].total;
-    const uint64_t* offsets = cd[j].offsets;
-    const uint64_t o = offsets[r];
-    if (r == 0 && o != 0) atomicOr(err, (uint32_t)ERR_OFFSETS);
-    if (r == n) {
-      if (o != total) atomicOr(err, (uint32_t)ERR_OFFSETS);
-      continue;
-    }
-    const uint64_t o1 = offsets[r + 1];
-    if (o1 < o || o1 > total) {
-      atomicOr(err, (uint32_t)ERR_OFFSETS);
-      continue;
-    }
-    if (o1 > o && o < total) {
-      const uint64_t at = cd[j].word0 * 32 + o;
-      atomicOr(reinterpret_cast<unsigned long long*>(&flags[at >> 5]), 1ull << (32 + (at & 31)));
-    }
+    read_start(cd[j].offsets, i - cd[j].read0, cd[j].n_reads, cd[j].total, cd[j].word0, flags,
+               err);
   }
 }
 
