@@ -461,6 +461,10 @@ typedef struct kc_server_stats {
   uint64_t reused;           /* ... a pooled context that needed no new memory */
   uint64_t grown;            /* ... a pooled context whose buffers had to grow */
   uint64_t evicted;          /* pooled contexts freed to make room */
+  uint64_t cached_bytes;     /* device blocks freed by the server's contexts and kept for later
+                                jobs (beyond the budget's bytes, up to the budget again) */
+  uint64_t device_allocs;    /* blocks the server has taken from the runtime */
+  uint64_t device_frees;     /* blocks it has given back to the runtime (past the cache limit) */
 } kc_server_stats;
 
 kc_status kc_server_usage(kc_server* srv, kc_server_stats* out);

@@ -97,7 +97,9 @@ class KcServerStats(ctypes.Structure):
                 ("queued", ctypes.c_uint32), ("running", ctypes.c_uint32),
                 ("pooled_contexts", ctypes.c_uint32), ("reserved_", ctypes.c_uint32),
                 ("created", ctypes.c_uint64), ("reused", ctypes.c_uint64),
-                ("grown", ctypes.c_uint64), ("evicted", ctypes.c_uint64)]
+                ("grown", ctypes.c_uint64), ("evicted", ctypes.c_uint64),
+                ("cached_bytes", ctypes.c_uint64), ("device_allocs", ctypes.c_uint64),
+                ("device_frees", ctypes.c_uint64)]
 
 
 class KcAdmitPooled(ctypes.Structure):

@@ -5,6 +5,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+#include <vector>
+
 #include "kc.h"
 
 namespace kc {
@@ -207,5 +211,55 @@ struct AllocStream {
 };
 // Keeps memory freed to the device's default pool cached there (once per device).
 void keep_pool_memory(int device);
+
+// ---- device block cache of the request server (kc_runtime.hip) ----
+// Size of the block that serves a request of n bytes: a multiple of 4 KiB up
+// to 16 KiB, then four sizes per octave (at most a quarter above n).
+uint64_t cache_round(uint64_t n);
+// Device blocks that the request server's contexts free, kept for the
+// server's later allocations instead of going back to the runtime (under
+// context churn the runtime's stream-ordered pool hands memory back and maps
+// it again, and the workers then wait tens of milliseconds).  A block is
+// reused for a request of at most half its size or more; one freed on another
+// stream is handed over behind an event wait, so reuse keeps stream order.
+// Blocks come from hipMalloc and go back with hipFree only past the cache
+// limit (largest first) or when the cache is drained.  Thread-safe.
+class BlockCache {
+ public:
+  explicit BlockCache(uint64_t limit) : limit_(limit) {}
+  hipError_t alloc(uint64_t want, hipStream_t s, void** p, uint64_t* got);
+  void give_back(void* p, uint64_t bytes, hipStream_t s);
+  // Frees every cached block; call with the device idle.
+  void drain();
+  // bytes cached now, blocks taken from and given back to the runtime so far
+  void usage(uint64_t* cached, uint64_t* allocs, uint64_t* frees) {
+    std::lock_guard<std::mutex> lk(mu_);
+    *cached = cached_;
+    *allocs = allocs_;
+    *frees = frees_;
+  }
+
+ private:
+  struct Block {
+    void* p;
+    hipStream_t s;   // stream of its last use
+    hipEvent_t ev;   // recorded there when it was given back (NULL: no wait needed)
+  };
+  void free_largest();
+  std::mutex mu_;
+  std::multimap<uint64_t, Block> free_;
+  std::vector<hipEvent_t> events_;
+  uint64_t cached_ = 0, allocs_ = 0, frees_ = 0;
+  const uint64_t limit_;
+};
+// While one lives, the calling thread's new library buffers come from cache k
+// (each buffer remembers where it came from and goes back there).
+struct UseCache {
+  explicit UseCache(BlockCache* k);
+  ~UseCache();
+  UseCache(const UseCache&) = delete;
+  UseCache& operator=(const UseCache&) = delete;
+  BlockCache* prev;
+};
 
 }  // namespace kc

@@ -59,6 +59,92 @@ AllocStream::~AllocStream() {
   t_async = prev_on;
 }
 
+thread_local BlockCache* t_cache = nullptr;
+UseCache::UseCache(BlockCache* k) : prev(t_cache) { t_cache = k; }
+UseCache::~UseCache() { t_cache = prev; }
+
+uint64_t cache_round(uint64_t n) {
+  if (n <= 16384) return std::max<uint64_t>(4096, (n + 4095) & ~4095ull);
+  const uint64_t step = 1ull << (63 - __builtin_clzll(n) - 2);
+  return (n + step - 1) & ~(step - 1);
+}
+
+hipError_t BlockCache::alloc(uint64_t want, hipStream_t s, void** p, uint64_t* got) {
+  const uint64_t r = cache_round(want);
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = free_.lower_bound(r);
+    if (it != free_.end() && it->first <= 2 * r) {
+      const Block b = it->second;
+      if (b.ev && b.s != s) {
+        const hipError_t e = hipStreamWaitEvent(s, b.ev, 0);
+        if (e != hipSuccess) return e;
+      }
+      if (b.ev) events_.push_back(b.ev);  // the wait is enqueued: the event may be recorded again
+      *p = b.p;
+      *got = it->first;
+      cached_ -= it->first;
+      free_.erase(it);
+      return hipSuccess;
+    }
+  }
+  hipError_t e = hipMalloc(p, r);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      while (!free_.empty()) free_largest();
+    }
+    e = hipMalloc(p, r);
+  }
+  if (e == hipSuccess) {
+    *got = r;
+    std::lock_guard<std::mutex> lk(mu_);
+    ++allocs_;
+  }
+  return e;
+}
+
+void BlockCache::give_back(void* p, uint64_t bytes, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(mu_);
+  hipEvent_t ev = nullptr;
+  if (!events_.empty()) {
+    ev = events_.back();
+    events_.pop_back();
+  } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    ev = nullptr;
+  }
+  if (!ev || hipEventRecord(ev, s) != hipSuccess) {
+    // no event: wait here for the work queued on s, so no later user has to
+    if (ev) events_.push_back(ev);
+    ev = nullptr;
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(s);
+  }
+  free_.emplace(bytes, Block{p, s, ev});
+  cached_ += bytes;
+  while (cached_ > limit_ && !free_.empty()) free_largest();
+}
+
+void BlockCache::free_largest() {
+  auto it = std::prev(free_.end());
+  if (it->second.ev) {
+    (void)hipEventSynchronize(it->second.ev);
+    events_.push_back(it->second.ev);
+  }
+  (void)hipFree(it->second.p);
+  ++frees_;
+  cached_ -= it->first;
+  free_.erase(it);
+}
+
+void BlockCache::drain() {
+  std::lock_guard<std::mutex> lk(mu_);
+  while (!free_.empty()) free_largest();
+  for (hipEvent_t e : events_) (void)hipEventDestroy(e);
+  events_.clear();
+}
+
 void keep_pool_memory(int device) {
   static std::once_flag once[64];
   if (device < 0 || device >= 64) return;
@@ -82,12 +168,15 @@ using kc::t_stream;
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
-  bool async = false;  // came from hipMallocAsync
+  bool async = false;               // came from hipMallocAsync
+  kc::BlockCache* cache = nullptr;  // came from (and goes back to) a server's block cache
   template <typename T>
   T* as() const { return static_cast<T*>(p); }
   void release() {
     if (p) {
-      if (async && t_async)
+      if (cache)
+        cache->give_back(p, bytes, t_async ? t_stream : nullptr);
+      else if (async && t_async)
         (void)hipFreeAsync(p, t_stream);
       else
         (void)hipFree(p);
@@ -95,11 +184,24 @@ struct DevBuf {
     p = nullptr;
     bytes = 0;
     async = false;
+    cache = nullptr;
   }
   hipError_t ensure(size_t want) {
     if (want == 0) want = 8;
     if (bytes >= want) return hipSuccess;
     release();
+    if (kc::t_cache) {
+      uint64_t got = 0;
+      const hipError_t e = kc::t_cache->alloc(want, t_async ? t_stream : nullptr, &p, &got);
+      if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        return e;
+      }
+      bytes = got;
+      cache = kc::t_cache;
+      return hipSuccess;
+    }
     hipError_t e = t_async ? hipMallocAsync(&p, want, t_stream) : hipMalloc(&p, want);
     if (e != hipSuccess) {
       p = nullptr;
@@ -591,8 +693,9 @@ uint64_t bytes_after(const kc_ctx* c, const kc_config* cfg, const uint64_t* part
   if (derive(&d) != KC_OK) return 0;
   const uint64_t nb1 = 1ull << d.a1, nb2 = 1ull << d.a2;
   const uint64_t nparts = 1ull << d.p_log2, nc = cfg->n_counters;
+  // the server's contexts allocate from its block cache: sizes as the cache rounds them
   auto mx = [&](const DevBuf kc_ctx::*buf, uint64_t need) {
-    return std::max<uint64_t>(c ? (c->*buf).bytes : 0, need);
+    return std::max<uint64_t>(c ? (c->*buf).bytes : 0, cache_round(std::max<uint64_t>(need, 8)));
   };
   // first-level scratch (largest insert) and the per-insert segments
   uint64_t packed = 0, hist = 0, lstart = 0, off = 0, parts = 0, keys1 = 0, runs = 0, keys = 0;
@@ -610,7 +713,9 @@ uint64_t bytes_after(const kc_ctx* c, const kc_config* cfg, const uint64_t* part
     parts = std::max<uint64_t>(parts, scan_parts(nhist) * 8);
     keys1 = std::max<uint64_t>(keys1, ntiles * kTilePos * 8);
     runs = std::max(runs, tile_desc_bytes(tiles2));
-    if (kmax) seg.push_back({kmax * 8, (nb1 + 1) * 12 + tiles2 * (nb2 + 1) * 4});
+    if (kmax)
+      seg.push_back({cache_round(kmax * 8), cache_round((nb1 + 1) * 8) + cache_round((nb1 + 1) * 4) +
+                                                cache_round(tiles2 * (nb2 + 1) * 4)});
     keys += kmax;
   }
   uint64_t n = mx(&kc_ctx::b1, d.bloom_words64 * 8) + mx(&kc_ctx::b2, d.bloom_words64 * 8) +

@@ -50,8 +50,13 @@ kc_config normalised(const kc_config& c) {
 }  // namespace
 
 struct kc_server {
+  explicit kc_server(uint64_t b) : budget(b), cache(b) {}
   int device = 0;
   uint64_t budget = 0;
+  // buffers of the server's contexts: freed ones are kept for later jobs (up
+  // to the budget again, beyond the admitted bytes) rather than returned to
+  // the runtime while serving
+  kc::BlockCache cache;
   uint32_t workers = 0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -114,6 +119,7 @@ namespace {
 kc_status run_job(kc_server* S, uint32_t w, const kc_request& req, kc_ctx** ctx, kc_stats* st) {
   hipStream_t s = S->streams[w];
   kc::AllocStream alloc_on(s);  // creation and growth allocate in order on the worker's stream
+  kc::UseCache from(&S->cache);
   kc_status r;
   if (*ctx) {
     r = kc_reset(*ctx);
@@ -230,10 +236,9 @@ kc_status kc_server_create(int device, uint64_t hbm_budget_bytes, uint32_t worke
     return KC_ERR_INVALID_ARG;
   }
   if (hipSetDevice(device) != hipSuccess) return KC_ERR_DEVICE;
-  kc_server* S = new (std::nothrow) kc_server();
+  kc_server* S = new (std::nothrow) kc_server(hbm_budget_bytes);
   if (!S) return KC_ERR_OUT_OF_MEMORY;
   S->device = device;
-  S->budget = hbm_budget_bytes;
   S->workers = workers;
   S->t0 = std::chrono::steady_clock::now();
   for (uint32_t w = 0; w < workers; ++w) {
@@ -399,6 +404,7 @@ kc_status kc_server_usage(kc_server* S, kc_server_stats* out) {
   out->reused = S->reused;
   out->grown = S->grown;
   out->evicted = S->evicted;
+  S->cache.usage(&out->cached_bytes, &out->device_allocs, &out->device_frees);
   return KC_OK;
 }
 
@@ -416,6 +422,8 @@ void kc_server_destroy(kc_server* S) {
   for (auto& kv : S->jobs)
     if (kv.second.resp.ctx) kc_destroy(kv.second.resp.ctx);
   for (Pooled& p : S->pool) kc_destroy(p.ctx);
+  (void)hipDeviceSynchronize();
+  S->cache.drain();
   for (hipStream_t s : S->streams) (void)hipStreamDestroy(s);
   delete S;
 }

@@ -85,7 +85,8 @@ class TableDigest:
 
 
 def words_digest(words: np.ndarray) -> str:
-    return hashlib.sha256(np.ascontiguousarray(words, dtype="<u8").tobytes()).hexdigest()
+    # hashed in place (levels of 2^36 bits are 8 GiB each)
+    return hashlib.sha256(memoryview(np.ascontiguousarray(words, dtype="<u8")).cast("B")).hexdigest()
 
 
 STAT_KEYS = ["n_valid", "n_pass", "entries", "sum_counts", "fp_singletons", "b1_popcount",

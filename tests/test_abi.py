@@ -53,8 +53,9 @@ int main(void) {
          offsetof(kc_chunk, total_bases), sizeof(kc_tune_trial), offsetof(kc_tune_trial, ms));
   printf("%zu %zu %zu %zu %zu\n", sizeof(kc_request), offsetof(kc_request, n_parts),
          sizeof(kc_response), offsetof(kc_response, ctx), offsetof(kc_response, footprint_bytes));
-  printf("%zu %zu %zu\n", offsetof(kc_config, shuffle_tile_log2),
-         offsetof(kc_tune_trial, shuffle_tile_log2), offsetof(kc_request, ready_event));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(kc_config, shuffle_tile_log2),
+         offsetof(kc_tune_trial, shuffle_tile_log2), offsetof(kc_request, ready_event),
+         sizeof(kc_server_stats), offsetof(kc_server_stats, device_frees));
   return 0;
 }
 ''')
@@ -69,7 +70,8 @@ int main(void) {
             ctypes.sizeof(kc.KcRequest), kc.KcRequest.n_parts.offset, ctypes.sizeof(kc.KcResponse),
             kc.KcResponse.ctx.offset, kc.KcResponse.footprint_bytes.offset,
             kc.KcConfig.shuffle_tile_log2.offset, kc.KcTuneTrial.shuffle_tile_log2.offset,
-            kc.KcRequest.ready_event.offset]
+            kc.KcRequest.ready_event.offset, ctypes.sizeof(kc.KcServerStats),
+            kc.KcServerStats.device_frees.offset]
     assert got == want
 
 

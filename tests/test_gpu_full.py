@@ -217,3 +217,62 @@ def test_batched_200mbp_whole_output_digest():
     assert got["sha256"] == want["sha256"]
     assert words_digest(b1) == want["b1"]
     assert words_digest(b2) == want["b2"]
+
+
+def test_spill_3gbp_whole_output_digest():
+    """The 3 Gbp workload at full size (2·10^8 reads of 100 bp, 1.4·10^10
+    k-mers, 2^36-bit levels, 2^20 partitions, every table resident), inserted
+    as 8 consecutive slices of the read stream as bench.py does: every
+    statistic, the sorted table (whole and per value range) and both levels
+    against the digest of the oracle's streamed value-range passes.  The
+    2.6·10^9-entry table is sorted on the device one value range at a time."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import synth
+    from digest import TableDigest
+    note("case: spill_3gbp full size (8 inserts of 2.5e7 reads x 100 bp), whole-output digest")
+    want = read_digest_file(os.path.join(GOLDEN, "digest_spill_3gbp.txt"))
+    w = synth.WORKLOADS["spill_3gbp"]
+    genome = w.make_genome(threads=16)
+    per = w.n_reads
+    while per * w.lmax >= 1 << 32:
+        per = (per + 1) // 2
+    cfg = workload_config(w)
+    with kc.KmerCounter(cfg) as c:
+        for f in range(0, w.n_reads, per):
+            b, o = w.make_reads(genome, first=f, n=min(per, w.n_reads - f), threads=16)
+            db, do = to_device(b, o)
+            del b, o
+            c.insert_reads(db, do)
+            torch.cuda.synchronize()
+            del db, do
+            note("inserted reads %d..%d" % (f, min(f + per, w.n_reads) - 1))
+        del genome
+        st = c.finalize()
+        for key in STAT_KEYS:
+            assert st[key] == want["stats"][key], (key, st[key], want["stats"][key])
+        b1, b2 = c.export_bloom()
+        assert words_digest(b1) == want["b1"]
+        assert words_digest(b2) == want["b2"]
+        del b1, b2
+        note("statistics and both levels equal; exporting %d entries" % st["entries"])
+        keys, counts = c.export()
+    kd = torch.from_numpy(keys.view(np.int64)).cuda()
+    del keys
+    cd = torch.from_numpy(np.ascontiguousarray(counts).view(np.int32)).cuda()
+    del counts
+    td = TableDigest(w.k)
+    top = kd >> (2 * w.k - td.rb)  # keys < 2^62: signed order is unsigned order
+    for q in range(1 << td.rb):
+        idx = torch.nonzero(top == q).squeeze(1)
+        kq = kd[idx]
+        order = torch.argsort(kq)
+        td.update(kq[order].cpu().numpy().view(np.uint64),
+                  cd[idx][order].cpu().numpy().view(np.uint32))
+        del idx, kq, order
+    del kd, cd, top
+    got = td.result()
+    for q, (g, r) in enumerate(zip(got["ranges"], want["ranges"])):
+        assert tuple(g) == tuple(r), ("value range", q, g, r)
+    assert got["sha256"] == want["sha256"]
