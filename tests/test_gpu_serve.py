@@ -102,6 +102,9 @@ def test_served_results_equal_alone_and_oracle():
         th.join()
         u = srv.usage()
         assert u["in_use"] == 0 and u["queued"] == 0 and u["running"] == 0
+        # freed context buffers stay in the server's block cache, within one budget
+        assert 0 < u["device_allocs"] and u["cached_bytes"] <= budget
+        assert u["device_allocs"] - u["device_frees"] >= 1
     assert seen["max_in_use"] <= budget
     workers = {r[3] for r in results}
     assert len(workers) > 1  # jobs ran on several workers
