@@ -125,6 +125,8 @@ struct QueryArgs {
   uint32_t* host_rows;     // indices of queries on spilled partitions
   uint64_t* host_keys;     // their canonical keys (same order)
   uint32_t* host_count;
+  const uint64_t* fkeys;   // filter: the table keys with bit 63 set where the slot's counts
+                           // pass the filter's thresholds (NULL: probe keys, then counts)
 };
 
 // ---- launchers (kc_kernels.hip) ----
@@ -162,6 +164,11 @@ hipError_t launch_stems(bool claim, const uint64_t* tkeys, const uint32_t* tcoun
 hipError_t launch_stem_flags(const uint64_t* skeys, uint64_t n, uint32_t* flags, hipStream_t s);
 hipError_t launch_stem_emit(const uint64_t* skeys, const uint64_t* off, uint64_t n,
                             uint64_t* stems, hipStream_t s);
+// fkeys[i] = tkeys[i] with bit 63 set when slot i's counts pass (tumour >=
+// tmin, normal <= nmax), for the nslots slots of the resident tables.
+hipError_t launch_filter_keys(const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,
+                              uint32_t nc, uint32_t tmin, uint32_t nmax, uint64_t* fkeys,
+                              hipStream_t s);
 hipError_t launch_filter(const QueryArgs& a, const uint64_t* packed, const uint64_t* flags,
                          uint64_t nwords, const uint64_t* offsets, uint64_t n_reads, uint64_t total,
                          uint32_t tmin, uint32_t nmax, uint32_t* hit, uint32_t* out, hipStream_t s);

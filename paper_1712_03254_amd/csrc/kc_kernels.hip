@@ -1478,12 +1478,60 @@ __global__ void __launch_bounds__(256) k_query(const QueryArgs A, const uint64_t
   if (nc > 1) out[i * nc + 1] = c1;
 }
 
+// The filter's selection rule on a key's counts: tumour count >= tmin and
+// normal count <= nmax (counters 1 and 0 of a two-counter table; normal 0
+// and tumour = the count for one counter; 0 and 0 when absent).
+__device__ __forceinline__ bool filter_pass(uint32_t nc, uint32_t c0, uint32_t c1, uint32_t tmin,
+                                            uint32_t nmax) {
+  const uint32_t tumour = nc > 1 ? c1 : c0, normal = nc > 1 ? c0 : 0u;
+  return tumour >= tmin && normal <= nmax;
+}
+
+constexpr uint64_t kSelBit = 1ull << 63;  // selection mark of a filter key (keys are < 2^62)
+
+// One thread per table slot: the slot's key, marked when its counts pass.
+__global__ void __launch_bounds__(256) k_filter_keys(const uint64_t* __restrict__ tkeys,
+                                                     const uint32_t* __restrict__ tcounts,
+                                                     uint64_t nslots, uint32_t nc, uint32_t tmin,
+                                                     uint32_t nmax, uint64_t* __restrict__ fkeys) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = tkeys[i];
+    const uint32_t c0 = tcounts[i * nc], c1 = nc > 1 ? tcounts[i * nc + 1] : 0u;
+    fkeys[i] = key == kEmpty ? kEmpty : key | (filter_pass(nc, c0, c1, tmin, nmax) ? kSelBit : 0);
+  }
+}
+
+// Whether canonical key x is selected: one probe sequence over the marked
+// keys of its partition table (one random line per lookup instead of a key
+// line and a count line), else the overflow table's counts, else absent.
+__device__ __forceinline__ bool filter_selected(const QueryArgs& A, uint64_t x, uint32_t tmin,
+                                                uint32_t nmax) {
+  const uint64_t th = (x ^ A.hc.salt[0]) * kTableMul;
+  const uint64_t u = top_bits(mix64(x ^ A.hc.salt[0]), A.hc.p_log2);
+  const uint64_t base = (uint64_t)A.slot_of[u] * A.cap;
+  uint64_t slot = home_slot(th, (uint32_t)A.cap);
+  for (uint32_t p = 0; p < A.probe_limit; ++p) {
+    const uint64_t cur = A.fkeys[base + slot];
+    if ((cur & ~kSelBit) == x) return (cur >> 63) != 0;
+    if (cur == kEmpty) break;
+    slot = slot + 1 == A.cap ? 0 : slot + 1;
+  }
+  uint32_t c0 = 0, c1 = 0;
+  uint64_t at;
+  if (*A.ovf_used && probe_table(A.okeys, 0, 1ull << A.ovf_log2, 1ull << A.ovf_log2,
+                                 mix64(th) >> (64 - A.ovf_log2), x, &at)) {
+    c0 = A.ocounts[at * A.hc.nc];
+    if (A.hc.nc > 1) c1 = A.ocounts[at * A.hc.nc + 1];
+  }
+  return filter_pass(A.hc.nc, c0, c1, tmin, nmax);
+}
+
 // Filter-unit lookup, first pass: bit j of hit[w] marks the window ending at
-// base j of packed word w when its canonical k-mer is selected: tumour count
-// >= tmin and normal count <= nmax (counters 1 and 0 of a two-counter table;
-// normal 0 and tumour = the count for one counter; 0 and 0 when absent).
+// base j of packed word w when its canonical k-mer is selected (filter_pass).
 // Four consecutive threads share a word, eight windows each; every table is
-// in HBM (the caller checks).
+// in HBM (the caller checks).  With A.fkeys the lookups read the marked keys
+// (filter_selected), otherwise keys and counts (table_counts).
 __global__ void __launch_bounds__(256) k_filter_windows(const QueryArgs A,
                                                         const uint64_t* __restrict__ packed,
                                                         const uint64_t* __restrict__ flags,
@@ -1499,10 +1547,15 @@ __global__ void __launch_bounds__(256) k_filter_windows(const QueryArgs A,
     for (int jj = 0; jj < kPP; ++jj) {
       uint64_t x;
       if (!window_key(c, A.hc.k, j0 + jj, &x)) continue;
-      uint32_t c0 = 0, c1 = 0;
-      table_counts(A, x & kKeyMask, &c0, &c1);
-      const uint32_t tumour = A.hc.nc > 1 ? c1 : c0, normal = A.hc.nc > 1 ? c0 : 0u;
-      if (tumour >= tmin && normal <= nmax) bits |= 1u << (j0 + jj);
+      bool sel;
+      if (A.fkeys) {
+        sel = filter_selected(A, x & kKeyMask, tmin, nmax);
+      } else {
+        uint32_t c0 = 0, c1 = 0;
+        table_counts(A, x & kKeyMask, &c0, &c1);
+        sel = filter_pass(A.hc.nc, c0, c1, tmin, nmax);
+      }
+      if (sel) bits |= 1u << (j0 + jj);
     }
   }
   bits |= __shfl_xor(bits, 1, 64);
@@ -1954,6 +2007,15 @@ hipError_t launch_stem_flags(const uint64_t* skeys, uint64_t n, uint32_t* flags,
 hipError_t launch_stem_emit(const uint64_t* skeys, const uint64_t* off, uint64_t n,
                             uint64_t* stems, hipStream_t s) {
   hipLaunchKernelGGL(k_stem_emit, dim3(stride_grid(n)), dim3(256), 0, s, skeys, off, n, stems);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_keys(const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,
+                              uint32_t nc, uint32_t tmin, uint32_t nmax, uint64_t* fkeys,
+                              hipStream_t s) {
+  if (!nslots) return hipSuccess;
+  hipLaunchKernelGGL(k_filter_keys, dim3(stride_grid(nslots)), dim3(256), 0, s, tkeys, tcounts,
+                     nslots, nc, tmin, nmax, fkeys);
   return hipGetLastError();
 }
 

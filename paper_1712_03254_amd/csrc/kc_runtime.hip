@@ -815,9 +815,12 @@ kc_status filter_checks(kc_ctx* c, const uint8_t* bases, const uint64_t* offsets
   return KC_OK;
 }
 
+// With fkeys (room for every resident slot) the lookups read the table keys
+// marked with the selection (launch_filter_keys) instead of keys and counts.
 kc_status filter_run(kc_ctx* c, const uint8_t* bases, const uint64_t* offsets, uint64_t n_reads,
                      uint64_t total_bases, uint32_t tumour_min, uint32_t normal_max, uint32_t* out,
-                     hipStream_t s, uint64_t* packed, uint64_t* flags, uint32_t* hit, bool timed) {
+                     hipStream_t s, uint64_t* packed, uint64_t* flags, uint32_t* hit, bool timed,
+                     uint64_t* fkeys) {
   const uint64_t nwords = (total_bases + 31) / 32;
   KC_HIP(c, launch_fill32(c->derr.as<uint32_t>(), 1, 0, s), "fill");
   QueryArgs a{};
@@ -832,8 +835,14 @@ kc_status filter_run(kc_ctx* c, const uint8_t* bases, const uint64_t* offsets, u
   a.ovf_used = c->ovf_used.as<uint32_t>();
   a.ovf_log2 = c->ovf_log2;
   a.err = c->derr.as<uint32_t>();
+  a.fkeys = fkeys;
   {
     StageTimer t(c, s, KC_T_FILTER, timed);
+    if (fkeys)
+      KC_HIP(c, launch_filter_keys(c->tkeys.as<uint64_t>(), c->tcounts.as<uint32_t>(),
+                                   (uint64_t)c->pool_slots * c->cap, c->cfg.n_counters, tumour_min,
+                                   normal_max, fkeys, s),
+             "filter keys");
     KC_HIP(c, launch_pack(bases, total_bases, nwords, packed, flags, s), "pack");
     KC_HIP(c, launch_rstart(offsets, n_reads, total_bases, flags, c->derr.as<uint32_t>(), s),
            "read starts");
@@ -1380,13 +1389,19 @@ kc_status kc_filter_reads(kc_ctx* c, const uint8_t* bases, const uint64_t* offse
   kc::AllocStream alloc_on(s);
   KC_HIP(c, hipSetDevice(c->device), "hipSetDevice");
   const uint64_t nwords = (total_bases + 31) / 32;
-  DevBuf packed, flags, hit;
-  ReleaseOnExit free_bufs{&packed, &flags, &hit};
+  DevBuf packed, flags, hit, fkeys;
+  ReleaseOnExit free_bufs{&packed, &flags, &hit, &fkeys};
   KC_HIP(c, packed.ensure(nwords * 8), "packed buffer");
   KC_HIP(c, flags.ensure(nwords * 8), "flag buffer");
   KC_HIP(c, hit.ensure(nwords * 4), "window bitmap");
+  // marking the slots reads every table once (8 + 4 n_counters bytes a slot,
+  // 8 written); it pays when the windows outnumber half the slots, since a
+  // marked lookup skips a random count line
+  const uint64_t nslots = (uint64_t)c->pool_slots * c->cap;
+  if (total_bases >= nslots / 2) KC_HIP(c, fkeys.ensure(nslots * 8), "filter keys");
   return filter_run(c, bases, offsets, n_reads, total_bases, tumour_min, normal_max, out, s,
-                    packed.as<uint64_t>(), flags.as<uint64_t>(), hit.as<uint32_t>(), true);
+                    packed.as<uint64_t>(), flags.as<uint64_t>(), hit.as<uint32_t>(), true,
+                    fkeys.as<uint64_t>());
 }
 
 kc_status kc_filter_reads_noalloc(kc_ctx* c, const uint8_t* bases, const uint64_t* offsets,
@@ -1408,7 +1423,7 @@ kc_status kc_filter_reads_noalloc(kc_ctx* c, const uint8_t* bases, const uint64_
   return filter_run(c, bases, offsets, n_reads, total_bases, tumour_min, normal_max, out,
                     as_stream(hip_stream), reinterpret_cast<uint64_t*>(p + kNaPackedOff),
                     reinterpret_cast<uint64_t*>(p + kNaFlagsOff),
-                    reinterpret_cast<uint32_t*>(p + kNaHitOff), false);
+                    reinterpret_cast<uint32_t*>(p + kNaHitOff), false, nullptr);
 }
 
 // ------------------------------------------------------------ checkpoints

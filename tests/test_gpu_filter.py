@@ -43,6 +43,11 @@ def oracle_table(cfg, chunks, counters):
 
 
 def gpu_filter(cfg, chunks, counters, probe, thresholds):
+    """kc_filter_reads at each threshold pair, checked equal to
+    kc_filter_reads_noalloc (which always probes keys, then counts; the
+    allocating entry point reads keys marked with the selection when the
+    windows outnumber half the table slots)."""
+    import torch
     out = []
     with kc.KmerCounter(cfg) as c:
         for (b, o), t in zip(chunks, counters):
@@ -50,20 +55,25 @@ def gpu_filter(cfg, chunks, counters, probe, thresholds):
             c.insert_reads(db, do, counter=t)
         st = c.finalize()
         pb, po = to_device(*probe)
+        direct = torch.empty(max(1, po.numel() - 1), dtype=torch.int32, device="cuda")
         for tmin, nmax in thresholds:
-            out.append(c.filter_reads(pb, po, tmin, nmax).cpu().numpy().view(np.uint32).copy())
+            got = c.filter_reads(pb, po, tmin, nmax).cpu().numpy().view(np.uint32).copy()
+            ref = c.filter_reads_noalloc(pb, po, tmin, nmax, direct)
+            assert np.array_equal(got, ref.cpu().numpy().view(np.uint32)), (tmin, nmax)
+            out.append(got)
     return st, out
 
 
 THRESHOLDS = [(2, 0), (1, 1), (3, 2), (0, 0xFFFFFFFF), (1, 0xFFFFFFFF)]
 
 
-@pytest.mark.parametrize("k,seed", [(21, 81), (27, 82), (31, 83)])
-def test_filter_joint_counters(k, seed):
-    note("case: filter, joint counters, k=%d, seed %d, tumour reads re-read" % (k, seed))
+@pytest.mark.parametrize("k,seed,slots", [(21, 81, 0), (27, 82, 0), (31, 83, 0), (31, 86, 128)])
+def test_filter_joint_counters(k, seed, slots):
+    note("case: filter, joint counters, k=%d, seed %d, table slots %s, tumour reads re-read"
+         % (k, seed, slots or "auto"))
     normal, tumour = joint(seed)
     cfg = kc.Config(k=k, n_counters=2, bloom_bits_log2=20, bloom_hashes=3, bloom_block_log2=13,
-                    partitions_log2=9, seed=seed)
+                    partitions_log2=9, table_slots=slots, seed=seed)
     st, got = gpu_filter(cfg, [normal, tumour], [0, 1], tumour, THRESHOLDS)
     res = oracle_table(cfg, [normal, tumour], [0, 1])
     for (tmin, nmax), g in zip(THRESHOLDS, got):
