@@ -417,7 +417,8 @@ def served_main(args, w):
                 "mean_ms": round(float(lat.mean()), 2), "span_ms": round(span_ms, 1),
                 "mean_service_ms": round(float(svc.mean()), 2),
                 "contexts": {k: u[k] for k in ("created", "reused", "grown", "evicted",
-                                               "pooled_contexts")}}
+                                               "pooled_contexts", "cached_bytes",
+                                               "device_allocs", "device_frees")}}
 
     budget = w.serve_budget
     res = {}
