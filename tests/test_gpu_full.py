@@ -263,15 +263,21 @@ def test_spill_3gbp_whole_output_digest():
     cd = torch.from_numpy(np.ascontiguousarray(counts).view(np.int32)).cuda()
     del counts
     td = TableDigest(w.k)
-    top = kd >> (2 * w.k - td.rb)  # keys < 2^62: signed order is unsigned order
+    shift = 2 * w.k - td.rb
+    step = 1 << 30  # torch's index selection is kept below 2^31 elements per call
     for q in range(1 << td.rb):
-        idx = torch.nonzero(top == q).squeeze(1)
-        kq = kd[idx]
-        order = torch.argsort(kq)
+        ks, cs = [], []
+        for lo in range(0, kd.numel(), step):
+            part = kd[lo:lo + step]
+            sel = (part >> shift) == q
+            ks.append(part[sel])
+            cs.append(cd[lo:lo + step][sel])
+        kq, cq = torch.cat(ks), torch.cat(cs)
+        order = torch.argsort(kq)  # keys < 2^62: signed order is unsigned order
         td.update(kq[order].cpu().numpy().view(np.uint64),
-                  cd[idx][order].cpu().numpy().view(np.uint32))
-        del idx, kq, order
-    del kd, cd, top
+                  cq[order].cpu().numpy().view(np.uint32))
+        del ks, cs, kq, cq, order
+    del kd, cd
     got = td.result()
     for q, (g, r) in enumerate(zip(got["ranges"], want["ranges"])):
         assert tuple(g) == tuple(r), ("value range", q, g, r)
