@@ -15,7 +15,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -352,14 +351,11 @@ def served_main(args, w):
     offs = torch.from_numpy(reads[0][1].view(np.int64)).to(dev)
     del reads
     plan = w.request_plan()
-    win = L - w.k + 1
 
     def request(i):
         n, s0, s1 = (int(v) for v in plan[i])
         half = n // 2
-        kmers = n * win
-        m = int(min(34, max(20, math.ceil(math.log2(8 * kmers)))))
-        pl = max(m - w.bloom_block_log2, int(round(math.log2(max(1, n * L) / 8192))))
+        kmers, m, pl = w.request_params(n)
         cfg = kc.Config(k=w.k, n_counters=2, min_count=w.min_count, bloom_bits_log2=m,
                         bloom_hashes=w.bloom_hashes, bloom_block_log2=w.bloom_block_log2,
                         seed=w.seed, partitions_log2=pl)

@@ -8,6 +8,7 @@ the CPU oracle and the GPU library read what these functions return.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -191,6 +192,18 @@ class Workload:
         s0 = (d[:, 1] % room).astype(np.int64)
         s1 = (d[:, 2] % room).astype(np.int64)
         return np.stack([2 * half, s0, s1], axis=1)
+
+    def request_params(self, n_reads: int):
+        """Counting parameters of a served request of n_reads fixed-length
+        reads: (k-mer windows, Bloom bits log2, partitions log2).  The Bloom
+        filter has 2^m bits, m = clamp(ceil(log2(8 * windows)), 20, 34); the
+        partition count (result-neutral) is about one per 2^13 bases, and at
+        least one per Bloom block."""
+        kmers = int(n_reads) * max(0, self.lmax - self.k + 1)
+        m = int(min(34, max(20, math.ceil(math.log2(max(1, 8 * kmers))))))
+        pl = max(m - self.bloom_block_log2,
+                 int(round(math.log2(max(1, int(n_reads) * self.lmax) / 8192))))
+        return kmers, m, pl
 
     def chunk_plan(self) -> np.ndarray:
         """Reads per chunk of a batched workload: floor(exp(U[ln lo, ln hi])),

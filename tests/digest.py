@@ -123,3 +123,56 @@ def read_digest_file(path: str) -> dict:
             elif parts[0] in ("b1", "b2"):
                 out[parts[0]] = parts[1]
     return out
+
+
+def served_subset(sizes, count: int = 16, seed: int = 0):
+    """Indices (into the timed requests) of the served requests checked
+    against the oracle: the largest and count - 1 others drawn with a seeded
+    generator, ascending."""
+    sizes = np.asarray(sizes)
+    big = int(np.argmax(sizes))
+    rest = np.array([i for i in range(sizes.size) if i != big])
+    pick = np.random.default_rng(seed).choice(rest, size=min(count - 1, rest.size), replace=False)
+    return sorted([big] + [int(i) for i in pick])
+
+
+def write_request_digests(path: str, header: list[str], records: list[dict]):
+    """One record per request: 'request i reads n normal s0 tumour s1 m M',
+    then its statistics, table, ranges and levels, each line led by i."""
+    with open(path, "w") as f:
+        for line in header:
+            f.write("# %s\n" % line)
+        for r in records:
+            i = r["index"]
+            f.write("request %d reads %d normal %d tumour %d m %d\n" % (
+                i, r["reads"], r["normal"], r["tumour"], r["m"]))
+            for name in STAT_KEYS:
+                f.write("stat %d %s %d\n" % (i, name, r["stats"][name]))
+            f.write("table %d %s\n" % (i, r["table"]["sha256"]))
+            for q, (n, s, h) in enumerate(r["table"]["ranges"]):
+                f.write("range %d %d %d %d %s\n" % (i, q, n, s, h))
+            f.write("b1 %d %s\n" % (i, r["b1"]))
+            f.write("b2 %d %s\n" % (i, r["b2"]))
+
+
+def read_request_digests(path: str) -> dict:
+    out = {}
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            p = line.split()
+            i = int(p[1])
+            if p[0] == "request":
+                out[i] = {"reads": int(p[3]), "normal": int(p[5]), "tumour": int(p[7]),
+                          "m": int(p[9]), "stats": {}, "ranges": []}
+            elif p[0] == "stat":
+                out[i]["stats"][p[2]] = int(p[3])
+            elif p[0] == "table":
+                out[i]["sha256"] = p[2]
+            elif p[0] == "range":
+                out[i]["ranges"].append((int(p[3]), int(p[4]), p[5]))
+            elif p[0] in ("b1", "b2"):
+                out[i][p[0]] = p[2]
+    return out

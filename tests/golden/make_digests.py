@@ -22,9 +22,11 @@ for p in (ROOT, os.path.dirname(HERE)):
     if p not in sys.path:
         sys.path.insert(0, p)
 
+import numpy as np  # noqa: E402
 import oracle  # noqa: E402
 import synth  # noqa: E402
-from digest import TableDigest, table_digests, words_digest, write_digest_file  # noqa: E402
+from digest import (TableDigest, served_subset, table_digests, words_digest,  # noqa: E402
+                    write_digest_file, write_request_digests)
 
 STATS = {"n_valid": "n_valid", "n_pass": "n_pass", "entries": "entries",
          "sum_counts": "sum_counts", "fp_singletons": "fp_singletons",
@@ -42,7 +44,8 @@ def main():
     args = ap.parse_args()
     w = synth.WORKLOADS[args.workload]
     if w.requests:
-        raise SystemExit("served workloads are checked per request, not as one stream")
+        served(w, args)
+        return
     t0 = time.time()
     genome = w.make_genome()
     # a batched workload's chunks are consecutive reads of one read stream
@@ -84,6 +87,63 @@ def main():
         "bits of the 2k-bit code: 'range q entries sum_of_counts sha256'.",
     ]
     write_digest_file(out, header, stats, table, b1, b2)
+    print("wrote %s in %.0f s" % (out, time.time() - t0))
+
+
+def served(w, args):
+    """A served workload: the whole output of each request of a seeded subset
+    (digest.served_subset of the timed requests: the largest and 15 others),
+    each request counted alone by the oracle with its own Bloom size
+    (Workload.request_params) and two counters, its normal reads in counter 0
+    and its tumour reads in counter 1."""
+    t0 = time.time()
+    normal = w.make_genome()
+    tumour = w.make_tumour(normal)
+    samples = [w.make_sample_reads(normal, 0), w.make_sample_reads(tumour, 1)]
+    del normal, tumour
+    plan = w.request_plan()[w.warmup_requests:]
+    pick = served_subset(plan[:, 0], seed=w.seed)
+    L = w.lmax
+    t1 = time.time()
+    records = []
+    for i in pick:
+        n, s0, s1 = (int(v) for v in plan[i])
+        half = n // 2
+        _, m, _ = w.request_params(n)
+        bases = np.concatenate([samples[0][0][s0 * L:(s0 + half) * L],
+                                samples[1][0][s1 * L:(s1 + half) * L]])
+        offsets = np.arange(2 * half + 1, dtype=np.uint64) * np.uint64(L)
+        tags = np.repeat(np.array([0, 1], np.uint8), half)
+        p = oracle.Params(k=w.k, n_counters=2, min_count=w.min_count, m_log2=m, h=w.bloom_hashes,
+                          block_log2=min(w.bloom_block_log2, m), seed=w.seed)
+        res = oracle.count_ranges(p, bases, offsets, tags=tags, threads=args.threads,
+                                  qbits=args.qbits)
+        records.append({"index": i, "reads": n, "normal": s0, "tumour": s1, "m": m,
+                        "stats": {k: res.stats[v] for k, v in STATS.items()},
+                        "table": table_digests(res.keys, res.counts, w.k),
+                        "b1": words_digest(res.b1), "b2": words_digest(res.b2)})
+        print("request %d: %d reads, m %d, %d entries" % (i, n, m, res.stats["entries"]),
+              flush=True)
+        del res, bases
+    t2 = time.time()
+    out = os.path.join(HERE, "digest_%s.txt" % w.name)
+    header = [
+        "Whole output of the CPU oracle (value-range passes) for a subset of the timed requests of",
+        "workload %s: the largest and 15 drawn with seed %d (digest.served_subset), each counted" % (
+            w.name, w.seed),
+        "alone: its normal reads (reads normal .. normal+n/2-1 of sample 0) in counter 0, its tumour",
+        "reads (tumour .. tumour+n/2-1 of sample 1) in counter 1; k=%d, min_count %d, Bloom 2^m bits"
+        % (w.k, w.min_count),
+        "per level (m per request), %d hashes, blocks of 2^%d bits; request i is timed request i."
+        % (w.bloom_hashes, w.bloom_block_log2),
+        "Written by: python tests/golden/make_digests.py %s%s (oracle %.0f s, input %.0f s)."
+        % (w.name, "".join(" --%s %d" % (k, v) for k, v in (("threads", args.threads),
+                                                           ("qbits", args.qbits)) if v),
+           t2 - t1, t1 - t0),
+        "Table stream per request: entries ascending by key, key <u8 then counts <u4 (normal,",
+        "tumour); ranges by the top 4 bits of the 2k-bit code.",
+    ]
+    write_request_digests(out, header, records)
     print("wrote %s in %.0f s" % (out, time.time() - t0))
 
 
