@@ -242,8 +242,8 @@ kc_status kc_export_bloom_words(kc_ctx* ctx, const uint64_t* word_idx_host, uint
  * (so a capacity of stats.entries always suffices); with a smaller capacity
  * the call fails with KC_ERR_INVALID_ARG after setting *n_out.  counts_dev
  * must be 4-byte aligned.  Spilled tables are staged back to HBM.  Scratch:
- * about 20 bytes of device memory per slot of a stem table of the next power
- * of two above 2 x entries, allocated and freed inside.  Synchronises. */
+ * about 12 bytes of device memory per entry (one record per table k-mer) and
+ * 12 bytes per stem partition, allocated and freed inside.  Synchronises. */
 kc_status kc_export_stems(kc_ctx* ctx, uint64_t* stems_dev, uint16_t* counts_dev, uint64_t capacity,
                           uint64_t* n_out, void* hip_stream);
 

@@ -157,13 +157,24 @@ int tally_threads();
 hipError_t launch_ovf_emit(const CountArgs& a, uint64_t* pstats_ovf, uint32_t blocks,
                            hipStream_t s);
 hipError_t launch_reduce(const uint64_t* rows, uint64_t nrows, uint64_t* out, hipStream_t s);
-hipError_t launch_stems(bool claim, const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,
-                        const uint32_t* live, uint32_t cap, uint32_t nc, uint32_t k,
-                        uint64_t* skeys, uint32_t s_log2, const uint64_t* off, uint16_t* items,
-                        uint32_t* err, hipStream_t s);
-hipError_t launch_stem_flags(const uint64_t* skeys, uint64_t n, uint32_t* flags, hipStream_t s);
-hipError_t launch_stem_emit(const uint64_t* skeys, const uint64_t* off, uint64_t n,
-                            uint64_t* stems, hipStream_t s);
+// Stem relayout by stem partitions (the top p_log2 bits of a stem's hash):
+// count the entries of each partition over a table pass (pcount[2^p_log2]),
+// scatter them as records (cursor[p] starts at partition p's offset), then
+// one workgroup per partition numbers its distinct stems and writes their
+// items (poff: 2^p_log2 + 1 offsets; cursor: the item count so far).
+hipError_t launch_stem_count(const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,
+                             const uint32_t* live, uint32_t cap, uint32_t nc, uint32_t k,
+                             uint32_t p_log2, uint32_t* pcount, hipStream_t s);
+hipError_t launch_stem_scatter(const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,
+                               const uint32_t* live, uint32_t cap, uint32_t nc, uint32_t k,
+                               uint32_t p_log2, uint64_t* cursor, uint64_t* rstem, uint32_t* rcnt,
+                               hipStream_t s);
+// Most records a partition may hold (its distinct stems fit the LDS table).
+uint32_t stem_part_max();
+hipError_t launch_stem_group(const uint64_t* poff, uint64_t nparts, const uint64_t* rstem,
+                             const uint32_t* rcnt, bool count_only, uint64_t* cursor,
+                             uint64_t capacity, uint64_t* stems, uint16_t* items, uint32_t* err,
+                             hipStream_t s);
 // fkeys[i] = tkeys[i] with bit 63 set when slot i's counts pass (tumour >=
 // tmin, normal <= nmax), for the nslots slots of the resident tables.
 hipError_t launch_filter_keys(const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,

@@ -1710,76 +1710,145 @@ __device__ __forceinline__ uint64_t stem_of(uint64_t x, uint32_t k, uint32_t* sl
   return s;
 }
 
-constexpr uint64_t kStemSalt = 0x2545F4914F6CDD1Dull;  // stem-table hash salt
+constexpr uint64_t kStemSalt = 0x2545F4914F6CDD1Dull;  // stem partition hash salt
 
-// One pass over table slots [0, nslots) (live[i / cap] gates the slots of
-// resident tables; nullptr for the overflow table and staged spilled
-// tables).  CLAIM: each k-mer's canonical stem takes a slot of the stem table
-// (open addressing, linear probing, CAS).  Otherwise: each k-mer finds its
-// stem's slot h and stores its counts, saturated to 16 bits, at 4a+b
-// (counter 0) and 16+4a+b (counter 1) of item off[h].  A stem not found
-// within the table sets err.
-template <bool CLAIM>
-__global__ void __launch_bounds__(256) k_stems(const uint64_t* __restrict__ tkeys,
-                                               const uint32_t* __restrict__ tcounts,
-                                               uint64_t nslots, const uint32_t* __restrict__ live,
-                                               uint32_t cap, uint32_t nc, uint32_t k,
-                                               uint64_t* __restrict__ skeys, uint32_t s_log2,
-                                               const uint64_t* __restrict__ off,
-                                               uint16_t* __restrict__ items,
-                                               uint32_t* __restrict__ err) {
-  const uint64_t mask = (1ull << s_log2) - 1;
+// Slot i of a table pass (live[i / cap] gates the slots of resident tables;
+// nullptr for the overflow table and staged spilled tables): false when it
+// holds no k-mer with a count, else its canonical stem, the k-mer's place
+// 4a + b in the stem's item (stem_of) and its two counts saturated to 16 bits
+// (counter 0 low, counter 1 high).
+__device__ __forceinline__ bool stem_entry(const uint64_t* __restrict__ tkeys,
+                                           const uint32_t* __restrict__ tcounts,
+                                           const uint32_t* __restrict__ live, uint64_t i,
+                                           uint32_t cap, uint32_t nc, uint32_t k, uint64_t* stem,
+                                           uint32_t* slot, uint32_t* c16) {
+  if (live && !live[i / cap]) return false;
+  const uint64_t key = tkeys[i];
+  const uint32_t c0 = tcounts[i * nc], c1 = nc > 1 ? tcounts[i * nc + 1] : 0u;
+  if (key == kEmpty || (c0 | c1) == 0) return false;
+  *stem = stem_of(key, k, slot);
+  *c16 = min(c0, 65535u) | (min(c1, 65535u) << 16);
+  return true;
+}
+
+// Partition of a stem: the top p_log2 bits of its hash (0 when p_log2 = 0).
+__device__ __forceinline__ uint64_t stem_part(uint64_t stem, uint32_t p_log2) {
+  return p_log2 ? mix64(stem ^ kStemSalt) >> (64 - p_log2) : 0;
+}
+
+// First pass: entries per stem partition.
+__global__ void __launch_bounds__(256) k_stem_count(const uint64_t* __restrict__ tkeys,
+                                                    const uint32_t* __restrict__ tcounts,
+                                                    uint64_t nslots,
+                                                    const uint32_t* __restrict__ live,
+                                                    uint32_t cap, uint32_t nc, uint32_t k,
+                                                    uint32_t p_log2,
+                                                    uint32_t* __restrict__ pcount) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots;
        i += (uint64_t)gridDim.x * blockDim.x) {
-    if (live && !live[i / cap]) continue;
-    const uint64_t key = tkeys[i];
-    const uint32_t c0 = tcounts[i * nc], c1 = nc > 1 ? tcounts[i * nc + 1] : 0u;
-    if (key == kEmpty || (c0 | c1) == 0) continue;
-    uint32_t slot;
-    const uint64_t stem = stem_of(key, k, &slot);
-    uint64_t h = mix64(stem ^ kStemSalt) & mask;
-    bool found = false;
-    for (uint64_t probe = 0; probe <= mask; ++probe) {
-      uint64_t cur = __hip_atomic_load(&skeys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (CLAIM && cur == kEmpty) {
-        cur = atomicCAS(reinterpret_cast<unsigned long long*>(&skeys[h]),
-                        (unsigned long long)kEmpty, (unsigned long long)stem);
-        if (cur == kEmpty) cur = stem;
-      }
-      if (cur == stem) {
-        found = true;
-        break;
-      }
-      if (!CLAIM && cur == kEmpty) break;
-      h = (h + 1) & mask;
-    }
-    if (!found) {
-      atomicOr(err, 1u);
-      continue;
-    }
-    if (!CLAIM) {
-      uint16_t* row = items + off[h] * 32;
-      row[slot] = (uint16_t)min(c0, 65535u);
-      row[16 + slot] = (uint16_t)min(c1, 65535u);
-    }
+    uint64_t stem;
+    uint32_t slot, c16;
+    if (stem_entry(tkeys, tcounts, live, i, cap, nc, k, &stem, &slot, &c16))
+      atomicAdd(&pcount[stem_part(stem, p_log2)], 1u);
   }
 }
 
-// flags[i] = slot i of the stem table holds a stem
-__global__ void k_stem_flags(const uint64_t* __restrict__ skeys, uint64_t n,
-                             uint32_t* __restrict__ flags) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x)
-    flags[i] = skeys[i] != kEmpty;
+// Second pass: each entry appended to its partition's range as a record, the
+// stem with the item place in bits 58-61 (stems have at most 58 bits) and
+// the saturated counts beside it.
+__global__ void __launch_bounds__(256) k_stem_scatter(const uint64_t* __restrict__ tkeys,
+                                                      const uint32_t* __restrict__ tcounts,
+                                                      uint64_t nslots,
+                                                      const uint32_t* __restrict__ live,
+                                                      uint32_t cap, uint32_t nc, uint32_t k,
+                                                      uint32_t p_log2,
+                                                      unsigned long long* __restrict__ cursor,
+                                                      uint64_t* __restrict__ rstem,
+                                                      uint32_t* __restrict__ rcnt) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t stem;
+    uint32_t slot, c16;
+    if (!stem_entry(tkeys, tcounts, live, i, cap, nc, k, &stem, &slot, &c16)) continue;
+    const uint64_t at = atomicAdd(&cursor[stem_part(stem, p_log2)], 1ull);
+    rstem[at] = stem | ((uint64_t)slot << 58);
+    rcnt[at] = c16;
+  }
 }
 
-// stems[off[i]] = the stem in slot i
-__global__ void k_stem_emit(const uint64_t* __restrict__ skeys, const uint64_t* __restrict__ off,
-                            uint64_t n, uint64_t* __restrict__ stems) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t v = skeys[i];
-    if (v != kEmpty) stems[off[i]] = v;
+constexpr uint32_t kStemTable = 4096;                      // LDS stem slots per partition
+constexpr uint32_t kStemPartMax = kStemTable * 3 / 4;      // most entries a partition may hold
+constexpr uint64_t kStemMask = (1ull << 58) - 1;
+
+// Third pass, one workgroup per partition: the partition's stems are made
+// distinct in an LDS table (linear probing, CAS) and numbered in slot order;
+// the workgroup takes the next free range of items with one atomic add, writes
+// each stem and zeroes its row, then each record stores its counts at its
+// place in its stem's row (the rows of one partition span at most 256 KB, so
+// these scattered stores stay in L2).  With count_only only the number of
+// distinct stems is added to the cursor.
+__global__ void __launch_bounds__(kThreads) k_stem_group(const uint64_t* __restrict__ poff,
+                                                         const uint64_t* __restrict__ rstem,
+                                                         const uint32_t* __restrict__ rcnt,
+                                                         int count_only,
+                                                         unsigned long long* __restrict__ cursor,
+                                                         uint64_t capacity,
+                                                         uint64_t* __restrict__ stems,
+                                                         uint16_t* __restrict__ items,
+                                                         uint32_t* __restrict__ err) {
+  __shared__ uint64_t tab[kStemTable];
+  __shared__ uint32_t idx[kStemTable + 1], scratch[kWaves + 1];
+  __shared__ unsigned long long base_s;
+  const uint64_t r0 = poff[blockIdx.x], r1 = poff[blockIdx.x + 1];
+  if (r1 - r0 > kStemPartMax) {  // the host sizes partitions below this
+    if (threadIdx.x == 0) atomicOr(err, 2u);
+    return;
+  }
+  for (uint32_t i = threadIdx.x; i < kStemTable; i += kThreads) tab[i] = kEmpty;
+  __syncthreads();
+  auto find = [&](uint64_t stem, bool insert) -> int {
+    uint32_t h = (uint32_t)(mix64(stem ^ kStemSalt) & (kStemTable - 1));
+    for (uint32_t probe = 0; probe < kStemTable; ++probe) {
+      uint64_t cur = tab[h];
+      if (insert && cur == kEmpty) {
+        cur = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[h]),
+                        (unsigned long long)kEmpty, (unsigned long long)stem);
+        if (cur == kEmpty) cur = stem;
+      }
+      if (cur == stem) return (int)h;
+      if (!insert && cur == kEmpty) return -1;
+      h = (h + 1) & (kStemTable - 1);
+    }
+    return -1;
+  };
+  for (uint64_t r = r0 + threadIdx.x; r < r1; r += kThreads)
+    if (find(rstem[r] & kStemMask, true) < 0) atomicOr(err, 1u);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < kStemTable; i += kThreads) idx[i] = tab[i] != kEmpty;
+  __syncthreads();
+  block_exclusive_scan(idx, idx, kStemTable, scratch);  // in place: every read precedes its first barrier
+  const uint32_t n = idx[kStemTable];
+  if (threadIdx.x == 0) base_s = atomicAdd(cursor, (unsigned long long)n);
+  __syncthreads();
+  const uint64_t base = base_s;
+  if (count_only || n == 0) return;
+  if (base + n > capacity) {
+    if (threadIdx.x == 0) atomicOr(err, 4u);
+    return;
+  }
+  for (uint32_t i = threadIdx.x; i < kStemTable; i += kThreads)
+    if (tab[i] != kEmpty) stems[base + idx[i]] = tab[i];
+  uint32_t* rows = reinterpret_cast<uint32_t*>(items + base * 32);
+  for (uint64_t i = threadIdx.x; i < (uint64_t)n * 16; i += kThreads) rows[i] = 0;
+  __syncthreads();
+  for (uint64_t r = r0 + threadIdx.x; r < r1; r += kThreads) {
+    const uint64_t v = rstem[r];
+    const int h = find(v & kStemMask, false);
+    if (h < 0) continue;  // reported by the insert loop
+    const uint32_t slot = (uint32_t)(v >> 58) & 15u, c = rcnt[r];
+    uint16_t* row = items + (base + idx[h]) * 32;
+    row[slot] = (uint16_t)(c & 0xFFFFu);
+    row[16 + slot] = (uint16_t)(c >> 16);
   }
 }
 
@@ -1985,28 +2054,37 @@ static uint32_t stride_grid(uint64_t n) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(n, 256), 8192));
 }
 
-hipError_t launch_stems(bool claim, const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,
-                        const uint32_t* live, uint32_t cap, uint32_t nc, uint32_t k,
-                        uint64_t* skeys, uint32_t s_log2, const uint64_t* off, uint16_t* items,
-                        uint32_t* err, hipStream_t s) {
+hipError_t launch_stem_count(const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,
+                             const uint32_t* live, uint32_t cap, uint32_t nc, uint32_t k,
+                             uint32_t p_log2, uint32_t* pcount, hipStream_t s) {
   if (!nslots) return hipSuccess;
-  if (claim)
-    hipLaunchKernelGGL(k_stems<true>, dim3(stride_grid(nslots)), dim3(256), 0, s, tkeys, tcounts,
-                       nslots, live, cap, nc, k, skeys, s_log2, off, items, err);
-  else
-    hipLaunchKernelGGL(k_stems<false>, dim3(stride_grid(nslots)), dim3(256), 0, s, tkeys, tcounts,
-                       nslots, live, cap, nc, k, skeys, s_log2, off, items, err);
+  hipLaunchKernelGGL(k_stem_count, dim3(stride_grid(nslots)), dim3(256), 0, s, tkeys, tcounts,
+                     nslots, live, cap, nc, k, p_log2, pcount);
   return hipGetLastError();
 }
 
-hipError_t launch_stem_flags(const uint64_t* skeys, uint64_t n, uint32_t* flags, hipStream_t s) {
-  hipLaunchKernelGGL(k_stem_flags, dim3(stride_grid(n)), dim3(256), 0, s, skeys, n, flags);
+hipError_t launch_stem_scatter(const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,
+                               const uint32_t* live, uint32_t cap, uint32_t nc, uint32_t k,
+                               uint32_t p_log2, uint64_t* cursor, uint64_t* rstem, uint32_t* rcnt,
+                               hipStream_t s) {
+  if (!nslots) return hipSuccess;
+  hipLaunchKernelGGL(k_stem_scatter, dim3(stride_grid(nslots)), dim3(256), 0, s, tkeys, tcounts,
+                     nslots, live, cap, nc, k, p_log2,
+                     reinterpret_cast<unsigned long long*>(cursor), rstem, rcnt);
   return hipGetLastError();
 }
 
-hipError_t launch_stem_emit(const uint64_t* skeys, const uint64_t* off, uint64_t n,
-                            uint64_t* stems, hipStream_t s) {
-  hipLaunchKernelGGL(k_stem_emit, dim3(stride_grid(n)), dim3(256), 0, s, skeys, off, n, stems);
+uint32_t stem_part_max() { return kStemPartMax; }
+
+hipError_t launch_stem_group(const uint64_t* poff, uint64_t nparts, const uint64_t* rstem,
+                             const uint32_t* rcnt, bool count_only, uint64_t* cursor,
+                             uint64_t capacity, uint64_t* stems, uint16_t* items, uint32_t* err,
+                             hipStream_t s) {
+  if (!nparts) return hipSuccess;
+  if (nparts > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_stem_group, dim3((uint32_t)nparts), dim3(kThreads), 0, s, poff, rstem, rcnt,
+                     count_only ? 1 : 0, reinterpret_cast<unsigned long long*>(cursor), capacity,
+                     stems, items, err);
   return hipGetLastError();
 }
 

@@ -165,6 +165,8 @@ namespace {
 using kc::t_async;
 using kc::t_stream;
 
+constexpr size_t kPinnedBytes = 4096;  // a context's pinned staging area for small readbacks
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -320,7 +322,7 @@ struct kc_ctx {
   hipEvent_t insert_done = nullptr;
   bool insert_done_valid = false;
 
-  uint64_t* pinned = nullptr;  // small pinned staging area (4 KiB)
+  uint64_t* pinned = nullptr;  // small pinned staging area (kPinnedBytes)
 
   // spill directory + pool (pinned host).  The pool holds whole partition
   // tables in their HBM layout (cap slots each), so host lookups probe them
@@ -560,6 +562,11 @@ kc_status ensure_spill_pool(kc_ctx* c, uint64_t tables) {
 }
 
 kc_status sync_read(kc_ctx* c, hipStream_t s, const void* dev, size_t bytes, void* host) {
+  if (bytes > kPinnedBytes) {  // larger than the pinned staging area: straight to the host buffer
+    KC_HIP(c, hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s), "readback");
+    KC_HIP(c, hipStreamSynchronize(s), "stream synchronise");
+    return KC_OK;
+  }
   KC_HIP(c, hipMemcpyAsync(c->pinned, dev, bytes, hipMemcpyDeviceToHost, s), "readback");
   KC_HIP(c, hipStreamSynchronize(s), "stream synchronise");
   memcpy(host, c->pinned, bytes);
@@ -970,7 +977,8 @@ kc_status kc_create(const kc_config* cfg, int device, kc_ctx** out) {
   if (c->dstat.ensure(kNst * 8 * 3) != hipSuccess || c->derr.ensure(8) != hipSuccess ||
       c->ovf_used.ensure(8) != hipSuccess || c->qcount.ensure(8) != hipSuccess)
     return bail(KC_ERR_OUT_OF_MEMORY, "device allocation failed");
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->pinned), 4096, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->pinned), kPinnedBytes, hipHostMallocDefault) !=
+      hipSuccess) {
     (void)hipGetLastError();
     c->pinned = nullptr;
     return bail(KC_ERR_OUT_OF_MEMORY, "pinned allocation failed");
@@ -1813,35 +1821,28 @@ kc_status kc_export_stems(kc_ctx* c, uint64_t* stems, uint16_t* items, uint64_t 
   AllocStream alloc_on(s);
   StageTimer tm(c, s, KC_T_STEMS);
   const uint32_t nc = c->cfg.n_counters, k = c->cfg.k;
-  const uint64_t E = c->st.entries;
-  const uint32_t s_log2 = std::max<uint32_t>(10, ceil_log2(2 * E + 1));  // load <= 1/2
-  const uint64_t S = 1ull << s_log2;
-  DevBuf skeys, flags, off, parts, err, stage_k, stage_c;
-  ReleaseOnExit free_bufs{&skeys, &flags, &off, &parts, &err, &stage_k, &stage_c};
-  KC_HIP(c, skeys.ensure(S * 8), "stem table");
-  KC_HIP(c, flags.ensure(S * 4), "stem flags");
-  KC_HIP(c, off.ensure((S + 1) * 8), "stem offsets");
-  KC_HIP(c, parts.ensure(scan_parts(S) * 8), "scan buffer");
+  const uint64_t E = c->st.entries, cap = c->cap;
+  DevBuf pcount, poff, parts, cursor, rstem, rcnt, err, icur, stage_k, stage_c;
+  ReleaseOnExit free_bufs{&pcount, &poff, &parts, &cursor, &rstem, &rcnt, &err, &icur,
+                          &stage_k, &stage_c};
   KC_HIP(c, err.ensure(4), "error flag");
-  KC_HIP(c, launch_fill64(skeys.as<uint64_t>(), S, kEmpty, s), "fill");
+  KC_HIP(c, icur.ensure(8), "item cursor");
   KC_HIP(c, launch_fill32(err.as<uint32_t>(), 1, 0, s), "fill");
   // spilled tables come back to HBM in batches of up to kStage tables
-  const uint64_t cap = c->cap;
   const uint64_t kStage = std::max<uint64_t>(1, std::min<uint64_t>(c->spill_used, 2048));
   if (c->spill_used) {
     KC_HIP(c, stage_k.ensure(kStage * cap * 8), "staging buffer");
     KC_HIP(c, stage_c.ensure(kStage * cap * 4 * nc), "staging buffer");
   }
-  auto pass = [&](bool claim) -> kc_status {
-    KC_HIP(c, launch_stems(claim, c->tkeys.as<uint64_t>(), c->tcounts.as<uint32_t>(),
-                           (uint64_t)c->pool_slots * cap, c->slot_live.as<uint32_t>(), c->cap, nc,
-                           k, skeys.as<uint64_t>(), s_log2, off.as<uint64_t>(), items,
-                           err.as<uint32_t>(), s),
-           "stem pass");
-    KC_HIP(c, launch_stems(claim, c->okeys.as<uint64_t>(), c->ocounts.as<uint32_t>(),
-                           1ull << c->ovf_log2, nullptr, 0, nc, k, skeys.as<uint64_t>(), s_log2,
-                           off.as<uint64_t>(), items, err.as<uint32_t>(), s),
-           "stem pass");
+  // fn(keys, counts, slots, live) over every table: resident, overflow, spilled
+  auto sources = [&](auto&& fn) -> kc_status {
+    hipError_t e;
+    if ((e = fn(c->tkeys.as<uint64_t>(), c->tcounts.as<uint32_t>(), (uint64_t)c->pool_slots * cap,
+                c->slot_live.as<uint32_t>())) != hipSuccess)
+      return hip_fail(c, e, "stem pass");
+    if ((e = fn(c->okeys.as<uint64_t>(), c->ocounts.as<uint32_t>(), 1ull << c->ovf_log2,
+                nullptr)) != hipSuccess)
+      return hip_fail(c, e, "stem pass");
     for (uint64_t t0 = 0; t0 < c->spill_used; t0 += kStage) {
       const uint64_t nt = std::min<uint64_t>(kStage, c->spill_used - t0);
       KC_HIP(c, hipMemcpyAsync(stage_k.p, c->spill_keys + t0 * cap, nt * cap * 8,
@@ -1850,33 +1851,79 @@ kc_status kc_export_stems(kc_ctx* c, uint64_t* stems, uint16_t* items, uint64_t 
       KC_HIP(c, hipMemcpyAsync(stage_c.p, c->spill_counts + t0 * cap * nc, nt * cap * 4 * nc,
                                hipMemcpyHostToDevice, s),
              "stage copy");
-      KC_HIP(c, launch_stems(claim, stage_k.as<uint64_t>(), stage_c.as<uint32_t>(), nt * cap,
-                             nullptr, 0, nc, k, skeys.as<uint64_t>(), s_log2, off.as<uint64_t>(),
-                             items, err.as<uint32_t>(), s),
-             "stem pass");
+      if ((e = fn(stage_k.as<uint64_t>(), stage_c.as<uint32_t>(), nt * cap, nullptr)) != hipSuccess)
+        return hip_fail(c, e, "stem pass");
     }
     return KC_OK;
   };
-  kc_status r = pass(true);
-  if (r != KC_OK) return r;
-  KC_HIP(c, launch_stem_flags(skeys.as<uint64_t>(), S, flags.as<uint32_t>(), s), "stem flags");
-  KC_HIP(c, launch_scan(flags.as<uint32_t>(), S, off.as<uint64_t>(), parts.as<uint64_t>(), s),
-         "stem scan");
-  uint64_t n = 0;
-  if ((r = sync_read(c, s, off.as<uint64_t>() + S, 8, &n)) != KC_OK) return r;
-  *n_out = n;
-  if (n > E) return fail(c, KC_ERR_DEVICE, "more stems than table entries");
-  if (n > capacity) return fail(c, KC_ERR_INVALID_ARG, "capacity smaller than the stem count");
-  if (n && (!stems || !items)) return fail(c, KC_ERR_INVALID_ARG, "stems_dev or counts_dev is NULL");
-  if (n) {
-    KC_HIP(c, launch_stem_emit(skeys.as<uint64_t>(), off.as<uint64_t>(), S, stems, s), "stem emit");
-    KC_HIP(c, launch_fill32(reinterpret_cast<uint32_t*>(items), n * 16, 0, s), "fill");
-    if ((r = pass(false)) != KC_OK) return r;
+  // stem partitions of at most stem_part_max() entries: about 1536 on average,
+  // doubled until the largest one fits
+  uint32_t p_log2 = 0;
+  while (p_log2 < 24 && (E >> p_log2) > 1536) ++p_log2;
+  kc_status r;
+  uint64_t P;
+  std::vector<uint32_t> hc;
+  for (;;) {
+    P = 1ull << p_log2;
+    KC_HIP(c, pcount.ensure(P * 4), "stem partition counts");
+    KC_HIP(c, launch_fill32(pcount.as<uint32_t>(), P, 0, s), "fill");
+    r = sources([&](const uint64_t* tk, const uint32_t* tcn, uint64_t n, const uint32_t* live) {
+      return launch_stem_count(tk, tcn, n, live, (uint32_t)cap, nc, k, p_log2,
+                               pcount.as<uint32_t>(), s);
+    });
+    if (r != KC_OK) return r;
+    hc.resize(P);
+    if ((r = sync_read(c, s, pcount.p, P * 4, hc.data())) != KC_OK) return r;
+    const uint32_t most = *std::max_element(hc.begin(), hc.end());
+    if (most <= stem_part_max()) break;
+    if (p_log2 >= 24) return fail(c, KC_ERR_DEVICE, "stem partitions stay too large");
+    ++p_log2;
   }
+  KC_HIP(c, poff.ensure((P + 1) * 8), "stem partition offsets");
+  KC_HIP(c, parts.ensure(scan_parts(P) * 8), "scan buffer");
+  KC_HIP(c, launch_scan(pcount.as<uint32_t>(), P, poff.as<uint64_t>(), parts.as<uint64_t>(), s),
+         "stem scan");
+  uint64_t R = 0;
+  if ((r = sync_read(c, s, poff.as<uint64_t>() + P, 8, &R)) != KC_OK) return r;
+  KC_HIP(c, cursor.ensure(P * 8), "stem cursors");
+  KC_HIP(c, hipMemcpyAsync(cursor.p, poff.p, P * 8, hipMemcpyDeviceToDevice, s), "cursor copy");
+  KC_HIP(c, rstem.ensure(std::max<uint64_t>(1, R) * 8), "stem records");
+  KC_HIP(c, rcnt.ensure(std::max<uint64_t>(1, R) * 4), "stem records");
+  r = sources([&](const uint64_t* tk, const uint32_t* tcn, uint64_t n, const uint32_t* live) {
+    return launch_stem_scatter(tk, tcn, n, live, (uint32_t)cap, nc, k, p_log2,
+                               cursor.as<uint64_t>(), rstem.as<uint64_t>(), rcnt.as<uint32_t>(), s);
+  });
+  if (r != KC_OK) return r;
+  // the item count first when the caller's capacity might not hold it
+  uint64_t n = 0;
+  if (capacity < E || !stems || !items) {
+    KC_HIP(c, launch_fill64(icur.as<uint64_t>(), 1, 0, s), "fill");
+    KC_HIP(c, launch_stem_group(poff.as<uint64_t>(), P, rstem.as<uint64_t>(), rcnt.as<uint32_t>(),
+                                true, icur.as<uint64_t>(), 0, nullptr, nullptr,
+                                err.as<uint32_t>(), s),
+           "stem count");
+    if ((r = sync_read(c, s, icur.p, 8, &n)) != KC_OK) return r;
+    *n_out = n;
+    if (n > E) return fail(c, KC_ERR_DEVICE, "more stems than table entries");
+    if (n > capacity) return fail(c, KC_ERR_INVALID_ARG, "capacity smaller than the stem count");
+    if (n && (!stems || !items)) return fail(c, KC_ERR_INVALID_ARG, "stems_dev or counts_dev is NULL");
+    if (n == 0) {
+      tm.stop();
+      return KC_OK;
+    }
+  }
+  KC_HIP(c, launch_fill64(icur.as<uint64_t>(), 1, 0, s), "fill");
+  KC_HIP(c, launch_stem_group(poff.as<uint64_t>(), P, rstem.as<uint64_t>(), rcnt.as<uint32_t>(),
+                              false, icur.as<uint64_t>(), capacity, stems, items,
+                              err.as<uint32_t>(), s),
+         "stem items");
+  if ((r = sync_read(c, s, icur.p, 8, &n)) != KC_OK) return r;
+  *n_out = n;
   uint32_t e = 0;
   if ((r = sync_read(c, s, err.p, 4, &e)) != KC_OK) return r;
   tm.stop();
-  if (e) return fail(c, KC_ERR_DEVICE, "stem table overflow");
+  if (e) return fail(c, KC_ERR_DEVICE, "stem partition table overflow");
+  if (n > E) return fail(c, KC_ERR_DEVICE, "more stems than table entries");
   return KC_OK;
 }
 
