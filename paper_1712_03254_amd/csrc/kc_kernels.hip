@@ -265,29 +265,49 @@ __device__ __forceinline__ uint32_t chunk_of(const ChunkDesc* cd, uint32_t n, ui
 }
 
 // k_pack over the chunks of a batch group: word w of the group stream is word
-// w - word0 of its chunk (positions past the chunk's end are invalid).
+// w - word0 of its chunk (positions past the chunk's end are invalid).  As in
+// k_pack, two threads per word, 16 bases each (one 16-byte load when aligned
+// and inside the chunk), joined by a lane exchange; the grid stride is even,
+// so the two threads of a word stay in step.
 __global__ void __launch_bounds__(256) k_pack_batch(const ChunkDesc* __restrict__ cd,
                                                     uint32_t nchunks, uint64_t nwords,
                                                     uint64_t* __restrict__ packed,
                                                     uint64_t* __restrict__ flags) {
-  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords;
-       w += (uint64_t)gridDim.x * blockDim.x) {
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < 2 * nwords;
+       t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t w = t >> 1;
     const uint32_t j = chunk_of(cd, nchunks, w, [](const ChunkDesc& d) { return d.word0; });
     const uint8_t* bases = cd[j].bases;
     const uint64_t total = cd[j].total;
-    const uint64_t p0 = (w - cd[j].word0) * 32;
-    uint64_t code = 0;
-    uint32_t inv = 0;
-#pragma unroll 8
-    for (int i = 0; i < 32; ++i) {
-      const uint32_t c = p0 + i < total ? bases[p0 + i] : (uint32_t)'N';
-      const bool ok = (c == 'A') | (c == 'C') | (c == 'G') | (c == 'T');
-      const uint32_t cdv = ((c >> 1) ^ (c >> 2)) & 3u;  // A->0 C->1 G->2 T->3
-      code = (code << 2) | (ok ? cdv : 0u);
-      inv |= (ok ? 0u : 1u) << i;
+    const uint64_t p0 = (w - cd[j].word0) * 32 + (t & 1) * 16;
+    uint32_t v[4];
+    if (p0 + 16 <= total && ((uintptr_t)(bases + p0) & 15) == 0) {
+      const uint4 q = *reinterpret_cast<const uint4*>(bases + p0);
+      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        uint32_t x = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint64_t p = p0 + 4 * g + i;
+          x |= (uint32_t)(p < total ? bases[p] : (uint8_t)'N') << (8 * i);
+        }
+        v[g] = x;
+      }
     }
-    packed[w] = code;
-    flags[w] = inv;
+    uint32_t code = 0, inv = 0;  // 16 bases: code (first base on top), invalid bits
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const uint32_t r = pack4(v[g]);
+      code |= (r & 0xFFu) << (24 - 8 * g);
+      inv |= (r >> 8) << (4 * g);
+    }
+    const uint32_t ocode = __shfl_xor(code, 1, 64), oinv = __shfl_xor(inv, 1, 64);
+    if ((t & 1) == 0)
+      packed[w] = ((uint64_t)code << 32) | ocode;
+    else
+      flags[w] = oinv | (inv << 16);  // read-start bits (high half) are set by k_rstart_batch
   }
 }
 
@@ -2112,8 +2132,8 @@ hipError_t launch_filter(const QueryArgs& a, const uint64_t* packed, const uint6
 hipError_t launch_pack_batch(const ChunkDesc* cd, uint32_t nchunks, uint64_t nwords,
                              uint64_t* packed, uint64_t* flags, hipStream_t s) {
   if (!nwords || !nchunks) return hipSuccess;
-  hipLaunchKernelGGL(k_pack_batch, dim3(stride_grid(nwords)), dim3(256), 0, s, cd, nchunks, nwords,
-                     packed, flags);
+  hipLaunchKernelGGL(k_pack_batch, dim3(stride_grid(2 * nwords)), dim3(256), 0, s, cd, nchunks,
+                     nwords, packed, flags);
   return hipGetLastError();
 }
 
