@@ -2074,11 +2074,18 @@ static uint32_t stride_grid(uint64_t n) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(n, 256), 8192));
 }
 
+// A thread per item (up to 2^30 threads; kernels still stride past that):
+// for kernels whose items each wait on a global atomic, which a hundred items
+// per thread would serialise (the stem passes: 14.2 -> 12.4 ms at 2.5e8 slots).
+static uint32_t wide_grid(uint64_t n) {
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(div_up(n, 256), 1u << 22));
+}
+
 hipError_t launch_stem_count(const uint64_t* tkeys, const uint32_t* tcounts, uint64_t nslots,
                              const uint32_t* live, uint32_t cap, uint32_t nc, uint32_t k,
                              uint32_t p_log2, uint32_t* pcount, hipStream_t s) {
   if (!nslots) return hipSuccess;
-  hipLaunchKernelGGL(k_stem_count, dim3(stride_grid(nslots)), dim3(256), 0, s, tkeys, tcounts,
+  hipLaunchKernelGGL(k_stem_count, dim3(wide_grid(nslots)), dim3(256), 0, s, tkeys, tcounts,
                      nslots, live, cap, nc, k, p_log2, pcount);
   return hipGetLastError();
 }
@@ -2088,7 +2095,7 @@ hipError_t launch_stem_scatter(const uint64_t* tkeys, const uint32_t* tcounts, u
                                uint32_t p_log2, uint64_t* cursor, uint64_t* rstem, uint32_t* rcnt,
                                hipStream_t s) {
   if (!nslots) return hipSuccess;
-  hipLaunchKernelGGL(k_stem_scatter, dim3(stride_grid(nslots)), dim3(256), 0, s, tkeys, tcounts,
+  hipLaunchKernelGGL(k_stem_scatter, dim3(wide_grid(nslots)), dim3(256), 0, s, tkeys, tcounts,
                      nslots, live, cap, nc, k, p_log2,
                      reinterpret_cast<unsigned long long*>(cursor), rstem, rcnt);
   return hipGetLastError();
