@@ -219,26 +219,31 @@ def test_batched_200mbp_whole_output_digest():
     assert words_digest(b2) == want["b2"]
 
 
-def test_spill_3gbp_whole_output_digest():
+@pytest.mark.parametrize("budget_gib", [0, 24])
+def test_spill_3gbp_whole_output_digest(budget_gib):
     """The 3 Gbp workload at full size (2·10^8 reads of 100 bp, 1.4·10^10
-    k-mers, 2^36-bit levels, 2^20 partitions, every table resident), inserted
-    as 8 consecutive slices of the read stream as bench.py does: every
-    statistic, the sorted table (whole and per value range) and both levels
-    against the digest of the oracle's streamed value-range passes.  The
-    2.6·10^9-entry table is sorted on the device one value range at a time."""
+    k-mers, 2^36-bit levels, 2^20 partitions), inserted as 8 consecutive
+    slices of the read stream as bench.py does, with its 64 GB table budget
+    (every table resident) and with a 24 GiB budget (about half the tables
+    counted in waves and spilled to pinned host memory, exported from there):
+    every statistic, the sorted table (whole and per value range) and both
+    levels against the digest of the oracle's streamed value-range passes.
+    The 2.6·10^9-entry table is sorted on the device one value range at a
+    time."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import synth
     from digest import TableDigest
-    note("case: spill_3gbp full size (8 inserts of 2.5e7 reads x 100 bp), whole-output digest")
+    note("case: spill_3gbp full size (8 inserts of 2.5e7 reads x 100 bp), table budget %s, "
+         "whole-output digest" % ("%d GiB" % budget_gib if budget_gib else "of the workload"))
     want = read_digest_file(os.path.join(GOLDEN, "digest_spill_3gbp.txt"))
     w = synth.WORKLOADS["spill_3gbp"]
     genome = w.make_genome(threads=16)
     per = w.n_reads
     while per * w.lmax >= 1 << 32:
         per = (per + 1) // 2
-    cfg = workload_config(w)
+    cfg = workload_config(w, **({"hbm_table_budget_bytes": budget_gib << 30} if budget_gib else {}))
     with kc.KmerCounter(cfg) as c:
         for f in range(0, w.n_reads, per):
             b, o = w.make_reads(genome, first=f, n=min(per, w.n_reads - f), threads=16)
@@ -252,6 +257,10 @@ def test_spill_3gbp_whole_output_digest():
         st = c.finalize()
         for key in STAT_KEYS:
             assert st[key] == want["stats"][key], (key, st[key], want["stats"][key])
+        if budget_gib:
+            assert st["spilled_partitions"] > 0
+            note("spilled %d partitions, %.1f GB" % (st["spilled_partitions"],
+                                                     st["spilled_bytes"] / 1e9))
         b1, b2 = c.export_bloom()
         assert words_digest(b1) == want["b1"]
         assert words_digest(b2) == want["b2"]
