@@ -267,47 +267,63 @@ __device__ __forceinline__ uint32_t chunk_of(const ChunkDesc* cd, uint32_t n, ui
 // k_pack over the chunks of a batch group: word w of the group stream is word
 // w - word0 of its chunk (positions past the chunk's end are invalid).  As in
 // k_pack, two threads per word, 16 bases each (one 16-byte load when aligned
-// and inside the chunk), joined by a lane exchange; the grid stride is even,
-// so the two threads of a word stay in step.
+// and inside the chunk), joined by a lane exchange.  A workgroup's 128 words
+// lie in one chunk or a few neighbouring ones: one search finds the first
+// word's chunk and each thread walks forward from it (a search per thread
+// cost 2.3% of the batched graph); the loads go through the global address
+// space (chunk pointers are device memory).
 __global__ void __launch_bounds__(256) k_pack_batch(const ChunkDesc* __restrict__ cd,
                                                     uint32_t nchunks, uint64_t nwords,
                                                     uint64_t* __restrict__ packed,
                                                     uint64_t* __restrict__ flags) {
-  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < 2 * nwords;
-       t += (uint64_t)gridDim.x * blockDim.x) {
+  __shared__ uint32_t j0s;
+  for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x; b0 < 2 * nwords;
+       b0 += (uint64_t)gridDim.x * blockDim.x) {
+    // the block's 128 words: one search for the first word's chunk, then a
+    // forward walk per thread
+    if (threadIdx.x == 0)
+      j0s = chunk_of(cd, nchunks, b0 >> 1, [](const ChunkDesc& d) { return d.word0; });
+    __syncthreads();
+    const uint64_t t = b0 + threadIdx.x;
     const uint64_t w = t >> 1;
-    const uint32_t j = chunk_of(cd, nchunks, w, [](const ChunkDesc& d) { return d.word0; });
-    const uint8_t* bases = cd[j].bases;
-    const uint64_t total = cd[j].total;
-    const uint64_t p0 = (w - cd[j].word0) * 32 + (t & 1) * 16;
-    uint32_t v[4];
-    if (p0 + 16 <= total && ((uintptr_t)(bases + p0) & 15) == 0) {
-      const uint4 q = *reinterpret_cast<const uint4*>(bases + p0);
-      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-    } else {
+    uint32_t j = j0s;
+    while (j + 1 < nchunks && cd[j + 1].word0 <= w) ++j;
+    if (t < 2 * nwords) {
+      typedef uint32_t g32x4 __attribute__((ext_vector_type(4)));
+      const __attribute__((address_space(1))) uint8_t* bases =
+          (const __attribute__((address_space(1))) uint8_t*)cd[j].bases;
+      const uint64_t total = cd[j].total;
+      const uint64_t p0 = (w - cd[j].word0) * 32 + (t & 1) * 16;
+      uint32_t v[4];
+      if (p0 + 16 <= total && ((uintptr_t)(cd[j].bases + p0) & 15) == 0) {
+        const g32x4 q = *reinterpret_cast<const __attribute__((address_space(1))) g32x4*>(bases + p0);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+      } else {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          uint32_t x = 0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const uint64_t p = p0 + 4 * g + i;
+            x |= (uint32_t)(p < total ? bases[p] : (uint8_t)'N') << (8 * i);
+          }
+          v[g] = x;
+        }
+      }
+      uint32_t code = 0, inv = 0;
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        uint32_t x = 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const uint64_t p = p0 + 4 * g + i;
-          x |= (uint32_t)(p < total ? bases[p] : (uint8_t)'N') << (8 * i);
-        }
-        v[g] = x;
+        const uint32_t r = pack4(v[g]);
+        code |= (r & 0xFFu) << (24 - 8 * g);
+        inv |= (r >> 8) << (4 * g);
       }
+      const uint32_t ocode = __shfl_xor(code, 1, 64), oinv = __shfl_xor(inv, 1, 64);
+      if ((t & 1) == 0)
+        packed[w] = ((uint64_t)code << 32) | ocode;
+      else
+        flags[w] = oinv | (inv << 16);
     }
-    uint32_t code = 0, inv = 0;  // 16 bases: code (first base on top), invalid bits
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const uint32_t r = pack4(v[g]);
-      code |= (r & 0xFFu) << (24 - 8 * g);
-      inv |= (r >> 8) << (4 * g);
-    }
-    const uint32_t ocode = __shfl_xor(code, 1, 64), oinv = __shfl_xor(inv, 1, 64);
-    if ((t & 1) == 0)
-      packed[w] = ((uint64_t)code << 32) | ocode;
-    else
-      flags[w] = oinv | (inv << 16);  // read-start bits (high half) are set by k_rstart_batch
+    __syncthreads();
   }
 }
 
