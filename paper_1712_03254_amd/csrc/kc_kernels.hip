@@ -333,11 +333,21 @@ __global__ void __launch_bounds__(256) k_rstart_batch(const ChunkDesc* __restric
                                                       uint32_t nchunks, uint64_t nslots,
                                                       uint64_t* __restrict__ flags,
                                                       uint32_t* __restrict__ err) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t j = chunk_of(cd, nchunks, i, [](const ChunkDesc& d) { return d.read0; });
-    read_start(cd[j].offsets, i - cd[j].read0, cd[j].n_reads, cd[j].total, cd[j].word0, flags,
-               err);
+  __shared__ uint32_t j0s;
+  for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x; b0 < nslots;
+       b0 += (uint64_t)gridDim.x * blockDim.x) {
+    // one search for the workgroup's first slot, then a forward walk (every
+    // chunk holds at least its end-check slot, so read0 increases)
+    if (threadIdx.x == 0)
+      j0s = chunk_of(cd, nchunks, b0, [](const ChunkDesc& d) { return d.read0; });
+    __syncthreads();
+    const uint64_t i = b0 + threadIdx.x;
+    uint32_t j = j0s;
+    while (j + 1 < nchunks && cd[j + 1].read0 <= i) ++j;
+    if (i < nslots)
+      read_start(cd[j].offsets, i - cd[j].read0, cd[j].n_reads, cd[j].total, cd[j].word0, flags,
+                 err);
+    __syncthreads();
   }
 }
 
