@@ -282,7 +282,11 @@ kc_status kc_restore(const char* path, int device, kc_ctx** out);
  * out_dev[r] (uint32, device) receives read r's number of selected windows.
  * Needs every partition table in HBM: after a spill it returns
  * KC_ERR_BAD_STATE (kc_query answers such tables from the host).  Scratch of
- * 2.5 bits per base, allocated and freed inside.  Synchronises. */
+ * 2.5 bits per base, and, when the bases number at least half the table
+ * slots, 8 bytes per table slot (the table keys marked with the selection,
+ * so that each lookup reads one line; without room for them the lookups read
+ * keys and counts, with the same results), allocated and freed inside.
+ * Synchronises. */
 kc_status kc_filter_reads(kc_ctx* ctx, const uint8_t* bases_dev, const uint64_t* offsets_dev,
                           uint64_t n_reads, uint64_t total_bases, uint32_t tumour_min,
                           uint32_t normal_max, uint32_t* out_dev, void* hip_stream);
