@@ -762,7 +762,12 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
                    max((uint32_t)kThreads * 3, 2 * nb2 + 2 + kWaves); // 1
   const uint64_t* offc = off1 + (uint64_t)c * ntiles1;
 
-  // gather: windows of kThreads first-level runs, binary search per key
+  // gather: windows of kThreads first-level runs, binary search per key.  A
+  // tile gathered in one window keeps its keys in registers: thread t holds
+  // positions t + q kThreads, the ones the sort below takes.
+  constexpr int kPer = kT2 / kThreads;
+  uint64_t v[kPer];
+  bool in_regs = false;
   uint64_t tw = desc >> 30;
   uint32_t got = 0;
   while (got < n) {
@@ -782,7 +787,6 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
     const uint32_t upto = min(n, *wend - p0);
     // each thread's kT2/kThreads positions: all run searches, then all loads,
     // then the LDS stores, so the loads are in flight together
-    constexpr int kPer = kT2 / kThreads;
     uint64_t src[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
@@ -794,14 +798,16 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
         if (wrel[r + step] <= P) r += step;
       src[q] = wsb[r] + P;
     }
-    uint64_t v[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q)
       v[q] = (got + threadIdx.x + q * kThreads < upto) ? keys1[src[q]] : 0;
+    in_regs = got == 0 && upto == n;  // block-uniform
+    if (!in_regs) {
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const uint32_t p = got + threadIdx.x + q * kThreads;
-      if (p < upto) stage[p] = v[q];
+      for (int q = 0; q < kPer; ++q) {
+        const uint32_t p = got + threadIdx.x + q * kThreads;
+        if (p < upto) stage[p] = v[q];
+      }
     }
     got = upto;
     tw += kThreads;
@@ -817,7 +823,7 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
   for (int r = 0; r < kT2 / kThreads; ++r) {
     const uint32_t i = threadIdx.x + r * kThreads;
     if (i < n) {
-      kv[r] = stage[i];
+      kv[r] = in_regs ? v[r] : stage[i];
       const uint32_t sub = (mix64_top31((kv[r] & kKeyMask) ^ s0) >> (32 - a1 - a2)) & (nb2 - 1);
       meta[r] = (sub << 16) | atomicAdd(&cnt[sub], 1u);
     }
