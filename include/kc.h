@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define KC_ABI_VERSION 8u
+#define KC_ABI_VERSION 9u
 
 typedef struct kc_ctx kc_ctx;
 

@@ -24,6 +24,15 @@ constexpr uint32_t kProbeLimit = 128;              // probes before a key goes t
 inline __host__ __device__ uint32_t probe_limit_of(uint64_t cap) {
   return cap < kProbeLimit ? (uint32_t)cap : kProbeLimit;
 }
+// Partition tables are cut into aligned buckets of kBucket slots (cap is a
+// multiple of 64).  A key's home slot is the first slot of one bucket, picked
+// by the top 32 bits of th = (x ^ s_0) * kTableMul; probing is linear from
+// there, so a key inserted while its bucket has room lies in that bucket, and
+// a count probe reads the bucket's keys at once.
+constexpr uint32_t kBucket = 4;
+inline __host__ __device__ uint32_t home_slot_of(uint64_t th, uint64_t cap) {
+  return (uint32_t)((((th >> 32) * (cap / kBucket)) >> 32) * kBucket);
+}
 constexpr int kThreads = 1024;                  // block size of the tile kernels
 constexpr int kWaves = kThreads / 64;
 constexpr int kTileWords = 256;                 // first-level tile: 256 packed words

@@ -1074,7 +1074,7 @@ __device__ __forceinline__ void bloom_positions(const HashCfg& hc, uint64_t x, u
 }
 
 __device__ __forceinline__ uint32_t home_slot(uint64_t th, uint32_t cap) {
-  return (uint32_t)(((th >> 32) * (uint64_t)cap) >> 32);
+  return home_slot_of(th, cap);
 }
 
 // Once more keys than ovf_limit have been placed the pass is void (the host
@@ -1267,11 +1267,10 @@ k_tally(const CountArgs A) {
     uint32_t slot = 0, probes = 0;
     if (have) {
       key = qk[lane_id()];
-      slot = qs[lane_id()];
-      // bit 31: the home slot held another key, so the walk starts after it
-      probes = slot >> 31;
-      slot &= 0x7FFFFFFFu;
-      if (probes) slot = slot + 1 == cap ? 0 : slot + 1;
+      // the walk's first slot (bits 0-27) and the slots before it already
+      // known to hold other keys (bits 28-30)
+      slot = qs[lane_id()] & 0x0FFFFFFFu;
+      probes = qs[lane_id()] >> 28;
     }
     const uint64_t x = key & kKeyMask;
     const uint32_t tag = (uint32_t)(key >> 62);
@@ -1314,34 +1313,59 @@ k_tally(const CountArgs A) {
   constexpr int B2 = 2;
   for_runs<kTallyWaves, B2, true>(A, u, u + 1, 1, [&](const uint64_t (&kv)[B2], uint32_t vmask,
                                                      uint32_t nbat, uint32_t /*sub*/) {
-    // One probe at the home slot per occurrence: a hit counts at once; any
-    // other outcome (a new key, or a key further along its chain) is queued.
-    uint64_t cur[B2];
-    uint32_t slot0[B2];
+    // One read of the home bucket per occurrence (its kBucket keys, two
+    // 16-byte LDS loads): a hit counts at once; any other outcome (a new
+    // key, or a key stored past its bucket) is queued with the first slot
+    // of the bucket not known to hold another key.  The loads are not
+    // atomic, so a key being written by another wave's CAS may be read torn,
+    // one half still from kEmpty (all ones); no canonical key has a 32-bit
+    // half of all ones (x < 2^62, and x ending in 16 T bases would have a
+    // smaller reverse complement for k <= 31), so a torn value never equals
+    // x and is never taken for a slot that holds another key.
+    constexpr int KB = (int)kBucket;
+    static_assert(KB == 4, "the bucket read is two 16-byte loads");
+    uint32_t hitm[B2], skip[B2], slot0[B2];
 #pragma unroll
     for (int b = 0; b < B2; ++b) {
       const uint64_t x = kv[b] & kKeyMask;
       slot0[b] = home_slot((x ^ hc.salt[0]) * kTableMul, cap);
-      cur[b] = ((vmask >> b) & 1u) ? __hip_atomic_load(&tk[slot0[b]], __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_WORKGROUP)
-                                   : 0;
+      uint64_t v[KB];
+      if ((vmask >> b) & 1u) {
+        typedef __attribute__((address_space(3))) const volatile u64x2 lds_pair;
+        const lds_pair* bp = (const lds_pair*)(tk + slot0[b]);
+        const u64x2 lo = bp[0], hi = bp[1];
+        v[0] = lo.x; v[1] = lo.y; v[2] = hi.x; v[3] = hi.y;
+      } else {
+#pragma unroll
+        for (int i = 0; i < KB; ++i) v[i] = kEmpty;
+      }
+      hitm[b] = 0;
+      uint32_t other = 0;
+#pragma unroll
+      for (int i = 0; i < KB; ++i) {
+        hitm[b] |= (uint32_t)(v[i] == x) << i;
+        other |= (uint32_t)((uint32_t)v[i] != 0xFFFFFFFFu && (uint32_t)(v[i] >> 32) != 0xFFFFFFFFu)
+                 << i;
+      }
+      // slots before the first one that is empty, torn or x hold other keys
+      skip[b] = (uint32_t)__builtin_ctz(~other);
     }
 #pragma unroll
     for (int b = 0; b < B2; ++b) {
       if (b >= (int)nbat) break;
       const uint64_t key = kv[b];
-      const uint64_t x = key & kKeyMask;
       const uint32_t tag = (uint32_t)(key >> 62);
       const bool valid = (vmask >> b) & 1u;
-      const bool hit = valid && cur[b] == x;
-      if (hit) atomicAdd(&tc[slot0[b] * nc + tag], 1u);
+      const bool hit = valid && hitm[b] != 0;
+      if (hit) atomicAdd(&tc[(slot0[b] + (uint32_t)__builtin_ctz(hitm[b])) * nc + tag], 1u);
       const bool miss = valid && !hit;
       const uint64_t mb = __ballot(miss);
       const uint32_t nm = (uint32_t)__popcll(mb);
       if (!nm) continue;
       const uint32_t rank = (uint32_t)__popcll(mb & ((1ull << lane_id()) - 1));
       const uint32_t room = 64 - qn;
-      const uint32_t qv = slot0[b] | (cur[b] != kEmpty ? 0x80000000u : 0u);
+      const uint32_t first = slot0[b] + skip[b] == cap ? 0u : slot0[b] + skip[b];
+      const uint32_t qv = first | (skip[b] << 28);
       if (miss && rank < room) {
         qk[qn + rank] = key;
         qs[qn + rank] = qv;

@@ -1301,7 +1301,7 @@ void host_probe(const kc_ctx* c, const SpillRec& rec, uint64_t x, uint32_t* out)
   const uint64_t cap = c->cap;
   const uint32_t nc = c->cfg.n_counters;
   const uint64_t th = (x ^ c->hc.salt[0]) * kTableMul;
-  uint64_t slot = ((th >> 32) * cap) >> 32;
+  uint64_t slot = home_slot_of(th, cap);
   const uint64_t* keys = c->spill_keys + rec.host_offset;
   const uint32_t* counts = c->spill_counts + rec.host_offset * nc;
   for (uint64_t n = 0, limit = probe_limit_of(cap); n < limit; ++n) {
