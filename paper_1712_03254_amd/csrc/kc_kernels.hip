@@ -1502,6 +1502,40 @@ __device__ __forceinline__ bool probe_table(const uint64_t* keys, uint64_t base,
   return false;
 }
 
+// Lookup of canonical key x in a partition table at keys[base ..] (cap slots,
+// home slot `slot`, at most `limit` probes; both multiples of kBucket): a
+// bucket's kBucket keys are read at once (two 16-byte loads of one aligned
+// 32-byte range) and scanned in probe order, which ends at x (true, its slot
+// index in *at) or at an empty slot (false: linear probing never stores a key
+// past an empty slot of its probe sequence).  With SEL, keys carry the
+// filter's selection mark in bit 63, ignored in the comparison; *stored is
+// the stored key of a hit.
+template <bool SEL>
+__device__ __forceinline__ bool probe_buckets(const uint64_t* keys, uint64_t base, uint32_t cap,
+                                              uint32_t limit, uint32_t slot, uint64_t x,
+                                              uint64_t* at, uint64_t* stored = nullptr) {
+  constexpr uint64_t kSel = 1ull << 63;
+  for (uint32_t p = 0; p < limit; p += kBucket) {
+    const u64x2* b = reinterpret_cast<const u64x2*>(keys + base + slot);
+    const u64x2 lo = b[0], hi = b[1];
+    const uint64_t v[4] = {lo.x, lo.y, hi.x, hi.y};
+    uint32_t found = 0, empty = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      found |= (uint32_t)(((SEL ? v[i] & ~kSel : v[i])) == x) << i;
+      empty |= (uint32_t)(v[i] == kEmpty) << i;
+    }
+    if (found | empty) {
+      const uint32_t i = (uint32_t)__builtin_ctz(found | empty);
+      *at = base + slot + i;
+      if (stored) *stored = i == 0 ? v[0] : i == 1 ? v[1] : i == 2 ? v[2] : v[3];
+      return (found >> i) & 1u;
+    }
+    slot = slot + kBucket == cap ? 0 : slot + kBucket;
+  }
+  return false;
+}
+
 // Counts of the canonical key x in the final tables: its partition's table in
 // HBM, else the overflow table (a key lives in one of the two, never both).
 // Returns 1 when found, 0 when absent, -1 when its partition's table is not
@@ -1515,8 +1549,8 @@ __device__ __forceinline__ int table_counts(const QueryArgs& A, uint64_t x, uint
   const uint32_t slot = A.slot_of[u];
   uint64_t at;
   if (slot != kNoSlot &&
-      probe_table(A.tkeys, (uint64_t)slot * A.cap, A.cap, A.probe_limit, home_slot(th, A.cap), x,
-                  &at)) {
+      probe_buckets<false>(A.tkeys, (uint64_t)slot * A.cap, (uint32_t)A.cap, A.probe_limit,
+                           home_slot(th, (uint32_t)A.cap), x, &at)) {
     *c0 = A.tcounts[at * nc];
     if (nc > 1) *c1 = A.tcounts[at * nc + 1];
     return 1;
@@ -1586,15 +1620,11 @@ __device__ __forceinline__ bool filter_selected(const QueryArgs& A, uint64_t x, 
   const uint64_t th = (x ^ A.hc.salt[0]) * kTableMul;
   const uint64_t u = top_bits(mix64(x ^ A.hc.salt[0]), A.hc.p_log2);
   const uint64_t base = (uint64_t)A.slot_of[u] * A.cap;
-  uint64_t slot = home_slot(th, (uint32_t)A.cap);
-  for (uint32_t p = 0; p < A.probe_limit; ++p) {
-    const uint64_t cur = A.fkeys[base + slot];
-    if ((cur & ~kSelBit) == x) return (cur >> 63) != 0;
-    if (cur == kEmpty) break;
-    slot = slot + 1 == A.cap ? 0 : slot + 1;
-  }
+  uint64_t at, stored;
+  if (probe_buckets<true>(A.fkeys, base, (uint32_t)A.cap, A.probe_limit,
+                          home_slot(th, (uint32_t)A.cap), x, &at, &stored))
+    return (stored >> 63) != 0;
   uint32_t c0 = 0, c1 = 0;
-  uint64_t at;
   if (*A.ovf_used && probe_table(A.okeys, 0, 1ull << A.ovf_log2, 1ull << A.ovf_log2,
                                  mix64(th) >> (64 - A.ovf_log2), x, &at)) {
     c0 = A.ocounts[at * A.hc.nc];
