@@ -940,6 +940,10 @@ __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint
         const uint32_t incl = FLAT ? wave_incl_scan(len) : 0u;
         const uint32_t total = FLAT ? __builtin_amdgcn_readlane(incl, 63) : 0u;
         const uint32_t excl = lane_id() < nj ? incl - len : total;
+        // FLAT: key index of position v in run j is rb(j) + v (mod 2^32),
+        // with rb(j) = tile(j) 2^t2s + start(j) - excl(j): one value per run
+        // to select per lane, instead of the run, its start and its offset
+        const uint32_t rb = FLAT ? ((tw + NW * lane_id()) << t2s) + mm0 - excl : 0u;
         uint32_t v0 = 0;  // FLAT: next position of the concatenation
         auto next_flat = [&](RunBatch<B>& r) {
           uint32_t off[B];
@@ -958,32 +962,26 @@ __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint
             const uint64_t le_hi = __ballot(excl <= vb + 63);
             const uint32_t jlo = le_lo ? 63 - (uint32_t)__builtin_clzll(le_lo) : 0u;
             const uint32_t jhi = le_hi ? 63 - (uint32_t)__builtin_clzll(le_hi) : 0u;
-            uint32_t jj, start, ex;
+            uint32_t base;
             if (jhi - jlo <= 8) {
               // few run starts inside the chunk: step through them (scalar reads)
-              jj = jlo;
-              start = __builtin_amdgcn_readlane(mm0, jlo);
-              ex = __builtin_amdgcn_readlane(excl, jlo);
+              base = __builtin_amdgcn_readlane(rb, jlo);
               for (uint32_t t = jlo + 1; t <= jhi; ++t) {
                 const uint32_t et = __builtin_amdgcn_readlane(excl, t);
-                const uint32_t st = __builtin_amdgcn_readlane(mm0, t);
-                const bool in = vc >= et;
-                jj = in ? t : jj;
-                start = in ? st : start;
-                ex = in ? et : ex;
+                const uint32_t bt = __builtin_amdgcn_readlane(rb, t);
+                base = vc >= et ? bt : base;
               }
             } else {
               // many short runs: binary search over the lanes' run starts
-              jj = 0;
+              uint32_t jj = 0;
 #pragma unroll
               for (int sp = 32; sp >= 1; sp >>= 1) {
                 const uint32_t e = __shfl(excl, jj + sp, 64);
                 jj = e <= vc ? jj + sp : jj;
               }
-              start = __shfl(mm0, jj, 64);
-              ex = __shfl(excl, jj, 64);
+              base = __shfl(rb, jj, 64);
             }
-            off[b] = ok ? ((tw + NW * jj) << t2s) + start + (vc - ex) : 0u;
+            off[b] = ok ? base + vc : 0u;
             r.vmask |= (uint32_t)ok << b;
           }
           v0 += 64 * B;
@@ -1314,9 +1312,11 @@ k_tally(const CountArgs A) {
   for_runs<kTallyWaves, B2, true>(A, u, u + 1, 1, [&](const uint64_t (&kv)[B2], uint32_t vmask,
                                                      uint32_t nbat, uint32_t /*sub*/) {
     // One read of the home bucket per occurrence (its kBucket keys, two
-    // 16-byte LDS loads): a hit counts at once; any other outcome (a new
-    // key, or a key stored past its bucket) is queued with the first slot
-    // of the bucket not known to hold another key.  The loads are not
+    // 16-byte LDS loads), scanned in probe order: x found before any open
+    // slot counts at once; any other outcome (a new key, a key stored past
+    // its bucket, or x behind a slot read while another wave filled it) is
+    // queued with the first slot of the bucket not known to hold another
+    // key, where the walk resolves it.  The loads are not
     // atomic, so a key being written by another wave's CAS may be read torn,
     // one half still from kEmpty (all ones); no canonical key has a 32-bit
     // half of all ones (x < 2^62, and x ending in 16 T bases would have a
@@ -1324,7 +1324,7 @@ k_tally(const CountArgs A) {
     // x and is never taken for a slot that holds another key.
     constexpr int KB = (int)kBucket;
     static_assert(KB == 4, "the bucket read is two 16-byte loads");
-    uint32_t hitm[B2], skip[B2], slot0[B2];
+    uint32_t stop[B2], slot0[B2];
 #pragma unroll
     for (int b = 0; b < B2; ++b) {
       const uint64_t x = kv[b] & kKeyMask;
@@ -1339,16 +1339,16 @@ k_tally(const CountArgs A) {
 #pragma unroll
         for (int i = 0; i < KB; ++i) v[i] = kEmpty;
       }
-      hitm[b] = 0;
-      uint32_t other = 0;
+      // The first slot, in probe order, that holds x (bit 3 set) or is empty
+      // or torn (a 32-bit half of all ones); KB when all hold other keys.
+      // On a miss the slots before it hold other keys.
+      stop[b] = KB;
 #pragma unroll
-      for (int i = 0; i < KB; ++i) {
-        hitm[b] |= (uint32_t)(v[i] == x) << i;
-        other |= (uint32_t)((uint32_t)v[i] != 0xFFFFFFFFu && (uint32_t)(v[i] >> 32) != 0xFFFFFFFFu)
-                 << i;
+      for (int i = KB - 1; i >= 0; --i) {
+        const bool is_x = v[i] == x;
+        const bool open = max((uint32_t)v[i], (uint32_t)(v[i] >> 32)) == 0xFFFFFFFFu;
+        stop[b] = is_x || open ? (uint32_t)i | (is_x ? 8u : 0u) : stop[b];
       }
-      // slots before the first one that is empty, torn or x hold other keys
-      skip[b] = (uint32_t)__builtin_ctz(~other);
     }
 #pragma unroll
     for (int b = 0; b < B2; ++b) {
@@ -1356,16 +1356,19 @@ k_tally(const CountArgs A) {
       const uint64_t key = kv[b];
       const uint32_t tag = (uint32_t)(key >> 62);
       const bool valid = (vmask >> b) & 1u;
-      const bool hit = valid && hitm[b] != 0;
-      if (hit) atomicAdd(&tc[(slot0[b] + (uint32_t)__builtin_ctz(hitm[b])) * nc + tag], 1u);
+      const bool hit = valid && (stop[b] & 8u);
+      const uint32_t skip = stop[b] & 7u;
+      if (hit) atomicAdd(&tc[(slot0[b] + skip) * nc + tag], 1u);
       const bool miss = valid && !hit;
       const uint64_t mb = __ballot(miss);
       const uint32_t nm = (uint32_t)__popcll(mb);
       if (!nm) continue;
-      const uint32_t rank = (uint32_t)__popcll(mb & ((1ull << lane_id()) - 1));
+      // missing lanes below this one (two mbcnt instructions)
+      const uint32_t rank =
+          __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
       const uint32_t room = 64 - qn;
-      const uint32_t first = slot0[b] + skip[b] == cap ? 0u : slot0[b] + skip[b];
-      const uint32_t qv = first | (skip[b] << 28);
+      const uint32_t first = slot0[b] + skip == cap ? 0u : slot0[b] + skip;
+      const uint32_t qv = first | (skip << 28);
       if (miss && rank < room) {
         qk[qn + rank] = key;
         qs[qn + rank] = qv;
