@@ -1236,7 +1236,10 @@ k_tally(const CountArgs A) {
   const uint32_t nc = hc.nc;
   const uint32_t blk = u >> A.upb_log2;
   const uint64_t bit0 = (uint64_t)blk << hc.bl;
-  const uint32_t* b2 = A.b2;
+  // the block's level-2 words from the word holding its first bit (a block
+  // of fewer than 32 bits lies inside that word, from bit b2_off on)
+  const uint32_t* b2 = A.b2 + (bit0 >> 5);
+  const uint32_t b2_off = (uint32_t)bit0 & 31u;
   uint64_t* tk = reinterpret_cast<uint64_t*>(lds);
   uint32_t* tc = reinterpret_cast<uint32_t*>(tk + cap);
   uint64_t* qk = reinterpret_cast<uint64_t*>(tc + (size_t)cap * nc) + wave_id() * 64;
@@ -1278,13 +1281,15 @@ k_tally(const CountArgs A) {
     const uint32_t mask = (1u << hc.bl) - 1u;
     const uint32_t a = (uint32_t)(u >> (64 - hc.bl));
     const uint32_t b = (uint32_t)(u >> (64 - 2 * hc.bl)) & mask;
-    uint32_t w[H];
+    uint32_t w[H], q[H];
 #pragma unroll
-    for (int i = 0; i < H; ++i) w[i] = b2[(bit0 + ((a + (uint32_t)i * b) & mask)) >> 5];
+    for (int i = 0; i < H; ++i) {
+      q[i] = b2_off + ((a + (uint32_t)i * b) & mask);
+      w[i] = b2[q[i] >> 5];
+    }
     bool pass = have;
 #pragma unroll
-    for (int i = 0; i < H; ++i)
-      pass &= ((w[i] >> ((uint32_t)(bit0 + ((a + (uint32_t)i * b) & mask)) & 31u)) & 1u) != 0;
+    for (int i = 0; i < H; ++i) pass &= ((w[i] >> (q[i] & 31u)) & 1u) != 0;
     if (pass) {
       const uint64_t th = (x ^ hc.salt[0]) * kTableMul;
       for (;;) {
@@ -1329,16 +1334,12 @@ k_tally(const CountArgs A) {
     for (int b = 0; b < B2; ++b) {
       const uint64_t x = kv[b] & kKeyMask;
       slot0[b] = home_slot((x ^ hc.salt[0]) * kTableMul, cap);
-      uint64_t v[KB];
-      if ((vmask >> b) & 1u) {
-        typedef __attribute__((address_space(3))) const volatile u64x2 lds_pair;
-        const lds_pair* bp = (const lds_pair*)(tk + slot0[b]);
-        const u64x2 lo = bp[0], hi = bp[1];
-        v[0] = lo.x; v[1] = lo.y; v[2] = hi.x; v[3] = hi.y;
-      } else {
-#pragma unroll
-        for (int i = 0; i < KB; ++i) v[i] = kEmpty;
-      }
+      // every lane reads a bucket (a lane without a key holds some stored
+      // key, so its slot is in range); the result counts only where valid
+      typedef __attribute__((address_space(3))) const volatile u64x2 lds_pair;
+      const lds_pair* bp = (const lds_pair*)(tk + slot0[b]);
+      const u64x2 lo = bp[0], hi = bp[1];
+      const uint64_t v[KB] = {lo.x, lo.y, hi.x, hi.y};
       // The first slot, in probe order, that holds x (bit 3 set) or is empty
       // or torn (a 32-bit half of all ones); KB when all hold other keys.
       // On a miss the slots before it hold other keys.
