@@ -495,6 +495,25 @@ __global__ void __launch_bounds__(kThreads) k_level1(const uint64_t* __restrict_
   uint32_t* cnt = reinterpret_cast<uint32_t*>(stage + kTilePos);
   uint32_t* start = cnt + nb;                               // nb + 1
   uint32_t* scratch = start + nb + 1;                       // kWaves
+  // Context of each of the tile's words, made once per word by the first
+  // kTileWords threads (four waves take a word's windows): packed words w-1
+  // and w, their reverse complements and the valid-window mask.  It sits in
+  // the stage area, which the sorted keys overwrite only after the barrier
+  // that ends the extraction.
+  uint64_t* cx = stage;                                           // 4 x kTileWords
+  uint32_t* cm = reinterpret_cast<uint32_t*>(stage + 4 * kTileWords);  // kTileWords
+  static_assert(5 * kTileWords <= kTilePos, "word context fits the stage area");
+  if (threadIdx.x < kTileWords) {
+    const uint64_t wt = tile * kTileWords + threadIdx.x;
+    if (wt < nwords) {
+      const WordCtx c = load_word(packed, flags, wt);
+      cx[threadIdx.x] = c.pp;
+      cx[kTileWords + threadIdx.x] = c.pc;
+      cx[2 * kTileWords + threadIdx.x] = c.qp;
+      cx[3 * kTileWords + threadIdx.x] = c.qc;
+      cm[threadIdx.x] = window_mask(c, k);
+    }
+  }
   for (uint32_t i = threadIdx.x; i < nb; i += kThreads) cnt[i] = 0;
   __syncthreads();
   // Lane l of wave v takes packed word (v mod kWordGroups) * 64 + l and in it
@@ -507,14 +526,19 @@ __global__ void __launch_bounds__(kThreads) k_level1(const uint64_t* __restrict_
                     kWordGroups * 64 == kTileWords,
                 "level-1 tile shape");
   const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint64_t w = tile * kTileWords + (wv % kWordGroups) * 64 + (threadIdx.x & 63);
+  const uint32_t wl = (wv % kWordGroups) * 64 + (threadIdx.x & 63);
+  const uint64_t w = tile * kTileWords + wl;
   uint64_t key[kPP];
   uint32_t meta[kPP];
   uint32_t valid = 0;
   if (w < nwords) {
-    const WordCtx c = load_word(packed, flags, w);
+    WordCtx c;
+    c.pp = cx[wl];
+    c.pc = cx[kTileWords + wl];
+    c.qp = cx[2 * kTileWords + wl];
+    c.qc = cx[3 * kTileWords + wl];
     const int j0 = (int)(wv / kWordGroups) * kPP;
-    valid = (window_mask(c, k) >> j0) & ((1u << kPP) - 1);
+    valid = (cm[wl] >> j0) & ((1u << kPP) - 1);
     // keys and hashes of all kPP windows, branch-free; only the count of a
     // valid one is taken
 #pragma unroll
