@@ -539,15 +539,20 @@ __global__ void __launch_bounds__(kThreads) k_level1(const uint64_t* __restrict_
     c.qc = cx[3 * kTileWords + wl];
     const int j0 = (int)(wv / kWordGroups) * kPP;
     valid = (cm[wl] >> j0) & ((1u << kPP) - 1);
-    // keys and hashes of all kPP windows, branch-free; only the count of a
-    // valid one is taken
+    // keys and hashes of all kPP windows, branch-free; every lane adds to
+    // its bucket's count (1 for a valid window, 0 otherwise), so the kPP
+    // atomics issue back to back and are waited for once
+    uint32_t bk[kPP], rk[kPP];
 #pragma unroll
     for (int jj = 0; jj < kPP; ++jj) {
       const uint64_t x = window_code(c, k, j0 + jj);
-      const uint32_t b = mix64_top31(x ^ s0) >> (32 - a1);
-      if ((valid >> jj) & 1u) meta[jj] = (b << 16) | atomicAdd(&cnt[b], 1u);
+      bk[jj] = mix64_top31(x ^ s0) >> (32 - a1);
       key[jj] = x | tag;
     }
+#pragma unroll
+    for (int jj = 0; jj < kPP; ++jj) rk[jj] = atomicAdd(&cnt[bk[jj]], (valid >> jj) & 1u);
+#pragma unroll
+    for (int jj = 0; jj < kPP; ++jj) meta[jj] = (bk[jj] << 16) | rk[jj];
   }
   __syncthreads();
   block_exclusive_scan(cnt, start, nb, scratch);
