@@ -95,10 +95,13 @@ __device__ void block_exclusive_scan(const uint32_t* in, uint32_t* out, uint32_t
     sum += v[q];
   }
   uint32_t inc = sum;
+  // waves whose counters all lie past n hold zeros and skip the wave scan
+  if ((t - lane_id()) * per < n) {
 #pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t o = __shfl_up(inc, d, 64);
-    if ((int)lane_id() >= d) inc += o;
+    for (int d = 1; d < 64; d <<= 1) {
+      uint32_t o = __shfl_up(inc, d, 64);
+      if ((int)lane_id() >= d) inc += o;
+    }
   }
   if (lane_id() == 63) scratch[wave_id()] = inc;
   __syncthreads();
