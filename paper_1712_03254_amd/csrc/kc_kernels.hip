@@ -862,14 +862,29 @@ __global__ void __launch_bounds__(kThreads) k_level2(const uint64_t* __restrict_
   }
   __syncthreads();
   block_exclusive_scan(cnt, start, nb2, scratch);
+  // sub-bucket starts read together, then the keys scattered; the sorted
+  // tile read back from LDS together, then stored
+  uint32_t bst[kT2 / kThreads];
+#pragma unroll
+  for (int r = 0; r < kT2 / kThreads; ++r)
+    bst[r] = start[threadIdx.x + r * kThreads < n ? meta[r] >> 16 : 0u];
 #pragma unroll
   for (int r = 0; r < kT2 / kThreads; ++r) {
     const uint32_t i = threadIdx.x + r * kThreads;
-    if (i < n) stage[start[meta[r] >> 16] + (meta[r] & 0xFFFF)] = kv[r];
+    if (i < n) stage[bst[r] + (meta[r] & 0xFFFF)] = kv[r];
   }
   __syncthreads();
   uint64_t* dst = keys2 + bo + p0;
-  for (uint32_t i = threadIdx.x; i < n; i += kThreads) dst[i] = stage[i];
+#pragma unroll
+  for (int r = 0; r < kT2 / kThreads; ++r) {
+    const uint32_t i = threadIdx.x + r * kThreads;
+    kv[r] = i < n ? stage[i] : 0ull;
+  }
+#pragma unroll
+  for (int r = 0; r < kT2 / kThreads; ++r) {
+    const uint32_t i = threadIdx.x + r * kThreads;
+    if (i < n) dst[i] = kv[r];
+  }
   for (uint32_t s = threadIdx.x; s <= nb2; s += kThreads)
     meta2[(uint64_t)tt * (nb2 + 1) + s] = start[s];
 }
