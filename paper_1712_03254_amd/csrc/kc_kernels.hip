@@ -1436,36 +1436,43 @@ k_tally(const CountArgs A) {
   if (qn) drain(qn);
   __syncthreads();
 
-  uint64_t st[kNst];
-#pragma unroll
-  for (int i = 0; i < kNst; ++i) st[i] = 0;
-  st[ST_OVF] = n_ovf;
+  // Per-wave statistics: slot counts (passed keys, false-positive
+  // singletons, entries) by ballot, wave-uniform; count sums per lane, then
+  // summed over the wave with the overflow occurrences (three wave sums
+  // instead of one per statistic).
+  uint64_t npass = 0, sum = 0, passed = 0, fp = 0, entries = 0;
   const uint64_t base = (uint64_t)(A.slot_base + lu) * cap;
   for (uint32_t i = threadIdx.x; i < cap; i += kTallyThreads) {
     const uint64_t key = tk[i];
     uint32_t c0 = tc[i * nc], c1 = nc > 1 ? tc[i * nc + 1] : 0;
-    if (key != kEmpty) {
-      const uint64_t tot = (uint64_t)c0 + c1;
-      st[ST_PASSED] += 1;
-      st[ST_NPASS] += tot;
-      st[ST_FP] += (tot == 1);
-      if (tot >= hc.min_count) {
-        st[ST_ENTRIES] += 1;
-        st[ST_SUM] += tot;
-      } else {
-        c0 = c1 = 0;
-      }
-    }
+    const bool used = key != kEmpty;
+    const uint64_t tot = (uint64_t)c0 + c1;
+    const bool kept = used && tot >= hc.min_count;
+    passed += (uint64_t)__popcll(__ballot(used));
+    fp += (uint64_t)__popcll(__ballot(used && tot == 1));
+    entries += (uint64_t)__popcll(__ballot(kept));
+    npass += used ? tot : 0;
+    sum += kept ? tot : 0;
+    if (!kept) c0 = c1 = 0;
     A.tkeys[base + i] = key;
     A.tcounts[(base + i) * nc] = c0;
     if (nc > 1) A.tcounts[(base + i) * nc + 1] = c1;
   }
   __syncthreads();
   uint64_t* red = reinterpret_cast<uint64_t*>(lds);
+  {
+    uint64_t st[kNst];
 #pragma unroll
-  for (int i = 0; i < kNst; ++i) {
-    const uint64_t v = wave_sum(st[i]);
-    if (lane_id() == 0) red[wave_id() * kNst + i] = v;
+    for (int i = 0; i < kNst; ++i) st[i] = 0;
+    st[ST_PASSED] = passed;
+    st[ST_FP] = fp;
+    st[ST_ENTRIES] = entries;
+    st[ST_NPASS] = wave_sum(npass);
+    st[ST_SUM] = wave_sum(sum);
+    st[ST_OVF] = wave_sum((uint64_t)n_ovf);
+    if (lane_id() == 0)
+#pragma unroll
+      for (int i = 0; i < kNst; ++i) red[wave_id() * kNst + i] = st[i];
   }
   __syncthreads();
   if (threadIdx.x < kNst) {
