@@ -72,11 +72,30 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T* cview(cons
   return (const __attribute__((address_space(4))) T*)p;
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-  return v;
+// 64-bit value of the lane CTRL names (a DPP row shift or row broadcast),
+// 0 where that lane is outside the row or the lane's row is not in ROWS.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROWS, 0xF, true);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, ROWS, 0xF, true);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Sum of a 64-bit value over the 64 lanes of a wave, returned to every lane:
+// within each row of 16 lanes, shifted adds by 1, 2, 4 and 8 leave the row's
+// sum in its lane 15; two row broadcasts then add row 0 into row 1 and rows
+// 0-1 into rows 2-3, so lane 63 holds the total (DPP moves, no LDS).
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
+  v += dpp_u64<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_u64<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_u64<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_u64<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_u64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_u64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, 63);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
 }
 
 // Exclusive scan over n <= 4 * kThreads LDS counters with all kThreads
