@@ -98,6 +98,36 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, true);
+}
+
+// 64-bit inclusive prefix sum across the 64 lanes of a wave (the DPP steps
+// of wave_sum, whose partial sums are the prefix sums).
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
+  v += dpp_u64<0x111, 0xF>(v);
+  v += dpp_u64<0x112, 0xF>(v);
+  v += dpp_u64<0x114, 0xF>(v);
+  v += dpp_u64<0x118, 0xF>(v);
+  v += dpp_u64<0x142, 0xA>(v);
+  v += dpp_u64<0x143, 0xC>(v);
+  return v;
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave: the same DPP steps as
+// wave_sum, whose partial sums are the prefix sums (each row's by the shifts,
+// then the rows before it by the two broadcasts).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  v += dpp_u32<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_u32<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_u32<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_u32<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_u32<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_u32<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
 // Exclusive scan over n <= 4 * kThreads LDS counters with all kThreads
 // threads: out[i] = sum(in[0..i)), out[n] = total.  scratch: kWaves words.
 // Must be reached by every thread of the block; ends with a barrier.
@@ -115,13 +145,7 @@ __device__ void block_exclusive_scan(const uint32_t* in, uint32_t* out, uint32_t
   }
   uint32_t inc = sum;
   // waves whose counters all lie past n hold zeros and skip the wave scan
-  if ((t - lane_id()) * per < n) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      uint32_t o = __shfl_up(inc, d, 64);
-      if ((int)lane_id() >= d) inc += o;
-    }
-  }
+  if ((t - lane_id()) * per < n) inc = wave_incl_scan(inc);
   if (lane_id() == 63) scratch[wave_id()] = inc;
   __syncthreads();
   uint32_t wave_off = 0;
@@ -640,12 +664,7 @@ __global__ void __launch_bounds__(kThreads) k_scan_parts(uint64_t* __restrict__ 
   for (uint64_t b = 0; b < nparts; b += kThreads) {
     uint64_t i = b + threadIdx.x;
     uint64_t v = i < nparts ? parts[i] : 0;
-    uint64_t inc = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      uint64_t o = __shfl_up(inc, d, 64);
-      if ((int)lane_id() >= d) inc += o;
-    }
+    const uint64_t inc = wave_incl_scan64(v);
     if (lane_id() == 63) red[wave_id()] = inc;
     __syncthreads();
     uint64_t off = carry;
@@ -669,12 +688,7 @@ __global__ void __launch_bounds__(kThreads) k_scan_down(const uint32_t* __restri
   uint64_t s = 0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) s += v[q];
-  uint64_t inc = s;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint64_t o = __shfl_up(inc, d, 64);
-    if ((int)lane_id() >= d) inc += o;
-  }
+  const uint64_t inc = wave_incl_scan64(s);
   if (lane_id() == 63) red[wave_id()] = inc;
   __syncthreads();
   uint64_t run = parts[blockIdx.x];
@@ -942,15 +956,6 @@ struct RunBatch {
   uint32_t n;      // chunks in the batch (wave-uniform)
 };
 
-// Inclusive prefix sum across the 64 lanes of a wave.
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t o = __shfl_up(v, d, 64);
-    if ((int)lane_id() >= d) v += o;
-  }
-  return v;
-}
 
 template <int NW, int B, bool FLAT, int SUBL = 0, typename F>
 __device__ __forceinline__ void for_runs(const CountArgs& A, uint32_t u_lo, uint32_t u_hi,
