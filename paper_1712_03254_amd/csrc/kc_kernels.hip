@@ -1319,8 +1319,12 @@ k_tally(const CountArgs A) {
   uint32_t n_ovf = 0;  // occurrences counted in the overflow table
   const uint32_t limit = A.probe_limit;
 
-  for (uint32_t i = threadIdx.x; i < cap; i += kTallyThreads) tk[i] = kEmpty;
-  for (uint32_t i = threadIdx.x; i < cap * nc; i += kTallyThreads) tc[i] = 0;
+  // the table cleared with 16-byte stores (cap is a multiple of 64, so both
+  // arrays are whole 16-byte units on 16-byte boundaries)
+  for (uint32_t i = threadIdx.x; i < cap / 2; i += kTallyThreads)
+    reinterpret_cast<u64x2*>(tk)[i] = u64x2{kEmpty, kEmpty};
+  for (uint32_t i = threadIdx.x; i < cap * nc / 4; i += kTallyThreads)
+    reinterpret_cast<u32x4*>(tc)[i] = u32x4{0u, 0u, 0u, 0u};
   __syncthreads();
 
   // Resolves the queued occurrences densely, 64 at a time.  Every queued key
@@ -1464,23 +1468,40 @@ k_tally(const CountArgs A) {
   // singletons, entries) by ballot, wave-uniform; count sums per lane, then
   // summed over the wave with the overflow occurrences (three wave sums
   // instead of one per statistic).
+  // Two slots per thread and step: 16-byte LDS reads of their keys (and of
+  // their counts with two counters) and 16- / 8-byte stores.
   uint64_t npass = 0, sum = 0, passed = 0, fp = 0, entries = 0;
   const uint64_t base = (uint64_t)(A.slot_base + lu) * cap;
-  for (uint32_t i = threadIdx.x; i < cap; i += kTallyThreads) {
-    const uint64_t key = tk[i];
-    uint32_t c0 = tc[i * nc], c1 = nc > 1 ? tc[i * nc + 1] : 0;
-    const bool used = key != kEmpty;
-    const uint64_t tot = (uint64_t)c0 + c1;
-    const bool kept = used && tot >= hc.min_count;
-    passed += (uint64_t)__popcll(__ballot(used));
-    fp += (uint64_t)__popcll(__ballot(used && tot == 1));
-    entries += (uint64_t)__popcll(__ballot(kept));
-    npass += used ? tot : 0;
-    sum += kept ? tot : 0;
-    if (!kept) c0 = c1 = 0;
-    A.tkeys[base + i] = key;
-    A.tcounts[(base + i) * nc] = c0;
-    if (nc > 1) A.tcounts[(base + i) * nc + 1] = c1;
+  for (uint32_t i2 = threadIdx.x; i2 < cap / 2; i2 += kTallyThreads) {
+    const uint32_t i = 2 * i2;
+    const u64x2 kp = reinterpret_cast<const u64x2*>(tk)[i2];
+    uint32_t c[2][2];
+    if (nc > 1) {
+      const u32x4 cq = reinterpret_cast<const u32x4*>(tc)[i2];
+      c[0][0] = cq.x; c[0][1] = cq.y; c[1][0] = cq.z; c[1][1] = cq.w;
+    } else {
+      const uint64_t cp = reinterpret_cast<const uint64_t*>(tc)[i2];
+      c[0][0] = (uint32_t)cp; c[0][1] = 0; c[1][0] = (uint32_t)(cp >> 32); c[1][1] = 0;
+    }
+    const uint64_t key[2] = {kp.x, kp.y};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const bool used = key[e] != kEmpty;
+      const uint64_t tot = (uint64_t)c[e][0] + c[e][1];
+      const bool kept = used && tot >= hc.min_count;
+      passed += (uint64_t)__popcll(__ballot(used));
+      fp += (uint64_t)__popcll(__ballot(used && tot == 1));
+      entries += (uint64_t)__popcll(__ballot(kept));
+      npass += used ? tot : 0;
+      sum += kept ? tot : 0;
+      if (!kept) c[e][0] = c[e][1] = 0;
+    }
+    *reinterpret_cast<u64x2*>(A.tkeys + base + i) = kp;
+    if (nc > 1)
+      *reinterpret_cast<u32x4*>(A.tcounts + (base + i) * 2) = u32x4{c[0][0], c[0][1], c[1][0], c[1][1]};
+    else
+      *reinterpret_cast<uint64_t*>(A.tcounts + base + i) =
+          (uint64_t)c[0][0] | ((uint64_t)c[1][0] << 32);
   }
   __syncthreads();
   uint64_t* red = reinterpret_cast<uint64_t*>(lds);
