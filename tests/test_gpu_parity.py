@@ -2,6 +2,8 @@
 
 Every case prints its name, seed and shape before touching the GPU.
 """
+import random
+
 import numpy as np
 import pytest
 
@@ -300,3 +302,36 @@ def test_bad_offsets_and_state_errors():
         c.insert_reads(db, torch.from_numpy(o.view(np.int64)).cuda())
         st = c.finalize()
         assert st["n_valid"] == (14 - 11 + 1) + (16 - 11 + 1)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("nc,pl", [(1, 4), (2, 6)])
+def test_contended_tables_parity(nc, pl):
+    """Few distinct k-mers seen from every wave at once: reads from a 300-base
+    genome at ~6,000x coverage, homopolymer and dinucleotide and trinucleotide
+    repeats, so the same table buckets are read while other waves insert into
+    them (the count pass reads buckets without atomics): 280 distinct keys
+    over 1.2 million occurrences, the largest count about 40,000; one and two
+    counters, 16 and 64 partitions."""
+    note("case: contended tables nc=%d partitions=2^%d" % (nc, pl))
+    rng = random.Random(77 + nc)
+    genome = "".join(rng.choice("ACGT") for _ in range(300))
+    comp = str.maketrans("ACGT", "TGCA")
+    reads = []
+    for i in range(18000):
+        L = rng.randint(60, 120)
+        st = rng.randint(0, len(genome) - L)
+        r = genome[st:st + L]
+        reads.append(r[::-1].translate(comp) if i & 1 else r)
+    for unit in ("A", "T", "C", "AC", "GT", "AGC", "TTG"):
+        for _ in range(300):
+            L = rng.randint(40, 150)
+            reads.append((unit * (L // len(unit) + 1))[:L])
+    rng.shuffle(reads)
+    half = len(reads) // 2
+    cfg = kc.Config(k=31, n_counters=nc, bloom_bits_log2=20, bloom_hashes=4, bloom_block_log2=14,
+                    seed=91 + nc, partitions_log2=pl)
+    if nc == 1:
+        assert_parity(cfg, [pack_reads(reads)])
+    else:
+        assert_parity(cfg, [pack_reads(reads[:half]), pack_reads(reads[half:])], counters=[0, 1])
