@@ -126,6 +126,7 @@ struct QueryArgs {
   const uint64_t* tkeys;
   const uint32_t* tcounts;
   const uint32_t* slot_of;  // partition -> its table slot in HBM, or kNoSlot if spilled
+  int64_t slot_first;       // >= 0: slot_of[u] is u - slot_first, kNoSlot below it
   const uint64_t* okeys;
   const uint32_t* ocounts;
   const uint32_t* ovf_used;

@@ -1639,6 +1639,15 @@ __device__ __forceinline__ bool probe_buckets(const uint64_t* keys, uint64_t bas
   return false;
 }
 
+// Table slot of partition u: computed when the slot map is the layout finalize
+// makes (partitions below slot_first spilled, the rest in order), which saves
+// a dependent load per lookup; read from the map otherwise.
+__device__ __forceinline__ uint32_t table_slot(const QueryArgs& A, uint64_t u) {
+  if (A.slot_first >= 0)
+    return u >= (uint64_t)A.slot_first ? (uint32_t)(u - (uint64_t)A.slot_first) : kNoSlot;
+  return A.slot_of[u];
+}
+
 // Counts of the canonical key x in the final tables: its partition's table in
 // HBM, else the overflow table (a key lives in one of the two, never both).
 // Returns 1 when found, 0 when absent, -1 when its partition's table is not
@@ -1649,7 +1658,7 @@ __device__ __forceinline__ int table_counts(const QueryArgs& A, uint64_t x, uint
   const uint32_t nc = A.hc.nc;
   const uint64_t u = top_bits(mix64(x ^ A.hc.salt[0]), A.hc.p_log2);
   const uint64_t th = (x ^ A.hc.salt[0]) * kTableMul;
-  const uint32_t slot = A.slot_of[u];
+  const uint32_t slot = table_slot(A, u);
   uint64_t at;
   if (slot != kNoSlot &&
       probe_buckets<false>(A.tkeys, (uint64_t)slot * A.cap, (uint32_t)A.cap, A.probe_limit,
@@ -1722,7 +1731,7 @@ __device__ __forceinline__ bool filter_selected(const QueryArgs& A, uint64_t x, 
                                                 uint32_t nmax) {
   const uint64_t th = (x ^ A.hc.salt[0]) * kTableMul;
   const uint64_t u = top_bits(mix64(x ^ A.hc.salt[0]), A.hc.p_log2);
-  const uint64_t base = (uint64_t)A.slot_of[u] * A.cap;
+  const uint64_t base = (uint64_t)table_slot(A, u) * A.cap;
   uint64_t at, stored;
   if (probe_buckets<true>(A.fkeys, base, (uint32_t)A.cap, A.probe_limit,
                           home_slot(th, (uint32_t)A.cap), x, &at, &stored))

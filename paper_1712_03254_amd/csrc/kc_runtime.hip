@@ -312,6 +312,10 @@ struct kc_ctx {
   DevBuf qrows, qkeys, qcount;
   uint32_t pool_slots = 0;            // partition tables held in HBM (the budget's share)
   std::vector<uint32_t> slot_of_h;    // host mirror of slot_of
+  // slot_of[u] = u - slot_first for u >= slot_first and kNoSlot below it, as
+  // finalize, restore and the batched form lay tables out; -1 once a single
+  // partition has been spilled (lookups then read slot_of)
+  int64_t slot_first = -1;
   hipStream_t copy_stream = nullptr;  // device-to-host spill copies
   hipEvent_t ev_tally[2] = {nullptr, nullptr}, ev_copy[2] = {nullptr, nullptr};
   uint32_t ovf_log2 = 12;
@@ -616,6 +620,7 @@ kc_status spill_partition(kc_ctx* c, uint32_t p, hipStream_t s, uint64_t* bytes)
   if (r != KC_OK) return r;
   c->spill_used += 1;
   c->slot_of_h[p] = kNoSlot;
+  c->slot_first = -1;
   add_spill_record(c, p, t, row[ST_ENTRIES]);
   if (bytes) *bytes += cap * c->slot_bytes;
   return KC_OK;
@@ -837,6 +842,7 @@ kc_status filter_run(kc_ctx* c, const uint8_t* bases, const uint64_t* offsets, u
   a.tkeys = c->tkeys.as<uint64_t>();
   a.tcounts = c->tcounts.as<uint32_t>();
   a.slot_of = c->slot_of.as<uint32_t>();
+  a.slot_first = c->slot_first;
   a.okeys = c->okeys.as<uint64_t>();
   a.ocounts = c->ocounts.as<uint32_t>();
   a.ovf_used = c->ovf_used.as<uint32_t>();
@@ -1280,6 +1286,7 @@ kc_status kc_finalize(kc_ctx* c, void* hip_stream, kc_stats* out) {
   KC_HIP(c, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(c->slot_live.p), 1, R, s), "slot map");
   c->slot_of_h.resize(nparts);
   for (uint64_t u = 0; u < nparts; ++u) c->slot_of_h[u] = u < n_spill ? kNoSlot : (uint32_t)(u - n_spill);
+  c->slot_first = (int64_t)n_spill;
   if (n_spill) {
     std::vector<uint64_t> rows(n_spill * kNst);
     KC_HIP(c, hipMemcpyAsync(rows.data(), c->pstats2.p, rows.size() * 8, hipMemcpyDeviceToHost, s),
@@ -1338,6 +1345,7 @@ kc_status kc_query(kc_ctx* c, const uint64_t* kmers, uint64_t n, uint32_t* count
   a.tkeys = c->tkeys.as<uint64_t>();
   a.tcounts = c->tcounts.as<uint32_t>();
   a.slot_of = c->slot_of.as<uint32_t>();
+  a.slot_first = c->slot_first;
   a.okeys = c->okeys.as<uint64_t>();
   a.ocounts = c->ocounts.as<uint32_t>();
   a.ovf_used = c->ovf_used.as<uint32_t>();
@@ -1693,6 +1701,7 @@ static kc_status restore_file(const char* path, int device, kc_ctx** out, kc_ctx
     return give_up(KC_ERR_DEVICE, "restore setup failed");
   c->slot_of_h.resize(P);
   for (uint64_t u = 0; u < P; ++u) c->slot_of_h[u] = u < n_spill ? kNoSlot : (uint32_t)(u - n_spill);
+  c->slot_first = (int64_t)n_spill;
   const uint64_t sp = c->st.spilled_partitions, sb = c->st.spilled_bytes;
   c->st = h.stats;
   c->st.spilled_partitions = sp;
@@ -2339,6 +2348,7 @@ kc_status kc_count_batch(kc_ctx* c, const kc_chunk* chunks, uint32_t n_chunks, u
   c->pool_slots = (uint32_t)nparts;
   c->slot_of_h.resize(nparts);
   for (uint64_t u = 0; u < nparts; ++u) c->slot_of_h[u] = (uint32_t)u;
+  c->slot_first = 0;
   c->state = FINALIZED;
   resolve_timers(c);
   if (out) *out = c->st;
